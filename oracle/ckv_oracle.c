@@ -1,0 +1,534 @@
+/*
+ * ckv_oracle.c -- plain FP64 CPU oracle for Cherenkov photon-bunch generation
+ * and propagation through a refracting plane-parallel atmosphere to telescope
+ * spheres (arXiv 2006.14927, App. A flow; App. B propagation tail; sec. 3.3
+ * atmosphere tables; sec. 2 fiducial spheres).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant generator with the HIP library: it is written
+ * separately from the definitions, step by step, in FP64, and is meant to be
+ * read against the paper.  Build with -ffp-contract=off (no FMA contraction):
+ * bunch counts must come out of the same IEEE operations as on the GPU.
+ *
+ * Where the paper is silent the following readings are used (each is listed
+ * in the design notes of the repository):
+ *  - yield: Frank-Tamm with an index independent of wavelength, expectation
+ *    value (no Poisson draw), band [lambda_min, lambda_max];
+ *  - one index per step, taken at the step midpoint (yield, threshold, angle);
+ *  - beta constant along a step, from total energy and mass;
+ *  - n_b = ceil(N / bunch_size) equal sub-steps, photons per bunch = N / n_b;
+ *  - emission point uniform inside its sub-step; emission time t0 + s/(beta c);
+ *  - azimuth uniform, frame from Duff et al. (JCGT 2017) orthonormal basis;
+ *  - wavelength drawn from a 1/lambda^2 spectrum by inverse CDF;
+ *  - plane-parallel atmosphere, psi = n^2-1 piecewise linear between nodes of a
+ *    uniform grid anchored at the observation level (sec. 3.3.2 fast
+ *    interpolation); refraction from cumulative moments of psi (a 5-term
+ *    binomial series of the exact Snell integrals);
+ *  - drop rules: w <= w_min, emission below the observation level or at/above
+ *    the table top; each reason counted;
+ *  - sphere test on the infinite line through the ground point along the
+ *    observed direction; tangent counts as a hit; several hits allowed.
+ *
+ * Units: m, ns, MeV, nm.  Directions (u, v, w) with w = -dh/ds (> 0 downward).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_C_M_PER_NS 0.299792458
+#define OR_ALPHA 7.2973525693e-3          /* CODATA 2018 */
+#define OR_MASS_E 0.51099895000           /* MeV, CODATA 2018 */
+#define OR_MASS_MU 105.6583755            /* MeV, CODATA 2018 */
+#define OR_TWO_PI (2.0 * 3.14159265358979323846)
+
+enum { OR_DROP_MASS = 0, OR_DROP_THRESHOLD, OR_DROP_NONFINITE, OR_DROP_BELOW_OBS,
+       OR_DROP_ABOVE_TOP, OR_DROP_UPWARD, OR_DROP_GRAZING, OR_N_DROP };
+
+typedef struct {
+    /* atmosphere: uniform grid h_i = h_obs + i*step, i = 0..n_nodes-1 */
+    int64_t n_nodes;
+    double h_obs, step;
+    const double* psi;     /* n_nodes */
+    const double* P;       /* 5 x n_nodes: P[(j-1)*n_nodes + i] = int_{h_obs}^{h_i} psi^j dh */
+    /* telescopes */
+    int32_t n_tel;
+    const double *tx, *ty, *tr;
+    /* parameters */
+    double bunch_size, lambda_min, lambda_max, w_min;
+    uint64_t seed;
+} or_config;
+
+typedef struct {
+    const double *x0, *y0, *h0, *u, *v, *w, *len, *t0, *energy;
+    const uint8_t* ptype;
+    const uint32_t* shower_id;  /* RNG counter word 2 */
+    const uint32_t* seg_id;     /* RNG counter word 1: index of the step in its shower */
+    const int32_t* bucket;      /* output group (shower index) */
+    const double* t_ref;        /* per-segment copy of its shower's time origin */
+    int64_t n;
+} or_segments;
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, "Parallel random numbers: */
+/* as easy as 1, 2, 3"): 10 rounds of a 4-word Feistel-like network; each      */
+/* round multiplies words 0 and 2 by fixed constants, swaps, and xors in the   */
+/* key; the key is advanced by two Weyl constants between rounds.             */
+/* ------------------------------------------------------------------------- */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* uniform in (0,1): (r + 1/2) / 2^32, exact in FP64 */
+static double or_uniform(uint32_t r) { return ((double)r + 0.5) * (1.0 / 4294967296.0); }
+
+/* ------------------------------------------------------------------------- */
+/* Atmosphere tables (sec. 3.3.1 linear interpolation of tabulated quantities; */
+/* sec. 3.3.2 fine tables with uniform altitude steps built once at start).    */
+/* ------------------------------------------------------------------------- */
+
+/* number of uniform nodes h_obs + i*step that lie inside [alt[0], alt[n-1]] */
+int64_t or_grid_size(const double* alt, int64_t n, double h_obs, double step)
+{
+    if (n < 2 || !(step > 0.0) || h_obs < alt[0] || h_obs >= alt[n - 1]) return -1;
+    int64_t m = (int64_t)floor((alt[n - 1] - h_obs) / step) + 1;
+    while (m > 1 && h_obs + (double)(m - 1) * step > alt[n - 1]) --m;
+    return m;
+}
+
+/* eta at altitude h by linear interpolation in the input table; a node of the
+   input is returned exactly (sec. 3.3.1: search the bracketing pair, then
+   interpolate linearly) */
+static double or_eta_at(const double* alt, const double* eta, int64_t n, double h)
+{
+    int64_t lo = 0, hi = n - 1;
+    while (hi - lo > 1) {               /* binary search: alt[lo] <= h < alt[hi] */
+        int64_t mid = (lo + hi) / 2;
+        if (alt[mid] <= h) lo = mid; else hi = mid;
+    }
+    if (h == alt[lo]) return eta[lo];
+    if (h == alt[hi]) return eta[hi];
+    double f = (h - alt[lo]) / (alt[hi] - alt[lo]);
+    return eta[lo] + f * (eta[hi] - eta[lo]);
+}
+
+/* psi_i = n_i^2 - 1 = eta_i (2 + eta_i) on the uniform grid, and the cumulative
+   moments P_j(h_i) = int_{h_obs}^{h_i} psi(h)^j dh, j = 1..5, for psi linear
+   inside each cell: the cell integral of (a + (b-a) t)^j is
+   step/(j+1) * sum_{m=0..j} a^(j-m) b^m.  Summed upward from h_obs. */
+int or_build_tables(const double* alt, const double* eta, int64_t n, double h_obs,
+                    double step, int64_t n_nodes, double* psi, double* P)
+{
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        double h = h_obs + (double)i * step;
+        double e = or_eta_at(alt, eta, n, h);
+        psi[i] = e * (2.0 + e);
+    }
+    for (int j = 1; j <= 5; ++j) P[(j - 1) * n_nodes + 0] = 0.0;
+    for (int64_t i = 0; i + 1 < n_nodes; ++i) {
+        double a = psi[i], b = psi[i + 1];
+        for (int j = 1; j <= 5; ++j) {
+            double sum = 0.0;
+            for (int m = 0; m <= j; ++m) sum += pow(a, j - m) * pow(b, m);
+            P[(j - 1) * n_nodes + i + 1] = P[(j - 1) * n_nodes + i] + step / (j + 1) * sum;
+        }
+    }
+    return 0;
+}
+
+/* psi(h) and P_1..P_5(h): locate the cell directly from the uniform step (no
+   search), interpolate psi linearly, and add the partial-cell integral. */
+void or_lookup(const or_config* cf, double h, double* psi_out, double P_out[5])
+{
+    int64_t N = cf->n_nodes;
+    double h_top = cf->h_obs + (double)(N - 1) * cf->step;
+    double hc = h < cf->h_obs ? cf->h_obs : (h > h_top ? h_top : h);
+    double x = (hc - cf->h_obs) * (1.0 / cf->step);
+    int64_t i = (int64_t)floor(x);
+    if (i > N - 2) i = N - 2;
+    double f = x - (double)i;
+    double a = cf->psi[i], b = cf->psi[i + 1];
+    double p = a + f * (b - a);
+    *psi_out = p;
+    if (P_out) {
+        double dz = f * cf->step;
+        for (int j = 1; j <= 5; ++j) {
+            double sum = 0.0;
+            for (int m = 0; m <= j; ++m) sum += pow(a, j - m) * pow(p, m);
+            P_out[j - 1] = cf->P[(j - 1) * N + i] + dz / (j + 1) * sum;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Per-step setup (App. A: for each step the number of emitted photons is     */
+/* computed; the step is cut into sub-steps with one bunch of about 5 photons */
+/* each).                                                                     */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t status;       /* -1 emits: >= 0 drop reason */
+    int64_t n_b;
+    double N, photons, cos_t, sin_t, beta, ds, inv_beta_c, n_mid, psi_mid;
+    double D[3], b1[3], b2[3];   /* physical direction (u, v, -w) and its frame */
+} or_setup;
+
+double or_frank_tamm_k(double lambda_min_nm, double lambda_max_nm)
+{
+    /* 2 pi alpha (1/l1 - 1/l2), in photons per metre for sin^2(theta) = 1 */
+    return OR_TWO_PI * OR_ALPHA * (1.0 / lambda_min_nm - 1.0 / lambda_max_nm) * 1e9;
+}
+
+void or_segment_setup(const or_config* cf, const or_segments* sg, int64_t i, or_setup* st)
+{
+    memset(st, 0, sizeof(*st));
+    st->status = -1;
+    double E = sg->energy[i], L = sg->len[i];
+    double vals[9] = {sg->x0[i], sg->y0[i], sg->h0[i], sg->u[i], sg->v[i], sg->w[i], L,
+                      sg->t0[i], E};
+    for (int q = 0; q < 9; ++q)
+        if (!isfinite(vals[q])) { st->status = OR_DROP_NONFINITE; return; }
+    if (!(L > 0.0)) { st->status = OR_DROP_NONFINITE; return; }
+    double m = sg->ptype[i] == 1 ? OR_MASS_MU : OR_MASS_E;
+    double r = m / E;
+    double r2 = r * r;                       /* 1/gamma^2 = 1 - beta^2 */
+    if (!(r2 < 1.0)) { st->status = OR_DROP_MASS; return; }
+    double h_mid = sg->h0[i] - (0.5 * L) * sg->w[i];
+    double psi;
+    or_lookup(cf, h_mid, &psi, NULL);
+    double n2 = 1.0 + psi;
+    double num = psi - n2 * r2;              /* = (1 - r2) n^2 - 1 = beta^2 n^2 - 1 */
+    if (!(num > 0.0)) { st->status = OR_DROP_THRESHOLD; return; }
+    double sin2 = num / (n2 * (1.0 - r2));   /* 1 - 1/(beta n)^2 */
+    double K = or_frank_tamm_k(cf->lambda_min, cf->lambda_max);
+    double N = (K * L) * sin2;
+    double nb = ceil(N / cf->bunch_size);
+    st->n_b = (int64_t)nb;
+    st->N = N;
+    st->photons = N / nb;
+    st->psi_mid = psi;
+    st->n_mid = sqrt(n2);
+    st->cos_t = 1.0 / sqrt((1.0 - r2) * n2);
+    st->sin_t = sqrt(sin2);
+    st->beta = sqrt(1.0 - r2);
+    st->ds = L / nb;
+    st->inv_beta_c = 1.0 / (st->beta * OR_C_M_PER_NS);
+    /* frame around D (Duff et al. 2017, branchless orthonormal basis) */
+    double Dx = sg->u[i], Dy = sg->v[i], Dz = -sg->w[i];
+    double sgn = copysign(1.0, Dz);
+    double a = -1.0 / (sgn + Dz);
+    double b = Dx * Dy * a;
+    st->D[0] = Dx; st->D[1] = Dy; st->D[2] = Dz;
+    st->b1[0] = 1.0 + sgn * Dx * Dx * a; st->b1[1] = sgn * b; st->b1[2] = -sgn * Dx;
+    st->b2[0] = b; st->b2[1] = sgn + Dy * Dy * a; st->b2[2] = -Dy;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Propagation to the observation level (App. B: emission direction replaced */
+/* by the observed one through n sin(theta) conservation, ground position     */
+/* displaced by the refraction offset, travel time added to emission time).   */
+/* Exact Snell integrals for a stratified medium, expanded in                 */
+/* x = (psi - psi_e) / (n_e^2 w^2):                                           */
+/*   horizontal advance = (tan theta_e) sum_k a_k q^k D_k,                    */
+/*   c * time = 1/(n_e w) sum_k a_k q^k (n_e^2 D_k + D_{k+1}),                */
+/* with D_k = int_{h_obs}^{h_e} (psi - psi_e)^k dh and a_k the coefficients  */
+/* of (1+x)^(-1/2).                                                           */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double x_g, y_g, T, u_o, v_o, w_o, n_e, psi_e, S;
+} or_prop;
+
+void or_propagate(const or_config* cf, double x_e, double y_e, double h_e, double u, double v,
+                  double w, or_prop* pr)
+{
+    static const double a_k[5] = {1.0, -1.0 / 2.0, 3.0 / 8.0, -5.0 / 16.0, 35.0 / 128.0};
+    static const double binom[6][6] = {{1}, {1, 1}, {1, 2, 1}, {1, 3, 3, 1}, {1, 4, 6, 4, 1},
+                                        {1, 5, 10, 10, 5, 1}};
+    double psi_e, P[5];
+    or_lookup(cf, h_e, &psi_e, P);
+    double dh = h_e - cf->h_obs;
+    double Pj[6] = {dh, P[0], P[1], P[2], P[3], P[4]};   /* P_0 = h_e - h_obs */
+    double D[6];
+    for (int k = 0; k <= 5; ++k) {
+        double sum = 0.0;
+        for (int j = 0; j <= k; ++j) sum += binom[k][j] * pow(-psi_e, k - j) * Pj[j];
+        D[k] = sum;
+    }
+    double ne2 = 1.0 + psi_e;
+    double ne = sqrt(ne2);
+    double q = 1.0 / (ne2 * w * w);
+    double S = 0.0, Tsum = 0.0;
+    for (int k = 0; k <= 4; ++k) {
+        double c = a_k[k] * pow(q, k);
+        S += c * D[k];
+        Tsum += c * (ne2 * D[k] + D[k + 1]);
+    }
+    double n_obs = sqrt(1.0 + cf->psi[0]);
+    pr->S = S;
+    pr->x_g = x_e + (u / w) * S;
+    pr->y_g = y_e + (v / w) * S;
+    pr->T = Tsum / (OR_C_M_PER_NS * ne * w);
+    pr->u_o = u * ne / n_obs;
+    pr->v_o = v * ne / n_obs;
+    pr->w_o = sqrt(1.0 - pr->u_o * pr->u_o - pr->v_o * pr->v_o);
+    pr->n_e = ne;
+    pr->psi_e = psi_e;
+}
+
+/* ------------------------------------------------------------------------- */
+/* One bunch k of a step: sub-step emission point, direction on the Cherenkov */
+/* cone, wavelength, drop rules, propagation.                                 */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t status;      /* -1 propagated; >= 0 drop reason */
+    uint32_t r[4];
+    double x_e, y_e, h_e, t_e, u, v, w, lambda, photons;
+    or_prop pr;
+    double t;            /* arrival time minus the shower's t_ref */
+} or_bunch;
+
+void or_make_bunch(const or_config* cf, const or_segments* sg, int64_t i, const or_setup* st,
+                   int64_t k, or_bunch* bn)
+{
+    memset(bn, 0, sizeof(*bn));
+    uint32_t ctr[4] = {(uint32_t)k, sg->seg_id[i], sg->shower_id[i], 0u};
+    uint32_t key[2] = {(uint32_t)cf->seed, (uint32_t)(cf->seed >> 32)};
+    or_philox4x32_10(ctr, key, bn->r);
+    double u0 = or_uniform(bn->r[0]), u1 = or_uniform(bn->r[1]), u2 = or_uniform(bn->r[2]);
+    /* emission point: uniform inside sub-step k */
+    double s = ((double)k + u0) * st->ds;
+    bn->x_e = sg->x0[i] + s * sg->u[i];
+    bn->y_e = sg->y0[i] + s * sg->v[i];
+    bn->h_e = sg->h0[i] - s * sg->w[i];
+    bn->t_e = sg->t0[i] + s * st->inv_beta_c;
+    /* direction: cone of half-angle theta_c around D, azimuth phi */
+    double phi = OR_TWO_PI * u1;
+    double cp = cos(phi), sp = sin(phi);
+    double C[3];
+    for (int a = 0; a < 3; ++a)
+        C[a] = st->cos_t * st->D[a] + st->sin_t * (cp * st->b1[a] + sp * st->b2[a]);
+    bn->u = C[0]; bn->v = C[1]; bn->w = -C[2];
+    /* wavelength from dN/dlambda ~ 1/lambda^2 on [l1, l2] */
+    double il1 = 1.0 / cf->lambda_min, il2 = 1.0 / cf->lambda_max;
+    bn->lambda = 1.0 / (il1 - u2 * (il1 - il2));
+    bn->photons = st->photons;
+    double h_top = cf->h_obs + (double)(cf->n_nodes - 1) * cf->step;
+    if (bn->h_e < cf->h_obs) { bn->status = OR_DROP_BELOW_OBS; return; }
+    if (bn->h_e >= h_top) { bn->status = OR_DROP_ABOVE_TOP; return; }
+    if (bn->w <= 0.0) { bn->status = OR_DROP_UPWARD; return; }
+    if (bn->w <= cf->w_min) { bn->status = OR_DROP_GRAZING; return; }
+    bn->status = -1;
+    or_propagate(cf, bn->x_e, bn->y_e, bn->h_e, bn->u, bn->v, bn->w, &bn->pr);
+    bn->t = bn->t_e + bn->pr.T - sg->t_ref[i];
+}
+
+/* sphere test: line through (x_g, y_g, h_obs) along the observed direction;
+   it meets the sphere of radius R centred at (X, Y, h_obs) iff the squared
+   distance of closest approach dx^2+dy^2-b^2 is <= R^2 */
+double or_sphere_disc(double x_g, double y_g, double u_o, double v_o, double X, double Y,
+                      double R)
+{
+    double dx = x_g - X, dy = y_g - Y;
+    double b = dx * u_o + dy * v_o;
+    return b * b - (dx * dx + dy * dy - R * R);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Whole run: every step, every bunch, every telescope (brute force).         */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t seg;        /* index into the segment arrays of the call */
+    int64_t k;          /* bunch index inside its step */
+    int32_t tel, bucket;
+    double rec[8];      /* dx, dy, u_o, v_o, t, h_e, photons, lambda */
+    double disc;
+} or_hit;
+
+typedef struct {
+    or_hit* hits;
+    int64_t n_hits, cap;
+    int64_t n_bunches;
+    int64_t n_emitting;
+    int64_t drops[OR_N_DROP];
+} or_result;
+
+static void or_push(or_result* r, const or_hit* h)
+{
+    if (r->n_hits == r->cap) {
+        r->cap = r->cap ? 2 * r->cap : 1024;
+        r->hits = (or_hit*)realloc(r->hits, (size_t)r->cap * sizeof(or_hit));
+    }
+    r->hits[r->n_hits++] = *h;
+}
+
+static void or_run_range(const or_config* cf, const or_segments* sg, int64_t lo, int64_t hi,
+                         or_result* r, int64_t* n_b_out)
+{
+    for (int64_t i = lo; i < hi; ++i) {
+        or_setup st;
+        or_segment_setup(cf, sg, i, &st);
+        if (n_b_out) n_b_out[i] = st.status >= 0 ? 0 : st.n_b;
+        if (st.status >= 0) { r->drops[st.status]++; continue; }
+        r->n_emitting++;
+        r->n_bunches += st.n_b;
+        for (int64_t k = 0; k < st.n_b; ++k) {
+            or_bunch bn;
+            or_make_bunch(cf, sg, i, &st, k, &bn);
+            if (bn.status >= 0) { r->drops[bn.status]++; continue; }
+            for (int32_t t = 0; t < cf->n_tel; ++t) {
+                double disc = or_sphere_disc(bn.pr.x_g, bn.pr.y_g, bn.pr.u_o, bn.pr.v_o,
+                                             cf->tx[t], cf->ty[t], cf->tr[t]);
+                if (disc >= 0.0) {
+                    or_hit h;
+                    h.seg = i; h.k = k; h.tel = t; h.bucket = sg->bucket[i];
+                    h.rec[0] = bn.pr.x_g - cf->tx[t];
+                    h.rec[1] = bn.pr.y_g - cf->ty[t];
+                    h.rec[2] = bn.pr.u_o;
+                    h.rec[3] = bn.pr.v_o;
+                    h.rec[4] = bn.t;
+                    h.rec[5] = bn.h_e;
+                    h.rec[6] = bn.photons;
+                    h.rec[7] = bn.lambda;
+                    h.disc = disc;
+                    or_push(r, &h);
+                }
+            }
+        }
+    }
+}
+
+/* Runs all segments; hits are returned in segment order, bunch order, then
+   telescope order.  Grouping by (bucket, telescope) is left to the caller.
+   Threads split the segments into contiguous ranges; results are joined in
+   range order, so the output does not depend on the thread count. */
+or_result* or_run(const or_config* cf, const or_segments* sg, int nthreads, int64_t* n_b_out)
+{
+    or_result* res = (or_result*)calloc(1, sizeof(or_result));
+    if (nthreads < 1) nthreads = 1;
+    or_result* parts = (or_result*)calloc((size_t)nthreads, sizeof(or_result));
+#pragma omp parallel for schedule(static, 1) num_threads(nthreads)
+    for (int t = 0; t < nthreads; ++t) {
+        int64_t lo = sg->n * t / nthreads, hi = sg->n * (t + 1) / nthreads;
+        or_run_range(cf, sg, lo, hi, &parts[t], n_b_out);
+    }
+    for (int t = 0; t < nthreads; ++t) {
+        for (int64_t h = 0; h < parts[t].n_hits; ++h) or_push(res, &parts[t].hits[h]);
+        res->n_bunches += parts[t].n_bunches;
+        res->n_emitting += parts[t].n_emitting;
+        for (int d = 0; d < OR_N_DROP; ++d) res->drops[d] += parts[t].drops[d];
+        free(parts[t].hits);
+    }
+    free(parts);
+    return res;
+}
+
+int64_t or_result_n_hits(const or_result* r) { return r->n_hits; }
+void or_result_counters(const or_result* r, int64_t* out /* 2 + OR_N_DROP */)
+{
+    out[0] = r->n_bunches;
+    out[1] = r->n_emitting;
+    for (int d = 0; d < OR_N_DROP; ++d) out[2 + d] = r->drops[d];
+}
+void or_result_copy(const or_result* r, int64_t* seg, int64_t* k, int32_t* tel, int32_t* bucket,
+                    double* rec /* n x 8 */, double* disc)
+{
+    for (int64_t h = 0; h < r->n_hits; ++h) {
+        seg[h] = r->hits[h].seg; k[h] = r->hits[h].k;
+        tel[h] = r->hits[h].tel; bucket[h] = r->hits[h].bucket;
+        memcpy(rec + 8 * h, r->hits[h].rec, 8 * sizeof(double));
+        disc[h] = r->hits[h].disc;
+    }
+}
+void or_result_free(or_result* r)
+{
+    if (!r) return;
+    free(r->hits);
+    free(r);
+}
+
+/* Details of selected bunches, rows of 28 doubles:
+   status, n_b, photons, cos_t, sin_t, x_e, y_e, h_e, t_e, u, v, w, lambda,
+   x_g, y_g, T, u_o, v_o, w_o, t, n_e, psi_e, S, r0, r1, r2, r3, ds */
+void or_bunch_details(const or_config* cf, const or_segments* sg, int64_t m,
+                      const int64_t* seg, const int64_t* k, double* out /* m x 28 */)
+{
+    for (int64_t q = 0; q < m; ++q) {
+        double* o = out + 28 * q;
+        or_setup st;
+        or_segment_setup(cf, sg, seg[q], &st);
+        for (int z = 0; z < 28; ++z) o[z] = NAN;
+        o[0] = st.status; o[1] = (double)st.n_b; o[2] = st.photons;
+        o[3] = st.cos_t; o[4] = st.sin_t;
+        if (st.status >= 0 || k[q] < 0 || k[q] >= st.n_b) continue;
+        or_bunch bn;
+        or_make_bunch(cf, sg, seg[q], &st, k[q], &bn);
+        o[0] = bn.status;
+        o[5] = bn.x_e; o[6] = bn.y_e; o[7] = bn.h_e; o[8] = bn.t_e;
+        o[9] = bn.u; o[10] = bn.v; o[11] = bn.w; o[12] = bn.lambda;
+        if (bn.status < 0) {
+            o[13] = bn.pr.x_g; o[14] = bn.pr.y_g; o[15] = bn.pr.T;
+            o[16] = bn.pr.u_o; o[17] = bn.pr.v_o; o[18] = bn.pr.w_o; o[19] = bn.t;
+            o[20] = bn.pr.n_e; o[21] = bn.pr.psi_e; o[22] = bn.pr.S;
+        }
+        for (int a = 0; a < 4; ++a) o[23 + a] = (double)bn.r[a];
+        o[27] = st.ds;
+    }
+}
+
+/* per-segment setup table: rows of 16 doubles
+   status, n_b, N, photons, cos_t, sin_t, beta, ds, inv_beta_c, n_mid, b1[3], b2[3] */
+void or_segment_details(const or_config* cf, const or_segments* sg, double* out)
+{
+    for (int64_t i = 0; i < sg->n; ++i) {
+        or_setup st;
+        or_segment_setup(cf, sg, i, &st);
+        double* o = out + 16 * i;
+        o[0] = st.status; o[1] = (double)st.n_b; o[2] = st.N; o[3] = st.photons;
+        o[4] = st.cos_t; o[5] = st.sin_t; o[6] = st.beta; o[7] = st.ds; o[8] = st.inv_beta_c;
+        o[9] = st.n_mid;
+        for (int a = 0; a < 3; ++a) { o[10 + a] = st.b1[a]; o[13 + a] = st.b2[a]; }
+    }
+}
+
+/* lookups at many altitudes: out rows psi, P1..P5 */
+void or_lookup_many(const or_config* cf, int64_t m, const double* h, double* out)
+{
+    for (int64_t q = 0; q < m; ++q) {
+        double P[5];
+        or_lookup(cf, h[q], out + 6 * q, P);
+        for (int j = 0; j < 5; ++j) out[6 * q + 1 + j] = P[j];
+    }
+}
+
+/* propagate arbitrary photons: rows of 9 = x_g, y_g, T, u_o, v_o, w_o, n_e, psi_e, S */
+void or_propagate_many(const or_config* cf, int64_t m, const double* in /* m x 6 */, double* out)
+{
+    for (int64_t q = 0; q < m; ++q) {
+        const double* p = in + 6 * q;
+        or_prop pr;
+        or_propagate(cf, p[0], p[1], p[2], p[3], p[4], p[5], &pr);
+        double* o = out + 9 * q;
+        o[0] = pr.x_g; o[1] = pr.y_g; o[2] = pr.T; o[3] = pr.u_o; o[4] = pr.v_o;
+        o[5] = pr.w_o; o[6] = pr.n_e; o[7] = pr.psi_e; o[8] = pr.S;
+    }
+}
