@@ -1,0 +1,214 @@
+/*
+ * ckv.h -- C ABI of the MI355X Cherenkov photon-bunch library.
+ *
+ * What it computes (arXiv 2006.14927): for every charged-particle track step
+ * the number of Cherenkov photons is computed and split into bunches of about
+ * five photons, one bunch per sub-step (App. A); every bunch is bent by
+ * atmospheric refraction and propagated to the observation level, where its
+ * position, observed direction and arrival time are obtained (App. B); the
+ * bunches that cross a telescope's fiducial sphere are written out per
+ * telescope (sec. 2; App. A, TELOUT).  Atmospheric quantities come from fine
+ * tables with a uniform altitude step, built once (sec. 3.3.2 "fast
+ * interpolation"), from a user-supplied profile (sec. 2, external profiles).
+ *
+ * Conventions: units m, ns, MeV, nm.  x, y horizontal, h altitude.  Directions
+ * are (u, v, w) = (dx/ds, dy/ds, -dh/ds): w > 0 is downward.  The atmosphere
+ * is plane-parallel.
+ *
+ * Errors: every call returns CKV_OK (0) or a negative code; no exception
+ * crosses the ABI.  ckv_last_error() gives a message for the calling thread.
+ * Arguments are validated on the host before anything is enqueued.  Conditions
+ * only visible on the device (capacity overflow, dropped bunches, bad segment
+ * values) do not fail the call: they are reported in ckv_result.
+ *
+ * Ownership: the caller owns every large device buffer (segments, records,
+ * offsets, result, workspace).  Handles (ckv_atmo, ckv_array) are immutable
+ * after creation, own only their small host and device tables, and may be
+ * shared by concurrent runs on different streams.  ckv_run is re-entrant
+ * given distinct workspaces and outputs.
+ */
+#ifndef CKV_H
+#define CKV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CKV_VERSION 100
+
+enum {
+    CKV_OK = 0,
+    CKV_ERR_ARG = -1,       /* invalid argument (null pointer, negative size, bad value) */
+    CKV_ERR_TABLE = -2,     /* invalid atmosphere profile or telescope list */
+    CKV_ERR_CAPACITY = -3,  /* workspace smaller than ckv_workspace_size() */
+    CKV_ERR_HIP = -4,       /* HIP runtime error (launch, copy, allocation of handle tables) */
+    CKV_ERR_NOMEM = -5      /* host allocation failed */
+};
+
+/* arithmetic of the per-bunch path (the per-step bunch count is always FP64) */
+enum { CKV_FP64 = 0, CKV_MIXED = 1 };
+
+/* particle types: mass used for beta */
+enum { CKV_ELECTRON = 0, CKV_MUON = 1 };
+
+/* reasons counted in ckv_result.drops */
+enum {
+    CKV_DROP_MASS = 0,       /* step: total energy <= mass */
+    CKV_DROP_THRESHOLD = 1,  /* step: beta n <= 1 at the step midpoint (no light) */
+    CKV_DROP_NONFINITE = 2,  /* step: non-finite value or length <= 0 */
+    CKV_DROP_BELOW_OBS = 3,  /* bunch: emitted below the observation level */
+    CKV_DROP_ABOVE_TOP = 4,  /* bunch: emitted at or above the table top */
+    CKV_DROP_UPWARD = 5,     /* bunch: w <= 0, never reaches the ground */
+    CKV_DROP_GRAZING = 6,    /* bunch: 0 < w <= w_min */
+    CKV_N_DROP = 8
+};
+
+typedef struct ckv_atmo ckv_atmo;
+typedef struct ckv_array ckv_array;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ckv_last_error(void);
+/* CKV_VERSION of the loaded library. */
+int ckv_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Atmosphere (sec. 3.3.1 tabulated refractive index vs altitude, linear
+ * interpolation between tabulated points; sec. 3.3.2 fine tables with a
+ * uniform step built once; sec. 2 external profiles).
+ *
+ * alt_m[n] strictly increasing, eta[n] = n-1 >= 0, host memory, copied.
+ * The library samples eta by linear interpolation onto the uniform grid
+ * h_i = obs_level_m + i*step_m inside [alt_m[0], alt_m[n-1]] (a grid node that
+ * coincides with an input node takes its value exactly), with step_m = 0
+ * meaning alt_m[1]-alt_m[0].  It stores psi = n^2-1 at the nodes and the
+ * cumulative moments P_j(h_i) = integral from obs level to h_i of psi^j dh,
+ * j = 1..5, for psi linear inside each cell; these drive the refraction
+ * offset and travel time.  Tables are uploaded to the current HIP device.
+ * Errors: CKV_ERR_ARG (null, n < 2, step < 0), CKV_ERR_TABLE (altitudes not
+ * increasing, eta < 0 or non-finite, obs level outside the table, fewer
+ * than 2 nodes), CKV_ERR_HIP.
+ * ------------------------------------------------------------------------- */
+int ckv_atmo_create(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
+                    double step_m, ckv_atmo** out);
+/* Grid of the handle: node count, observation level, step. */
+int ckv_atmo_info(const ckv_atmo* atmo, int64_t* n_nodes, double* obs_level_m, double* step_m);
+/* Host copies of the tables: psi[n_nodes], P[5*n_nodes] with
+   P[(j-1)*n_nodes + i] = P_j(h_i).  Either pointer may be NULL. */
+int ckv_atmo_tables(const ckv_atmo* atmo, double* psi, double* P);
+int ckv_atmo_destroy(ckv_atmo* atmo);
+
+/* ---------------------------------------------------------------------------
+ * Telescopes (sec. 2: fiducial spheres at positions on the ground).
+ * Centres (x_m, y_m) at the observation level, sphere radii r_m > 0; host
+ * memory, copied.  1 <= n_tel <= CKV_MAX_TEL.  The library builds a uniform
+ * 2-D candidate grid so each bunch tests only nearby spheres.
+ * Errors: CKV_ERR_ARG, CKV_ERR_TABLE (non-finite or r <= 0), CKV_ERR_HIP.
+ * ------------------------------------------------------------------------- */
+#define CKV_MAX_TEL 1024
+int ckv_array_create(const double* x_m, const double* y_m, const double* r_m, int32_t n_tel,
+                     ckv_array** out);
+int ckv_array_destroy(ckv_array* arr);
+
+/* ---------------------------------------------------------------------------
+ * Run inputs.  All pointers below are DEVICE pointers.
+ * ------------------------------------------------------------------------- */
+
+/* Track steps, structure of arrays, n entries each, grouped by shower
+   (App. A: each particle track is subdivided into steps).  Start point
+   (x0, y0, h0) [m], unit direction (u, v, w) with w = -dh/ds, length [m],
+   start time t0 [ns], total energy [MeV], particle type (CKV_ELECTRON or
+   CKV_MUON; charge 1). */
+typedef struct {
+    const double *x0, *y0, *h0, *u, *v, *w, *length, *t0, *energy;
+    const uint8_t* ptype;
+    int64_t n;
+} ckv_segments;
+
+/* Showers: steps of shower s are [seg_offsets[s], seg_offsets[s+1]),
+   seg_offsets[0] = 0, seg_offsets[n_showers] = n.  t_ref[s] is subtracted
+   from arrival times.  Random numbers of bunch k of the step with index j in
+   its shower come from Philox4x32-10 with counter
+   (k, seg_id_base[s] + j, shower_ids[s], 0) and the 64-bit seed as key
+   (sec. 5.2: runs reproduce the same random sequence); shower_ids NULL means
+   shower_ids[s] = s, seg_id_base NULL means 0.  Splitting a shower's steps
+   into several runs with the matching seg_id_base gives the same bunches. */
+typedef struct {
+    const int64_t* seg_offsets;   /* n_showers + 1 */
+    const double* t_ref;          /* n_showers */
+    const uint32_t* shower_ids;   /* n_showers or NULL */
+    const int64_t* seg_id_base;   /* n_showers or NULL */
+    int32_t n_showers;
+} ckv_showers;
+
+typedef struct {
+    double bunch_size;     /* photons per bunch target (App. A: typically 5), > 0 */
+    double lambda_min_nm;  /* Cherenkov band, 0 < lambda_min < lambda_max */
+    double lambda_max_nm;
+    double w_min;          /* bunches with w <= w_min are dropped (0 <= w_min < 1) */
+    uint64_t seed;         /* Philox key */
+    int32_t precision;     /* CKV_FP64 or CKV_MIXED */
+    int32_t tile_segments; /* steps per emit tile, 0 = default (32) */
+    int32_t grid;          /* emit workgroups, 0 = one per compute unit */
+    int32_t reserved;
+} ckv_params;
+
+/* Device-side report, written by ckv_run (the caller syncs the stream before
+   reading it). */
+typedef struct {
+    int64_t n_bunches;       /* bunches generated: sum of n_b over steps */
+    int64_t n_hits;          /* records found (sphere crossings) */
+    int64_t n_records;       /* records written = min(n_hits, capacity) if no overflow */
+    int64_t n_emitting;      /* steps with at least one bunch */
+    int64_t n_tiles;         /* emit tiles processed */
+    int64_t drops[CKV_N_DROP];
+    int32_t overflow;        /* 1: n_hits > capacity; records and ids are not valid,
+                                tel_offsets are; rerun with capacity >= n_hits */
+    int32_t error;           /* bit 0: seg_offsets not non-decreasing or out of range;
+                                bit 1: a tile of tile_segments steps held >= 2^30 bunches
+                                (its bunches were skipped) */
+} ckv_result;
+
+/* Output.  records: capacity x 8 floats per record
+     (x - X_tel, y - Y_tel, u_obs, v_obs, t - t_ref, h_emit, photons, lambda)
+   [m, m, -, -, ns, m, photons, nm].  Records of shower s and telescope k are
+   records[tel_offsets[s*n_tel + k] .. tel_offsets[s*n_tel + k + 1]), in
+   ascending (step, bunch) order.  ids (optional, NULL to skip): capacity x 2
+   int64 per record = (index of the step in the segment arrays, bunch k). */
+typedef struct {
+    float* records;
+    int64_t* ids;
+    int64_t capacity;
+    int64_t* tel_offsets;    /* n_showers * n_tel + 1 */
+    ckv_result* result;
+} ckv_output;
+
+/* Bytes of device workspace ckv_run needs for these sizes. */
+size_t ckv_workspace_size(int64_t n_segments, int32_t n_showers, int32_t n_tel,
+                          int64_t capacity, const ckv_params* params);
+
+/* Generate and propagate every bunch of every step, test it against every
+   telescope sphere, and write the crossing records per (shower, telescope).
+   Fully asynchronous on `stream` (a hipStream_t; NULL = default stream);
+   enqueues kernels only, so it can be captured into a HIP graph.
+   workspace: device memory of ws_bytes >= ckv_workspace_size(...), any
+   content.  Errors (synchronous): CKV_ERR_ARG for null pointers, n < 0,
+   n_showers < 1, bad params; CKV_ERR_CAPACITY for a small workspace;
+   CKV_ERR_HIP if a launch fails. */
+int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
+            const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
+            ckv_output* out, void* stream);
+
+/* Bunch count per step only (the first stage of ckv_run): n_b[i] for every
+   step (0 for dropped steps), FP64, the same values ckv_run uses.  n_b is a
+   device int64 array of n entries.  Asynchronous on `stream`. */
+int ckv_count(const ckv_segments* segs, const ckv_params* params, const ckv_atmo* atmo,
+              int64_t* n_b, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CKV_H */

@@ -167,7 +167,8 @@ class Config:
 class SegView:
     """Per-segment arrays in the layout the C oracle reads."""
 
-    def __init__(self, segs, *, seg_id_base: Optional[np.ndarray] = None):
+    def __init__(self, segs, *, seg_id_base: Optional[np.ndarray] = None,
+                 seg_id: Optional[np.ndarray] = None):
         n = segs.n
         self.arrs = {}
         for f in segs.FIELDS:
@@ -177,9 +178,12 @@ class SegView:
         counts = np.diff(offs)
         bucket = np.repeat(np.arange(segs.n_showers, dtype=np.int32), counts)
         first = np.repeat(offs[:-1], counts)
+        explicit_id = seg_id
         seg_id = (np.arange(n, dtype=np.int64) - first)
         if seg_id_base is not None:
             seg_id = seg_id + np.repeat(np.asarray(seg_id_base, dtype=np.int64), counts)
+        if explicit_id is not None:
+            seg_id = np.asarray(explicit_id, dtype=np.int64)
         self.arrs["seg_id"] = seg_id.astype(np.uint32)
         self.arrs["shower_id"] = np.repeat(np.asarray(segs.shower_ids, dtype=np.uint32), counts)
         self.arrs["bucket"] = bucket
@@ -213,8 +217,11 @@ class Result:
     disc: np.ndarray
 
 
-def run(cfg: Config, segs, nthreads: int = 1, seg_id_base=None) -> Result:
-    sv = SegView(segs, seg_id_base=seg_id_base)
+def run(cfg: Config, segs, nthreads: int = 1, seg_id_base=None, seg_id=None) -> Result:
+    """All bunches of all steps.  seg_id (optional, per step) overrides the
+    step's index in its shower, the RNG counter word 1 (used to run a subset of
+    a shower's steps with their original random numbers)."""
+    sv = SegView(segs, seg_id_base=seg_id_base, seg_id=seg_id)
     L = lib()
     n_b = np.zeros(sv.n, dtype=np.int64)
     r = L.or_run(C.byref(cfg.c), C.byref(sv.c), int(nthreads), _p(n_b))

@@ -1,0 +1,269 @@
+"""Python binding of libckv.so (ctypes): argument marshalling only.
+
+Every step of the computation runs in the HIP library; PyTorch supplies device
+memory and the stream.  Importing this module does not load the library;
+the first call does, and raises if `libckv.so` has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libckv.so")
+
+CKV_FP64 = 0
+CKV_MIXED = 1
+DROP_NAMES = ("mass", "threshold", "nonfinite", "below_obs", "above_top", "upward", "grazing")
+RECORD_FIELDS = ("dx", "dy", "u_obs", "v_obs", "t", "h_emit", "photons", "lambda")
+
+EXPORTED = ("ckv_last_error", "ckv_version", "ckv_atmo_create", "ckv_atmo_info", "ckv_atmo_tables",
+            "ckv_atmo_destroy", "ckv_array_create", "ckv_array_destroy", "ckv_workspace_size",
+            "ckv_run", "ckv_count")
+
+
+class CkvError(RuntimeError):
+    pass
+
+
+class _Segments(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in ("x0", "y0", "h0", "u", "v", "w", "length", "t0",
+                                          "energy", "ptype")] + [("n", C.c_int64)]
+
+
+class _Showers(C.Structure):
+    _fields_ = [("seg_offsets", C.c_void_p), ("t_ref", C.c_void_p), ("shower_ids", C.c_void_p),
+                ("seg_id_base", C.c_void_p), ("n_showers", C.c_int32)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("bunch_size", C.c_double), ("lambda_min_nm", C.c_double),
+                ("lambda_max_nm", C.c_double), ("w_min", C.c_double), ("seed", C.c_uint64),
+                ("precision", C.c_int32), ("tile_segments", C.c_int32), ("grid", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("n_bunches", C.c_int64), ("n_hits", C.c_int64), ("n_records", C.c_int64),
+                ("n_emitting", C.c_int64), ("n_tiles", C.c_int64), ("drops", C.c_int64 * 8),
+                ("overflow", C.c_int32), ("error", C.c_int32)]
+
+
+class _Output(C.Structure):
+    _fields_ = [("records", C.c_void_p), ("ids", C.c_void_p), ("capacity", C.c_int64),
+                ("tel_offsets", C.c_void_p), ("result", C.c_void_p)]
+
+
+RESULT_BYTES = C.sizeof(_Result)
+_lib = None
+
+
+def lib():
+    """The loaded library; raises CkvError if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CkvError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.ckv_last_error.restype = C.c_char_p
+        L.ckv_version.restype = C.c_int
+        L.ckv_atmo_create.argtypes = [P, P, I64, D, D, C.POINTER(P)]
+        L.ckv_atmo_info.argtypes = [P, P, P, P]
+        L.ckv_atmo_tables.argtypes = [P, P, P]
+        L.ckv_atmo_destroy.argtypes = [P]
+        L.ckv_array_create.argtypes = [P, P, P, I32, C.POINTER(P)]
+        L.ckv_array_destroy.argtypes = [P]
+        L.ckv_workspace_size.restype = C.c_size_t
+        L.ckv_workspace_size.argtypes = [I64, I32, I32, I64, C.POINTER(_Params)]
+        L.ckv_run.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params), P, P,
+                              P, C.c_size_t, C.POINTER(_Output), P]
+        L.ckv_count.argtypes = [C.POINTER(_Segments), C.POINTER(_Params), P, P, P]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise CkvError(f"ckv error {rc}: {lib().ckv_last_error().decode()}")
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# handles
+# ---------------------------------------------------------------------------
+
+class Atmosphere:
+    """ckv_atmo: uniform fine tables built from a tabulated n-1 profile."""
+
+    def __init__(self, alt, eta, obs_level: float, step: float = 0.0):
+        self._alt = np.ascontiguousarray(alt, dtype=np.float64)
+        self._eta = np.ascontiguousarray(eta, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().ckv_atmo_create(_np_ptr(self._alt), _np_ptr(self._eta), self._alt.shape[0],
+                                     float(obs_level), float(step), C.byref(h)))
+        self.handle = h
+
+    def info(self):
+        n = C.c_int64()
+        h = C.c_double()
+        st = C.c_double()
+        _check(lib().ckv_atmo_info(self.handle, C.byref(n), C.byref(h), C.byref(st)))
+        return n.value, h.value, st.value
+
+    def tables(self):
+        n, _, _ = self.info()
+        psi = np.empty(n)
+        P = np.empty((5, n))
+        _check(lib().ckv_atmo_tables(self.handle, _np_ptr(psi), _np_ptr(P)))
+        return psi, P
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ckv_atmo_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+class TelescopeArray:
+    """ckv_array: telescope spheres and their candidate grid."""
+
+    def __init__(self, x, y, r):
+        self.x = np.ascontiguousarray(x, dtype=np.float64)
+        self.y = np.ascontiguousarray(y, dtype=np.float64)
+        self.r = np.ascontiguousarray(r, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().ckv_array_create(_np_ptr(self.x), _np_ptr(self.y), _np_ptr(self.r),
+                                      self.x.shape[0], C.byref(h)))
+        self.handle = h
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ckv_array_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+# ---------------------------------------------------------------------------
+# device inputs
+# ---------------------------------------------------------------------------
+
+class DeviceSegments:
+    """Segments and shower bookkeeping resident in device memory (torch)."""
+
+    FIELDS = ("x0", "y0", "h0", "u", "v", "w", "length", "t0", "energy")
+
+    def __init__(self, segs, device="cuda", seg_id_base=None):
+        import torch
+        self.t = {f: torch.as_tensor(np.ascontiguousarray(getattr(segs, f), dtype=np.float64),
+                                     device=device) for f in self.FIELDS}
+        self.t["ptype"] = torch.as_tensor(np.ascontiguousarray(segs.ptype, dtype=np.uint8),
+                                          device=device)
+        self.seg_offsets = torch.as_tensor(np.asarray(segs.seg_offsets, dtype=np.int64), device=device)
+        self.t_ref = torch.as_tensor(np.asarray(segs.t_ref, dtype=np.float64), device=device)
+        self.shower_ids = torch.as_tensor(np.asarray(segs.shower_ids, dtype=np.uint32).view(np.int32),
+                                          device=device)
+        self.seg_id_base = None if seg_id_base is None else torch.as_tensor(
+            np.asarray(seg_id_base, dtype=np.int64), device=device)
+        self.n = segs.n
+        self.n_showers = segs.n_showers
+
+    def c_segments(self) -> _Segments:
+        t = self.t
+        return _Segments(*[t[f].data_ptr() for f in self.FIELDS], t["ptype"].data_ptr(), self.n)
+
+    def c_showers(self) -> _Showers:
+        return _Showers(self.seg_offsets.data_ptr(), self.t_ref.data_ptr(),
+                        self.shower_ids.data_ptr(),
+                        self.seg_id_base.data_ptr() if self.seg_id_base is not None else None,
+                        self.n_showers)
+
+
+def make_params(*, precision=CKV_MIXED, bunch_size=5.0, lambda_min=300.0, lambda_max=600.0,
+                w_min=0.1, seed=0x14927, tile_segments=0, grid=0) -> _Params:
+    return _Params(bunch_size, lambda_min, lambda_max, w_min, int(seed) & (2**64 - 1),
+                   int(precision), int(tile_segments), int(grid), 0)
+
+
+def workspace_size(n_segments, n_showers, n_tel, capacity, params: _Params) -> int:
+    return int(lib().ckv_workspace_size(n_segments, n_showers, n_tel, capacity, C.byref(params)))
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class RunOutput:
+    records: "object"       # torch float32 (capacity, 8)
+    ids: "object"           # torch int64 (capacity, 2) or None
+    tel_offsets: "object"   # torch int64 (n_showers*n_tel + 1)
+    result_raw: "object"    # torch uint8 (RESULT_BYTES)
+
+    def result(self) -> dict:
+        r = _Result.from_buffer_copy(self.result_raw.cpu().numpy().tobytes())
+        return dict(n_bunches=r.n_bunches, n_hits=r.n_hits, n_records=r.n_records,
+                    n_emitting=r.n_emitting, n_tiles=r.n_tiles,
+                    drops=dict(zip(DROP_NAMES, list(r.drops)[:7])), overflow=r.overflow,
+                    error=r.error)
+
+
+class Runner:
+    """Holds the workspace and outputs for repeated ckv_run calls of one shape."""
+
+    def __init__(self, dsegs: DeviceSegments, atmo: Atmosphere, tels: TelescopeArray,
+                 params: _Params, capacity: int, want_ids: bool = True, device="cuda"):
+        import torch
+        self.dsegs, self.atmo, self.tels, self.params = dsegs, atmo, tels, params
+        self.capacity = int(capacity)
+        ws = workspace_size(dsegs.n, dsegs.n_showers, tels.n, self.capacity, params)
+        self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+        self.records = torch.empty((max(self.capacity, 1), 8), dtype=torch.float32, device=device)
+        self.ids = torch.empty((max(self.capacity, 1), 2), dtype=torch.int64, device=device) \
+            if want_ids else None
+        self.tel_offsets = torch.empty(dsegs.n_showers * tels.n + 1, dtype=torch.int64, device=device)
+        self.result_raw = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
+        self._segs = dsegs.c_segments()
+        self._showers = dsegs.c_showers()
+        self._out = _Output(self.records.data_ptr(),
+                            self.ids.data_ptr() if self.ids is not None else None,
+                            self.capacity, self.tel_offsets.data_ptr(), self.result_raw.data_ptr())
+
+    def run(self, stream=None) -> RunOutput:
+        _check(lib().ckv_run(C.byref(self._segs), C.byref(self._showers), C.byref(self.params),
+                             self.atmo.handle, self.tels.handle, C.c_void_p(self.workspace.data_ptr()),
+                             self.workspace.numel(), C.byref(self._out), _stream_ptr(stream)))
+        return RunOutput(self.records, self.ids, self.tel_offsets, self.result_raw)
+
+
+def count(dsegs: DeviceSegments, atmo: Atmosphere, params: _Params, stream=None):
+    """Bunches per step (device int64 tensor)."""
+    import torch
+    n_b = torch.empty(max(dsegs.n, 1), dtype=torch.int64, device=dsegs.t["x0"].device)
+    segs = dsegs.c_segments()
+    _check(lib().ckv_count(C.byref(segs), C.byref(params), atmo.handle,
+                           C.c_void_p(n_b.data_ptr()), _stream_ptr(stream)))
+    return n_b[:dsegs.n]
+
+
+def run(segs, atmo: Atmosphere, tels: TelescopeArray, *, capacity: int, want_ids=True,
+        stream=None, **param_kw) -> RunOutput:
+    """One-shot convenience: segments (synth.Segments or DeviceSegments) -> records."""
+    d = segs if isinstance(segs, DeviceSegments) else DeviceSegments(segs)
+    return Runner(d, atmo, tels, make_params(**param_kw), capacity, want_ids).run(stream)

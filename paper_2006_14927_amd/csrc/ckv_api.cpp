@@ -1,0 +1,314 @@
+// C ABI entry points: argument validation, handle construction, workspace
+// layout and the launch of one run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ckv_internal.h"
+
+namespace ckv {
+
+namespace {
+thread_local std::string g_error;
+
+int hip_fail(const char* what, hipError_t e)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return CKV_ERR_HIP;
+}
+
+template <typename T>
+int upload(const T* host, size_t count, T** dev)
+{
+    hipError_t e = hipMalloc((void**)dev, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return hip_fail("hipMalloc", e);
+    e = hipMemcpy(*dev, host, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail("hipMemcpy", e);
+    return CKV_OK;
+}
+
+double frank_tamm_k(double lambda_min_nm, double lambda_max_nm)
+{
+    // photons per metre of track per unit sin^2(theta_c): 2 pi alpha (1/l1 - 1/l2)
+    return 2.0 * kPi * kFineStructure * (1.0 / lambda_min_nm - 1.0 / lambda_max_nm) * 1e9;
+}
+
+int check_params(const ckv_params* p)
+{
+    if (!p) { set_error("params is NULL"); return CKV_ERR_ARG; }
+    if (!(p->bunch_size > 0.0) || !std::isfinite(p->bunch_size)) {
+        set_error("bunch_size must be > 0"); return CKV_ERR_ARG;
+    }
+    if (!(p->lambda_min_nm > 0.0) || !(p->lambda_max_nm > p->lambda_min_nm) ||
+        !std::isfinite(p->lambda_max_nm)) {
+        set_error("need 0 < lambda_min < lambda_max"); return CKV_ERR_ARG;
+    }
+    if (!(p->w_min >= 0.0) || !(p->w_min < 1.0)) { set_error("need 0 <= w_min < 1"); return CKV_ERR_ARG; }
+    if (p->precision != CKV_FP64 && p->precision != CKV_MIXED) {
+        set_error("unknown precision"); return CKV_ERR_ARG;
+    }
+    if (p->tile_segments < 0 || p->tile_segments > kMaxTileSegs) {
+        set_error("tile_segments must be in [0, 64]"); return CKV_ERR_ARG;
+    }
+    if (p->grid < 0) { set_error("grid must be >= 0"); return CKV_ERR_ARG; }
+    return CKV_OK;
+}
+
+int check_segments(const ckv_segments* s)
+{
+    if (!s) { set_error("segments is NULL"); return CKV_ERR_ARG; }
+    if (s->n < 0) { set_error("segment count < 0"); return CKV_ERR_ARG; }
+    if (s->n > 0 && (!s->x0 || !s->y0 || !s->h0 || !s->u || !s->v || !s->w || !s->length ||
+                     !s->t0 || !s->energy || !s->ptype)) {
+        set_error("a segment array is NULL"); return CKV_ERR_ARG;
+    }
+    if (s->n >= ((int64_t)1 << 40)) { set_error("too many segments"); return CKV_ERR_ARG; }
+    return CKV_OK;
+}
+
+int current_device(int want)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail("hipGetDevice", e);
+    if (dev != want) { set_error("handle was created on another device"); return CKV_ERR_ARG; }
+    return CKV_OK;
+}
+
+constexpr int kDefaultTileSegs = 32;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, int64_t capacity,
+                        const ckv_params* p, RunPlan* plan, void* base)
+{
+    const int ts = (p && p->tile_segments > 0) ? p->tile_segments : kDefaultTileSegs;
+    const int64_t max_tiles = n_segments / ts + n_showers + 1;
+    const int64_t max_blocks = max_tiles / kRowBlock + n_showers + 1;
+    const int64_t grid = (p && p->grid > 0) ? p->grid : kMaxEmitGrid;
+    const int64_t n_waves = grid * kMaxEmitWaves;
+    // crossings fill blocks back to back; each wave leaves at most one partial block
+    const int64_t slots_needed = capacity + (n_waves + 1) * kStageBlock;
+    const int64_t stage_blocks = (slots_needed + kStageBlock - 1) / kStageBlock;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    size_t o_ctrl = take(sizeof(int64_t) * kCtrlSlots);
+    size_t o_tb = take(sizeof(int64_t) * (n_showers + 1));
+    size_t o_bb = take(sizeof(int64_t) * (n_showers + 1));
+    size_t o_counts = take(sizeof(int32_t) * (size_t)max_tiles * n_tel);
+    size_t o_bsum = take(sizeof(int32_t) * (size_t)max_blocks * n_tel);
+    size_t o_st = take(sizeof(int32_t) * (size_t)n_showers * n_tel);
+    size_t o_fill = take(sizeof(int32_t) * (size_t)stage_blocks);
+    size_t o_stage = take(sizeof(StageEntry) * (size_t)stage_blocks * kStageBlock);
+    if (plan) {
+        char* b = (char*)base;
+        plan->tile_segs = ts;
+        plan->max_tiles = max_tiles;
+        plan->max_row_blocks = max_blocks;
+        plan->stage_slots = stage_blocks * kStageBlock;
+        plan->ctrl = (int64_t*)(b + o_ctrl);
+        plan->tiles_before = (int64_t*)(b + o_tb);
+        plan->blocks_before = (int64_t*)(b + o_bb);
+        plan->counts = (int32_t*)(b + o_counts);
+        plan->block_sums = (int32_t*)(b + o_bsum);
+        plan->shower_tel = (int32_t*)(b + o_st);
+        plan->stage_fill = (int32_t*)(b + o_fill);
+        plan->stage = (StageEntry*)(b + o_stage);
+    }
+    return off;
+}
+
+}  // namespace ckv
+
+using namespace ckv;
+
+extern "C" {
+
+const char* ckv_last_error(void) { return g_error.c_str(); }
+
+int ckv_version(void) { return CKV_VERSION; }
+
+int ckv_atmo_create(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
+                    double step_m, ckv_atmo** out)
+{
+    if (!alt_m || !eta || !out) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    *out = nullptr;
+    if (n < 2) { set_error("atmosphere needs at least 2 points"); return CKV_ERR_ARG; }
+    if (!(step_m >= 0.0) || !std::isfinite(step_m)) { set_error("step must be >= 0"); return CKV_ERR_ARG; }
+    if (!std::isfinite(obs_level_m)) { set_error("observation level not finite"); return CKV_ERR_ARG; }
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(alt_m[i]) || !std::isfinite(eta[i]) || eta[i] < 0.0) {
+            set_error("atmosphere: non-finite altitude or eta < 0"); return CKV_ERR_TABLE;
+        }
+        if (i > 0 && !(alt_m[i] > alt_m[i - 1])) {
+            set_error("atmosphere: altitudes must increase strictly"); return CKV_ERR_TABLE;
+        }
+    }
+    ckv_atmo* a = new (std::nothrow) ckv_atmo();
+    if (!a) { set_error("out of host memory"); return CKV_ERR_NOMEM; }
+    int rc = build_atmo_tables(alt_m, eta, n, obs_level_m, step_m, a);
+    if (rc) { delete a; return rc; }
+    if (a->n_nodes > (1 << 20)) { delete a; set_error("atmosphere table too fine"); return CKV_ERR_TABLE; }
+    hipGetDevice(&a->device);
+    const int64_t m = a->n_nodes;
+    std::vector<double> node(m * kNode64);
+    for (int64_t i = 0; i < m; ++i) {
+        node[i * kNode64] = a->psi[i];
+        for (int j = 0; j < 5; ++j) node[i * kNode64 + 1 + j] = a->P[j * m + i];
+    }
+    std::vector<float> cell((m - 1) * kCell32, 0.0f);
+    for (int64_t i = 0; i + 1 < m; ++i) {
+        float* c = &cell[i * kCell32];
+        c[0] = (float)a->psi[i];
+        c[1] = (float)(a->psi[i + 1] - a->psi[i]);
+        for (int j = 0; j < 5; ++j) c[2 + j] = (float)a->P[j * m + i];
+        c[7] = 0.0f;
+    }
+    if ((rc = upload(node.data(), node.size(), &a->d_node64)) ||
+        (rc = upload(cell.data(), cell.size(), &a->d_cell32))) {
+        ckv_atmo_destroy(a);
+        return rc;
+    }
+    *out = a;
+    return CKV_OK;
+}
+
+int ckv_atmo_info(const ckv_atmo* a, int64_t* n_nodes, double* obs_level_m, double* step_m)
+{
+    if (!a) { set_error("NULL atmosphere"); return CKV_ERR_ARG; }
+    if (n_nodes) *n_nodes = a->n_nodes;
+    if (obs_level_m) *obs_level_m = a->h_obs;
+    if (step_m) *step_m = a->step;
+    return CKV_OK;
+}
+
+int ckv_atmo_tables(const ckv_atmo* a, double* psi, double* P)
+{
+    if (!a) { set_error("NULL atmosphere"); return CKV_ERR_ARG; }
+    if (psi) std::memcpy(psi, a->psi.data(), sizeof(double) * a->psi.size());
+    if (P) std::memcpy(P, a->P.data(), sizeof(double) * a->P.size());
+    return CKV_OK;
+}
+
+int ckv_atmo_destroy(ckv_atmo* a)
+{
+    if (!a) return CKV_OK;
+    if (a->d_node64) hipFree(a->d_node64);
+    if (a->d_cell32) hipFree(a->d_cell32);
+    delete a;
+    return CKV_OK;
+}
+
+int ckv_array_create(const double* x_m, const double* y_m, const double* r_m, int32_t n_tel,
+                     ckv_array** out)
+{
+    if (!x_m || !y_m || !r_m || !out) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    *out = nullptr;
+    if (n_tel < 1 || n_tel > CKV_MAX_TEL) { set_error("need 1 <= n_tel <= CKV_MAX_TEL"); return CKV_ERR_ARG; }
+    for (int32_t k = 0; k < n_tel; ++k)
+        if (!std::isfinite(x_m[k]) || !std::isfinite(y_m[k]) || !std::isfinite(r_m[k]) || !(r_m[k] > 0.0)) {
+            set_error("telescopes: non-finite position or radius <= 0"); return CKV_ERR_TABLE;
+        }
+    ckv_array* arr = new (std::nothrow) ckv_array();
+    if (!arr) { set_error("out of host memory"); return CKV_ERR_NOMEM; }
+    arr->n_tel = n_tel;
+    arr->x.assign(x_m, x_m + n_tel);
+    arr->y.assign(y_m, y_m + n_tel);
+    arr->r.assign(r_m, r_m + n_tel);
+    int rc = build_array_grid(arr);
+    if (rc) { delete arr; return rc; }
+    hipGetDevice(&arr->device);
+    std::vector<double> tel(4 * (size_t)n_tel);
+    for (int32_t k = 0; k < n_tel; ++k) {
+        tel[4 * k] = x_m[k];
+        tel[4 * k + 1] = y_m[k];
+        tel[4 * k + 2] = r_m[k];
+        tel[4 * k + 3] = r_m[k] * r_m[k];
+    }
+    if ((rc = upload(tel.data(), tel.size(), &arr->d_tel)) ||
+        (rc = upload(arr->cell_off.data(), arr->cell_off.size(), &arr->d_cell_off)) ||
+        (rc = upload(arr->cell_list.data(), arr->cell_list.size(), &arr->d_cell_list))) {
+        ckv_array_destroy(arr);
+        return rc;
+    }
+    *out = arr;
+    return CKV_OK;
+}
+
+int ckv_array_destroy(ckv_array* arr)
+{
+    if (!arr) return CKV_OK;
+    if (arr->d_tel) hipFree(arr->d_tel);
+    if (arr->d_cell_off) hipFree(arr->d_cell_off);
+    if (arr->d_cell_list) hipFree(arr->d_cell_list);
+    delete arr;
+    return CKV_OK;
+}
+
+size_t ckv_workspace_size(int64_t n_segments, int32_t n_showers, int32_t n_tel, int64_t capacity,
+                          const ckv_params* params)
+{
+    if (n_segments < 0 || n_showers < 1 || n_tel < 1 || capacity < 0) return 0;
+    return workspace_layout(n_segments, n_showers, n_tel, capacity, params, nullptr, nullptr);
+}
+
+int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
+            const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
+            ckv_output* out, void* stream)
+{
+    int rc;
+    if ((rc = check_segments(segs)) || (rc = check_params(params))) return rc;
+    if (!showers || !atmo || !arr || !out || !workspace) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    if (showers->n_showers < 1 || !showers->seg_offsets || !showers->t_ref) {
+        set_error("showers: need n_showers >= 1, seg_offsets and t_ref"); return CKV_ERR_ARG;
+    }
+    if (!out->tel_offsets || !out->result || out->capacity < 0 || (out->capacity > 0 && !out->records)) {
+        set_error("output: tel_offsets, result and records (capacity > 0) are required");
+        return CKV_ERR_ARG;
+    }
+    if ((rc = current_device(atmo->device)) || (rc = current_device(arr->device))) return rc;
+    RunPlan plan{};
+    size_t need = workspace_layout(segs->n, showers->n_showers, arr->n_tel, out->capacity, params,
+                                   &plan, workspace);
+    if (ws_bytes < need) {
+        set_error("workspace smaller than ckv_workspace_size()"); return CKV_ERR_CAPACITY;
+    }
+    plan.segs = *segs;
+    plan.showers = *showers;
+    plan.params = *params;
+    plan.atmo = atmo;
+    plan.arr = arr;
+    plan.out = *out;
+    plan.stream = (hipStream_t)stream;
+    plan.k_ft = frank_tamm_k(params->lambda_min_nm, params->lambda_max_nm);
+    int n_cu = 256;
+    {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    }
+    plan.emit_grid = params->grid > 0 ? params->grid : std::min(n_cu, kMaxEmitGrid);
+    plan.emit_waves = kMaxEmitWaves;
+    return launch_run(plan);
+}
+
+int ckv_count(const ckv_segments* segs, const ckv_params* params, const ckv_atmo* atmo,
+              int64_t* n_b, void* stream)
+{
+    int rc;
+    if ((rc = check_segments(segs)) || (rc = check_params(params))) return rc;
+    if (!atmo || (!n_b && segs->n > 0)) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    if ((rc = current_device(atmo->device))) return rc;
+    return launch_count(segs, params, atmo, frank_tamm_k(params->lambda_min_nm, params->lambda_max_nm),
+                        n_b, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Internal definitions shared by the library's host and device sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ckv.h"
+
+namespace ckv {
+
+// physical constants (CODATA 2018) in m, ns, MeV
+constexpr double kSpeedOfLight = 0.299792458;      // m / ns
+constexpr double kFineStructure = 7.2973525693e-3;
+constexpr double kMassElectron = 0.51099895000;     // MeV
+constexpr double kMassMuon = 105.6583755;           // MeV
+constexpr double kPi = 3.14159265358979323846;
+
+// Bunch-path launch geometry.
+constexpr int kWave = 64;              // CDNA wavefront
+constexpr int kMaxTileSegs = 64;       // steps per tile (one per lane at most)
+constexpr int kStageBlock = 256;       // staging slots a wave claims at once
+constexpr int kMaxEmitGrid = 512;      // bound on bunch-kernel workgroups (workspace sizing)
+constexpr int kMaxEmitWaves = 16;     // waves per bunch-kernel workgroup
+constexpr int kRowBlock = 64;          // tiles per block of the per-telescope scan
+constexpr double kGridWLo = 0.2;       // candidate grid valid for observed w >= this
+
+// Layout of one cell of the FP32 table: psi_i, psi_{i+1}-psi_i, P1_i..P5_i, 0.
+constexpr int kCell32 = 8;
+// Layout of one node of the FP64 table: psi_i, P1_i..P5_i.
+constexpr int kNode64 = 6;
+
+// Staging entry written by the bunch kernel for every sphere crossing.
+struct alignas(16) StageEntry {
+    float rec[8];        // dx, dy, u_o, v_o, t, h_e, photons, lambda
+    uint32_t tile;       // emit tile
+    uint32_t tel;        // telescope
+    uint32_t rank;       // index among this tile's crossings of this telescope
+    uint32_t shower;     // shower index
+    int64_t seg;         // step index in the call
+    int64_t k;           // bunch index in the step
+};
+static_assert(sizeof(StageEntry) == 64, "staging entry is 64 bytes");
+
+// Control block in the workspace (zeroed by the first kernel of a run).
+enum CtrlSlot {
+    kTileCounter = 0,   // next tile to claim
+    kBlockCounter,      // next staging block to claim
+    kNumTiles,          // tiles of this run
+    kNumRowBlocks,      // row blocks of the per-telescope scan
+    kHits,              // crossings found
+    kBunches,           // bunches generated
+    kEmitting,          // steps with light
+    kStageOverflow,     // a staging claim went past the end
+    kDrop0,             // CKV_N_DROP drop counters follow
+    kCtrlSlots = kDrop0 + CKV_N_DROP + 4
+};
+
+}  // namespace ckv
+
+struct ckv_atmo {
+    int device = 0;
+    int64_t n_nodes = 0;
+    double h_obs = 0, step = 0, inv_step = 0, h_top = 0;
+    double n_obs = 1;                // sqrt(1 + psi_0)
+    std::vector<double> psi;         // host, n_nodes
+    std::vector<double> P;           // host, 5 x n_nodes
+    double* d_node64 = nullptr;      // device, n_nodes x kNode64
+    float* d_cell32 = nullptr;       // device, (n_nodes - 1) x kCell32
+};
+
+struct ckv_array {
+    int device = 0;
+    int32_t n_tel = 0;
+    std::vector<double> x, y, r;
+    // candidate grid: cells of size `cell` starting at (gx0, gy0); the list of
+    // cell c holds, in ascending order, every telescope whose sphere can be
+    // crossed by a line through a ground point in c with observed w >= kGridWLo
+    double gx0 = 0, gy0 = 0, cell = 1, inv_cell = 1;
+    int32_t nx = 0, ny = 0;
+    std::vector<int32_t> cell_off;   // nx*ny + 1
+    std::vector<uint16_t> cell_list;
+    double* d_tel = nullptr;         // device, n_tel x 4: X, Y, R, R^2
+    int32_t* d_cell_off = nullptr;
+    uint16_t* d_cell_list = nullptr;
+};
+
+namespace ckv {
+
+void set_error(const std::string& msg);
+
+// host builders (ckv_tables.cpp)
+int build_atmo_tables(const double* alt, const double* eta, int64_t n, double h_obs, double step,
+                      ckv_atmo* a);
+int build_array_grid(ckv_array* arr);
+
+// kernel launchers (ckv_kernels.hip)
+struct RunPlan {
+    // inputs
+    ckv_segments segs;
+    ckv_showers showers;
+    ckv_params params;
+    const ckv_atmo* atmo;
+    const ckv_array* arr;
+    ckv_output out;
+    hipStream_t stream;
+    // derived
+    int32_t tile_segs;
+    int64_t max_tiles, max_row_blocks, stage_slots;
+    int32_t emit_grid, emit_waves;
+    double k_ft;
+    // workspace carve-out
+    int64_t* ctrl;
+    int64_t* tiles_before;      // n_showers + 1
+    int64_t* blocks_before;     // n_showers + 1
+    int32_t* counts;            // max_tiles x n_tel
+    int32_t* block_sums;        // max_row_blocks x n_tel
+    int32_t* shower_tel;        // n_showers x n_tel
+    int32_t* stage_fill;        // stage_slots / kStageBlock
+    StageEntry* stage;          // stage_slots
+};
+
+size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, int64_t capacity,
+                        const ckv_params* p, RunPlan* plan, void* base);
+int launch_run(RunPlan& plan);
+int launch_count(const ckv_segments* segs, const ckv_params* p, const ckv_atmo* atmo, double k_ft,
+                 int64_t* n_b, hipStream_t stream);
+int emit_config(int precision, int n_tel, const ckv_atmo* atmo, int tile_segs, int* waves,
+                size_t* lds_bytes);
+
+}  // namespace ckv

@@ -1,0 +1,1020 @@
+// HIP kernels of the Cherenkov photon-bunch path for gfx950 (CDNA4).
+//
+// Pipeline of one run (all on the caller's stream, no host synchronisation):
+//   init      - zero the control block, validate shower offsets, count tiles
+//               (a tile = up to tile_segs consecutive steps of one shower);
+//   emit      - persistent: each wavefront claims tiles; per tile it computes
+//               the step setups (FP64, one step per lane: photon yield, bunch
+//               count, Cherenkov angle, frame), scans the bunch counts across
+//               the wave, then walks the tile's bunches 64 at a time (one per
+//               lane): Philox draws, sub-step emission point, direction on the
+//               cone, LDS-staged atmosphere tables, refraction series, ground
+//               point, candidate spheres, and records every crossing in a
+//               staging area together with its rank among the tile's crossings
+//               of the same telescope;
+//   finalize  - per-telescope prefix sums over tiles, CSR offsets per
+//               (shower, telescope), and a scatter of the staged records to
+//               their final slots (ascending step, then bunch).
+// Paper mapping: App. A (steps -> photon count -> bunches of ~5 photons, one
+// per sub-step -> propagation -> telescope output), App. B (observed
+// direction, displacement, travel time), sec. 3.3.2 (uniform fine tables).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "ckv_internal.h"
+
+namespace ckv {
+
+// --------------------------------------------------------------------------
+// kernel arguments
+// --------------------------------------------------------------------------
+struct Args {
+    const double *x0, *y0, *h0, *u, *v, *w, *len, *t0, *energy;
+    const uint8_t* ptype;
+    int64_t n;
+    const int64_t* seg_offsets;
+    const double* t_ref;
+    const uint32_t* shower_ids;
+    const int64_t* seg_id_base;
+    int32_t n_showers;
+    // atmosphere
+    int32_t n_nodes;
+    double h_obs, step, inv_step, h_top, n_obs;
+    const double* node64;
+    const float* cell32;
+    // telescopes and candidate grid
+    int32_t n_tel;
+    const double* tel;          // X, Y, R, R^2
+    double gx0, gy0, inv_cell;
+    int32_t nx, ny;
+    const int32_t* cell_off;
+    const uint16_t* cell_list;
+    // parameters
+    double bunch_size, k_ft, inv_l1, dl, w_min;
+    uint32_t key0, key1;
+    int32_t tile_segs;
+    // workspace and output
+    int64_t* ctrl;
+    int64_t* tiles_before;
+    int64_t* blocks_before;
+    int32_t* counts;
+    int32_t* block_sums;
+    int32_t* shower_tel;
+    int32_t* stage_fill;
+    StageEntry* stage;
+    int64_t stage_blocks;
+    int64_t max_tiles;
+    float* records;
+    int64_t* ids;
+    int64_t capacity;
+    int64_t* tel_offsets;
+    ckv_result* result;
+};
+
+// --------------------------------------------------------------------------
+// wave helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t x)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int wave_min(int x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d));
+    return x;
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t x)
+{
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+    return x;
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__device__ __forceinline__ T uniform(T x)
+{
+    return __shfl(x, 0);
+}
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers applied to
+// words 0 and 2, key advanced by the Weyl constants between rounds.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t r[4])
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    r[0] = c0; r[1] = c1; r[2] = c2; r[3] = c3;
+}
+
+// --------------------------------------------------------------------------
+// Step setup, FP64, without FMA contraction: the bunch count must come out of
+// exactly these IEEE operations.  App. A: photons per step, split into
+// bunches of about bunch_size photons, one per equal sub-step.
+// --------------------------------------------------------------------------
+struct Setup {
+    int status;        // -1: emits light; otherwise CKV_DROP_*
+    int64_t nb;
+    double photons, cos_t, sin_t, ds, inv_bc;
+    double b1x, b1y, b1z, b2x, b2y, b2z;
+};
+
+__device__ __forceinline__ double psi_fp64(const Args& a, double h)
+{
+#pragma clang fp contract(off)
+    double hc = h < a.h_obs ? a.h_obs : (h > a.h_top ? a.h_top : h);
+    double x = (hc - a.h_obs) * a.inv_step;
+    int64_t i = (int64_t)floor(x);
+    if (i > a.n_nodes - 2) i = a.n_nodes - 2;
+    double f = x - (double)i;
+    double lo = a.node64[kNode64 * i], hi = a.node64[kNode64 * (i + 1)];
+    return lo + f * (hi - lo);
+}
+
+__device__ __forceinline__ void step_setup(const Args& a, int64_t i, Setup& st)
+{
+#pragma clang fp contract(off)
+    st.nb = 0;
+    st.status = -1;
+    const double x0 = a.x0[i], y0 = a.y0[i], h0 = a.h0[i];
+    const double u = a.u[i], v = a.v[i], w = a.w[i];
+    const double L = a.len[i], t0 = a.t0[i], E = a.energy[i];
+    const bool finite = isfinite(x0) && isfinite(y0) && isfinite(h0) && isfinite(u) &&
+                        isfinite(v) && isfinite(w) && isfinite(L) && isfinite(t0) && isfinite(E);
+    if (!finite || !(L > 0.0)) { st.status = CKV_DROP_NONFINITE; return; }
+    const double m = a.ptype[i] == CKV_MUON ? kMassMuon : kMassElectron;
+    const double r = m / E;
+    const double r2 = r * r;                           // 1 - beta^2
+    if (!(r2 < 1.0)) { st.status = CKV_DROP_MASS; return; }
+    const double h_mid = h0 - (0.5 * L) * w;           // index at the step midpoint
+    const double psi = psi_fp64(a, h_mid);
+    const double n2 = 1.0 + psi;
+    const double num = psi - n2 * r2;                  // beta^2 n^2 - 1
+    if (!(num > 0.0)) { st.status = CKV_DROP_THRESHOLD; return; }
+    const double sin2 = num / (n2 * (1.0 - r2));       // sin^2 of the Cherenkov angle
+    const double N = (a.k_ft * L) * sin2;              // Frank-Tamm photon count
+    const double nbd = ceil(N / a.bunch_size);
+    st.nb = (int64_t)nbd;
+    st.photons = N / nbd;
+    st.cos_t = 1.0 / sqrt((1.0 - r2) * n2);           // 1 / (beta n)
+    st.sin_t = sqrt(sin2);
+    st.ds = L / nbd;
+    st.inv_bc = 1.0 / (sqrt(1.0 - r2) * kSpeedOfLight);
+    // orthonormal frame around D = (u, v, -w) (Duff et al., JCGT 2017)
+    const double Dx = u, Dy = v, Dz = -w;
+    const double sgn = copysign(1.0, Dz);
+    const double ia = -1.0 / (sgn + Dz);
+    const double ib = Dx * Dy * ia;
+    st.b1x = 1.0 + sgn * Dx * Dx * ia;
+    st.b1y = sgn * ib;
+    st.b1z = -sgn * Dx;
+    st.b2x = ib;
+    st.b2y = sgn + Dy * Dy * ia;
+    st.b2z = -Dy;
+}
+
+// --------------------------------------------------------------------------
+// sin and cos of 2 pi (r + 1/2) / 2^32 in FP32, from the integer: the top two
+// bits give the quadrant, the rest the angle inside it, folded to [0, pi/4]
+// and evaluated with Taylor polynomials (errors below 2e-9 there).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void sincos_turns(uint32_t r, float& s, float& c)
+{
+    const uint32_t q = r >> 30;
+    const uint32_t low = r & 0x3FFFFFFFu;
+    const bool upper = low >= 0x20000000u;
+    const uint32_t m = upper ? (0x3FFFFFFFu - low) : low;
+    const float kq = 1.46291807926715968e-9f;          // (pi/2) / 2^30
+    const float a = fmaf((float)m, kq, 0.5f * kq);
+    const float a2 = a * a;
+    float sa = fmaf(a2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+    sa = fmaf(a2, sa, 1.0f / 120.0f);
+    sa = fmaf(a2, sa, -1.0f / 6.0f);
+    sa = a * fmaf(a2, sa, 1.0f);
+    float ca = fmaf(a2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+    ca = fmaf(a2, ca, -1.0f / 720.0f);
+    ca = fmaf(a2, ca, 1.0f / 24.0f);
+    ca = fmaf(a2, ca, -0.5f);
+    ca = fmaf(a2, ca, 1.0f);
+    const float cq = upper ? sa : ca;
+    const float sq = upper ? ca : sa;
+    c = (q == 0) ? cq : (q == 1) ? -sq : (q == 2) ? -cq : sq;
+    s = (q == 0) ? sq : (q == 1) ? cq : (q == 2) ? -sq : -cq;
+}
+
+// --------------------------------------------------------------------------
+// LDS layout of the bunch kernel
+// --------------------------------------------------------------------------
+template <int PREC>
+struct Layout;
+
+// PREC 0: FP64 throughout; FP64 node table {psi, P1..P5}
+template <>
+struct Layout<0> {
+    using T = double;
+    static constexpr int kStashD = 17;   // doubles per step in the stash
+    static constexpr int kStashF = 0;
+    __host__ __device__ static size_t table_bytes(int n_nodes) { return (size_t)n_nodes * kNode64 * sizeof(double); }
+};
+// PREC 1: mixed; FP32 cell table {psi, dpsi, P1..P5, 0}
+template <>
+struct Layout<1> {
+    using T = float;
+    static constexpr int kStashD = 10;
+    static constexpr int kStashF = 7;
+    __host__ __device__ static size_t table_bytes(int n_nodes) { return (size_t)(n_nodes - 1) * kCell32 * sizeof(float); }
+};
+
+// per-wave counters kept in LDS (wave-uniform increments by lane 0)
+enum WaveCounter { kWcBunches = 0, kWcEmitting, kWcHits, kWcDrop0, kWcCount = kWcDrop0 + CKV_N_DROP };
+
+__host__ __device__ inline size_t wave_bytes(int prec, int tile_segs, int n_tel)
+{
+    const int sd = prec == 0 ? 17 : 10, sf = prec == 0 ? 0 : 7;
+    size_t b = (size_t)sd * tile_segs * 8 + (size_t)sf * tile_segs * 4 + (size_t)(tile_segs + 1) * 4 +
+               (size_t)n_tel * 4;
+    b = (b + 7) & ~(size_t)7;
+    b += (size_t)kWcCount * 8;
+    return (b + 15) & ~(size_t)15;
+}
+
+// stash field indices (doubles): 0 x0, 1 y0, 2 h0, 3 t0, 4 u, 5 v, 6 w, 7 cos_t,
+// 8 ds, 9 inv_bc, then (PREC 0) 10..15 sin_t*b1, sin_t*b2, 16 photons;
+// (PREC 1) floats 0..5 sin_t*b1, sin_t*b2, 6 photons.
+
+
+// --------------------------------------------------------------------------
+// the bunch kernel
+// --------------------------------------------------------------------------
+template <int PREC>
+__global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
+{
+    using L = Layout<PREC>;
+    using T = typename L::T;
+    extern __shared__ __align__(16) unsigned char lds[];
+
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    const int TS = a.tile_segs;
+
+    // ---- stage the atmosphere table once per workgroup
+    const size_t tab_bytes = L::table_bytes(a.n_nodes);
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(PREC == 0 ? (const void*)a.node64
+                                                                    : (const void*)a.cell32);
+        uint4* dst = reinterpret_cast<uint4*>(lds);
+        const int n16 = (int)(tab_bytes / 16);
+        for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
+    }
+    unsigned char* wbase = lds + ((tab_bytes + 15) & ~(size_t)15) + (size_t)wave * wave_bytes(PREC, TS, a.n_tel);
+    double* sd = reinterpret_cast<double*>(wbase);
+    float* sf = reinterpret_cast<float*>(wbase + (size_t)L::kStashD * TS * 8);
+    int32_t* boff = reinterpret_cast<int32_t*>(wbase + (size_t)L::kStashD * TS * 8 + (size_t)L::kStashF * TS * 4);
+    int32_t* tcount = boff + (TS + 1);
+    int64_t* wcnt = reinterpret_cast<int64_t*>(
+        reinterpret_cast<uintptr_t>(tcount + a.n_tel + 1) & ~(uintptr_t)7);
+    for (int k = lane; k < a.n_tel; k += kWave) tcount[k] = 0;
+    if (lane < kWcCount) wcnt[lane] = 0;
+    __syncthreads();
+
+    const double* tab64 = reinterpret_cast<const double*>(lds);
+    const float* tab32 = reinterpret_cast<const float*>(lds);
+    const T a1 = (T)-0.5, a2 = (T)0.375, a3 = (T)-0.3125, a4 = (T)0.2734375;
+    const double inv_c = 1.0 / kSpeedOfLight;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // (1 + delta_obs) with delta = psi / (1 + sqrt(1 + psi)) = n - 1
+    const float d_obs = (float)(a.n_obs - 1.0);
+    const float inv_1pdobs = 1.0f / (1.0f + d_obs);
+
+    int64_t blk = -1;          // current staging block; -1: none yet, -2: staging full
+    int blk_fill = 0;
+    const int64_t n_tiles = a.ctrl[kNumTiles];
+
+    for (;;) {
+        int64_t t = 0;
+        if (lane == 0) t = (int64_t)atomicAdd((unsigned long long*)&a.ctrl[kTileCounter], 1ull);
+        t = uniform(t);
+        if (t >= n_tiles) break;
+        // shower of the tile
+        int lo = 0, hi = a.n_showers;   // tiles_before[lo] <= t < tiles_before[hi]
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (a.tiles_before[mid] <= t) lo = mid; else hi = mid;
+        }
+        const int s = lo;
+        const int64_t sfirst = a.seg_offsets[s];
+        const int64_t g0 = sfirst + (t - a.tiles_before[s]) * (int64_t)TS;
+        const int64_t gend = min(g0 + (int64_t)TS, a.seg_offsets[s + 1]);
+        const int nseg = (int)(gend - g0);
+        const uint32_t shower_id = a.shower_ids ? a.shower_ids[s] : (uint32_t)s;
+        const int64_t seg_id0 = (a.seg_id_base ? a.seg_id_base[s] : 0) + (g0 - sfirst);
+        const double t_ref = a.t_ref[s];
+
+        // ---- step setups, one per lane
+        int64_t nb = 0;
+        int status = -2;   // -2: no step in this lane
+        if (lane < nseg) {
+            Setup st;
+            step_setup(a, g0 + lane, st);
+            status = st.status;
+            if (st.status < 0) {
+                nb = st.nb;
+                const int64_t g = g0 + lane;
+                sd[0 * TS + lane] = a.x0[g];
+                sd[1 * TS + lane] = a.y0[g];
+                sd[2 * TS + lane] = a.h0[g];
+                sd[3 * TS + lane] = a.t0[g];
+                sd[4 * TS + lane] = a.u[g];
+                sd[5 * TS + lane] = a.v[g];
+                sd[6 * TS + lane] = a.w[g];
+                sd[7 * TS + lane] = st.cos_t;
+                sd[8 * TS + lane] = st.ds;
+                sd[9 * TS + lane] = st.inv_bc;
+                const double p[7] = {st.sin_t * st.b1x, st.sin_t * st.b1y, st.sin_t * st.b1z,
+                                     st.sin_t * st.b2x, st.sin_t * st.b2y, st.sin_t * st.b2z,
+                                     st.photons};
+                if (PREC == 0) {
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) sd[(10 + q) * TS + lane] = p[q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) sf[q * TS + lane] = (float)p[q];
+                }
+            }
+        }
+        int64_t incl = wave_incl_scan(nb);
+        int64_t total = __shfl(incl, kWave - 1);
+        if (total >= ((int64_t)1 << 30)) {
+            // bunch offsets inside a tile are 32-bit: refuse such a tile
+            if (lane == 0) atomicOr(&a.result->error, 2);
+            total = 0;
+            incl = 0;
+            nb = 0;
+        }
+        if (lane < nseg) boff[lane] = (int32_t)(incl - nb);
+        if (lane >= nseg && lane <= TS) boff[lane] = (int32_t)total;
+        {
+            const int n_emit = __popcll(__ballot(status == -1));
+            int dcount[3];
+            dcount[0] = __popcll(__ballot(status == CKV_DROP_MASS));
+            dcount[1] = __popcll(__ballot(status == CKV_DROP_THRESHOLD));
+            dcount[2] = __popcll(__ballot(status == CKV_DROP_NONFINITE));
+            if (lane == 0) {
+                wcnt[kWcBunches] += total;
+                wcnt[kWcEmitting] += n_emit;
+                wcnt[kWcDrop0 + CKV_DROP_MASS] += dcount[0];
+                wcnt[kWcDrop0 + CKV_DROP_THRESHOLD] += dcount[1];
+                wcnt[kWcDrop0 + CKV_DROP_NONFINITE] += dcount[2];
+            }
+        }
+        wave_lds_sync();
+
+        // ---- bunches of the tile, one per lane
+        for (int64_t c0 = 0; c0 < total; c0 += kWave) {
+            const int32_t j = (int32_t)(c0 + lane);
+            const bool active = j < total;
+            // step of bunch j: largest si with boff[si] <= j
+            int si = 0;
+            for (int stp = kMaxTileSegs / 2; stp >= 1; stp >>= 1)
+                if (si + stp < TS && boff[si + stp] <= j) si += stp;
+            const int32_t k = j - boff[si];
+
+            bool alive = false;
+            int drop_why = -1;
+            double xg = 0, yg = 0, he = 0, tarr = 0;
+            float uo = 0, vo = 0, lam = 0, photons = 0, he_f = 0, t_f = 0;
+            if (active) {
+                uint32_t r[4];
+                philox4x32_10((uint32_t)k, (uint32_t)(seg_id0 + si), shower_id, 0u, a.key0, a.key1, r);
+                // emission point, uniform inside sub-step k (FP64)
+                const double u0 = ((double)r[0] + 0.5) * 2.3283064365386963e-10;
+                const double s_along = ((double)k + u0) * sd[8 * TS + si];
+                const double tu = sd[4 * TS + si], tv = sd[5 * TS + si], tw = sd[6 * TS + si];
+                const double xe = sd[0 * TS + si] + s_along * tu;
+                const double ye = sd[1 * TS + si] + s_along * tv;
+                he = sd[2 * TS + si] - s_along * tw;
+                const double te = sd[3 * TS + si] + s_along * sd[9 * TS + si];
+                const double ct = sd[7 * TS + si];
+                // direction on the Cherenkov cone
+                double pu, pv, pw;
+                if (PREC == 0) {
+                    const double phi = 6.283185307179586 * (((double)r[1] + 0.5) * 2.3283064365386963e-10);
+                    double sp, cp;
+                    sincos(phi, &sp, &cp);
+                    pu = ct * tu + (cp * sd[10 * TS + si] + sp * sd[13 * TS + si]);
+                    pv = ct * tv + (cp * sd[11 * TS + si] + sp * sd[14 * TS + si]);
+                    pw = ct * tw - (cp * sd[12 * TS + si] + sp * sd[15 * TS + si]);
+                    photons = (float)sd[16 * TS + si];
+                    lam = (float)(1.0 / (a.inv_l1 - (((double)r[2] + 0.5) * 2.3283064365386963e-10) * a.dl));
+                } else {
+                    float sp, cp;
+                    sincos_turns(r[1], sp, cp);
+                    const float px = fmaf(cp, sf[0 * TS + si], sp * sf[3 * TS + si]);
+                    const float py = fmaf(cp, sf[1 * TS + si], sp * sf[4 * TS + si]);
+                    const float pz = fmaf(cp, sf[2 * TS + si], sp * sf[5 * TS + si]);
+                    pu = fma(ct, tu, (double)px);
+                    pv = fma(ct, tv, (double)py);
+                    pw = fma(ct, tw, -(double)pz);
+                    photons = sf[6 * TS + si];
+                    const float u2 = fmaf((float)r[2], 2.3283064365386963e-10f, 1.16415321826934814e-10f);
+                    lam = __builtin_amdgcn_rcpf(fmaf(-u2, (float)a.dl, (float)a.inv_l1));
+                }
+                // drop rules
+                int why = -1;
+                if (he < a.h_obs) why = CKV_DROP_BELOW_OBS;
+                else if (he >= a.h_top) why = CKV_DROP_ABOVE_TOP;
+                else if (pw <= 0.0) why = CKV_DROP_UPWARD;
+                else if (pw <= a.w_min) why = CKV_DROP_GRAZING;
+                if (why >= 0) {
+                    drop_why = why;
+                } else {
+                    alive = true;
+                    // ---- atmosphere at the emission altitude (uniform table, no search)
+                    const double x = (he - a.h_obs) * a.inv_step;
+                    int ci = (int)x;
+                    ci = min(ci, a.n_nodes - 2);
+                    const T f = (T)(x - (double)ci);
+                    T psi_i, dpsi, P1, P2, P3, P4, P5;
+                    if (PREC == 0) {
+                        const double* nd = tab64 + (size_t)kNode64 * ci;
+                        psi_i = nd[0];
+                        dpsi = nd[kNode64] - nd[0];
+                        P1 = nd[1]; P2 = nd[2]; P3 = nd[3]; P4 = nd[4]; P5 = nd[5];
+                    } else {
+                        const float4* cc = reinterpret_cast<const float4*>(tab32 + (size_t)kCell32 * ci);
+                        const float4 c_0 = cc[0], c_1 = cc[1];
+                        psi_i = c_0.x; dpsi = c_0.y; P1 = c_0.z; P2 = c_0.w;
+                        P3 = c_1.x; P4 = c_1.y; P5 = c_1.z;
+                    }
+                    const T psi_e = psi_i + f * dpsi;
+                    const T dz = f * (T)a.step;
+                    // partial-cell moments: P_j += dz/(j+1) * sum_m psi_i^(j-m) psi_e^m
+                    const T b_1 = psi_e, b_2 = b_1 * psi_e, b_3 = b_2 * psi_e, b_4 = b_3 * psi_e,
+                            b_5 = b_4 * psi_e;
+                    const T h1 = psi_i + b_1;
+                    const T h2 = psi_i * h1 + b_2;
+                    const T h3 = psi_i * h2 + b_3;
+                    const T h4 = psi_i * h3 + b_4;
+                    const T h5 = psi_i * h4 + b_5;
+                    const T Q1 = P1 + dz * h1 * (T)0.5;
+                    const T Q2 = P2 + dz * h2 * (T)(1.0 / 3.0);
+                    const T Q3 = P3 + dz * h3 * (T)0.25;
+                    const T Q4 = P4 + dz * h4 * (T)0.2;
+                    const T Q5 = P5 + dz * h5 * (T)(1.0 / 6.0);
+                    // D_k = int (psi - psi_e)^k dh = sum_j C(k,j) (-psi_e)^(k-j) P_j
+                    const double dh = he - a.h_obs;
+                    const T dhT = (T)dh;
+                    const T c1 = -psi_e, c2 = c1 * c1, c3 = c2 * c1, c4 = c3 * c1, c5 = c4 * c1;
+                    const T D1 = Q1 + c1 * dhT;
+                    const T D2 = Q2 + (T)2 * c1 * Q1 + c2 * dhT;
+                    const T D3 = Q3 + (T)3 * c1 * Q2 + (T)3 * c2 * Q1 + c3 * dhT;
+                    const T D4 = Q4 + (T)4 * c1 * Q3 + (T)6 * c2 * Q2 + (T)4 * c3 * Q1 + c4 * dhT;
+                    const T D5 = Q5 + (T)5 * c1 * Q4 + (T)10 * c2 * Q3 + (T)10 * c3 * Q2 +
+                                 (T)5 * c4 * Q1 + c5 * dhT;
+                    // index at emission: n_e = 1 + delta_e
+                    const T ne2 = (T)1 + psi_e;
+                    double ne;
+                    T ratio;   // n_e / n_obs
+                    if (PREC == 0) {
+                        ne = sqrt(1.0 + (double)psi_e);
+                        ratio = (T)(ne / a.n_obs);
+                    } else {
+                        const float de = (float)psi_e * __builtin_amdgcn_rcpf(1.0f + __builtin_sqrtf(1.0f + (float)psi_e));
+                        ne = 1.0 + (double)de;
+                        ratio = 1.0f + (de - d_obs) * inv_1pdobs;
+                    }
+                    double inv_w;
+                    T q;
+                    if (PREC == 0) {
+                        inv_w = 1.0 / pw;
+                        q = (T)1 / (ne2 * (T)(pw * pw));
+                    } else {
+                        // reciprocal with two Newton steps (FP64-accurate)
+                        double r0 = __builtin_amdgcn_rcp(pw);
+                        r0 = fma(r0, fma(-pw, r0, 1.0), r0);
+                        inv_w = fma(r0, fma(-pw, r0, 1.0), r0);
+                        q = (T)__builtin_amdgcn_rcpf((float)ne2 * (float)(pw * pw));
+                    }
+                    // horizontal advance: S = dh + sum_{k>=1} a_k q^k D_k
+                    const T s_corr = q * (a1 * D1 + q * (a2 * D2 + q * (a3 * D3 + q * a4 * D4)));
+                    const double S = dh + (double)s_corr;
+                    // c * time * w * n_e = n_e^2 dh + D1 + sum_{k>=1} a_k q^k (n_e^2 D_k + D_{k+1})
+                    const T t_corr = D1 + q * (a1 * (ne2 * D1 + D2) +
+                                           q * (a2 * (ne2 * D2 + D3) +
+                                           q * (a3 * (ne2 * D3 + D4) + q * a4 * (ne2 * D4 + D5))));
+                    double ctw;
+                    if (PREC == 0) ctw = ne * dh + (double)t_corr / ne;
+                    else ctw = ne * dh + (double)((float)t_corr * __builtin_amdgcn_rcpf((float)ne));
+                    const double T_travel = ctw * inv_w * inv_c;
+                    xg = xe + pu * inv_w * S;
+                    yg = ye + pv * inv_w * S;
+                    tarr = te + T_travel - t_ref;
+                    uo = (float)((T)pu * ratio);
+                    vo = (float)((T)pv * ratio);
+                    t_f = (float)tarr;
+                    he_f = (float)he;
+                }
+            }
+
+            {
+                const int d0 = __popcll(__ballot(drop_why == CKV_DROP_BELOW_OBS));
+                const int d1 = __popcll(__ballot(drop_why == CKV_DROP_ABOVE_TOP));
+                const int d2 = __popcll(__ballot(drop_why == CKV_DROP_UPWARD));
+                const int d3 = __popcll(__ballot(drop_why == CKV_DROP_GRAZING));
+                if (lane == 0 && (d0 | d1 | d2 | d3)) {
+                    wcnt[kWcDrop0 + CKV_DROP_BELOW_OBS] += d0;
+                    wcnt[kWcDrop0 + CKV_DROP_ABOVE_TOP] += d1;
+                    wcnt[kWcDrop0 + CKV_DROP_UPWARD] += d2;
+                    wcnt[kWcDrop0 + CKV_DROP_GRAZING] += d3;
+                }
+            }
+            const double uod = (double)uo, vod = (double)vo;
+            // ---- candidate spheres (ascending telescope index)
+            int cur = 0, cend = 0;
+            bool brute = false;
+            if (alive) {
+                const double wo2 = 1.0 - uod * uod - vod * vod;
+                if (wo2 >= kGridWLo * kGridWLo + 1e-6) {
+                    const double fx = (xg - a.gx0) * a.inv_cell, fy = (yg - a.gy0) * a.inv_cell;
+                    if (fx >= 0.0 && fy >= 0.0 && fx < (double)a.nx && fy < (double)a.ny) {
+                        const int cidx = (int)fx * a.ny + (int)fy;
+                        cur = a.cell_off[cidx];
+                        cend = a.cell_off[cidx + 1];
+                    }
+                } else {
+                    brute = true;
+                    cend = a.n_tel;
+                }
+            }
+            int my_next = INT_MAX;
+            auto advance = [&]() {
+                my_next = INT_MAX;
+                while (cur < cend) {
+                    const int kt = brute ? cur : (int)a.cell_list[cur];
+                    ++cur;
+                    const double* tp = a.tel + 4 * kt;
+                    const double dx = xg - tp[0], dy = yg - tp[1];
+                    const double b = dx * uod + dy * vod;
+                    const double disc = b * b - (dx * dx + dy * dy - tp[3]);
+                    if (disc >= 0.0) { my_next = kt; break; }
+                }
+            };
+            advance();
+            // ---- record crossings; telescopes in ascending order, lanes (bunches) in order
+            while (__ballot(my_next != INT_MAX)) {
+                const int kmin = wave_min(my_next);
+                const bool mine = my_next == kmin;
+                const uint64_t mask = __ballot(mine);
+                const int nmine = __popcll(mask);
+                const int below = __popcll(mask & lt_mask);
+                const int rank0 = tcount[kmin];
+                if (lane == 0) wcnt[kWcHits] += nmine;
+                // staging slots: the first `room` crossings fill the current
+                // block, the rest start a newly claimed one
+                const int room = blk >= 0 ? kStageBlock - blk_fill : 0;
+                int64_t nbk = -2;
+                if (nmine > room && blk != -2) {
+                    if (blk >= 0 && lane == 0) a.stage_fill[blk] = kStageBlock;
+                    if (lane == 0) nbk = (int64_t)atomicAdd((unsigned long long*)&a.ctrl[kBlockCounter], 1ull);
+                    nbk = uniform(nbk);
+                    if (nbk >= a.stage_blocks) {
+                        nbk = -2;
+                        if (lane == 0) atomicExch((unsigned long long*)&a.ctrl[kStageOverflow], 1ull);
+                    }
+                }
+                if (mine) {
+                    int64_t slot = -1;
+                    if (below < room) slot = blk * kStageBlock + blk_fill + below;
+                    else if (nbk >= 0) slot = nbk * kStageBlock + (below - room);
+                    if (slot >= 0) {
+                        StageEntry* e = a.stage + slot;
+                        const double* tp = a.tel + 4 * kmin;
+                        const float4 r0 = make_float4((float)(xg - tp[0]), (float)(yg - tp[1]), uo, vo);
+                        const float4 r1 = make_float4(t_f, he_f, photons, lam);
+                        float4* ef = reinterpret_cast<float4*>(e);
+                        ef[0] = r0;
+                        ef[1] = r1;
+                        uint4* eu = reinterpret_cast<uint4*>(e);
+                        eu[2] = make_uint4((uint32_t)t, (uint32_t)kmin, (uint32_t)(rank0 + below), (uint32_t)s);
+                        int64_t* el = reinterpret_cast<int64_t*>(e);
+                        el[6] = g0 + si;
+                        el[7] = k;
+                    }
+                }
+                if (nmine > room) {
+                    if (blk != -2) {
+                        blk = nbk;               // -2 when the staging area is full
+                        blk_fill = nmine - room;
+                    }
+                } else {
+                    blk_fill += nmine;
+                }
+                if (lane == 0) tcount[kmin] = rank0 + nmine;
+                wave_lds_sync();
+                if (mine) advance();
+            }
+        }
+        // ---- per-telescope crossings of this tile
+        wave_lds_sync();
+        if (t < a.max_tiles) {
+            int32_t* row = a.counts + t * (int64_t)a.n_tel;
+            for (int k = lane; k < a.n_tel; k += kWave) {
+                row[k] = tcount[k];
+                tcount[k] = 0;
+            }
+        }
+        wave_lds_sync();
+    }
+
+    // ---- close the staging block and publish counters
+    if (blk >= 0 && lane == 0) a.stage_fill[blk] = blk_fill;
+    wave_lds_sync();
+    if (lane == 0) {
+        const int64_t v_b = wcnt[kWcBunches], v_e = wcnt[kWcEmitting], v_h = wcnt[kWcHits];
+        if (v_h) atomicAdd((unsigned long long*)&a.ctrl[kHits], (unsigned long long)v_h);
+        if (v_b) atomicAdd((unsigned long long*)&a.ctrl[kBunches], (unsigned long long)v_b);
+        if (v_e) atomicAdd((unsigned long long*)&a.ctrl[kEmitting], (unsigned long long)v_e);
+        for (int d = 0; d < CKV_N_DROP; ++d) {
+            const int64_t v = wcnt[kWcDrop0 + d];
+            if (v) atomicAdd((unsigned long long*)&a.ctrl[kDrop0 + d], (unsigned long long)v);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// init: control block, shower validation, tile and row-block counts
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) init_kernel(Args a)
+{
+    __shared__ int64_t sh_t[1024], sh_b[1024];
+    __shared__ int err;
+    for (int q = threadIdx.x; q < kCtrlSlots; q += blockDim.x) a.ctrl[q] = 0;
+    if (threadIdx.x == 0) err = 0;
+    __syncthreads();
+    const int64_t TS = a.tile_segs;
+    int64_t run_t = 0, run_b = 0;
+    for (int base = 0; base < a.n_showers; base += blockDim.x) {
+        const int s = base + threadIdx.x;
+        int64_t nt = 0, nbk = 0;
+        if (s < a.n_showers) {
+            const int64_t lo = a.seg_offsets[s], hi = a.seg_offsets[s + 1];
+            if (lo < 0 || hi < lo || hi > a.n || (s == 0 && lo != 0) ||
+                (s == a.n_showers - 1 && hi != a.n))
+                err = 1;
+            const int64_t cnt = hi >= lo ? hi - lo : 0;
+            nt = (cnt + TS - 1) / TS;
+            nbk = (nt + kRowBlock - 1) / kRowBlock;
+        }
+        sh_t[threadIdx.x] = nt;
+        sh_b[threadIdx.x] = nbk;
+        __syncthreads();
+        for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+            int64_t xt = 0, xb = 0;
+            if ((int)threadIdx.x >= d) { xt = sh_t[threadIdx.x - d]; xb = sh_b[threadIdx.x - d]; }
+            __syncthreads();
+            sh_t[threadIdx.x] += xt;
+            sh_b[threadIdx.x] += xb;
+            __syncthreads();
+        }
+        if (s < a.n_showers) {
+            a.tiles_before[s] = run_t + sh_t[threadIdx.x] - nt;
+            a.blocks_before[s] = run_b + sh_b[threadIdx.x] - nbk;
+        }
+        run_t += sh_t[blockDim.x - 1];
+        run_b += sh_b[blockDim.x - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.tiles_before[a.n_showers] = run_t;
+        a.blocks_before[a.n_showers] = run_b;
+        if (run_t > a.max_tiles) err = 1;
+        a.ctrl[kNumTiles] = err ? 0 : run_t;
+        a.ctrl[kNumRowBlocks] = err ? 0 : run_b;
+        a.result->error = err;
+    }
+}
+
+// --------------------------------------------------------------------------
+// finalize
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int find_shower(const int64_t* before, int n_showers, int64_t x)
+{
+    int lo = 0, hi = n_showers;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (before[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// A: per row block, per telescope: sum of crossings over the block's tiles
+__global__ void __launch_bounds__(256) rowblock_sum_kernel(Args a)
+{
+    const int64_t nblk = a.ctrl[kNumRowBlocks];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int s = find_shower(a.blocks_before, a.n_showers, b);
+        const int64_t t0 = a.tiles_before[s] + (b - a.blocks_before[s]) * kRowBlock;
+        const int64_t t1 = min(t0 + kRowBlock, a.tiles_before[s + 1]);
+        for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x) {
+            int32_t sum = 0;
+            for (int64_t t = t0; t < t1; ++t) sum += a.counts[t * a.n_tel + k];
+            a.block_sums[b * a.n_tel + k] = sum;
+        }
+    }
+}
+
+// B: per (shower, telescope): exclusive scan over the shower's row blocks
+__global__ void __launch_bounds__(256) rowblock_scan_kernel(Args a)
+{
+    const int64_t nst = (int64_t)a.n_showers * a.n_tel;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nst;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(q / a.n_tel), k = (int)(q % a.n_tel);
+        int32_t run = 0;
+        if (a.ctrl[kNumTiles] > 0)
+            for (int64_t b = a.blocks_before[s]; b < a.blocks_before[s + 1]; ++b) {
+                const int32_t x = a.block_sums[b * a.n_tel + k];
+                a.block_sums[b * a.n_tel + k] = run;
+                run += x;
+            }
+        a.shower_tel[q] = run;
+    }
+}
+
+// C: per tile, per telescope: crossings of the same shower in earlier tiles
+__global__ void __launch_bounds__(256) tile_prefix_kernel(Args a)
+{
+    const int64_t nblk = a.ctrl[kNumRowBlocks];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int s = find_shower(a.blocks_before, a.n_showers, b);
+        const int64_t t0 = a.tiles_before[s] + (b - a.blocks_before[s]) * kRowBlock;
+        const int64_t t1 = min(t0 + kRowBlock, a.tiles_before[s + 1]);
+        for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x) {
+            int32_t run = a.block_sums[b * a.n_tel + k];
+            for (int64_t t = t0; t < t1; ++t) {
+                const int32_t x = a.counts[t * a.n_tel + k];
+                a.counts[t * a.n_tel + k] = run;
+                run += x;
+            }
+        }
+    }
+}
+
+// D: CSR offsets over (shower, telescope) and the run report
+__global__ void __launch_bounds__(1024) csr_kernel(Args a)
+{
+    __shared__ int64_t sh[1024];
+    const int64_t nst = (int64_t)a.n_showers * a.n_tel;
+    int64_t run = 0;
+    for (int64_t base = 0; base < nst; base += blockDim.x) {
+        const int64_t q = base + threadIdx.x;
+        const int64_t x = q < nst ? (int64_t)a.shower_tel[q] : 0;
+        sh[threadIdx.x] = x;
+        __syncthreads();
+        for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+            int64_t y = (int)threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (q < nst) a.tel_offsets[q] = run + sh[threadIdx.x] - x;
+        run += sh[blockDim.x - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.tel_offsets[nst] = run;
+        ckv_result* r = a.result;
+        const int64_t hits = a.ctrl[kHits];
+        const int overflow = (hits > a.capacity) || (a.ctrl[kStageOverflow] != 0);
+        r->n_bunches = a.ctrl[kBunches];
+        r->n_hits = hits;
+        r->n_records = overflow ? 0 : hits;
+        r->n_emitting = a.ctrl[kEmitting];
+        r->n_tiles = a.ctrl[kNumTiles];
+        for (int d = 0; d < CKV_N_DROP; ++d) r->drops[d] = a.ctrl[kDrop0 + d];
+        r->overflow = overflow;
+    }
+}
+
+// E: scatter the staged records to their final slots
+__global__ void __launch_bounds__(256) scatter_kernel(Args a)
+{
+    const int64_t hits = a.ctrl[kHits];
+    if (hits > a.capacity || a.ctrl[kStageOverflow] != 0) return;
+    const int64_t nblk = min(a.ctrl[kBlockCounter], a.stage_blocks);
+    const int64_t nslots = nblk * kStageBlock;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nslots;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = q / kStageBlock;
+        if ((int)(q - b * kStageBlock) >= a.stage_fill[b]) continue;
+        const StageEntry* e = a.stage + q;
+        const uint4 meta = reinterpret_cast<const uint4*>(e)[2];
+        const uint32_t tile = meta.x, tel = meta.y, rank = meta.z, shower = meta.w;
+        if (tel >= (uint32_t)a.n_tel || shower >= (uint32_t)a.n_showers || tile >= (uint64_t)a.max_tiles)
+            continue;
+        const int64_t pos = a.tel_offsets[(int64_t)shower * a.n_tel + tel] +
+                            a.counts[(int64_t)tile * a.n_tel + tel] + rank;
+        if (pos < 0 || pos >= a.capacity) continue;
+        const float4* src = reinterpret_cast<const float4*>(e);
+        float4* dst = reinterpret_cast<float4*>(a.records + 8 * pos);
+        dst[0] = src[0];
+        dst[1] = src[1];
+        if (a.ids) {
+            const int64_t* el = reinterpret_cast<const int64_t*>(e);
+            a.ids[2 * pos] = el[6];
+            a.ids[2 * pos + 1] = el[7];
+        }
+    }
+}
+
+// standalone bunch count per step (FP64, same operations as the bunch kernel)
+__global__ void __launch_bounds__(256) count_kernel(Args a, int64_t* n_b)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        Setup st;
+        step_setup(a, i, st);
+        n_b[i] = st.status >= 0 ? 0 : st.nb;
+    }
+}
+
+// --------------------------------------------------------------------------
+// host side
+// --------------------------------------------------------------------------
+namespace {
+
+Args make_args(const RunPlan& p)
+{
+    Args a{};
+    const ckv_segments& s = p.segs;
+    a.x0 = s.x0; a.y0 = s.y0; a.h0 = s.h0; a.u = s.u; a.v = s.v; a.w = s.w;
+    a.len = s.length; a.t0 = s.t0; a.energy = s.energy; a.ptype = s.ptype; a.n = s.n;
+    a.seg_offsets = p.showers.seg_offsets;
+    a.t_ref = p.showers.t_ref;
+    a.shower_ids = p.showers.shower_ids;
+    a.seg_id_base = p.showers.seg_id_base;
+    a.n_showers = p.showers.n_showers;
+    const ckv_atmo* at = p.atmo;
+    a.n_nodes = (int32_t)at->n_nodes;
+    a.h_obs = at->h_obs; a.step = at->step; a.inv_step = at->inv_step; a.h_top = at->h_top;
+    a.n_obs = at->n_obs;
+    a.node64 = at->d_node64;
+    a.cell32 = at->d_cell32;
+    const ckv_array* ar = p.arr;
+    if (ar) {
+        a.n_tel = ar->n_tel;
+        a.tel = ar->d_tel;
+        a.gx0 = ar->gx0; a.gy0 = ar->gy0; a.inv_cell = ar->inv_cell;
+        a.nx = ar->nx; a.ny = ar->ny;
+        a.cell_off = ar->d_cell_off;
+        a.cell_list = ar->d_cell_list;
+    }
+    a.bunch_size = p.params.bunch_size;
+    a.k_ft = p.k_ft;
+    a.inv_l1 = 1.0 / p.params.lambda_min_nm;
+    a.dl = 1.0 / p.params.lambda_min_nm - 1.0 / p.params.lambda_max_nm;
+    a.w_min = p.params.w_min;
+    a.key0 = (uint32_t)p.params.seed;
+    a.key1 = (uint32_t)(p.params.seed >> 32);
+    a.tile_segs = p.tile_segs;
+    a.ctrl = p.ctrl;
+    a.tiles_before = p.tiles_before;
+    a.blocks_before = p.blocks_before;
+    a.counts = p.counts;
+    a.block_sums = p.block_sums;
+    a.shower_tel = p.shower_tel;
+    a.stage_fill = p.stage_fill;
+    a.stage = p.stage;
+    a.stage_blocks = p.stage_slots / kStageBlock;
+    a.max_tiles = p.max_tiles;
+    a.records = p.out.records;
+    a.ids = p.out.ids;
+    a.capacity = p.out.capacity;
+    a.tel_offsets = p.out.tel_offsets;
+    a.result = p.out.result;
+    return a;
+}
+
+int check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string(what) + ": " + hipGetErrorString(e));
+        return CKV_ERR_HIP;
+    }
+    return CKV_OK;
+}
+
+}  // namespace
+
+int emit_config(int precision, int n_tel, const ckv_atmo* atmo, int tile_segs, int* waves,
+                size_t* lds_bytes)
+{
+    const size_t tab = precision == 0 ? Layout<0>::table_bytes((int)atmo->n_nodes)
+                                      : Layout<1>::table_bytes((int)atmo->n_nodes);
+    const size_t cap = 160 * 1024;
+    const size_t per = wave_bytes(precision, tile_segs, n_tel);
+    const int max_waves = precision == 0 ? kMaxEmitWaves / 2 : kMaxEmitWaves;
+    for (int wv = max_waves; wv >= 1; wv /= 2) {
+        size_t tot = ((tab + 15) & ~(size_t)15) + (size_t)wv * per;
+        if (tot <= cap) {
+            *waves = wv;
+            *lds_bytes = tot;
+            return CKV_OK;
+        }
+    }
+    set_error("atmosphere table too large for LDS");
+    return CKV_ERR_TABLE;
+}
+
+int launch_run(RunPlan& p)
+{
+    Args a = make_args(p);
+    hipStream_t st = p.stream;
+    init_kernel<<<1, 1024, 0, st>>>(a);
+    if (int rc = check_launch("init")) return rc;
+    int waves = 0;
+    size_t lds = 0;
+    if (int rc = emit_config(p.params.precision, a.n_tel, p.atmo, p.tile_segs, &waves, &lds)) return rc;
+    if (waves > p.emit_waves) waves = p.emit_waves;
+    lds = ((p.params.precision == 0 ? Layout<0>::table_bytes(a.n_nodes)
+                                    : Layout<1>::table_bytes(a.n_nodes)) + 15 & ~(size_t)15) +
+          (size_t)waves * wave_bytes(p.params.precision, p.tile_segs, a.n_tel);
+    if (p.params.precision == 0) {
+        static bool attr0 = false;
+        if (!attr0) {
+            (void)hipFuncSetAttribute((const void*)emit_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr0 = true;
+        }
+        emit_kernel<0><<<p.emit_grid, waves * kWave, lds, st>>>(a);
+    } else {
+        static bool attr1 = false;
+        if (!attr1) {
+            (void)hipFuncSetAttribute((const void*)emit_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr1 = true;
+        }
+        emit_kernel<1><<<p.emit_grid, waves * kWave, lds, st>>>(a);
+    }
+    if (int rc = check_launch("emit")) return rc;
+    const int fin_grid = 1024;
+    rowblock_sum_kernel<<<fin_grid, 256, 0, st>>>(a);
+    if (int rc = check_launch("rowblock_sum")) return rc;
+    rowblock_scan_kernel<<<fin_grid, 256, 0, st>>>(a);
+    if (int rc = check_launch("rowblock_scan")) return rc;
+    tile_prefix_kernel<<<fin_grid, 256, 0, st>>>(a);
+    if (int rc = check_launch("tile_prefix")) return rc;
+    csr_kernel<<<1, 1024, 0, st>>>(a);
+    if (int rc = check_launch("csr")) return rc;
+    scatter_kernel<<<4096, 256, 0, st>>>(a);
+    return check_launch("scatter");
+}
+
+int launch_count(const ckv_segments* segs, const ckv_params* prm, const ckv_atmo* atmo, double k_ft,
+                 int64_t* n_b, hipStream_t stream)
+{
+    RunPlan p{};
+    p.segs = *segs;
+    p.params = *prm;
+    p.atmo = atmo;
+    p.arr = nullptr;
+    p.k_ft = k_ft;
+    p.tile_segs = 1;
+    Args a = make_args(p);
+    if (segs->n == 0) return CKV_OK;
+    const int64_t blocks = std::min<int64_t>((segs->n + 255) / 256, 65536);
+    count_kernel<<<(unsigned)blocks, 256, 0, stream>>>(a, n_b);
+    return check_launch("count");
+}
+
+}  // namespace ckv

@@ -1,0 +1,247 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bit-exact: bunch counts per step, drop counters, telescope offsets and the
+(step, bunch) identity of every record in the FP64 path; in the mixed path the
+crossing sets agree except inside the guard band |disc| <= 2 R eps + eps^2,
+eps = 1 mm, and the record fields stay within the stated tolerances.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_14927_amd import ckv, synth
+
+from gpu_helpers import compare_records, gpu_run, handles, params, say
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = [ckv.CKV_FP64, ckv.CKV_MIXED]
+
+
+@pytest.fixture(scope="module")
+def vg():
+    wl = synth.vertical_gamma()
+    cfg = oracle.Config.from_workload(wl)
+    return wl, cfg, oracle.run(cfg, wl.segs, nthreads=8)
+
+
+@pytest.fixture(scope="module")
+def tev():
+    wl = synth.single_tev()
+    return wl, oracle.Config.from_workload(wl)
+
+
+# ---------------------------------------------------------------------------
+# tables and bunch counts
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("make", [synth.vertical_gamma, lambda: synth.single_tev(10)])
+def test_tables_match_oracle(make):
+    wl = make()
+    cfg = oracle.Config.from_workload(wl)
+    atmo, _ = handles(wl)
+    psi, P = atmo.tables()
+    np.testing.assert_array_equal(psi, cfg.tables.psi)          # bit-exact: drives n_b
+    np.testing.assert_allclose(P, cfg.tables.P, rtol=1e-13, atol=0)
+
+
+def test_count_bit_exact_vertical_gamma(vg):
+    wl, cfg, r = vg
+    atmo, _ = handles(wl)
+    say("[gpu] count vertical_gamma")
+    n_b = ckv.count(ckv.DeviceSegments(wl.segs), atmo, params(wl, ckv.CKV_MIXED)).cpu().numpy()
+    np.testing.assert_array_equal(n_b, r.n_b)
+
+
+def test_count_bit_exact_single_tev_full(tev):
+    wl, cfg = tev
+    atmo, _ = handles(wl)
+    say("[gpu] count single_tev 2e6")
+    n_b = ckv.count(ckv.DeviceSegments(wl.segs), atmo, params(wl, ckv.CKV_MIXED)).cpu().numpy()
+    sd = oracle.segment_details(cfg, wl.segs)
+    np.testing.assert_array_equal(n_b, sd["n_b"].astype(np.int64))
+
+
+def test_count_at_threshold_edges():
+    """Steps just above and below the Cherenkov threshold at table nodes."""
+    wl = synth.vertical_gamma(10)
+    cfg = oracle.Config.from_workload(wl)
+    grid = cfg.tables.h_obs + np.arange(cfg.tables.n_nodes) * cfg.tables.step
+    h_nodes = grid[5:400:7]
+    n = len(h_nodes)
+    e_thr = 0.51099895 / np.sqrt(1.0 - 1.0 / (1.0 + cfg.tables.psi[5:400:7]))
+    # +-1e-12: inside rounding noise, exercises identical IEEE decisions on both
+    # sides; +-1e-9: the closed-form threshold decides
+    E = np.concatenate([e_thr * (1 - 1e-9), e_thr * (1 + 1e-9), e_thr * (1 - 1e-12),
+                        e_thr * (1 + 1e-12)])
+    h0 = np.tile(h_nodes + 5.0, 4)
+    m = 4 * n
+    segs = synth.Segments(np.zeros(m), np.zeros(m), h0, np.zeros(m), np.zeros(m), np.ones(m),
+                          np.full(m, 10.0), np.zeros(m), E, np.zeros(m, np.uint8),
+                          np.array([0, m]), np.array([0.0]), np.array([0], np.uint32))
+    atmo, _ = handles(wl)
+    n_b = ckv.count(ckv.DeviceSegments(segs), atmo, params(wl, ckv.CKV_FP64)).cpu().numpy()
+    sd = oracle.segment_details(cfg, segs)
+    np.testing.assert_array_equal(n_b, sd["n_b"].astype(np.int64))
+    assert (n_b[n:2 * n] > 0).all() and (n_b[:n] == 0).all()
+
+
+# ---------------------------------------------------------------------------
+# full parity on the vertical gamma shower (2e4 steps, ~1e6 bunches)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_vertical_gamma_parity(vg, precision):
+    wl, cfg, r = vg
+    g = gpu_run(wl, precision)
+    res = g["result"]
+    assert res["error"] == 0 and res["overflow"] == 0
+    assert res["n_bunches"] == r.n_bunches
+    assert res["n_emitting"] == r.n_emitting
+    assert res["drops"] == r.drops
+    if precision == ckv.CKV_FP64:
+        np.testing.assert_array_equal(g["offsets"], r.offsets)
+    rep = compare_records(wl, cfg, r, g, precision)
+    say(f"[gpu] vertical_gamma prec={precision}: {rep}")
+
+
+# ---------------------------------------------------------------------------
+# the 1 TeV shower at full size (2e6 steps, ~1.2e8 bunches), sampled parity
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_single_tev_full_size_sampled(tev, precision):
+    wl, cfg = tev
+    g = gpu_run(wl, precision, capacity=8_000_000)
+    res = g["result"]
+    assert res["error"] == 0 and res["overflow"] == 0
+    sd = oracle.segment_details(cfg, wl.segs)
+    assert res["n_bunches"] == int(sd["n_b"].sum())
+    assert res["n_emitting"] == int((sd["status"] == -1).sum())
+    assert res["drops"]["threshold"] == int((sd["status"] == 1).sum())
+    # oracle on every 41st step, with their original random numbers
+    idx = np.arange(0, wl.segs.n, 41)
+    sub = wl.segs.take(idx)
+    ores = oracle.run(cfg, sub, nthreads=8, seg_id=idx)
+    keep = np.isin(g["ids"][:, 0], idx)
+    counts = np.diff(g["offsets"])
+    group = np.repeat(np.arange(len(counts)), counts)
+    gk = group[keep]
+    sub_off = np.zeros_like(g["offsets"])
+    sub_off[1:] = np.cumsum(np.bincount(gk, minlength=len(counts)))
+    gs = dict(offsets=sub_off, rec=g["rec"][keep], ids=g["ids"][keep])
+    rep = compare_records(wl, cfg, ores, gs, precision, segs=sub, seg_map=idx)
+    say(f"[gpu] single_tev prec={precision}: hits={res['n_hits']} bunches={res['n_bunches']} {rep}")
+
+
+# ---------------------------------------------------------------------------
+# determinism and invariance
+# ---------------------------------------------------------------------------
+
+def test_reruns_and_tilings_give_identical_bytes(vg):
+    wl, cfg, r = vg
+    base = gpu_run(wl, ckv.CKV_MIXED)
+    for kw in (dict(), dict(tile_segments=16), dict(tile_segments=64), dict(grid=37),
+               dict(tile_segments=8, grid=300)):
+        g = gpu_run(wl, ckv.CKV_MIXED, **kw)
+        np.testing.assert_array_equal(g["offsets"], base["offsets"])
+        np.testing.assert_array_equal(g["rec"].view(np.uint32), base["rec"].view(np.uint32))
+        np.testing.assert_array_equal(g["ids"], base["ids"])
+
+
+def test_chunked_run_equals_one_shot(vg):
+    wl, cfg, r = vg
+    whole = gpu_run(wl, ckv.CKV_FP64)
+    cuts = [0, 7001, 13999, wl.segs.n]
+    parts = []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        sub = wl.segs.take(np.arange(a, b))
+        parts.append(gpu_run(wl, ckv.CKV_FP64, segs=sub, seg_id_base=[a]))
+    n_tel = wl.tels.n
+    for t in range(n_tel):
+        rec = np.concatenate([p["rec"][p["offsets"][t]:p["offsets"][t + 1]] for p in parts])
+        np.testing.assert_array_equal(rec, whole["rec"][whole["offsets"][t]:whole["offsets"][t + 1]])
+
+
+def test_overflow_reports_required_capacity(vg):
+    wl, cfg, r = vg
+    g = gpu_run(wl, ckv.CKV_FP64, capacity=1000)
+    res = g["result"]
+    assert res["overflow"] == 1 and res["n_records"] == 0
+    assert res["n_hits"] == len(r.seg)
+    np.testing.assert_array_equal(g["offsets"], r.offsets)     # offsets stay valid
+    g2 = gpu_run(wl, ckv.CKV_FP64, capacity=int(res["n_hits"]))
+    assert g2["result"]["overflow"] == 0
+    np.testing.assert_array_equal(g2["offsets"], r.offsets)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def _custom_segments(rows, offsets=None):
+    a = np.array(rows, dtype=np.float64).reshape(-1, 10)
+    m = a.shape[0]
+    offs = np.array([0, m] if offsets is None else offsets, dtype=np.int64)
+    ns = len(offs) - 1
+    return synth.Segments(*[a[:, i].copy() for i in range(9)], a[:, 9].astype(np.uint8), offs,
+                          np.zeros(ns), np.arange(ns, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_drop_paths_and_empty_showers(precision):
+    wl = synth.vertical_gamma(10)
+    cfg = oracle.Config.from_workload(wl)
+    s = np.sin(np.radians(85.0))
+    rows = [
+        # x0 y0 h0 u v w L t0 E ptype
+        [0, 0, 8000, 0, 0, 1, 20, 0, 1e3, 0],                 # normal
+        [0, 0, 8000, 0, 0, -1, 20, 0, 1e3, 0],                # upward track: upward photons
+        [0, 0, 8000, s, 0, np.cos(np.radians(85.0)), 20, 0, 1e3, 0],   # grazing
+        [0, 0, 2205, 0, 0, 1, 40, 0, 1e3, 0],                 # crosses the observation level
+        [0, 0, 99950, 0, 0, -1, 300, 0, 1e5, 0],              # leaves the table top
+        [0, 0, 99950, 0, 0, -1, 300, 0, 1e5, 0],
+        [0, 0, 99950, 0, 0, -1, 300, 0, 1e5, 0],
+        [0, 0, 8000, 0, 0, 1, 20, 0, 0.3, 0],                 # E < m
+        [0, 0, 8000, 0, 0, 1, 20, 0, 20.0, 0],                # below threshold
+        [0, 0, 8000, 0, 0, 1, np.nan, 0, 1e3, 0],             # non-finite
+        [0, 0, 8000, 0, 0, 1, -5, 0, 1e3, 0],                 # negative length
+        [30, -20, 12000, 0.05, 0.02, 0.9985, 80, 0, 5e4, 1],  # muon
+    ]
+    # showers: [0,4) , empty, [4,12)
+    segs = _custom_segments(rows, offsets=[0, 4, 4, 12])
+    ores = oracle.run(cfg, segs)
+    g = gpu_run(wl, precision, segs=segs)
+    res = g["result"]
+    assert res["error"] == 0
+    assert res["drops"] == ores.drops and res["n_bunches"] == ores.n_bunches
+    assert ores.drops["upward"] > 0 and ores.drops["grazing"] > 0 and ores.drops["below_obs"] > 0
+    assert ores.drops["above_top"] > 0
+    if precision == ckv.CKV_FP64:
+        np.testing.assert_array_equal(g["offsets"], ores.offsets)
+    compare_records(wl, cfg, ores, g, precision, segs=segs)
+
+
+def test_no_segments_and_single_telescope():
+    wl = synth.vertical_gamma(10)
+    empty = _custom_segments(np.zeros((0, 10)))
+    g = gpu_run(wl, ckv.CKV_MIXED, segs=empty)
+    assert g["result"]["n_bunches"] == 0 and g["result"]["n_hits"] == 0
+    assert np.all(g["offsets"] == 0)
+    wl1 = synth.vertical_gamma(3000)
+    wl1.tels = synth.Telescopes(np.array([0.0]), np.array([0.0]), np.array([40.0]))
+    cfg = oracle.Config.from_workload(wl1)
+    ores = oracle.run(cfg, wl1.segs, nthreads=8)
+    g = gpu_run(wl1, ckv.CKV_FP64)
+    np.testing.assert_array_equal(g["offsets"], ores.offsets)
+    compare_records(wl1, cfg, ores, g, ckv.CKV_FP64)
+
+
+def test_bad_shower_offsets_flagged_on_device():
+    wl = synth.vertical_gamma(100)
+    segs = wl.segs
+    bad = synth.Segments(*[getattr(segs, f) for f in segs.FIELDS], segs.ptype,
+                         np.array([0, 150], dtype=np.int64), segs.t_ref, segs.shower_ids)
+    g = gpu_run(wl, ckv.CKV_MIXED, segs=bad)
+    assert g["result"]["error"] == 1 and g["result"]["n_bunches"] == 0
