@@ -1,0 +1,292 @@
+"""Throughput of the Cherenkov bunch path on one MI355X.
+
+One step = one ckv_run over the 1 TeV gamma-like shower at 20 deg zenith
+(2e6 track steps, ~1.2e8 bunches, 100 telescopes, 5-layer atmosphere on a
+50 m grid): bunch counts, emission, propagation, sphere tests and the ordered
+per-telescope output, with the inputs already resident in HBM.
+
+The reported value is bunches generated and propagated per second in the
+mixed FP32/FP64 path; the FP64 path is timed the same way and reported beside
+it.  The roofline entry refers to the bunch kernel (the dominant kernel); its
+duration is measured with HIP events recorded around that kernel on the
+stream it runs on.  The CPU baseline is the FP64 oracle timed on a sample of
+the same shower.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# --- algorithmic VALU issue slots per generated bunch (one slot = one lane of
+# one full-rate VALU operation; quarter-rate operations -- 32x32->64 integer
+# multiplies, reciprocals, square roots -- count 4).  Derivation per step of
+# the algorithm in the design notes.
+SLOTS_MIXED = {
+    "philox4x32-10: 20 mul32x32->64 (x4) + 40 xor": 120,
+    "uniforms, emission point and time (FP64)": 13,
+    "azimuth sin/cos (FP32 polynomial, quadrant fold)": 19,
+    "direction on the cone (FP32 perpendicular, FP64 sum)": 12,
+    "wavelength (inverse CDF, rcp)": 7,
+    "drop tests": 4,
+    "table index and partial-cell moments P1..P5": 28,
+    "moment transform D1..D5": 25,
+    "index at emission (sqrt, rcp)": 11,
+    "1/w (FP64 rcp + 2 Newton steps)": 8,
+    "series variable q (rcp)": 7,
+    "advance series, ground point": 13,
+    "time series, arrival time": 24,
+    "observed direction cosines": 4,
+    "candidate cell + one sphere test (FP64)": 18,
+}
+SLOTS_FP64 = {
+    "philox4x32-10": 120,
+    "uniforms, emission point and time": 13,
+    "azimuth sincos (FP64 library)": 50,
+    "direction on the cone": 9,
+    "wavelength (FP64 divide)": 12,
+    "drop tests": 4,
+    "table index and partial-cell moments": 28,
+    "moment transform D1..D5": 25,
+    "index at emission (FP64 sqrt, divide)": 24,
+    "1/w and q (FP64 divides)": 24,
+    "advance series, ground point": 13,
+    "time series, arrival time (FP64 divide)": 36,
+    "observed direction cosines": 4,
+    "candidate cell + one sphere test": 18,
+}
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate VALU issue
+PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+SEG_BYTES = 9 * 8 + 1            # SoA step record read once
+STAGE_BYTES = 64                 # staging entry written and read back
+RECORD_BYTES = 32                # output record
+
+
+def _hip():
+    for name in ("libamdhip64.so", "/opt/rocm/lib/libamdhip64.so"):
+        try:
+            h = C.CDLL(name)
+            h.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+            h.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
+            h.hipEventSynchronize.argtypes = [C.c_void_p]
+            h.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+            h.hipEventDestroy.argtypes = [C.c_void_p]
+            return h
+        except OSError:
+            continue
+    raise RuntimeError("libamdhip64.so not found")
+
+
+def _event(hip):
+    e = C.c_void_p()
+    if hip.hipEventCreate(C.byref(e)) != 0:
+        raise RuntimeError("hipEventCreate failed")
+    return e
+
+
+def _elapsed_ms(hip, a, b) -> float:
+    ms = C.c_float()
+    if hip.hipEventElapsedTime(C.byref(ms), a, b) != 0:
+        raise RuntimeError("hipEventElapsedTime failed")
+    return float(ms.value)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2006_14927_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(name: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_path(hip, ckv, dsegs, atmo, tels, params, capacity, steps, warmup, stream):
+    """warmup + steps launches on `stream`; returns (ms per step, bunch-kernel ms, result)."""
+    import torch
+    r = ckv.Runner(dsegs, atmo, tels, params, capacity, want_ids=False)
+    for _ in range(warmup):
+        r.run(stream)
+    torch.cuda.synchronize()
+    ev_k = [(_event(hip), _event(hip)) for _ in range(steps)]
+    t_begin, t_end = _event(hip), _event(hip)
+    sp = C.c_void_p(stream.cuda_stream)
+    hip.hipEventRecord(t_begin, sp)
+    for b, e in ev_k:
+        r.params.event_begin = b.value
+        r.params.event_end = e.value
+        out = r.run(stream)
+    hip.hipEventRecord(t_end, sp)
+    hip.hipEventSynchronize(t_end)
+    torch.cuda.synchronize()
+    total_ms = _elapsed_ms(hip, t_begin, t_end)
+    kern_ms = [_elapsed_ms(hip, b, e) for (b, e) in ev_k]
+    r.params.event_begin = None
+    r.params.event_end = None
+    for b, e in ev_k + [(t_begin, t_end)]:
+        hip.hipEventDestroy(b)
+        hip.hipEventDestroy(e)
+    return total_ms / steps, sum(kern_ms) / len(kern_ms), out.result()
+
+
+def cpu_baseline(wl, target_cpu_seconds: float = 20.0):
+    """The FP64 oracle on an evenly spaced sample of the shower's steps."""
+    import numpy as np
+
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    cfg = oracle.Config.from_workload(wl)
+    # probe the rate on a small sample, then size the timed sample
+    probe = np.arange(0, wl.segs.n, max(1, wl.segs.n // 4000))
+    t0 = time.perf_counter()
+    r = oracle.run(cfg, wl.segs.take(probe), nthreads=threads, seg_id=probe)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    rate_cpu_s = r.n_bunches / (dt * threads)          # bunches per CPU-second
+    want_bunches = target_cpu_seconds * rate_cpu_s
+    mean_b = max(r.n_bunches / len(probe), 1e-9)
+    stride = max(1, int(wl.segs.n * mean_b / max(want_bunches, 1.0)))
+    idx = np.arange(0, wl.segs.n, stride)
+    t0 = time.perf_counter()
+    r = oracle.run(cfg, wl.segs.take(idx), nthreads=threads, seg_id=idx)
+    dt = time.perf_counter() - t0
+    return {"value": r.n_bunches / dt, "unit": "bunches/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th step of the shower ({len(idx)} steps, {r.n_bunches} "
+                      f"bunches, {len(r.seg)} records), FP64, {dt:.2f} s wall"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--segments", type=int, default=2_000_000,
+                    help="steps in the shower (default: the 2e6-step TeV shower)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (HBM counter calibration)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(showers and step ranges shard independently; see the design notes).",
+              file=sys.stderr)
+        return 2
+    import torch
+
+    from paper_2006_14927_amd import ckv, synth
+    ckv.lib()      # fails loudly when the HIP library is missing
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    hip = _hip()
+
+    wl = synth.single_tev(args.segments)
+    atmo = ckv.Atmosphere(wl.atmo.alt, wl.atmo.eta, wl.atmo.obs_level, wl.fine_step)
+    tels = ckv.TelescopeArray(wl.tels.x, wl.tels.y, wl.tels.r)
+    dsegs = ckv.DeviceSegments(wl.segs)
+    capacity = max(1 << 16, wl.segs.n * 2)
+
+    def mk(precision):
+        return ckv.make_params(precision=precision, bunch_size=wl.bunch_size,
+                               lambda_min=wl.lambda_min, lambda_max=wl.lambda_max, seed=wl.seed)
+
+    print(f"# workload {wl.name}: {wl.segs.n} steps, {wl.tels.n} telescopes", file=sys.stderr,
+          flush=True)
+    ms_mixed, kms_mixed, res_mixed = time_path(hip, ckv, dsegs, atmo, tels, mk(ckv.CKV_MIXED),
+                                               capacity, args.steps, args.warmup, stream)
+    print(f"# mixed: {ms_mixed:.3f} ms/step, bunch kernel {kms_mixed:.3f} ms", file=sys.stderr,
+          flush=True)
+    ms_fp64, kms_fp64, res_fp64 = time_path(hip, ckv, dsegs, atmo, tels, mk(ckv.CKV_FP64),
+                                            capacity, args.steps, args.warmup, stream)
+    print(f"# fp64: {ms_fp64:.3f} ms/step, bunch kernel {kms_fp64:.3f} ms", file=sys.stderr,
+          flush=True)
+    for res in (res_mixed, res_fp64):
+        if res["error"] or res["overflow"]:
+            raise RuntimeError(f"run reported a problem: {res}")
+    nb = res_mixed["n_bunches"]
+    assert nb == res_fp64["n_bunches"]
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"# copy probe: {args.copy_probe_mib} MiB read + written, 3 launches", file=sys.stderr)
+
+    slots_mixed = sum(SLOTS_MIXED.values())
+    achieved = slots_mixed * nb / (kms_mixed * 1e-3) / 1e12
+    peak = PEAK_SLOTS_PER_S / 1e12
+    traffic = stored_traffic("bunch_kernel_single_tev_mixed")
+    hits = res_mixed["n_hits"]
+    alg_bytes = wl.segs.n * SEG_BYTES + hits * STAGE_BYTES
+    line = {
+        "metric": "bunches/s gen+propagated, mixed vs FP64 plain at oracle tol; fwd+bwd ms/shower",
+        "value": nb / (ms_mixed * 1e-3),
+        "unit": "bunches/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_mixed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "steps_in_shower": wl.segs.n, "telescopes": wl.tels.n,
+                   "zenith_deg": 20.0, "atmosphere": "5-layer exponential, 50 m grid to 120 km",
+                   "bunch_size": wl.bunch_size, "band_nm": [wl.lambda_min, wl.lambda_max],
+                   "precision": "mixed"},
+        "bunches_per_step": nb,
+        "records_per_step": hits,
+        "fp64_plain": {"value": nb / (ms_fp64 * 1e-3), "ms_per_step": ms_fp64,
+                       "bunch_kernel_ms": kms_fp64,
+                       "roofline_frac": sum(SLOTS_FP64.values()) * nb / (kms_fp64 * 1e-3)
+                       / PEAK_SLOTS_PER_S},
+        "mixed_over_fp64": ms_fp64 / ms_mixed,
+        "bunch_kernel_ms": kms_mixed,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "frac": achieved / peak,
+                     "traffic": traffic},
+        "hbm": {"algorithmic_bytes_per_launch": alg_bytes,
+                "achieved_GBs": alg_bytes / (kms_mixed * 1e-3) / 1e9,
+                "frac": alg_bytes / (kms_mixed * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "fwd_bwd_ms_per_shower": None,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -150,9 +150,11 @@ typedef struct {
     double w_min;          /* bunches with w <= w_min are dropped (0 <= w_min < 1) */
     uint64_t seed;         /* Philox key */
     int32_t precision;     /* CKV_FP64 or CKV_MIXED */
-    int32_t tile_segments; /* steps per emit tile, 0 = default (32) */
+    int32_t tile_segments; /* steps per emit tile: 8, 16, 32 or 64; 0 = default (32) */
     int32_t grid;          /* emit workgroups, 0 = one per compute unit */
     int32_t reserved;
+    void* event_begin;     /* optional hipEvent_t recorded on the stream just before */
+    void* event_end;       /* and just after the bunch kernel (profiling); NULL = none */
 } ckv_params;
 
 /* Device-side report, written by ckv_run (the caller syncs the stream before

@@ -45,7 +45,7 @@ class _Params(C.Structure):
     _fields_ = [("bunch_size", C.c_double), ("lambda_min_nm", C.c_double),
                 ("lambda_max_nm", C.c_double), ("w_min", C.c_double), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("tile_segments", C.c_int32), ("grid", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("event_begin", C.c_void_p), ("event_end", C.c_void_p)]
 
 
 class _Result(C.Structure):
@@ -194,9 +194,10 @@ class DeviceSegments:
 
 
 def make_params(*, precision=CKV_MIXED, bunch_size=5.0, lambda_min=300.0, lambda_max=600.0,
-                w_min=0.1, seed=0x14927, tile_segments=0, grid=0) -> _Params:
+                w_min=0.1, seed=0x14927, tile_segments=0, grid=0, event_begin=None,
+                event_end=None) -> _Params:
     return _Params(bunch_size, lambda_min, lambda_max, w_min, int(seed) & (2**64 - 1),
-                   int(precision), int(tile_segments), int(grid), 0)
+                   int(precision), int(tile_segments), int(grid), 0, event_begin, event_end)
 
 
 def workspace_size(n_segments, n_showers, n_tel, capacity, params: _Params) -> int:

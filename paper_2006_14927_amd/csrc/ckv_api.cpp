@@ -51,8 +51,9 @@ int check_params(const ckv_params* p)
     if (p->precision != CKV_FP64 && p->precision != CKV_MIXED) {
         set_error("unknown precision"); return CKV_ERR_ARG;
     }
-    if (p->tile_segments < 0 || p->tile_segments > kMaxTileSegs) {
-        set_error("tile_segments must be in [0, 64]"); return CKV_ERR_ARG;
+    if (p->tile_segments != 0 && p->tile_segments != 8 && p->tile_segments != 16 &&
+        p->tile_segments != 32 && p->tile_segments != 64) {
+        set_error("tile_segments must be 0 (default), 8, 16, 32 or 64"); return CKV_ERR_ARG;
     }
     if (p->grid < 0) { set_error("grid must be >= 0"); return CKV_ERR_ARG; }
     return CKV_OK;

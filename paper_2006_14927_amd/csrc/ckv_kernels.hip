@@ -22,6 +22,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "ckv_internal.h"
 
@@ -66,6 +67,7 @@ struct Args {
     StageEntry* stage;
     int64_t stage_blocks;
     int64_t max_tiles;
+    int64_t max_row_blocks;
     float* records;
     int64_t* ids;
     int64_t capacity;
@@ -235,61 +237,67 @@ __device__ __forceinline__ void sincos_turns(uint32_t r, float& s, float& c)
 
 // --------------------------------------------------------------------------
 // LDS layout of the bunch kernel
+//   [atmosphere table][wave 0 area][wave 1 area]...
+// wave area: TS step entries (the emitting steps of the current tile,
+// compacted), a 64-entry flag row used to map bunches to steps, the per-
+// telescope crossing counters of the tile, and the wave's run counters.
 // --------------------------------------------------------------------------
 template <int PREC>
-struct Layout;
+struct StepEntry;
 
-// PREC 0: FP64 throughout; FP64 node table {psi, P1..P5}
+// mixed: FP64 position/time/direction, FP32 perpendicular cone vectors
 template <>
-struct Layout<0> {
-    using T = double;
-    static constexpr int kStashD = 17;   // doubles per step in the stash
-    static constexpr int kStashF = 0;
-    __host__ __device__ static size_t table_bytes(int n_nodes) { return (size_t)n_nodes * kNode64 * sizeof(double); }
+struct alignas(16) StepEntry<1> {
+    double x0, y0, h0, t0, u, v, w, cos_t, ds, inv_bc;
+    float sb1x, sb1y, sb1z, sb2x, sb2y, sb2z, photons;
+    int32_t boff;   // first bunch of the step inside the tile
+    int32_t sidx;   // index of the step inside the tile
+    int32_t pad[3];
 };
-// PREC 1: mixed; FP32 cell table {psi, dpsi, P1..P5, 0}
+static_assert(sizeof(StepEntry<1>) == 128, "step entry size");
+
 template <>
-struct Layout<1> {
-    using T = float;
-    static constexpr int kStashD = 10;
-    static constexpr int kStashF = 7;
-    __host__ __device__ static size_t table_bytes(int n_nodes) { return (size_t)(n_nodes - 1) * kCell32 * sizeof(float); }
+struct alignas(16) StepEntry<0> {
+    double x0, y0, h0, t0, u, v, w, cos_t, ds, inv_bc;
+    double sb1x, sb1y, sb1z, sb2x, sb2y, sb2z, photons;
+    int32_t boff;
+    int32_t sidx;
 };
+static_assert(sizeof(StepEntry<0>) == 144, "step entry size");
 
 // per-wave counters kept in LDS (wave-uniform increments by lane 0)
 enum WaveCounter { kWcBunches = 0, kWcEmitting, kWcHits, kWcDrop0, kWcCount = kWcDrop0 + CKV_N_DROP };
 
-__host__ __device__ inline size_t wave_bytes(int prec, int tile_segs, int n_tel)
+__host__ __device__ inline size_t table_bytes(int prec, int n_nodes)
 {
-    const int sd = prec == 0 ? 17 : 10, sf = prec == 0 ? 0 : 7;
-    size_t b = (size_t)sd * tile_segs * 8 + (size_t)sf * tile_segs * 4 + (size_t)(tile_segs + 1) * 4 +
-               (size_t)n_tel * 4;
-    b = (b + 7) & ~(size_t)7;
-    b += (size_t)kWcCount * 8;
-    return (b + 15) & ~(size_t)15;
+    return prec == 0 ? (size_t)n_nodes * kNode64 * sizeof(double)
+                     : (size_t)(n_nodes - 1) * kCell32 * sizeof(float);
 }
 
-// stash field indices (doubles): 0 x0, 1 y0, 2 h0, 3 t0, 4 u, 5 v, 6 w, 7 cos_t,
-// 8 ds, 9 inv_bc, then (PREC 0) 10..15 sin_t*b1, sin_t*b2, 16 photons;
-// (PREC 1) floats 0..5 sin_t*b1, sin_t*b2, 6 photons.
-
+__host__ __device__ inline size_t wave_bytes(int prec, int tile_segs, int n_tel)
+{
+    size_t b = (size_t)tile_segs * (prec == 0 ? sizeof(StepEntry<0>) : sizeof(StepEntry<1>));
+    b += kWave * sizeof(int32_t);                       // flag row
+    b += (size_t)kWcCount * sizeof(int64_t);            // counters
+    b += ((size_t)n_tel * sizeof(int32_t) + 15) & ~(size_t)15;   // telescope counters
+    return (b + 15) & ~(size_t)15;
+}
 
 // --------------------------------------------------------------------------
 // the bunch kernel
 // --------------------------------------------------------------------------
-template <int PREC>
+template <int PREC, int TS>
 __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
 {
-    using L = Layout<PREC>;
-    using T = typename L::T;
+    using T = typename std::conditional<PREC == 0, double, float>::type;
+    using Entry = StepEntry<PREC>;
     extern __shared__ __align__(16) unsigned char lds[];
 
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
-    const int TS = a.tile_segs;
 
     // ---- stage the atmosphere table once per workgroup
-    const size_t tab_bytes = L::table_bytes(a.n_nodes);
+    const size_t tab_bytes = table_bytes(PREC, a.n_nodes);
     {
         const uint4* src = reinterpret_cast<const uint4*>(PREC == 0 ? (const void*)a.node64
                                                                     : (const void*)a.cell32);
@@ -297,15 +305,15 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
         const int n16 = (int)(tab_bytes / 16);
         for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
     }
-    unsigned char* wbase = lds + ((tab_bytes + 15) & ~(size_t)15) + (size_t)wave * wave_bytes(PREC, TS, a.n_tel);
-    double* sd = reinterpret_cast<double*>(wbase);
-    float* sf = reinterpret_cast<float*>(wbase + (size_t)L::kStashD * TS * 8);
-    int32_t* boff = reinterpret_cast<int32_t*>(wbase + (size_t)L::kStashD * TS * 8 + (size_t)L::kStashF * TS * 4);
-    int32_t* tcount = boff + (TS + 1);
-    int64_t* wcnt = reinterpret_cast<int64_t*>(
-        reinterpret_cast<uintptr_t>(tcount + a.n_tel + 1) & ~(uintptr_t)7);
+    unsigned char* wbase = lds + ((tab_bytes + 15) & ~(size_t)15) +
+                           (size_t)wave * wave_bytes(PREC, TS, a.n_tel);
+    Entry* stash = reinterpret_cast<Entry*>(wbase);
+    int32_t* flags = reinterpret_cast<int32_t*>(wbase + TS * sizeof(Entry));
+    int64_t* wcnt = reinterpret_cast<int64_t*>(flags + kWave);
+    int32_t* tcount = reinterpret_cast<int32_t*>(wcnt + kWcCount);
     for (int k = lane; k < a.n_tel; k += kWave) tcount[k] = 0;
     if (lane < kWcCount) wcnt[lane] = 0;
+    flags[lane] = 0;
     __syncthreads();
 
     const double* tab64 = reinterpret_cast<const double*>(lds);
@@ -313,7 +321,8 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
     const T a1 = (T)-0.5, a2 = (T)0.375, a3 = (T)-0.3125, a4 = (T)0.2734375;
     const double inv_c = 1.0 / kSpeedOfLight;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // (1 + delta_obs) with delta = psi / (1 + sqrt(1 + psi)) = n - 1
+    const uint64_t le_mask = lt_mask | (1ull << lane);
+    // n - 1 at the observation level, for the observed direction
     const float d_obs = (float)(a.n_obs - 1.0);
     const float inv_1pdobs = 1.0f / (1.0f + d_obs);
 
@@ -341,37 +350,14 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
         const int64_t seg_id0 = (a.seg_id_base ? a.seg_id_base[s] : 0) + (g0 - sfirst);
         const double t_ref = a.t_ref[s];
 
-        // ---- step setups, one per lane
+        // ---- step setups, one per lane; emitting steps are compacted
         int64_t nb = 0;
         int status = -2;   // -2: no step in this lane
+        Setup st;
         if (lane < nseg) {
-            Setup st;
             step_setup(a, g0 + lane, st);
             status = st.status;
-            if (st.status < 0) {
-                nb = st.nb;
-                const int64_t g = g0 + lane;
-                sd[0 * TS + lane] = a.x0[g];
-                sd[1 * TS + lane] = a.y0[g];
-                sd[2 * TS + lane] = a.h0[g];
-                sd[3 * TS + lane] = a.t0[g];
-                sd[4 * TS + lane] = a.u[g];
-                sd[5 * TS + lane] = a.v[g];
-                sd[6 * TS + lane] = a.w[g];
-                sd[7 * TS + lane] = st.cos_t;
-                sd[8 * TS + lane] = st.ds;
-                sd[9 * TS + lane] = st.inv_bc;
-                const double p[7] = {st.sin_t * st.b1x, st.sin_t * st.b1y, st.sin_t * st.b1z,
-                                     st.sin_t * st.b2x, st.sin_t * st.b2y, st.sin_t * st.b2z,
-                                     st.photons};
-                if (PREC == 0) {
-#pragma unroll
-                    for (int q = 0; q < 7; ++q) sd[(10 + q) * TS + lane] = p[q];
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 7; ++q) sf[q * TS + lane] = (float)p[q];
-                }
-            }
+            if (st.status < 0) nb = st.nb;
         }
         int64_t incl = wave_incl_scan(nb);
         int64_t total = __shfl(incl, kWave - 1);
@@ -381,21 +367,44 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
             total = 0;
             incl = 0;
             nb = 0;
+            status = status == -1 ? -3 : status;
         }
-        if (lane < nseg) boff[lane] = (int32_t)(incl - nb);
-        if (lane >= nseg && lane <= TS) boff[lane] = (int32_t)total;
+        const bool emits = status == -1;
+        const uint64_t emit_mask = __ballot(emits);
+        const int excl = (int)(incl - nb);      // first bunch of this lane's step
+        if (emits) {
+            Entry& e = stash[__popcll(emit_mask & lt_mask)];
+            const int64_t g = g0 + lane;
+            e.x0 = a.x0[g];
+            e.y0 = a.y0[g];
+            e.h0 = a.h0[g];
+            e.t0 = a.t0[g];
+            e.u = a.u[g];
+            e.v = a.v[g];
+            e.w = a.w[g];
+            e.cos_t = st.cos_t;
+            e.ds = st.ds;
+            e.inv_bc = st.inv_bc;
+            e.sb1x = (T)(st.sin_t * st.b1x);
+            e.sb1y = (T)(st.sin_t * st.b1y);
+            e.sb1z = (T)(st.sin_t * st.b1z);
+            e.sb2x = (T)(st.sin_t * st.b2x);
+            e.sb2y = (T)(st.sin_t * st.b2y);
+            e.sb2z = (T)(st.sin_t * st.b2z);
+            e.photons = (T)st.photons;
+            e.boff = excl;
+            e.sidx = lane;
+        }
         {
-            const int n_emit = __popcll(__ballot(status == -1));
-            int dcount[3];
-            dcount[0] = __popcll(__ballot(status == CKV_DROP_MASS));
-            dcount[1] = __popcll(__ballot(status == CKV_DROP_THRESHOLD));
-            dcount[2] = __popcll(__ballot(status == CKV_DROP_NONFINITE));
+            const int d_mass = __popcll(__ballot(status == CKV_DROP_MASS));
+            const int d_thr = __popcll(__ballot(status == CKV_DROP_THRESHOLD));
+            const int d_nf = __popcll(__ballot(status == CKV_DROP_NONFINITE));
             if (lane == 0) {
                 wcnt[kWcBunches] += total;
-                wcnt[kWcEmitting] += n_emit;
-                wcnt[kWcDrop0 + CKV_DROP_MASS] += dcount[0];
-                wcnt[kWcDrop0 + CKV_DROP_THRESHOLD] += dcount[1];
-                wcnt[kWcDrop0 + CKV_DROP_NONFINITE] += dcount[2];
+                wcnt[kWcEmitting] += __popcll(emit_mask);
+                wcnt[kWcDrop0 + CKV_DROP_MASS] += d_mass;
+                wcnt[kWcDrop0 + CKV_DROP_THRESHOLD] += d_thr;
+                wcnt[kWcDrop0 + CKV_DROP_NONFINITE] += d_nf;
             }
         }
         wave_lds_sync();
@@ -404,61 +413,84 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
         for (int64_t c0 = 0; c0 < total; c0 += kWave) {
             const int32_t j = (int32_t)(c0 + lane);
             const bool active = j < total;
-            // step of bunch j: largest si with boff[si] <= j
-            int si = 0;
-            for (int stp = kMaxTileSegs / 2; stp >= 1; stp >>= 1)
-                if (si + stp < TS && boff[si + stp] <= j) si += stp;
-            const int32_t k = j - boff[si];
+            // step of bunch j: emitting steps starting at or before c0, plus the
+            // steps starting inside this chunk at or before j (flag row)
+            const int cnt0 = __popcll(__ballot(emits && excl <= (int)c0));
+            if (emits && excl > (int)c0 && excl < (int)c0 + kWave) flags[excl - (int)c0] = 1;
+            wave_lds_sync();
+            const uint64_t starts = __ballot(flags[lane] != 0);
+            flags[lane] = 0;
+            const int si = cnt0 - 1 + __popcll(starts & le_mask);
+            // Philox round keys, advanced on the scalar unit inside the loop
+            const uint32_t opaque = (uint32_t)(c0 >> 40);   // 0; keeps the schedule in the loop
+            uint32_t kr0 = a.key0 + opaque, kr1 = a.key1 + opaque;
 
             bool alive = false;
             int drop_why = -1;
             double xg = 0, yg = 0, he = 0, tarr = 0;
             float uo = 0, vo = 0, lam = 0, photons = 0, he_f = 0, t_f = 0;
+            int32_t k = 0, sidx = 0;
             if (active) {
-                uint32_t r[4];
-                philox4x32_10((uint32_t)k, (uint32_t)(seg_id0 + si), shower_id, 0u, a.key0, a.key1, r);
+                const Entry& e = stash[si];
+                k = j - e.boff;
+                sidx = e.sidx;
+                // Philox4x32-10 with counter (k, step index in shower, shower id, 0)
+                uint32_t c_0 = (uint32_t)k, c_1 = (uint32_t)(seg_id0 + sidx), c_2 = shower_id, c_3 = 0u;
+#pragma unroll
+                for (int rr = 0; rr < 10; ++rr) {
+                    const uint64_t p0 = (uint64_t)0xD2511F53u * c_0;
+                    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c_2;
+                    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c_1, kr0, 0x96);
+                    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c_3, kr1, 0x96);
+                    c_1 = (uint32_t)p1;
+                    c_3 = (uint32_t)p0;
+                    c_0 = n0;
+                    c_2 = n2;
+                    kr0 += 0x9E3779B9u;
+                    kr1 += 0xBB67AE85u;
+                }
+                const uint32_t r0 = c_0, r1 = c_1, r2 = c_2;
                 // emission point, uniform inside sub-step k (FP64)
-                const double u0 = ((double)r[0] + 0.5) * 2.3283064365386963e-10;
-                const double s_along = ((double)k + u0) * sd[8 * TS + si];
-                const double tu = sd[4 * TS + si], tv = sd[5 * TS + si], tw = sd[6 * TS + si];
-                const double xe = sd[0 * TS + si] + s_along * tu;
-                const double ye = sd[1 * TS + si] + s_along * tv;
-                he = sd[2 * TS + si] - s_along * tw;
-                const double te = sd[3 * TS + si] + s_along * sd[9 * TS + si];
-                const double ct = sd[7 * TS + si];
+                const double u0 = fma((double)r0, 2.3283064365386963e-10, 1.1641532182693481e-10);
+                const double s_along = ((double)k + u0) * e.ds;
+                const double tu = e.u, tv = e.v, tw = e.w;
+                const double xe = fma(s_along, tu, e.x0);
+                const double ye = fma(s_along, tv, e.y0);
+                he = fma(-s_along, tw, e.h0);
+                const double te = fma(s_along, e.inv_bc, e.t0);
+                const double ct = e.cos_t;
                 // direction on the Cherenkov cone
                 double pu, pv, pw;
                 if (PREC == 0) {
-                    const double phi = 6.283185307179586 * (((double)r[1] + 0.5) * 2.3283064365386963e-10);
+                    const double phi = 6.283185307179586 * fma((double)r1, 2.3283064365386963e-10,
+                                                               1.1641532182693481e-10);
                     double sp, cp;
                     sincos(phi, &sp, &cp);
-                    pu = ct * tu + (cp * sd[10 * TS + si] + sp * sd[13 * TS + si]);
-                    pv = ct * tv + (cp * sd[11 * TS + si] + sp * sd[14 * TS + si]);
-                    pw = ct * tw - (cp * sd[12 * TS + si] + sp * sd[15 * TS + si]);
-                    photons = (float)sd[16 * TS + si];
-                    lam = (float)(1.0 / (a.inv_l1 - (((double)r[2] + 0.5) * 2.3283064365386963e-10) * a.dl));
+                    pu = ct * tu + (cp * (double)e.sb1x + sp * (double)e.sb2x);
+                    pv = ct * tv + (cp * (double)e.sb1y + sp * (double)e.sb2y);
+                    pw = ct * tw - (cp * (double)e.sb1z + sp * (double)e.sb2z);
+                    photons = (float)e.photons;
+                    lam = (float)(1.0 / (a.inv_l1 - fma((double)r2, 2.3283064365386963e-10,
+                                                        1.1641532182693481e-10) * a.dl));
                 } else {
                     float sp, cp;
-                    sincos_turns(r[1], sp, cp);
-                    const float px = fmaf(cp, sf[0 * TS + si], sp * sf[3 * TS + si]);
-                    const float py = fmaf(cp, sf[1 * TS + si], sp * sf[4 * TS + si]);
-                    const float pz = fmaf(cp, sf[2 * TS + si], sp * sf[5 * TS + si]);
+                    sincos_turns(r1, sp, cp);
+                    const float px = fmaf(cp, (float)e.sb1x, sp * (float)e.sb2x);
+                    const float py = fmaf(cp, (float)e.sb1y, sp * (float)e.sb2y);
+                    const float pz = fmaf(cp, (float)e.sb1z, sp * (float)e.sb2z);
                     pu = fma(ct, tu, (double)px);
                     pv = fma(ct, tv, (double)py);
                     pw = fma(ct, tw, -(double)pz);
-                    photons = sf[6 * TS + si];
-                    const float u2 = fmaf((float)r[2], 2.3283064365386963e-10f, 1.16415321826934814e-10f);
+                    photons = (float)e.photons;
+                    const float u2 = fmaf((float)r2, 2.3283064365386963e-10f, 1.16415321826934814e-10f);
                     lam = __builtin_amdgcn_rcpf(fmaf(-u2, (float)a.dl, (float)a.inv_l1));
                 }
                 // drop rules
-                int why = -1;
-                if (he < a.h_obs) why = CKV_DROP_BELOW_OBS;
-                else if (he >= a.h_top) why = CKV_DROP_ABOVE_TOP;
-                else if (pw <= 0.0) why = CKV_DROP_UPWARD;
-                else if (pw <= a.w_min) why = CKV_DROP_GRAZING;
-                if (why >= 0) {
-                    drop_why = why;
-                } else {
+                if (he < a.h_obs) drop_why = CKV_DROP_BELOW_OBS;
+                else if (he >= a.h_top) drop_why = CKV_DROP_ABOVE_TOP;
+                else if (pw <= 0.0) drop_why = CKV_DROP_UPWARD;
+                else if (pw <= a.w_min) drop_why = CKV_DROP_GRAZING;
+                if (drop_why < 0) {
                     alive = true;
                     // ---- atmosphere at the emission altitude (uniform table, no search)
                     const double x = (he - a.h_obs) * a.inv_step;
@@ -473,16 +505,15 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                         P1 = nd[1]; P2 = nd[2]; P3 = nd[3]; P4 = nd[4]; P5 = nd[5];
                     } else {
                         const float4* cc = reinterpret_cast<const float4*>(tab32 + (size_t)kCell32 * ci);
-                        const float4 c_0 = cc[0], c_1 = cc[1];
-                        psi_i = c_0.x; dpsi = c_0.y; P1 = c_0.z; P2 = c_0.w;
-                        P3 = c_1.x; P4 = c_1.y; P5 = c_1.z;
+                        const float4 c_a = cc[0], c_b = cc[1];
+                        psi_i = c_a.x; dpsi = c_a.y; P1 = c_a.z; P2 = c_a.w;
+                        P3 = c_b.x; P4 = c_b.y; P5 = c_b.z;
                     }
                     const T psi_e = psi_i + f * dpsi;
                     const T dz = f * (T)a.step;
                     // partial-cell moments: P_j += dz/(j+1) * sum_m psi_i^(j-m) psi_e^m
-                    const T b_1 = psi_e, b_2 = b_1 * psi_e, b_3 = b_2 * psi_e, b_4 = b_3 * psi_e,
-                            b_5 = b_4 * psi_e;
-                    const T h1 = psi_i + b_1;
+                    const T b_2 = psi_e * psi_e, b_3 = b_2 * psi_e, b_4 = b_3 * psi_e, b_5 = b_4 * psi_e;
+                    const T h1 = psi_i + psi_e;
                     const T h2 = psi_i * h1 + b_2;
                     const T h3 = psi_i * h2 + b_3;
                     const T h4 = psi_i * h3 + b_4;
@@ -504,49 +535,44 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                                  (T)5 * c4 * Q1 + c5 * dhT;
                     // index at emission: n_e = 1 + delta_e
                     const T ne2 = (T)1 + psi_e;
-                    double ne;
-                    T ratio;   // n_e / n_obs
+                    double ne, inv_w;
+                    T ratio, q, inv_ne;
                     if (PREC == 0) {
                         ne = sqrt(1.0 + (double)psi_e);
                         ratio = (T)(ne / a.n_obs);
+                        inv_w = 1.0 / pw;
+                        q = (T)1 / (ne2 * (T)(pw * pw));
+                        inv_ne = (T)(1.0 / ne);
                     } else {
                         const float de = (float)psi_e * __builtin_amdgcn_rcpf(1.0f + __builtin_sqrtf(1.0f + (float)psi_e));
                         ne = 1.0 + (double)de;
                         ratio = 1.0f + (de - d_obs) * inv_1pdobs;
-                    }
-                    double inv_w;
-                    T q;
-                    if (PREC == 0) {
-                        inv_w = 1.0 / pw;
-                        q = (T)1 / (ne2 * (T)(pw * pw));
-                    } else {
-                        // reciprocal with two Newton steps (FP64-accurate)
-                        double r0 = __builtin_amdgcn_rcp(pw);
-                        r0 = fma(r0, fma(-pw, r0, 1.0), r0);
-                        inv_w = fma(r0, fma(-pw, r0, 1.0), r0);
+                        // reciprocal of w with two Newton steps (FP64-accurate)
+                        double r_w = __builtin_amdgcn_rcp(pw);
+                        r_w = fma(r_w, fma(-pw, r_w, 1.0), r_w);
+                        inv_w = fma(r_w, fma(-pw, r_w, 1.0), r_w);
                         q = (T)__builtin_amdgcn_rcpf((float)ne2 * (float)(pw * pw));
+                        inv_ne = (T)__builtin_amdgcn_rcpf(1.0f + de);
                     }
                     // horizontal advance: S = dh + sum_{k>=1} a_k q^k D_k
                     const T s_corr = q * (a1 * D1 + q * (a2 * D2 + q * (a3 * D3 + q * a4 * D4)));
                     const double S = dh + (double)s_corr;
-                    // c * time * w * n_e = n_e^2 dh + D1 + sum_{k>=1} a_k q^k (n_e^2 D_k + D_{k+1})
+                    // c * time * w = n_e dh + (1/n_e) [D1 + sum_{k>=1} a_k q^k (n_e^2 D_k + D_{k+1})]
                     const T t_corr = D1 + q * (a1 * (ne2 * D1 + D2) +
                                            q * (a2 * (ne2 * D2 + D3) +
                                            q * (a3 * (ne2 * D3 + D4) + q * a4 * (ne2 * D4 + D5))));
-                    double ctw;
-                    if (PREC == 0) ctw = ne * dh + (double)t_corr / ne;
-                    else ctw = ne * dh + (double)((float)t_corr * __builtin_amdgcn_rcpf((float)ne));
+                    const double ctw = fma(ne, dh, (double)(t_corr * inv_ne));
                     const double T_travel = ctw * inv_w * inv_c;
-                    xg = xe + pu * inv_w * S;
-                    yg = ye + pv * inv_w * S;
-                    tarr = te + T_travel - t_ref;
+                    const double adv = inv_w * S;
+                    xg = fma(pu, adv, xe);
+                    yg = fma(pv, adv, ye);
+                    tarr = (te - t_ref) + T_travel;
                     uo = (float)((T)pu * ratio);
                     vo = (float)((T)pv * ratio);
                     t_f = (float)tarr;
                     he_f = (float)he;
                 }
             }
-
             {
                 const int d0 = __popcll(__ballot(drop_why == CKV_DROP_BELOW_OBS));
                 const int d1 = __popcll(__ballot(drop_why == CKV_DROP_ABOVE_TOP));
@@ -618,17 +644,15 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                     if (below < room) slot = blk * kStageBlock + blk_fill + below;
                     else if (nbk >= 0) slot = nbk * kStageBlock + (below - room);
                     if (slot >= 0) {
-                        StageEntry* e = a.stage + slot;
+                        StageEntry* se = a.stage + slot;
                         const double* tp = a.tel + 4 * kmin;
-                        const float4 r0 = make_float4((float)(xg - tp[0]), (float)(yg - tp[1]), uo, vo);
-                        const float4 r1 = make_float4(t_f, he_f, photons, lam);
-                        float4* ef = reinterpret_cast<float4*>(e);
-                        ef[0] = r0;
-                        ef[1] = r1;
-                        uint4* eu = reinterpret_cast<uint4*>(e);
+                        float4* ef = reinterpret_cast<float4*>(se);
+                        ef[0] = make_float4((float)(xg - tp[0]), (float)(yg - tp[1]), uo, vo);
+                        ef[1] = make_float4(t_f, he_f, photons, lam);
+                        uint4* eu = reinterpret_cast<uint4*>(se);
                         eu[2] = make_uint4((uint32_t)t, (uint32_t)kmin, (uint32_t)(rank0 + below), (uint32_t)s);
-                        int64_t* el = reinterpret_cast<int64_t*>(e);
-                        el[6] = g0 + si;
+                        int64_t* el = reinterpret_cast<int64_t*>(se);
+                        el[6] = g0 + sidx;
                         el[7] = k;
                     }
                 }
@@ -649,9 +673,9 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
         wave_lds_sync();
         if (t < a.max_tiles) {
             int32_t* row = a.counts + t * (int64_t)a.n_tel;
-            for (int k = lane; k < a.n_tel; k += kWave) {
-                row[k] = tcount[k];
-                tcount[k] = 0;
+            for (int kk = lane; kk < a.n_tel; kk += kWave) {
+                row[kk] = tcount[kk];
+                tcount[kk] = 0;
             }
         }
         wave_lds_sync();
@@ -738,6 +762,8 @@ __device__ __forceinline__ int find_shower(const int64_t* before, int n_showers,
     return lo;
 }
 
+// Block sums are stored telescope-major: block_sums[k * max_row_blocks + b].
+
 // A: per row block, per telescope: sum of crossings over the block's tiles
 __global__ void __launch_bounds__(256) rowblock_sum_kernel(Args a)
 {
@@ -748,27 +774,37 @@ __global__ void __launch_bounds__(256) rowblock_sum_kernel(Args a)
         const int64_t t1 = min(t0 + kRowBlock, a.tiles_before[s + 1]);
         for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x) {
             int32_t sum = 0;
+#pragma unroll 8
             for (int64_t t = t0; t < t1; ++t) sum += a.counts[t * a.n_tel + k];
-            a.block_sums[b * a.n_tel + k] = sum;
+            a.block_sums[k * a.max_row_blocks + b] = sum;
         }
     }
 }
 
-// B: per (shower, telescope): exclusive scan over the shower's row blocks
+// B: per (shower, telescope), one wave: exclusive scan over the shower's row
+// blocks, 64 blocks per step
 __global__ void __launch_bounds__(256) rowblock_scan_kernel(Args a)
 {
+    const int lane = lane_id();
     const int64_t nst = (int64_t)a.n_showers * a.n_tel;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nst;
-         q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    const bool have_tiles = a.ctrl[kNumTiles] > 0;
+    for (int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; q < nst;
+         q += waves) {
         const int s = (int)(q / a.n_tel), k = (int)(q % a.n_tel);
-        int32_t run = 0;
-        if (a.ctrl[kNumTiles] > 0)
-            for (int64_t b = a.blocks_before[s]; b < a.blocks_before[s + 1]; ++b) {
-                const int32_t x = a.block_sums[b * a.n_tel + k];
-                a.block_sums[b * a.n_tel + k] = run;
-                run += x;
+        int64_t run = 0;
+        if (have_tiles) {
+            int32_t* col = a.block_sums + (int64_t)k * a.max_row_blocks;
+            const int64_t b_end = a.blocks_before[s + 1];
+            for (int64_t b0 = a.blocks_before[s]; b0 < b_end; b0 += kWave) {
+                const int64_t b = b0 + lane;
+                const int64_t x = b < b_end ? col[b] : 0;
+                const int64_t incl = wave_incl_scan(x);
+                if (b < b_end) col[b] = (int32_t)(run + incl - x);
+                run += __shfl(incl, kWave - 1);
             }
-        a.shower_tel[q] = run;
+        }
+        if (lane == 0) a.shower_tel[q] = (int32_t)run;
     }
 }
 
@@ -781,7 +817,7 @@ __global__ void __launch_bounds__(256) tile_prefix_kernel(Args a)
         const int64_t t0 = a.tiles_before[s] + (b - a.blocks_before[s]) * kRowBlock;
         const int64_t t1 = min(t0 + kRowBlock, a.tiles_before[s + 1]);
         for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x) {
-            int32_t run = a.block_sums[b * a.n_tel + k];
+            int32_t run = a.block_sums[k * a.max_row_blocks + b];
             for (int64_t t = t0; t < t1; ++t) {
                 const int32_t x = a.counts[t * a.n_tel + k];
                 a.counts[t * a.n_tel + k] = run;
@@ -918,6 +954,7 @@ Args make_args(const RunPlan& p)
     a.stage = p.stage;
     a.stage_blocks = p.stage_slots / kStageBlock;
     a.max_tiles = p.max_tiles;
+    a.max_row_blocks = p.max_row_blocks;
     a.records = p.out.records;
     a.ids = p.out.ids;
     a.capacity = p.out.capacity;
@@ -941,13 +978,12 @@ int check_launch(const char* what)
 int emit_config(int precision, int n_tel, const ckv_atmo* atmo, int tile_segs, int* waves,
                 size_t* lds_bytes)
 {
-    const size_t tab = precision == 0 ? Layout<0>::table_bytes((int)atmo->n_nodes)
-                                      : Layout<1>::table_bytes((int)atmo->n_nodes);
+    const size_t tab = (table_bytes(precision, (int)atmo->n_nodes) + 15) & ~(size_t)15;
     const size_t cap = 160 * 1024;
     const size_t per = wave_bytes(precision, tile_segs, n_tel);
     const int max_waves = precision == 0 ? kMaxEmitWaves / 2 : kMaxEmitWaves;
     for (int wv = max_waves; wv >= 1; wv /= 2) {
-        size_t tot = ((tab + 15) & ~(size_t)15) + (size_t)wv * per;
+        const size_t tot = tab + (size_t)wv * per;
         if (tot <= cap) {
             *waves = wv;
             *lds_bytes = tot;
@@ -958,6 +994,36 @@ int emit_config(int precision, int n_tel, const ckv_atmo* atmo, int tile_segs, i
     return CKV_ERR_TABLE;
 }
 
+namespace {
+
+template <int PREC, int TS>
+int launch_emit(const Args& a, int grid, int waves, size_t lds, hipStream_t st)
+{
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)emit_kernel<PREC, TS>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    emit_kernel<PREC, TS><<<grid, waves * kWave, lds, st>>>(a);
+    return check_launch("emit");
+}
+
+template <int PREC>
+int launch_emit_ts(const Args& a, int ts, int grid, int waves, size_t lds, hipStream_t st)
+{
+    switch (ts) {
+        case 8: return launch_emit<PREC, 8>(a, grid, waves, lds, st);
+        case 16: return launch_emit<PREC, 16>(a, grid, waves, lds, st);
+        case 32: return launch_emit<PREC, 32>(a, grid, waves, lds, st);
+        case 64: return launch_emit<PREC, 64>(a, grid, waves, lds, st);
+    }
+    set_error("tile_segments must be 8, 16, 32 or 64");
+    return CKV_ERR_ARG;
+}
+
+}  // namespace
+
 int launch_run(RunPlan& p)
 {
     Args a = make_args(p);
@@ -967,35 +1033,21 @@ int launch_run(RunPlan& p)
     int waves = 0;
     size_t lds = 0;
     if (int rc = emit_config(p.params.precision, a.n_tel, p.atmo, p.tile_segs, &waves, &lds)) return rc;
-    if (waves > p.emit_waves) waves = p.emit_waves;
-    lds = ((p.params.precision == 0 ? Layout<0>::table_bytes(a.n_nodes)
-                                    : Layout<1>::table_bytes(a.n_nodes)) + 15 & ~(size_t)15) +
-          (size_t)waves * wave_bytes(p.params.precision, p.tile_segs, a.n_tel);
-    if (p.params.precision == 0) {
-        static bool attr0 = false;
-        if (!attr0) {
-            (void)hipFuncSetAttribute((const void*)emit_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr0 = true;
-        }
-        emit_kernel<0><<<p.emit_grid, waves * kWave, lds, st>>>(a);
-    } else {
-        static bool attr1 = false;
-        if (!attr1) {
-            (void)hipFuncSetAttribute((const void*)emit_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr1 = true;
-        }
-        emit_kernel<1><<<p.emit_grid, waves * kWave, lds, st>>>(a);
-    }
-    if (int rc = check_launch("emit")) return rc;
+    if (p.params.event_begin) (void)hipEventRecord((hipEvent_t)p.params.event_begin, st);
+    int rc = p.params.precision == 0
+                 ? launch_emit_ts<0>(a, p.tile_segs, p.emit_grid, waves, lds, st)
+                 : launch_emit_ts<1>(a, p.tile_segs, p.emit_grid, waves, lds, st);
+    if (rc) return rc;
+    if (p.params.event_end) (void)hipEventRecord((hipEvent_t)p.params.event_end, st);
     const int fin_grid = 1024;
     rowblock_sum_kernel<<<fin_grid, 256, 0, st>>>(a);
-    if (int rc = check_launch("rowblock_sum")) return rc;
+    if (int rc2 = check_launch("rowblock_sum")) return rc2;
     rowblock_scan_kernel<<<fin_grid, 256, 0, st>>>(a);
-    if (int rc = check_launch("rowblock_scan")) return rc;
+    if (int rc2 = check_launch("rowblock_scan")) return rc2;
     tile_prefix_kernel<<<fin_grid, 256, 0, st>>>(a);
-    if (int rc = check_launch("tile_prefix")) return rc;
+    if (int rc2 = check_launch("tile_prefix")) return rc2;
     csr_kernel<<<1, 1024, 0, st>>>(a);
-    if (int rc = check_launch("csr")) return rc;
+    if (int rc2 = check_launch("csr")) return rc2;
     scatter_kernel<<<4096, 256, 0, st>>>(a);
     return check_launch("scatter");
 }

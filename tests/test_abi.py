@@ -41,7 +41,7 @@ def test_version(L):
 
 def test_struct_sizes_match_header_layout():
     assert C.sizeof(ckv._Segments) == 11 * 8
-    assert C.sizeof(ckv._Params) == 4 * 8 + 8 + 4 * 4
+    assert C.sizeof(ckv._Params) == 4 * 8 + 8 + 4 * 4 + 2 * 8
     assert C.sizeof(ckv._Result) == 5 * 8 + 8 * 8 + 2 * 4
     assert C.sizeof(ckv._Output) == 5 * 8
 
