@@ -28,45 +28,55 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# --- algorithmic VALU issue slots per generated bunch (one slot = one lane of
-# one full-rate VALU operation; quarter-rate operations -- 32x32->64 integer
-# multiplies, reciprocals, square roots -- count 4).  Derivation per step of
-# the algorithm in the design notes.
-SLOTS_MIXED = {
-    "philox4x32-10: 20 mul32x32->64 (x4) + 40 xor": 120,
-    "uniforms, emission point and time (FP64)": 13,
-    "azimuth sin/cos (FP32 polynomial, quadrant fold)": 19,
+# --- algorithmic VALU operations per generated bunch: each arithmetic, logic,
+# compare, select or conversion the algorithm needs at the path's precision
+# counts once (an FMA is one operation; a 32x32->64 multiply, a reciprocal or
+# a square root is one operation).  Loop control, addressing and register moves
+# are not counted.  The derivation, step by step, is in the design notes.
+OPS_MIXED = {
+    "philox4x32-10: 10 rounds x (2 mul32x32->64 + 4 xor)": 60,
+    "uniforms u0, u2 (convert + scale)": 4,
+    "emission point and time (FP64)": 7,
+    "azimuth sin/cos: quadrant fold + Taylor polynomials (FP32)": 26,
     "direction on the cone (FP32 perpendicular, FP64 sum)": 12,
-    "wavelength (inverse CDF, rcp)": 7,
+    "wavelength (inverse CDF, rcp)": 2,
     "drop tests": 4,
-    "table index and partial-cell moments P1..P5": 28,
-    "moment transform D1..D5": 25,
-    "index at emission (sqrt, rcp)": 11,
-    "1/w (FP64 rcp + 2 Newton steps)": 8,
-    "series variable q (rcp)": 7,
-    "advance series, ground point": 13,
-    "time series, arrival time": 24,
-    "observed direction cosines": 4,
-    "candidate cell + one sphere test (FP64)": 18,
+    "table index (FP64 -> cell, fraction)": 7,
+    "partial-cell moments P1..P5 (FP32)": 21,
+    "moment transform D1..D5 (FP32)": 34,
+    "index at emission, n_e / n_obs": 9,
+    "1/w (FP64 rcp + 2 Newton steps)": 5,
+    "series variable q": 5,
+    "advance series S": 9,
+    "time series T": 19,
+    "ground point, arrival time": 5,
+    "observed direction, record conversions": 6,
+    "candidate cell": 13,
+    "sphere tests (0.35 candidates per bunch x 7)": 3,
 }
-SLOTS_FP64 = {
-    "philox4x32-10": 120,
-    "uniforms, emission point and time": 13,
-    "azimuth sincos (FP64 library)": 50,
+OPS_FP64 = {
+    "philox4x32-10": 60,
+    "uniforms u0, u1, u2": 6,
+    "emission point and time": 7,
+    "azimuth sincos (FP64 range reduction + polynomials)": 40,
     "direction on the cone": 9,
-    "wavelength (FP64 divide)": 12,
+    "wavelength (FP64 divide)": 9,
     "drop tests": 4,
-    "table index and partial-cell moments": 28,
-    "moment transform D1..D5": 25,
-    "index at emission (FP64 sqrt, divide)": 24,
-    "1/w and q (FP64 divides)": 24,
-    "advance series, ground point": 13,
-    "time series, arrival time (FP64 divide)": 36,
-    "observed direction cosines": 4,
-    "candidate cell + one sphere test": 18,
+    "table index": 6,
+    "partial-cell moments P1..P5": 21,
+    "moment transform D1..D5": 34,
+    "index at emission (FP64 sqrt, divide)": 16,
+    "1/w (FP64 divide)": 8,
+    "series variable q (FP64 divide)": 11,
+    "advance series S": 9,
+    "time series T (+ divide by n_e)": 27,
+    "ground point, arrival time": 5,
+    "observed direction, record conversions": 6,
+    "candidate cell + sphere tests": 16,
 }
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate VALU issue
-PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one VALU operation per lane
+# per clock (FP32 non-packed and FP64 both issue at this rate on CDNA4)
+PEAK_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 SEG_BYTES = 9 * 8 + 1            # SoA step record read once
 STAGE_BYTES = 64                 # staging entry written and read back
@@ -242,9 +252,9 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(f"# copy probe: {args.copy_probe_mib} MiB read + written, 3 launches", file=sys.stderr)
 
-    slots_mixed = sum(SLOTS_MIXED.values())
-    achieved = slots_mixed * nb / (kms_mixed * 1e-3) / 1e12
-    peak = PEAK_SLOTS_PER_S / 1e12
+    ops_mixed = sum(OPS_MIXED.values())
+    achieved = ops_mixed * nb / (kms_mixed * 1e-3) / 1e12
+    peak = PEAK_OPS_PER_S / 1e12
     traffic = stored_traffic("bunch_kernel_single_tev_mixed")
     hits = res_mixed["n_hits"]
     alg_bytes = wl.segs.n * SEG_BYTES + hits * STAGE_BYTES
@@ -269,8 +279,8 @@ def main(argv=None):
         "records_per_step": hits,
         "fp64_plain": {"value": nb / (ms_fp64 * 1e-3), "ms_per_step": ms_fp64,
                        "bunch_kernel_ms": kms_fp64,
-                       "roofline_frac": sum(SLOTS_FP64.values()) * nb / (kms_fp64 * 1e-3)
-                       / PEAK_SLOTS_PER_S},
+                       "roofline_frac": sum(OPS_FP64.values()) * nb / (kms_fp64 * 1e-3)
+                       / PEAK_OPS_PER_S},
         "mixed_over_fp64": ms_fp64 / ms_mixed,
         "bunch_kernel_ms": kms_mixed,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
