@@ -199,6 +199,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune-cache", action="store_true",
+                    help="re-run the launch-shape autotuner instead of using its cache")
     ap.add_argument("--segments", type=int, default=2_000_000,
                     help="steps in the shower (default: the 2e6-step TeV shower)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -229,11 +231,22 @@ def main(argv=None):
 
     print(f"# workload {wl.name}: {wl.segs.n} steps, {wl.tels.n} telescopes", file=sys.stderr,
           flush=True)
-    ms_mixed, kms_mixed, res_mixed = time_path(hip, ckv, dsegs, atmo, tels, mk(ckv.CKV_MIXED),
+    # launch shapes from the autotuner (untimed; cached per GPU arch and workload)
+    from paper_2006_14927_amd import autotune
+    tuned = {}
+    for prec in (ckv.CKV_MIXED, ckv.CKV_FP64):
+        tuned[prec] = autotune.tune(dsegs, atmo, tels, mk(prec), capacity,
+                                    use_cache=not args.no_tune_cache)
+        print(f"# autotune precision {prec}: tile_segments={tuned[prec]['tile_segments']} "
+              f"waves_per_group={tuned[prec]['waves_per_group']} ({tuned[prec]['ms']:.3f} ms)",
+              file=sys.stderr, flush=True)
+    ms_mixed, kms_mixed, res_mixed = time_path(hip, ckv, dsegs, atmo, tels,
+                                               autotune.apply(mk(ckv.CKV_MIXED), tuned[ckv.CKV_MIXED]),
                                                capacity, args.steps, args.warmup, stream)
     print(f"# mixed: {ms_mixed:.3f} ms/step, bunch kernel {kms_mixed:.3f} ms", file=sys.stderr,
           flush=True)
-    ms_fp64, kms_fp64, res_fp64 = time_path(hip, ckv, dsegs, atmo, tels, mk(ckv.CKV_FP64),
+    ms_fp64, kms_fp64, res_fp64 = time_path(hip, ckv, dsegs, atmo, tels,
+                                            autotune.apply(mk(ckv.CKV_FP64), tuned[ckv.CKV_FP64]),
                                             capacity, args.steps, args.warmup, stream)
     print(f"# fp64: {ms_fp64:.3f} ms/step, bunch kernel {kms_fp64:.3f} ms", file=sys.stderr,
           flush=True)
@@ -274,7 +287,9 @@ def main(argv=None):
         "config": {"workload": wl.name, "steps_in_shower": wl.segs.n, "telescopes": wl.tels.n,
                    "zenith_deg": 20.0, "atmosphere": "5-layer exponential, 50 m grid to 120 km",
                    "bunch_size": wl.bunch_size, "band_nm": [wl.lambda_min, wl.lambda_max],
-                   "precision": "mixed"},
+                   "precision": "mixed",
+                   "launch": {"tile_segments": tuned[ckv.CKV_MIXED]["tile_segments"],
+                              "waves_per_group": tuned[ckv.CKV_MIXED]["waves_per_group"]}},
         "bunches_per_step": nb,
         "records_per_step": hits,
         "fp64_plain": {"value": nb / (ms_fp64 * 1e-3), "ms_per_step": ms_fp64,

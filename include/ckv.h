@@ -151,8 +151,10 @@ typedef struct {
     uint64_t seed;         /* Philox key */
     int32_t precision;     /* CKV_FP64 or CKV_MIXED */
     int32_t tile_segments; /* steps per emit tile: 8, 16, 32 or 64; 0 = default (32) */
-    int32_t grid;          /* emit workgroups, 0 = one per compute unit */
-    int32_t reserved;
+    int32_t grid;          /* bunch-kernel workgroups, 0 = one per compute unit */
+    int32_t waves_per_group; /* bunch-kernel waves per workgroup: 1, 2, 4, 8 or 16 (FP64:
+                              <= 8); 0 = the most that fit the LDS; a value that does not
+                              fit is lowered to one that does */
     void* event_begin;     /* optional hipEvent_t recorded on the stream just before */
     void* event_end;       /* and just after the bunch kernel (profiling); NULL = none */
 } ckv_params;

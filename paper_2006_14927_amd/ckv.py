@@ -45,7 +45,8 @@ class _Params(C.Structure):
     _fields_ = [("bunch_size", C.c_double), ("lambda_min_nm", C.c_double),
                 ("lambda_max_nm", C.c_double), ("w_min", C.c_double), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("tile_segments", C.c_int32), ("grid", C.c_int32),
-                ("reserved", C.c_int32), ("event_begin", C.c_void_p), ("event_end", C.c_void_p)]
+                ("waves_per_group", C.c_int32), ("event_begin", C.c_void_p),
+                ("event_end", C.c_void_p)]
 
 
 class _Result(C.Structure):
@@ -194,10 +195,11 @@ class DeviceSegments:
 
 
 def make_params(*, precision=CKV_MIXED, bunch_size=5.0, lambda_min=300.0, lambda_max=600.0,
-                w_min=0.1, seed=0x14927, tile_segments=0, grid=0, event_begin=None,
-                event_end=None) -> _Params:
+                w_min=0.1, seed=0x14927, tile_segments=0, grid=0, waves_per_group=0,
+                event_begin=None, event_end=None) -> _Params:
     return _Params(bunch_size, lambda_min, lambda_max, w_min, int(seed) & (2**64 - 1),
-                   int(precision), int(tile_segments), int(grid), 0, event_begin, event_end)
+                   int(precision), int(tile_segments), int(grid), int(waves_per_group),
+                   event_begin, event_end)
 
 
 def workspace_size(n_segments, n_showers, n_tel, capacity, params: _Params) -> int:
@@ -268,3 +270,25 @@ def run(segs, atmo: Atmosphere, tels: TelescopeArray, *, capacity: int, want_ids
     """One-shot convenience: segments (synth.Segments or DeviceSegments) -> records."""
     d = segs if isinstance(segs, DeviceSegments) else DeviceSegments(segs)
     return Runner(d, atmo, tels, make_params(**param_kw), capacity, want_ids).run(stream)
+
+
+class GraphRunner:
+    """A Runner's ckv_run captured once into a HIP graph and replayed.
+
+    ckv_run enqueues kernels only (no allocation, copy or memset), so the whole
+    bunch path is one graph; one eager run first sets the kernels' launch
+    attributes outside the capture."""
+
+    def __init__(self, runner: Runner):
+        import torch
+        self.runner = runner
+        runner.run()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        self.stream = torch.cuda.Stream()
+        with torch.cuda.graph(self.graph, stream=self.stream):
+            self.out = runner.run()
+
+    def replay(self) -> RunOutput:
+        self.graph.replay()
+        return self.out

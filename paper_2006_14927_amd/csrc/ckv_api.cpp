@@ -56,6 +56,10 @@ int check_params(const ckv_params* p)
         set_error("tile_segments must be 0 (default), 8, 16, 32 or 64"); return CKV_ERR_ARG;
     }
     if (p->grid < 0) { set_error("grid must be >= 0"); return CKV_ERR_ARG; }
+    if (p->waves_per_group != 0 && p->waves_per_group != 1 && p->waves_per_group != 2 &&
+        p->waves_per_group != 4 && p->waves_per_group != 8 && p->waves_per_group != 16) {
+        set_error("waves_per_group must be 0, 1, 2, 4, 8 or 16"); return CKV_ERR_ARG;
+    }
     return CKV_OK;
 }
 
@@ -297,7 +301,7 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
         hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     }
     plan.emit_grid = params->grid > 0 ? params->grid : std::min(n_cu, kMaxEmitGrid);
-    plan.emit_waves = kMaxEmitWaves;
+    plan.emit_waves = params->waves_per_group > 0 ? params->waves_per_group : kMaxEmitWaves;
     return launch_run(plan);
 }
 

@@ -1033,6 +1033,11 @@ int launch_run(RunPlan& p)
     int waves = 0;
     size_t lds = 0;
     if (int rc = emit_config(p.params.precision, a.n_tel, p.atmo, p.tile_segs, &waves, &lds)) return rc;
+    if (p.emit_waves < waves) {
+        waves = p.emit_waves;
+        lds = ((table_bytes(p.params.precision, a.n_nodes) + 15) & ~(size_t)15) +
+              (size_t)waves * wave_bytes(p.params.precision, p.tile_segs, a.n_tel);
+    }
     if (p.params.event_begin) (void)hipEventRecord((hipEvent_t)p.params.event_begin, st);
     int rc = p.params.precision == 0
                  ? launch_emit_ts<0>(a, p.tile_segs, p.emit_grid, waves, lds, st)

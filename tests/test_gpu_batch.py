@@ -1,0 +1,91 @@
+"""Batching: many showers of uneven size in one persistent launch, the whole run
+captured into a HIP graph, and the launch-shape autotuner."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_14927_amd import autotune, ckv, synth
+
+from gpu_helpers import compare_records, gpu_run, handles, params, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def batched():
+    # 256 showers, 30 GeV..30 TeV, step counts scaled by 5e-4 (5 .. 2000 steps each)
+    wl = synth.batched_showers(256, seg_scale=5e-4)
+    cfg = oracle.Config.from_workload(wl)
+    return wl, cfg, oracle.run(cfg, wl.segs, nthreads=8)
+
+
+@pytest.mark.parametrize("precision", [ckv.CKV_FP64, ckv.CKV_MIXED])
+def test_batched_showers_parity(batched, precision):
+    wl, cfg, r = batched
+    sizes = np.diff(wl.segs.seg_offsets)
+    assert wl.segs.n_showers == 256 and sizes.min() < 32 < sizes.max()
+    g = gpu_run(wl, precision)
+    res = g["result"]
+    assert res["error"] == 0 and res["overflow"] == 0
+    assert res["n_bunches"] == r.n_bunches and res["drops"] == r.drops
+    if precision == ckv.CKV_FP64:
+        np.testing.assert_array_equal(g["offsets"], r.offsets)
+    rep = compare_records(wl, cfg, r, g, precision)
+    say(f"[gpu] batched prec={precision}: tiles={res['n_tiles']} {rep}")
+
+
+def test_graph_replays_match_eager(batched):
+    import torch
+    wl, cfg, r = batched
+    atmo, tels = handles(wl)
+    d = ckv.DeviceSegments(wl.segs)
+    p = params(wl, ckv.CKV_MIXED)
+    cap = len(r.seg) + 4096
+    eager = ckv.Runner(d, atmo, tels, p, cap)
+    out = eager.run()
+    torch.cuda.synchronize()
+    n = out.result()["n_records"]
+    ref = (out.tel_offsets.cpu().clone(), out.records[:n].cpu().clone(), out.ids[:n].cpu().clone())
+    gr = ckv.GraphRunner(ckv.Runner(d, atmo, tels, p, cap))
+    other = ckv.Runner(ckv.DeviceSegments(synth.vertical_gamma(3000).segs), atmo, tels, p, 100000)
+    for rep in range(4):
+        o = gr.runner
+        o.records.fill_(float("nan"))
+        o.tel_offsets.fill_(-1)
+        o.result_raw.zero_()
+        other.run()                       # eager work on the same device between replays
+        torch.cuda.synchronize()
+        go = gr.replay()
+        torch.cuda.synchronize()
+        res = go.result()
+        assert res["n_records"] == n and res["overflow"] == 0
+        assert torch.equal(go.tel_offsets.cpu(), ref[0])
+        assert torch.equal(go.records[:n].cpu().view(torch.int32), ref[1].view(torch.int32))
+        assert torch.equal(go.ids[:n].cpu(), ref[2])
+        say(f"[gpu] graph replay {rep} ok")
+
+
+def test_autotune_candidates_identical_and_cached(tmp_path, monkeypatch):
+    import torch
+    monkeypatch.setattr(autotune, "CACHE_PATH", str(tmp_path / "tune.json"))
+    wl = synth.vertical_gamma()
+    atmo, tels = handles(wl)
+    d = ckv.DeviceSegments(wl.segs)
+    p = params(wl, ckv.CKV_MIXED)
+    cands = [(16, 16), (32, 8), (64, 4), (32, 16)]
+    entry = autotune.tune(d, atmo, tels, p, 200000, candidates=cands, reps=2)
+    assert (entry["tile_segments"], entry["waves_per_group"]) in cands
+    assert len(entry["table"]) == len(cands)
+    again = autotune.tune(d, atmo, tels, p, 200000, candidates=cands, reps=2)
+    assert again == entry                                   # served from the cache
+    outs = []
+    for ts, wv in cands:
+        q = autotune.apply(p, {"tile_segments": ts, "waves_per_group": wv})
+        o = ckv.Runner(d, atmo, tels, q, 200000).run()
+        torch.cuda.synchronize()
+        n = o.result()["n_records"]
+        outs.append((o.tel_offsets.cpu().numpy(), o.records[:n].cpu().numpy().view(np.uint32)))
+    for off, rec in outs[1:]:
+        np.testing.assert_array_equal(off, outs[0][0])
+        np.testing.assert_array_equal(rec, outs[0][1])
