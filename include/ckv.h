@@ -211,6 +211,69 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
 int ckv_count(const ckv_segments* segs, const ckv_params* params, const ckv_atmo* atmo,
               int64_t* n_b, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Differentiation.  A smooth per-telescope response and its gradient with
+ * respect to the atmosphere, for fitting atmospheric profiles to telescope
+ * data (no counterpart in the paper; built on the same bunch path).
+ *
+ * Soft response of shower s at telescope k (sphere centre X, radius R):
+ *   S_sk = sum over bunches of photons * Phi(z),
+ *   A_sk = sum over bunches of photons * Phi(z) * t,
+ *   z = (R^2 - rho^2) / (2 R sigma),
+ * rho the distance of closest approach between the observed ray and the
+ * sphere centre, Phi the standard normal CDF; Phi(z) = 0 for z < -40 (exactly
+ * zero in FP64).  Bunch counts are frozen: n_b_frozen[i] (from ckv_count at a
+ * reference atmosphere) fixes the sub-steps, while yield, angle and photons
+ * per bunch follow the current atmosphere; a step below threshold at the
+ * current atmosphere emits nothing.  FP64 throughout.
+ * ------------------------------------------------------------------------- */
+
+/* log eta(h) = log eta0 - sum_l overlap([0, h], layer l) / H_l + Lambda(h):
+   H_l constant inside layer l = [bounds[l], bounds[l+1]) (the last layer extends
+   upward), Lambda the linear interpolant of n_knots values at
+   h_j = j * knot_top / (n_knots - 1), constant above knot_top.  The profile is
+   sampled at obs_level + i*step up to top.  theta = (knot values, H_l [m]). */
+typedef struct {
+    double eta0;
+    int32_t n_layers;
+    int32_t n_knots;
+    const double* layer_bounds_m;   /* host, n_layers + 1, increasing */
+    double knot_top_m;
+    double obs_level_m;
+    double step_m;
+    double top_m;
+} ckv_atmo_param_spec;
+
+/* Atmosphere handle of the parameterised profile at theta (host memory). */
+int ckv_atmo_from_params(const ckv_atmo_param_spec* spec, const double* theta, ckv_atmo** out);
+/* Chain rule from table gradients to parameters: given dL/dpsi_i (n_nodes) and
+   dL/dP_j(h_i) (5 x n_nodes, as from ckv_soft_backward, copied to host) of the
+   handle built from (spec, theta), writes dL/dtheta (n_knots + n_layers).
+   Host only, synchronous. */
+int ckv_atmo_params_backward(const ckv_atmo_param_spec* spec, const double* theta,
+                             const ckv_atmo* atmo, const double* g_psi, const double* g_P,
+                             double* g_theta);
+/* Telescope handle that also carries the candidate grid of the soft response
+   for edge width sigma_m > 0 (see ckv_array_create for the other arguments). */
+int ckv_array_create_soft(const double* x_m, const double* y_m, const double* r_m, int32_t n_tel,
+                          double sigma_m, ckv_array** out);
+/* S and A (device, n_showers x n_tel FP64, overwritten).  Same inputs as
+   ckv_run plus n_b_frozen (device int64, one per step); the workspace is the
+   one ckv_workspace_size(n, n_showers, n_tel, 0, params) gives.  arr must come
+   from ckv_array_create_soft.  params->precision is ignored (FP64).
+   Asynchronous on `stream`. */
+int ckv_soft_forward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
+                     const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
+                     double* S, double* A, void* workspace, size_t ws_bytes, void* stream);
+/* Reverse pass: given dL/dS and dL/dA (device, n_showers x n_tel), recomputes
+   every bunch from its random numbers and writes dL/dpsi_i (device, n_nodes)
+   and dL/dP_j(h_i) (device, 5 x n_nodes), both overwritten; psi_0 also
+   carries the observation-level index.  Asynchronous on `stream`. */
+int ckv_soft_backward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
+                      const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
+                      const double* dL_dS, const double* dL_dA, double* g_psi, double* g_P,
+                      void* workspace, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

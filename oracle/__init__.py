@@ -89,6 +89,8 @@ def _declare(L):
     L.or_sphere_disc.argtypes = [D] * 7
     L.or_frank_tamm_k.restype = D
     L.or_frank_tamm_k.argtypes = [D, D]
+    L.or_soft.argtypes = [C.POINTER(_Config), C.POINTER(_Segments), P, D, C.c_int32, C.c_int, P, P]
+    L.or_eta_param_many.argtypes = [D, C.c_int32, P, C.c_int32, D, P, I64, P, P]
 
 
 def _p(a: np.ndarray):
@@ -313,3 +315,59 @@ def sphere_disc(x_g, y_g, u_o, v_o, X, Y, R) -> float:
 
 def frank_tamm_k(lambda_min=300.0, lambda_max=600.0) -> float:
     return lib().or_frank_tamm_k(lambda_min, lambda_max)
+
+
+# ---------------------------------------------------------------------------
+# differentiation pattern: parameterised atmosphere and soft telescope response
+# ---------------------------------------------------------------------------
+
+@dataclass
+class AtmoParamSpec:
+    """log eta(h) = log eta0 - int_0^h dh'/H(h') + Lambda(h).
+
+    H is constant inside each layer [bounds[l], bounds[l+1]) (the last layer
+    extends upward); Lambda interpolates knot values linearly at
+    h_j = j * knot_top / (n_knots - 1) and is constant above knot_top."""
+    eta0: float
+    layer_bounds: np.ndarray     # n_layers + 1, starting at 0
+    n_knots: int
+    knot_top: float
+    obs_level: float
+    step: float
+    top: float
+
+    @property
+    def n_layers(self) -> int:
+        return len(self.layer_bounds) - 1
+
+    def grid(self) -> np.ndarray:
+        n = int(np.floor((self.top - self.obs_level) / self.step)) + 1
+        return self.obs_level + np.arange(n) * self.step
+
+
+def eta_from_params(spec: AtmoParamSpec, theta, h) -> np.ndarray:
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    assert theta.shape[0] == spec.n_knots + spec.n_layers
+    h = np.ascontiguousarray(np.atleast_1d(h), dtype=np.float64)
+    b = np.ascontiguousarray(spec.layer_bounds, dtype=np.float64)
+    out = np.empty_like(h)
+    lib().or_eta_param_many(spec.eta0, spec.n_layers, _p(b), spec.n_knots, spec.knot_top,
+                            _p(theta), h.shape[0], _p(h), _p(out))
+    return out
+
+
+def tables_from_params(spec: AtmoParamSpec, theta) -> Tables:
+    """Tables of the parameterised profile sampled at the grid nodes."""
+    g = spec.grid()
+    return build_tables(g, eta_from_params(spec, theta, g), spec.obs_level, spec.step)
+
+
+def soft(cfg: Config, segs, n_b_frozen, sigma: float, nthreads: int = 1):
+    """(S, A), each (n_showers, n_tel): soft photon counts and photon-weighted times."""
+    sv = SegView(segs)
+    nb = np.ascontiguousarray(n_b_frozen, dtype=np.int64)
+    S = np.zeros(sv.n_showers * cfg.n_tel)
+    A = np.zeros(sv.n_showers * cfg.n_tel)
+    lib().or_soft(C.byref(cfg.c), C.byref(sv.c), _p(nb), float(sigma), sv.n_showers,
+                  int(nthreads), _p(S), _p(A))
+    return S.reshape(sv.n_showers, cfg.n_tel), A.reshape(sv.n_showers, cfg.n_tel)

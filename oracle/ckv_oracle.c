@@ -532,3 +532,103 @@ void or_propagate_many(const or_config* cf, int64_t m, const double* in /* m x 6
         o[5] = pr.w_o; o[6] = pr.n_e; o[7] = pr.psi_e; o[8] = pr.S;
     }
 }
+
+/* ------------------------------------------------------------------------- */
+/* Soft telescope response (differentiation pattern; no counterpart in the    */
+/* paper).  For shower s and telescope k:                                     */
+/*   S_sk = sum over bunches of photons * Phi(z),                             */
+/*   A_sk = sum over bunches of photons * Phi(z) * t,                         */
+/*   z = (R_k^2 - rho^2) / (2 R_k sigma),  rho^2 = dx^2 + dy^2 - b^2,         */
+/* rho the distance of closest approach of the observed ray to the centre and */
+/* Phi the standard normal CDF.  Bunch counts are frozen (n_b_frozen per      */
+/* step): yield, angle and photons per bunch follow the current tables, the   */
+/* sub-step positions do not.  A step whose current sin^2(theta_c) <= 0       */
+/* emits nothing.  Every telescope is visited (brute force).                  */
+/* ------------------------------------------------------------------------- */
+static double or_phi(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
+void or_soft(const or_config* cf, const or_segments* sg, const int64_t* n_b_frozen, double sigma,
+             int32_t n_showers, int nthreads, double* S, double* A)
+{
+    int64_t nsk = (int64_t)n_showers * cf->n_tel;
+    if (nthreads < 1) nthreads = 1;
+    double* part = (double*)calloc((size_t)nthreads * 2 * nsk, sizeof(double));
+#pragma omp parallel for schedule(static, 1) num_threads(nthreads)
+    for (int th = 0; th < nthreads; ++th) {
+        double* pS = part + (size_t)th * 2 * nsk;
+        double* pA = pS + nsk;
+        int64_t lo = sg->n * th / nthreads, hi = sg->n * (th + 1) / nthreads;
+        for (int64_t i = lo; i < hi; ++i) {
+            if (n_b_frozen[i] <= 0) continue;
+            or_setup st;
+            or_segment_setup(cf, sg, i, &st);
+            if (st.status >= 0) continue;          /* no light at the current tables */
+            /* frozen count: photons per bunch and sub-step length use n_b_frozen */
+            double nb = (double)n_b_frozen[i];
+            st.n_b = n_b_frozen[i];
+            st.photons = st.N / nb;
+            st.ds = sg->len[i] / nb;
+            for (int64_t k = 0; k < st.n_b; ++k) {
+                or_bunch bn;
+                or_make_bunch(cf, sg, i, &st, k, &bn);
+                if (bn.status >= 0) continue;
+                for (int32_t t = 0; t < cf->n_tel; ++t) {
+                    double dx = bn.pr.x_g - cf->tx[t], dy = bn.pr.y_g - cf->ty[t];
+                    double b = dx * bn.pr.u_o + dy * bn.pr.v_o;
+                    double rho2 = dx * dx + dy * dy - b * b;
+                    double R = cf->tr[t];
+                    double z = (R * R - rho2) / (2.0 * R * sigma);
+                    double W = or_phi(z);
+                    if (W == 0.0) continue;
+                    int64_t q = (int64_t)sg->bucket[i] * cf->n_tel + t;
+                    pS[q] += bn.photons * W;
+                    pA[q] += bn.photons * W * bn.t;
+                }
+            }
+        }
+    }
+    for (int64_t q = 0; q < nsk; ++q) {
+        double s = 0.0, a = 0.0;
+        for (int th = 0; th < nthreads; ++th) {
+            s += part[(size_t)th * 2 * nsk + q];
+            a += part[(size_t)th * 2 * nsk + nsk + q];
+        }
+        S[q] = s;
+        A[q] = a;
+    }
+    free(part);
+}
+
+/* Parameterised atmosphere: log eta(h) = log eta0 - sum_l overlap([0,h], layer l)/H_l
+   + Lambda(h), with Lambda the linear interpolant of knot values at
+   h_j = j * knot_top / (n_knots - 1), constant above knot_top.  The last
+   layer extends upward.  theta = (knots[n_knots], H[n_layers]). */
+double or_log_eta_param(double eta0, int32_t n_layers, const double* bounds, int32_t n_knots,
+                        double knot_top, const double* theta, double h)
+{
+    const double* knots = theta;
+    const double* H = theta + n_knots;
+    double depth = 0.0;
+    for (int32_t l = 0; l < n_layers; ++l) {
+        double top = (l + 1 < n_layers) ? bounds[l + 1] : INFINITY;
+        double hi = h < top ? h : top;
+        double over = hi - bounds[l];
+        if (over > 0.0) depth += over / H[l];
+    }
+    double hc = h < knot_top ? h : knot_top;
+    double dk = knot_top / (double)(n_knots - 1);
+    double x = hc / dk;
+    int32_t j = (int32_t)floor(x);
+    if (j > n_knots - 2) j = n_knots - 2;
+    if (j < 0) j = 0;
+    double f = x - (double)j;
+    double lam = knots[j] + f * (knots[j + 1] - knots[j]);
+    return log(eta0) - depth + lam;
+}
+
+void or_eta_param_many(double eta0, int32_t n_layers, const double* bounds, int32_t n_knots,
+                       double knot_top, const double* theta, int64_t m, const double* h, double* eta)
+{
+    for (int64_t q = 0; q < m; ++q)
+        eta[q] = exp(or_log_eta_param(eta0, n_layers, bounds, n_knots, knot_top, theta, h[q]));
+}

@@ -24,7 +24,8 @@ RECORD_FIELDS = ("dx", "dy", "u_obs", "v_obs", "t", "h_emit", "photons", "lambda
 
 EXPORTED = ("ckv_last_error", "ckv_version", "ckv_atmo_create", "ckv_atmo_info", "ckv_atmo_tables",
             "ckv_atmo_destroy", "ckv_array_create", "ckv_array_destroy", "ckv_workspace_size",
-            "ckv_run", "ckv_count")
+            "ckv_run", "ckv_count", "ckv_atmo_from_params", "ckv_atmo_params_backward",
+            "ckv_array_create_soft", "ckv_soft_forward", "ckv_soft_backward")
 
 
 class CkvError(RuntimeError):
@@ -53,6 +54,12 @@ class _Result(C.Structure):
     _fields_ = [("n_bunches", C.c_int64), ("n_hits", C.c_int64), ("n_records", C.c_int64),
                 ("n_emitting", C.c_int64), ("n_tiles", C.c_int64), ("drops", C.c_int64 * 8),
                 ("overflow", C.c_int32), ("error", C.c_int32)]
+
+
+class _ParamSpec(C.Structure):
+    _fields_ = [("eta0", C.c_double), ("n_layers", C.c_int32), ("n_knots", C.c_int32),
+                ("layer_bounds_m", C.c_void_p), ("knot_top_m", C.c_double),
+                ("obs_level_m", C.c_double), ("step_m", C.c_double), ("top_m", C.c_double)]
 
 
 class _Output(C.Structure):
@@ -85,6 +92,13 @@ def lib():
         L.ckv_run.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params), P, P,
                               P, C.c_size_t, C.POINTER(_Output), P]
         L.ckv_count.argtypes = [C.POINTER(_Segments), C.POINTER(_Params), P, P, P]
+        L.ckv_atmo_from_params.argtypes = [C.POINTER(_ParamSpec), P, C.POINTER(P)]
+        L.ckv_atmo_params_backward.argtypes = [C.POINTER(_ParamSpec), P, P, P, P, P]
+        L.ckv_array_create_soft.argtypes = [P, P, P, I32, D, C.POINTER(P)]
+        L.ckv_soft_forward.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params),
+                                       P, P, P, P, P, P, C.c_size_t, P]
+        L.ckv_soft_backward.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params),
+                                        P, P, P, P, P, P, P, P, C.c_size_t, P]
         _lib = L
     return _lib
 
@@ -105,7 +119,10 @@ def _np_ptr(a: np.ndarray):
 class Atmosphere:
     """ckv_atmo: uniform fine tables built from a tabulated n-1 profile."""
 
-    def __init__(self, alt, eta, obs_level: float, step: float = 0.0):
+    def __init__(self, alt=None, eta=None, obs_level: float = 0.0, step: float = 0.0, handle=None):
+        if handle is not None:          # adopt a handle made by another constructor
+            self.handle = handle
+            return
         self._alt = np.ascontiguousarray(alt, dtype=np.float64)
         self._eta = np.ascontiguousarray(eta, dtype=np.float64)
         h = C.c_void_p()
@@ -136,15 +153,21 @@ class Atmosphere:
 
 
 class TelescopeArray:
-    """ckv_array: telescope spheres and their candidate grid."""
+    """ckv_array: telescope spheres and their candidate grid (and, with
+    soft_sigma > 0, the grid of the soft response)."""
 
-    def __init__(self, x, y, r):
+    def __init__(self, x, y, r, soft_sigma: float = 0.0):
         self.x = np.ascontiguousarray(x, dtype=np.float64)
         self.y = np.ascontiguousarray(y, dtype=np.float64)
         self.r = np.ascontiguousarray(r, dtype=np.float64)
+        self.soft_sigma = float(soft_sigma)
         h = C.c_void_p()
-        _check(lib().ckv_array_create(_np_ptr(self.x), _np_ptr(self.y), _np_ptr(self.r),
-                                      self.x.shape[0], C.byref(h)))
+        if soft_sigma > 0:
+            _check(lib().ckv_array_create_soft(_np_ptr(self.x), _np_ptr(self.y), _np_ptr(self.r),
+                                               self.x.shape[0], self.soft_sigma, C.byref(h)))
+        else:
+            _check(lib().ckv_array_create(_np_ptr(self.x), _np_ptr(self.y), _np_ptr(self.r),
+                                          self.x.shape[0], C.byref(h)))
         self.handle = h
 
     @property
@@ -292,3 +315,134 @@ class GraphRunner:
     def replay(self) -> RunOutput:
         self.graph.replay()
         return self.out
+
+
+
+# ---------------------------------------------------------------------------
+# differentiation: soft telescope response and its gradient
+# ---------------------------------------------------------------------------
+
+class ParamSpec:
+    """ckv_atmo_param_spec (see include/ckv.h)."""
+
+    def __init__(self, eta0, layer_bounds, n_knots, knot_top, obs_level, step, top):
+        self.bounds = np.ascontiguousarray(layer_bounds, dtype=np.float64)
+        self.c = _ParamSpec(float(eta0), self.bounds.shape[0] - 1, int(n_knots),
+                            _np_ptr(self.bounds).value, float(knot_top), float(obs_level),
+                            float(step), float(top))
+
+    @property
+    def n_theta(self) -> int:
+        return self.c.n_knots + self.c.n_layers
+
+    def atmosphere(self, theta) -> Atmosphere:
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().ckv_atmo_from_params(C.byref(self.c), _np_ptr(th), C.byref(h)))
+        return Atmosphere(handle=h)
+
+    def backward(self, theta, atmo: Atmosphere, g_psi, g_P) -> np.ndarray:
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        gp = np.ascontiguousarray(g_psi, dtype=np.float64)
+        gq = np.ascontiguousarray(g_P, dtype=np.float64)
+        out = np.empty(self.n_theta)
+        _check(lib().ckv_atmo_params_backward(C.byref(self.c), _np_ptr(th), atmo.handle,
+                                              _np_ptr(gp), _np_ptr(gq), _np_ptr(out)))
+        return out
+
+
+class SoftModel:
+    """theta -> (S, A) per (shower, telescope), with bunch counts frozen at theta0."""
+
+    def __init__(self, segs, tels, spec: ParamSpec, theta0, sigma: float, *, bunch_size=5.0,
+                 lambda_min=300.0, lambda_max=600.0, seed=0x14927, device="cuda"):
+        import torch
+        self.spec = spec
+        self.dsegs = segs if isinstance(segs, DeviceSegments) else DeviceSegments(segs, device=device)
+        self.tels = TelescopeArray(tels.x, tels.y, tels.r, soft_sigma=sigma)
+        self.params = make_params(precision=CKV_FP64, bunch_size=bunch_size, lambda_min=lambda_min,
+                                  lambda_max=lambda_max, seed=seed)
+        self.atmo0 = spec.atmosphere(theta0)
+        self.n_b = count(self.dsegs, self.atmo0, self.params).contiguous()
+        ws = workspace_size(self.dsegs.n, self.dsegs.n_showers, self.tels.n, 0, self.params)
+        self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+        n_nodes = self.atmo0.info()[0]
+        self.g_psi = torch.empty(n_nodes, dtype=torch.float64, device=device)
+        self.g_P = torch.empty(5 * n_nodes, dtype=torch.float64, device=device)
+        self.shape = (self.dsegs.n_showers, self.tels.n)
+        self._segs = self.dsegs.c_segments()
+        self._showers = self.dsegs.c_showers()
+        self._cache = None
+
+    def _atmo(self, theta):
+        th = np.asarray(theta, dtype=np.float64)
+        if self._cache is None or not np.array_equal(self._cache[0], th):
+            self._cache = (th.copy(), self.spec.atmosphere(th))
+        return self._cache[1]
+
+    def forward(self, theta, stream=None):
+        import torch
+        atmo = self._atmo(theta)
+        S = torch.empty(self.shape, dtype=torch.float64, device=self.g_psi.device)
+        A = torch.empty_like(S)
+        _check(lib().ckv_soft_forward(C.byref(self._segs), C.byref(self._showers), C.byref(self.params),
+                                      atmo.handle, self.tels.handle, C.c_void_p(self.n_b.data_ptr()),
+                                      C.c_void_p(S.data_ptr()), C.c_void_p(A.data_ptr()),
+                                      C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                      _stream_ptr(stream)))
+        return S, A
+
+    def backward_tables(self, theta, gS, gA, stream=None):
+        """Device dL/dpsi (n_nodes) and dL/dP (5 x n_nodes)."""
+        atmo = self._atmo(theta)
+        gS = gS.to(self.g_psi.device, dtype=self.g_psi.dtype).contiguous()
+        gA = gA.to(self.g_psi.device, dtype=self.g_psi.dtype).contiguous()
+        _check(lib().ckv_soft_backward(C.byref(self._segs), C.byref(self._showers), C.byref(self.params),
+                                       atmo.handle, self.tels.handle, C.c_void_p(self.n_b.data_ptr()),
+                                       C.c_void_p(gS.data_ptr()), C.c_void_p(gA.data_ptr()),
+                                       C.c_void_p(self.g_psi.data_ptr()), C.c_void_p(self.g_P.data_ptr()),
+                                       C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                       _stream_ptr(stream)))
+        return self.g_psi, self.g_P
+
+    def backward(self, theta, gS, gA, stream=None) -> np.ndarray:
+        import torch
+        g_psi, g_P = self.backward_tables(theta, gS, gA, stream)
+        torch.cuda.synchronize()
+        return self.spec.backward(theta, self._atmo(theta), g_psi.cpu().numpy(), g_P.cpu().numpy())
+
+
+def _soft_function():
+    import torch
+
+    class SoftResponse(torch.autograd.Function):
+        """(S, A) = soft telescope response at atmosphere parameters theta.
+
+        The backward pass runs the adjoint kernel (bunches recomputed from their
+        random numbers) and the table chain rule in the library."""
+
+        @staticmethod
+        def forward(ctx, theta, model):
+            ctx.model = model
+            ctx.save_for_backward(theta)
+            return model.forward(theta.detach().cpu().numpy())
+
+        @staticmethod
+        def backward(ctx, gS, gA):
+            (theta,) = ctx.saved_tensors
+            th = theta.detach().cpu().numpy()
+            g = ctx.model.backward(th, gS, gA)
+            return torch.as_tensor(g, dtype=theta.dtype, device=theta.device), None
+
+    return SoftResponse
+
+
+_SOFT = None
+
+
+def soft_response(theta, model: SoftModel):
+    """Differentiable (S, A) of shape (n_showers, n_tel) for torch tensor theta."""
+    global _SOFT
+    if _SOFT is None:
+        _SOFT = _soft_function()
+    return _SOFT.apply(theta, model)

@@ -135,6 +135,9 @@ size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, in
 
 using namespace ckv;
 
+static int atmo_create(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
+                       double step_m, ckv_atmo** out);
+
 extern "C" {
 
 const char* ckv_last_error(void) { return g_error.c_str(); }
@@ -157,32 +160,30 @@ int ckv_atmo_create(const double* alt_m, const double* eta, int64_t n, double ob
             set_error("atmosphere: altitudes must increase strictly"); return CKV_ERR_TABLE;
         }
     }
-    ckv_atmo* a = new (std::nothrow) ckv_atmo();
-    if (!a) { set_error("out of host memory"); return CKV_ERR_NOMEM; }
-    int rc = build_atmo_tables(alt_m, eta, n, obs_level_m, step_m, a);
-    if (rc) { delete a; return rc; }
-    if (a->n_nodes > (1 << 20)) { delete a; set_error("atmosphere table too fine"); return CKV_ERR_TABLE; }
-    hipGetDevice(&a->device);
-    const int64_t m = a->n_nodes;
-    std::vector<double> node(m * kNode64);
-    for (int64_t i = 0; i < m; ++i) {
-        node[i * kNode64] = a->psi[i];
-        for (int j = 0; j < 5; ++j) node[i * kNode64 + 1 + j] = a->P[j * m + i];
-    }
-    std::vector<float> cell((m - 1) * kCell32, 0.0f);
-    for (int64_t i = 0; i + 1 < m; ++i) {
-        float* c = &cell[i * kCell32];
-        c[0] = (float)a->psi[i];
-        c[1] = (float)(a->psi[i + 1] - a->psi[i]);
-        for (int j = 0; j < 5; ++j) c[2 + j] = (float)a->P[j * m + i];
-        c[7] = 0.0f;
-    }
-    if ((rc = upload(node.data(), node.size(), &a->d_node64)) ||
-        (rc = upload(cell.data(), cell.size(), &a->d_cell32))) {
-        ckv_atmo_destroy(a);
-        return rc;
-    }
-    *out = a;
+    return atmo_create(alt_m, eta, n, obs_level_m, step_m, out);
+}
+
+
+int ckv_atmo_from_params(const ckv_atmo_param_spec* spec, const double* theta, ckv_atmo** out)
+{
+    if (!out) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    *out = nullptr;
+    int rc = param_spec_check(spec, theta);
+    if (rc) return rc;
+    std::vector<double> alt, eta;
+    param_profile(spec, theta, &alt, &eta);
+    if (alt.size() < 2) { set_error("fewer than two nodes"); return CKV_ERR_ARG; }
+    return atmo_create(alt.data(), eta.data(), (int64_t)alt.size(), spec->obs_level_m, spec->step_m, out);
+}
+
+int ckv_atmo_params_backward(const ckv_atmo_param_spec* spec, const double* theta,
+                             const ckv_atmo* atmo, const double* g_psi, const double* g_P,
+                             double* g_theta)
+{
+    int rc = param_spec_check(spec, theta);
+    if (rc) return rc;
+    if (!atmo || !g_psi || !g_P || !g_theta) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    param_backward(spec, theta, atmo, g_psi, g_P, g_theta);
     return CKV_OK;
 }
 
@@ -212,12 +213,30 @@ int ckv_atmo_destroy(ckv_atmo* a)
     return CKV_OK;
 }
 
-int ckv_array_create(const double* x_m, const double* y_m, const double* r_m, int32_t n_tel,
-                     ckv_array** out)
+static int upload_grid(ckv_grid* g)
+{
+    int rc;
+    if ((rc = upload(g->cell_off.data(), g->cell_off.size(), &g->d_cell_off)) ||
+        (rc = upload(g->cell_list.data(), g->cell_list.size(), &g->d_cell_list)))
+        return rc;
+    return CKV_OK;
+}
+
+static void free_grid(ckv_grid* g)
+{
+    if (g->d_cell_off) hipFree(g->d_cell_off);
+    if (g->d_cell_list) hipFree(g->d_cell_list);
+    g->d_cell_off = nullptr;
+    g->d_cell_list = nullptr;
+}
+
+static int array_create(const double* x_m, const double* y_m, const double* r_m, int32_t n_tel,
+                        double sigma, ckv_array** out)
 {
     if (!x_m || !y_m || !r_m || !out) { set_error("NULL argument"); return CKV_ERR_ARG; }
     *out = nullptr;
     if (n_tel < 1 || n_tel > CKV_MAX_TEL) { set_error("need 1 <= n_tel <= CKV_MAX_TEL"); return CKV_ERR_ARG; }
+    if (!(sigma >= 0.0) || !std::isfinite(sigma)) { set_error("sigma must be >= 0"); return CKV_ERR_ARG; }
     for (int32_t k = 0; k < n_tel; ++k)
         if (!std::isfinite(x_m[k]) || !std::isfinite(y_m[k]) || !std::isfinite(r_m[k]) || !(r_m[k] > 0.0)) {
             set_error("telescopes: non-finite position or radius <= 0"); return CKV_ERR_TABLE;
@@ -228,7 +247,15 @@ int ckv_array_create(const double* x_m, const double* y_m, const double* r_m, in
     arr->x.assign(x_m, x_m + n_tel);
     arr->y.assign(y_m, y_m + n_tel);
     arr->r.assign(r_m, r_m + n_tel);
-    int rc = build_array_grid(arr);
+    arr->soft_sigma = sigma;
+    int rc = build_array_grid(arr, arr->r, &arr->hit);
+    if (!rc && sigma > 0.0) {
+        // beyond sqrt(R^2 + 2 R sigma z_cut) the soft weight is exactly zero
+        std::vector<double> reff(n_tel);
+        for (int32_t k = 0; k < n_tel; ++k)
+            reff[k] = std::sqrt(r_m[k] * r_m[k] + 2.0 * r_m[k] * sigma * kSoftZCut) * (1.0 + 1e-9);
+        rc = build_array_grid(arr, reff, &arr->soft);
+    }
     if (rc) { delete arr; return rc; }
     hipGetDevice(&arr->device);
     std::vector<double> tel(4 * (size_t)n_tel);
@@ -238,9 +265,8 @@ int ckv_array_create(const double* x_m, const double* y_m, const double* r_m, in
         tel[4 * k + 2] = r_m[k];
         tel[4 * k + 3] = r_m[k] * r_m[k];
     }
-    if ((rc = upload(tel.data(), tel.size(), &arr->d_tel)) ||
-        (rc = upload(arr->cell_off.data(), arr->cell_off.size(), &arr->d_cell_off)) ||
-        (rc = upload(arr->cell_list.data(), arr->cell_list.size(), &arr->d_cell_list))) {
+    if ((rc = upload(tel.data(), tel.size(), &arr->d_tel)) || (rc = upload_grid(&arr->hit)) ||
+        (sigma > 0.0 && (rc = upload_grid(&arr->soft)))) {
         ckv_array_destroy(arr);
         return rc;
     }
@@ -248,12 +274,25 @@ int ckv_array_create(const double* x_m, const double* y_m, const double* r_m, in
     return CKV_OK;
 }
 
+int ckv_array_create(const double* x_m, const double* y_m, const double* r_m, int32_t n_tel,
+                     ckv_array** out)
+{
+    return array_create(x_m, y_m, r_m, n_tel, 0.0, out);
+}
+
+int ckv_array_create_soft(const double* x_m, const double* y_m, const double* r_m, int32_t n_tel,
+                          double sigma_m, ckv_array** out)
+{
+    if (!(sigma_m > 0.0)) { set_error("sigma must be > 0"); return CKV_ERR_ARG; }
+    return array_create(x_m, y_m, r_m, n_tel, sigma_m, out);
+}
+
 int ckv_array_destroy(ckv_array* arr)
 {
     if (!arr) return CKV_OK;
     if (arr->d_tel) hipFree(arr->d_tel);
-    if (arr->d_cell_off) hipFree(arr->d_cell_off);
-    if (arr->d_cell_list) hipFree(arr->d_cell_list);
+    free_grid(&arr->hit);
+    free_grid(&arr->soft);
     delete arr;
     return CKV_OK;
 }
@@ -305,6 +344,80 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
     return launch_run(plan);
 }
 
+static int soft_common(const ckv_segments* segs, const ckv_showers* showers,
+                       const ckv_params* params, const ckv_atmo* atmo, const ckv_array* arr,
+                       const int64_t* n_b_frozen, void* workspace, size_t ws_bytes, void* stream,
+                       RunPlan* plan)
+{
+    int rc;
+    if ((rc = check_segments(segs)) || (rc = check_params(params))) return rc;
+    if (!showers || !atmo || !arr || !workspace || (!n_b_frozen && segs->n > 0)) {
+        set_error("NULL argument"); return CKV_ERR_ARG;
+    }
+    if (showers->n_showers < 1 || !showers->seg_offsets || !showers->t_ref) {
+        set_error("showers: need n_showers >= 1, seg_offsets and t_ref"); return CKV_ERR_ARG;
+    }
+    if (!(arr->soft_sigma > 0.0)) {
+        set_error("telescope handle has no soft grid (use ckv_array_create_soft)"); return CKV_ERR_ARG;
+    }
+    if ((rc = current_device(atmo->device)) || (rc = current_device(arr->device))) return rc;
+    size_t need = workspace_layout(segs->n, showers->n_showers, arr->n_tel, 0, params, plan, workspace);
+    if (ws_bytes < need) { set_error("workspace smaller than ckv_workspace_size()"); return CKV_ERR_CAPACITY; }
+    plan->segs = *segs;
+    plan->showers = *showers;
+    plan->params = *params;
+    plan->atmo = atmo;
+    plan->arr = arr;
+    plan->stream = (hipStream_t)stream;
+    plan->k_ft = frank_tamm_k(params->lambda_min_nm, params->lambda_max_nm);
+    int n_cu = 256;
+    {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    }
+    plan->emit_grid = params->grid > 0 ? params->grid : std::min(n_cu, kMaxEmitGrid);
+    plan->emit_waves = 4;
+    return CKV_OK;
+}
+
+int ckv_soft_forward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
+                     const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
+                     double* S, double* A, void* workspace, size_t ws_bytes, void* stream)
+{
+    RunPlan plan{};
+    if (int rc = soft_common(segs, showers, params, atmo, arr, n_b_frozen, workspace, ws_bytes,
+                             stream, &plan))
+        return rc;
+    if (!S || !A) { set_error("NULL output"); return CKV_ERR_ARG; }
+    SoftPlan sp{};
+    sp.n_b_frozen = n_b_frozen;
+    sp.sigma = arr->soft_sigma;
+    sp.S = S;
+    sp.A = A;
+    return launch_soft(plan, sp, 0);
+}
+
+int ckv_soft_backward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
+                      const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
+                      const double* dL_dS, const double* dL_dA, double* g_psi, double* g_P,
+                      void* workspace, size_t ws_bytes, void* stream)
+{
+    RunPlan plan{};
+    if (int rc = soft_common(segs, showers, params, atmo, arr, n_b_frozen, workspace, ws_bytes,
+                             stream, &plan))
+        return rc;
+    if (!dL_dS || !dL_dA || !g_psi || !g_P) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    SoftPlan sp{};
+    sp.n_b_frozen = n_b_frozen;
+    sp.sigma = arr->soft_sigma;
+    sp.gS = dL_dS;
+    sp.gA = dL_dA;
+    sp.g_psi = g_psi;
+    sp.g_P = g_P;
+    return launch_soft(plan, sp, 1);
+}
+
 int ckv_count(const ckv_segments* segs, const ckv_params* params, const ckv_atmo* atmo,
               int64_t* n_b, void* stream)
 {
@@ -317,3 +430,35 @@ int ckv_count(const ckv_segments* segs, const ckv_params* params, const ckv_atmo
 }
 
 }  // extern "C"
+
+static int atmo_create(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
+                       double step_m, ckv_atmo** out)
+{
+    ckv_atmo* a = new (std::nothrow) ckv_atmo();
+    if (!a) { set_error("out of host memory"); return CKV_ERR_NOMEM; }
+    int rc = build_atmo_tables(alt_m, eta, n, obs_level_m, step_m, a);
+    if (rc) { delete a; return rc; }
+    if (a->n_nodes > (1 << 20)) { delete a; set_error("atmosphere table too fine"); return CKV_ERR_TABLE; }
+    hipGetDevice(&a->device);
+    const int64_t m = a->n_nodes;
+    std::vector<double> node(m * kNode64);
+    for (int64_t i = 0; i < m; ++i) {
+        node[i * kNode64] = a->psi[i];
+        for (int j = 0; j < 5; ++j) node[i * kNode64 + 1 + j] = a->P[j * m + i];
+    }
+    std::vector<float> cell((m - 1) * kCell32, 0.0f);
+    for (int64_t i = 0; i + 1 < m; ++i) {
+        float* c = &cell[i * kCell32];
+        c[0] = (float)a->psi[i];
+        c[1] = (float)(a->psi[i + 1] - a->psi[i]);
+        for (int j = 0; j < 5; ++j) c[2 + j] = (float)a->P[j * m + i];
+        c[7] = 0.0f;
+    }
+    if ((rc = upload(node.data(), node.size(), &a->d_node64)) ||
+        (rc = upload(cell.data(), cell.size(), &a->d_cell32))) {
+        ckv_atmo_destroy(a);
+        return rc;
+    }
+    *out = a;
+    return CKV_OK;
+}

@@ -58,6 +58,8 @@ enum CtrlSlot {
     kCtrlSlots = kDrop0 + CKV_N_DROP + 4
 };
 
+
+
 }  // namespace ckv
 
 struct ckv_atmo {
@@ -71,20 +73,26 @@ struct ckv_atmo {
     float* d_cell32 = nullptr;       // device, (n_nodes - 1) x kCell32
 };
 
-struct ckv_array {
-    int device = 0;
-    int32_t n_tel = 0;
-    std::vector<double> x, y, r;
-    // candidate grid: cells of size `cell` starting at (gx0, gy0); the list of
-    // cell c holds, in ascending order, every telescope whose sphere can be
-    // crossed by a line through a ground point in c with observed w >= kGridWLo
+// Candidate grid: cells of size `cell` starting at (gx0, gy0); the list of
+// cell c holds, in ascending order, every telescope whose (effective) sphere
+// can be met by a line through a ground point in c with observed w >= kGridWLo.
+struct ckv_grid {
     double gx0 = 0, gy0 = 0, cell = 1, inv_cell = 1;
     int32_t nx = 0, ny = 0;
     std::vector<int32_t> cell_off;   // nx*ny + 1
     std::vector<uint16_t> cell_list;
-    double* d_tel = nullptr;         // device, n_tel x 4: X, Y, R, R^2
     int32_t* d_cell_off = nullptr;
     uint16_t* d_cell_list = nullptr;
+};
+
+struct ckv_array {
+    int device = 0;
+    int32_t n_tel = 0;
+    std::vector<double> x, y, r;
+    double* d_tel = nullptr;         // device, n_tel x 4: X, Y, R, R^2
+    ckv_grid hit;                    // radii R (sphere crossings)
+    ckv_grid soft;                   // radii sqrt(R^2 + 2 R sigma z_cut) (soft response)
+    double soft_sigma = 0;           // 0: no soft grid
 };
 
 namespace ckv {
@@ -94,7 +102,15 @@ void set_error(const std::string& msg);
 // host builders (ckv_tables.cpp)
 int build_atmo_tables(const double* alt, const double* eta, int64_t n, double h_obs, double step,
                       ckv_atmo* a);
-int build_array_grid(ckv_array* arr);
+int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ckv_grid* g);
+constexpr double kSoftZCut = 40.0;   // Phi(-40) underflows to exactly 0 in FP64
+int param_spec_check(const ckv_atmo_param_spec* sp, const double* theta);
+void param_profile(const ckv_atmo_param_spec* sp, const double* theta, std::vector<double>* alt,
+                   std::vector<double>* eta);
+void param_backward(const ckv_atmo_param_spec* sp, const double* theta, const ckv_atmo* a,
+                    const double* g_psi, const double* g_P, double* g_theta);
+
+
 
 // kernel launchers (ckv_kernels.hip)
 struct RunPlan {
@@ -129,5 +145,17 @@ int launch_count(const ckv_segments* segs, const ckv_params* p, const ckv_atmo* 
                  int64_t* n_b, hipStream_t stream);
 int emit_config(int precision, int n_tel, const ckv_atmo* atmo, int tile_segs, int* waves,
                 size_t* lds_bytes);
+
+struct SoftPlan {
+    const int64_t* n_b_frozen;
+    double sigma;
+    const double* gS;       // backward: dL/dS per (shower, telescope)
+    const double* gA;       // backward: dL/dA
+    double* S;              // forward outputs
+    double* A;
+    double* g_psi;          // backward outputs (n_nodes)
+    double* g_P;            // backward outputs (5 x n_nodes)
+};
+int launch_soft(RunPlan& plan, const SoftPlan& sp, int mode);
 
 }  // namespace ckv

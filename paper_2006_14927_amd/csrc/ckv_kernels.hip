@@ -745,7 +745,7 @@ __global__ void __launch_bounds__(1024) init_kernel(Args a)
         if (run_t > a.max_tiles) err = 1;
         a.ctrl[kNumTiles] = err ? 0 : run_t;
         a.ctrl[kNumRowBlocks] = err ? 0 : run_b;
-        a.result->error = err;
+        if (a.result) a.result->error = err;
     }
 }
 
@@ -906,6 +906,398 @@ __global__ void __launch_bounds__(256) count_kernel(Args a, int64_t* n_b)
 }
 
 // --------------------------------------------------------------------------
+// Soft telescope response and its adjoint (differentiation pattern), FP64.
+//   S_sk = sum photons * Phi(z),  A_sk = sum photons * Phi(z) * t,
+//   z = (R^2 - rho^2) / (2 R sigma),
+// with bunch counts frozen per step.  MODE 0 accumulates S and A; MODE 1
+// recomputes every bunch from its random numbers and accumulates dL/dpsi_i and
+// dL/dP_j(h_i) given dL/dS and dL/dA.
+// --------------------------------------------------------------------------
+struct SoftArgs {
+    const int64_t* nb_frozen;
+    double sigma;
+    const double* gS;
+    const double* gA;
+    double* S;
+    double* A;
+    double* g_psi;
+    double* g_P;
+    double gx0, gy0, inv_cell;
+    int32_t nx, ny;
+    const int32_t* cell_off;
+    const uint16_t* cell_list;
+};
+
+struct alignas(16) SoftStep {
+    double x0, y0, h0, t0, u, v, w;
+    double cos_t, sin_t, photons, ds, inv_bc;
+    double b1x, b1y, b1z, b2x, b2y, b2z;
+    double r2, g1, f_m, kl_nb;
+    double g_cos, g_sin, g_phot;     // adjoint accumulators of the step
+    int32_t i_m, boff, sidx, pad;
+};
+static_assert(sizeof(SoftStep) % 16 == 0, "soft step entry alignment");
+
+constexpr int kSoftTS = 32;
+constexpr int kSoftWaves = 4;
+
+__host__ __device__ inline size_t soft_wave_bytes(int n_tel)
+{
+    return kSoftTS * sizeof(SoftStep) + kWave * sizeof(int32_t) + (size_t)2 * n_tel * sizeof(double);
+}
+
+__host__ __device__ inline size_t soft_bin_bytes(int mode, int n_nodes)
+{
+    return mode == 1 ? (size_t)6 * n_nodes * sizeof(double) : 0;
+}
+
+// step setup with a frozen bunch count; false when the step emits nothing
+__device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, SoftStep& e)
+{
+    const double x0 = a.x0[i], y0 = a.y0[i], h0 = a.h0[i];
+    const double u = a.u[i], v = a.v[i], w = a.w[i];
+    const double L = a.len[i], t0 = a.t0[i], E = a.energy[i];
+    if (!(isfinite(x0) && isfinite(y0) && isfinite(h0) && isfinite(u) && isfinite(v) &&
+          isfinite(w) && isfinite(L) && isfinite(t0) && isfinite(E)) || !(L > 0.0) || nb <= 0)
+        return false;
+    const double m = a.ptype[i] == CKV_MUON ? kMassMuon : kMassElectron;
+    const double r = m / E;
+    const double r2 = r * r;
+    if (!(r2 < 1.0)) return false;
+    const double h_mid = h0 - (0.5 * L) * w;
+    const double hc = h_mid < a.h_obs ? a.h_obs : (h_mid > a.h_top ? a.h_top : h_mid);
+    const double x = (hc - a.h_obs) * a.inv_step;
+    int64_t im = (int64_t)floor(x);
+    if (im > a.n_nodes - 2) im = a.n_nodes - 2;
+    const double fm = x - (double)im;
+    const double lo = a.node64[kNode64 * im], hi = a.node64[kNode64 * (im + 1)];
+    const double psi = lo + fm * (hi - lo);
+    const double n2 = 1.0 + psi;
+    const double num = psi - n2 * r2;
+    if (!(num > 0.0)) return false;
+    const double sin2 = num / (n2 * (1.0 - r2));
+    const double nbd = (double)nb;
+    e.x0 = x0; e.y0 = y0; e.h0 = h0; e.t0 = t0; e.u = u; e.v = v; e.w = w;
+    e.photons = (a.k_ft * L) * sin2 / nbd;
+    e.g1 = (1.0 - r2) * n2;
+    e.cos_t = 1.0 / sqrt(e.g1);
+    e.sin_t = sqrt(sin2);
+    e.ds = L / nbd;
+    e.inv_bc = 1.0 / (sqrt(1.0 - r2) * kSpeedOfLight);
+    const double Dx = u, Dy = v, Dz = -w;
+    const double sgn = copysign(1.0, Dz);
+    const double ia = -1.0 / (sgn + Dz);
+    const double ib = Dx * Dy * ia;
+    e.b1x = 1.0 + sgn * Dx * Dx * ia;
+    e.b1y = sgn * ib;
+    e.b1z = -sgn * Dx;
+    e.b2x = ib;
+    e.b2y = sgn + Dy * Dy * ia;
+    e.b2z = -Dy;
+    e.r2 = r2;
+    e.f_m = fm;
+    e.i_m = (int32_t)im;
+    e.kl_nb = a.k_ft * L / nbd;
+    e.g_cos = e.g_sin = e.g_phot = 0.0;
+    return true;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) soft_kernel(Args a, SoftArgs sa)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    const int N = a.n_nodes;
+    double* gpsi_l = reinterpret_cast<double*>(lds);
+    double* gP_l = gpsi_l + N;
+    unsigned char* wbase = lds + soft_bin_bytes(MODE, N) + (size_t)wave * soft_wave_bytes(a.n_tel);
+    SoftStep* stash = reinterpret_cast<SoftStep*>(wbase);
+    int32_t* flags = reinterpret_cast<int32_t*>(wbase + kSoftTS * sizeof(SoftStep));
+    double* acc = reinterpret_cast<double*>(flags + kWave);     // MODE 0: S then A per telescope
+    if (MODE == 1)
+        for (int q = threadIdx.x; q < 6 * N; q += blockDim.x) gpsi_l[q] = 0.0;
+    for (int q = lane; q < 2 * a.n_tel; q += kWave) acc[q] = 0.0;
+    flags[lane] = 0;
+    __syncthreads();
+
+    const double a1 = -0.5, a2 = 0.375, a3 = -0.3125, a4 = 0.2734375;
+    const double ak[5] = {1.0, a1, a2, a3, a4};
+    const double inv_c = 1.0 / kSpeedOfLight;
+    const double inv_sqrt2 = 0.70710678118654752440;
+    const double inv_sqrt2pi = 0.39894228040143267794;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t le_mask = lt_mask | (1ull << lane);
+    const double nobs = a.n_obs;
+    double g_psi0 = 0.0;
+    const int64_t n_tiles = a.ctrl[kNumTiles];
+
+    for (;;) {
+        int64_t t = 0;
+        if (lane == 0) t = (int64_t)atomicAdd((unsigned long long*)&a.ctrl[kTileCounter], 1ull);
+        t = uniform(t);
+        if (t >= n_tiles) break;
+        int lo = 0, hi = a.n_showers;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (a.tiles_before[mid] <= t) lo = mid; else hi = mid;
+        }
+        const int s = lo;
+        const int64_t sfirst = a.seg_offsets[s];
+        const int64_t g0 = sfirst + (t - a.tiles_before[s]) * (int64_t)kSoftTS;
+        const int64_t gend = min(g0 + (int64_t)kSoftTS, a.seg_offsets[s + 1]);
+        const int nseg = (int)(gend - g0);
+        const uint32_t shower_id = a.shower_ids ? a.shower_ids[s] : (uint32_t)s;
+        const int64_t seg_id0 = (a.seg_id_base ? a.seg_id_base[s] : 0) + (g0 - sfirst);
+        const double t_ref = a.t_ref[s];
+
+        SoftStep st;
+        int64_t nb = 0;
+        bool emits = false;
+        if (lane < nseg) {
+            const int64_t nbf = sa.nb_frozen[g0 + lane];
+            emits = soft_step_setup(a, g0 + lane, nbf, st);
+            if (emits) nb = nbf;
+        }
+        const int64_t incl = wave_incl_scan(nb);
+        const int64_t total = __shfl(incl, kWave - 1);
+        if (total >= ((int64_t)1 << 30)) {
+            if (lane == 0 && a.result) atomicOr(&a.result->error, 2);
+            continue;
+        }
+        const uint64_t emit_mask = __ballot(emits);
+        const int excl = (int)(incl - nb);
+        if (emits) {
+            st.boff = excl;
+            st.sidx = lane;
+            stash[__popcll(emit_mask & lt_mask)] = st;
+        }
+        wave_lds_sync();
+
+        for (int64_t c0 = 0; c0 < total; c0 += kWave) {
+            const int32_t j = (int32_t)(c0 + lane);
+            const bool active = j < total;
+            const int cnt0 = __popcll(__ballot(emits && excl <= (int)c0));
+            if (emits && excl > (int)c0 && excl < (int)c0 + kWave) flags[excl - (int)c0] = 1;
+            wave_lds_sync();
+            const uint64_t starts = __ballot(flags[lane] != 0);
+            flags[lane] = 0;
+            const int si = cnt0 - 1 + __popcll(starts & le_mask);
+            if (!active) continue;
+            SoftStep& e = stash[si];
+            const int32_t k = j - e.boff;
+            uint32_t r[4];
+            philox4x32_10((uint32_t)k, (uint32_t)(seg_id0 + e.sidx), shower_id, 0u, a.key0, a.key1, r);
+            const double u0 = ((double)r[0] + 0.5) * 2.3283064365386963e-10;
+            const double s_along = ((double)k + u0) * e.ds;
+            const double xe = e.x0 + s_along * e.u;
+            const double ye = e.y0 + s_along * e.v;
+            const double he = e.h0 - s_along * e.w;
+            const double te = e.t0 + s_along * e.inv_bc;
+            const double phi = 6.283185307179586 * (((double)r[1] + 0.5) * 2.3283064365386963e-10);
+            double sp, cp;
+            sincos(phi, &sp, &cp);
+            const double Ex = cp * e.b1x + sp * e.b2x;
+            const double Ey = cp * e.b1y + sp * e.b2y;
+            const double Ez = cp * e.b1z + sp * e.b2z;
+            const double pu = e.cos_t * e.u + e.sin_t * Ex;
+            const double pv = e.cos_t * e.v + e.sin_t * Ey;
+            const double pw = e.cos_t * e.w - e.sin_t * Ez;
+            if (he < a.h_obs || he >= a.h_top || pw <= a.w_min) continue;
+            // atmosphere at emission
+            const double x = (he - a.h_obs) * a.inv_step;
+            int ie = (int)x;
+            ie = min(ie, N - 2);
+            const double fe = x - (double)ie;
+            const double* nd = a.node64 + (size_t)kNode64 * ie;
+            const double pa = nd[0], pb = nd[kNode64];
+            const double psi_e = pa + fe * (pb - pa);
+            const double dz = fe * a.step;
+            double P[6], D[6];
+            double pow_a[6], pow_b[6];
+            pow_a[0] = pow_b[0] = 1.0;
+            for (int q = 1; q <= 5; ++q) { pow_a[q] = pow_a[q - 1] * pa; pow_b[q] = pow_b[q - 1] * psi_e; }
+            const double dh = he - a.h_obs;
+            P[0] = dh;
+            for (int jj = 1; jj <= 5; ++jj) {
+                double hs = 0.0;
+                for (int q = 0; q <= jj; ++q) hs += pow_a[jj - q] * pow_b[q];
+                P[jj] = nd[jj] + dz / (double)(jj + 1) * hs;
+            }
+            const double cneg = -psi_e;
+            for (int kk = 0; kk <= 5; ++kk) {
+                // D_k = sum_j C(k,j) (-psi_e)^(k-j) P_j
+                double sum = 0.0, binom = 1.0, cp_pow = 1.0;
+                for (int q = kk; q >= 0; --q) {
+                    sum += binom * cp_pow * P[q];
+                    binom = binom * (double)q / (double)(kk - q + 1);
+                    cp_pow *= cneg;
+                }
+                D[kk] = sum;
+            }
+            const double ne2 = 1.0 + psi_e;
+            const double ne = sqrt(ne2);
+            const double q = 1.0 / (ne2 * pw * pw);
+            double qk[5];
+            qk[0] = 1.0;
+            for (int kk = 1; kk < 5; ++kk) qk[kk] = qk[kk - 1] * q;
+            double Sser = 0.0, U = 0.0;
+            for (int kk = 0; kk < 5; ++kk) {
+                Sser += ak[kk] * qk[kk] * D[kk];
+                U += ak[kk] * qk[kk] * (ne2 * D[kk] + D[kk + 1]);
+            }
+            const double T = U / (ne * pw) * inv_c;
+            const double xg = xe + pu * Sser / pw;
+            const double yg = ye + pv * Sser / pw;
+            const double tt = te + T - t_ref;
+            const double uo = pu * ne / nobs;
+            const double vo = pv * ne / nobs;
+            const double p = e.photons;
+
+            // soft weights over candidate spheres
+            double g_xg = 0, g_yg = 0, g_uo = 0, g_vo = 0, g_t = 0, g_p = 0;
+            int cur = 0, cend = 0;
+            bool brute = false;
+            const double wo2 = 1.0 - uo * uo - vo * vo;
+            if (wo2 >= kGridWLo * kGridWLo + 1e-6) {
+                const double fx = (xg - sa.gx0) * sa.inv_cell, fy = (yg - sa.gy0) * sa.inv_cell;
+                if (fx >= 0.0 && fy >= 0.0 && fx < (double)sa.nx && fy < (double)sa.ny) {
+                    const int cidx = (int)fx * sa.ny + (int)fy;
+                    cur = sa.cell_off[cidx];
+                    cend = sa.cell_off[cidx + 1];
+                }
+            } else {
+                brute = true;
+                cend = a.n_tel;
+            }
+            for (; cur < cend; ++cur) {
+                const int kt = brute ? cur : (int)sa.cell_list[cur];
+                const double* tp = a.tel + 4 * kt;
+                const double dx = xg - tp[0], dy = yg - tp[1];
+                const double b = dx * uo + dy * vo;
+                const double rho2 = dx * dx + dy * dy - b * b;
+                const double R = tp[2];
+                const double z = (tp[3] - rho2) / (2.0 * R * sa.sigma);
+                if (z < -kSoftZCut) continue;
+                const double W = 0.5 * erfc(-z * inv_sqrt2);
+                if (MODE == 0) {
+                    atomicAdd(&acc[kt], p * W);
+                    atomicAdd(&acc[a.n_tel + kt], p * W * tt);
+                } else {
+                    const double gSk = sa.gS[(int64_t)s * a.n_tel + kt];
+                    const double gAk = sa.gA[(int64_t)s * a.n_tel + kt];
+                    g_p += gSk * W + gAk * W * tt;
+                    g_t += gAk * p * W;
+                    const double g_z = (gSk * p + gAk * p * tt) * inv_sqrt2pi * exp(-0.5 * z * z);
+                    const double g_r2 = -g_z / (2.0 * R * sa.sigma);
+                    g_xg += g_r2 * (2.0 * dx - 2.0 * b * uo);
+                    g_yg += g_r2 * (2.0 * dy - 2.0 * b * vo);
+                    g_uo += g_r2 * (-2.0 * b * dx);
+                    g_vo += g_r2 * (-2.0 * b * dy);
+                }
+            }
+            if (MODE == 1 && (g_xg != 0.0 || g_yg != 0.0 || g_uo != 0.0 || g_vo != 0.0 || g_t != 0.0 ||
+                              g_p != 0.0)) {
+                // ---- reverse through propagation
+                double g_pu = g_uo * ne / nobs + g_xg * Sser / pw;
+                double g_pv = g_vo * ne / nobs + g_yg * Sser / pw;
+                double g_ne = (g_uo * pu + g_vo * pv) / nobs;
+                g_psi0 += -(g_uo * pu + g_vo * pv) * ne / (nobs * nobs) / (2.0 * nobs);
+                const double g_T = g_t;
+                const double g_U = g_T * inv_c / (ne * pw);
+                g_ne += -g_T * T / ne;
+                double g_pw = -g_T * T / pw;
+                const double XS = g_xg * pu + g_yg * pv;
+                const double g_S = XS / pw;
+                g_pw += -XS * Sser / (pw * pw);
+                double gD[6] = {0, 0, 0, 0, 0, 0};
+                double g_q = 0.0;
+                for (int kk = 0; kk < 5; ++kk) {
+                    const double akq = ak[kk] * qk[kk];
+                    gD[kk] += g_S * akq + g_U * akq * ne2;
+                    gD[kk + 1] += g_U * akq;
+                    if (kk >= 1)
+                        g_q += (g_S * D[kk] + g_U * (ne2 * D[kk] + D[kk + 1])) * (double)kk * ak[kk] * qk[kk - 1];
+                }
+                double g_ne2 = g_U * Sser;
+                g_ne2 += -g_q * q / ne2;
+                g_pw += -2.0 * g_q * q / pw;
+                g_ne2 += g_ne / (2.0 * ne);
+                double g_psie = g_ne2;
+                for (int kk = 1; kk <= 5; ++kk) g_psie += -(double)kk * gD[kk] * D[kk - 1];
+                // dL/dP_j = sum_{k>=j} gD_k C(k,j) (-psi_e)^(k-j)
+                double g_pa = 0.0;
+                for (int jj = 1; jj <= 5; ++jj) {
+                    double gP = 0.0, binom = 1.0, cp_pow = 1.0;
+                    for (int kk = jj; kk <= 5; ++kk) {
+                        gP += gD[kk] * binom * cp_pow;
+                        binom = binom * (double)(kk + 1) / (double)(kk + 1 - jj);
+                        cp_pow *= cneg;
+                    }
+                    atomicAdd(&gP_l[(size_t)(jj - 1) * N + ie], gP);
+                    // partial-cell moment: dz/(j+1) h_j(pa, psi_e)
+                    double dha = 0.0, dhb = 0.0;
+                    for (int qq = 0; qq <= jj; ++qq) {
+                        if (jj - qq >= 1) dha += (double)(jj - qq) * pow_a[jj - qq - 1] * pow_b[qq];
+                        if (qq >= 1) dhb += (double)qq * pow_a[jj - qq] * pow_b[qq - 1];
+                    }
+                    const double wgt = dz / (double)(jj + 1);
+                    g_pa += gP * wgt * dha;
+                    g_psie += gP * wgt * dhb;
+                }
+                atomicAdd(&gpsi_l[ie], g_pa + (1.0 - fe) * g_psie);
+                atomicAdd(&gpsi_l[ie + 1], fe * g_psie);
+                // ---- reverse through the direction on the cone and the yield
+                const double g_cos = g_pu * e.u + g_pv * e.v + g_pw * e.w;
+                const double g_sin = g_pu * Ex + g_pv * Ey - g_pw * Ez;
+                atomicAdd(&e.g_cos, g_cos);
+                atomicAdd(&e.g_sin, g_sin);
+                atomicAdd(&e.g_phot, g_p);
+            }
+        }
+        wave_lds_sync();
+        if (MODE == 0) {
+            for (int kk = lane; kk < a.n_tel; kk += kWave) {
+                const double vs = acc[kk], va = acc[a.n_tel + kk];
+                if (vs != 0.0) atomicAdd(&sa.S[(int64_t)s * a.n_tel + kk], vs);
+                if (va != 0.0) atomicAdd(&sa.A[(int64_t)s * a.n_tel + kk], va);
+                acc[kk] = 0.0;
+                acc[a.n_tel + kk] = 0.0;
+            }
+        } else if (emits) {
+            // ---- reverse through the step setup (index at the step midpoint)
+            const SoftStep& es = stash[__popcll(emit_mask & lt_mask)];
+            const double sin2 = es.sin_t * es.sin_t;
+            double g_sin2 = es.g_phot * es.kl_nb;
+            if (sin2 > 0.0) g_sin2 += es.g_sin / (2.0 * es.sin_t);
+            // cos_t = g1^(-1/2), sin2 = 1 - 1/g1
+            const double g_g1 = -0.5 * es.g_cos * es.cos_t * es.cos_t * es.cos_t + g_sin2 / (es.g1 * es.g1);
+            const double g_psim = g_g1 * (1.0 - es.r2);
+            if (g_psim != 0.0) {
+                atomicAdd(&gpsi_l[es.i_m], (1.0 - es.f_m) * g_psim);
+                atomicAdd(&gpsi_l[es.i_m + 1], es.f_m * g_psim);
+            }
+        }
+        wave_lds_sync();
+    }
+    if (MODE == 1) {
+        if (g_psi0 != 0.0) atomicAdd(&gpsi_l[0], g_psi0);
+        __syncthreads();
+        for (int qq = threadIdx.x; qq < 6 * N; qq += blockDim.x) {
+            const double v = gpsi_l[qq];
+            if (v != 0.0) atomicAdd(qq < N ? &sa.g_psi[qq] : &sa.g_P[qq - N], v);
+        }
+    }
+}
+
+__global__ void zero_kernel(double* p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// --------------------------------------------------------------------------
 // host side
 // --------------------------------------------------------------------------
 namespace {
@@ -931,10 +1323,10 @@ Args make_args(const RunPlan& p)
     if (ar) {
         a.n_tel = ar->n_tel;
         a.tel = ar->d_tel;
-        a.gx0 = ar->gx0; a.gy0 = ar->gy0; a.inv_cell = ar->inv_cell;
-        a.nx = ar->nx; a.ny = ar->ny;
-        a.cell_off = ar->d_cell_off;
-        a.cell_list = ar->d_cell_list;
+        a.gx0 = ar->hit.gx0; a.gy0 = ar->hit.gy0; a.inv_cell = ar->hit.inv_cell;
+        a.nx = ar->hit.nx; a.ny = ar->hit.ny;
+        a.cell_off = ar->hit.d_cell_off;
+        a.cell_list = ar->hit.d_cell_list;
     }
     a.bunch_size = p.params.bunch_size;
     a.k_ft = p.k_ft;
@@ -1055,6 +1447,64 @@ int launch_run(RunPlan& p)
     if (int rc2 = check_launch("csr")) return rc2;
     scatter_kernel<<<4096, 256, 0, st>>>(a);
     return check_launch("scatter");
+}
+
+int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
+{
+    Args a = make_args(p);
+    hipStream_t st = p.stream;
+    const ckv_array* ar = p.arr;
+    SoftArgs s{};
+    s.nb_frozen = sp.n_b_frozen;
+    s.sigma = sp.sigma;
+    s.gS = sp.gS;
+    s.gA = sp.gA;
+    s.S = sp.S;
+    s.A = sp.A;
+    s.g_psi = sp.g_psi;
+    s.g_P = sp.g_P;
+    s.gx0 = ar->soft.gx0;
+    s.gy0 = ar->soft.gy0;
+    s.inv_cell = ar->soft.inv_cell;
+    s.nx = ar->soft.nx;
+    s.ny = ar->soft.ny;
+    s.cell_off = ar->soft.d_cell_off;
+    s.cell_list = ar->soft.d_cell_list;
+    const size_t lds = soft_bin_bytes(mode, a.n_nodes) + (size_t)kSoftWaves * soft_wave_bytes(a.n_tel);
+    if (lds > 160 * 1024) {
+        set_error("soft response: atmosphere table or telescope count too large for LDS");
+        return CKV_ERR_TABLE;
+    }
+    init_kernel<<<1, 1024, 0, st>>>(a);
+    if (int rc = check_launch("init")) return rc;
+    const int64_t nst = (int64_t)a.n_showers * a.n_tel;
+    if (mode == 0) {
+        zero_kernel<<<64, 256, 0, st>>>(s.S, nst);
+        zero_kernel<<<64, 256, 0, st>>>(s.A, nst);
+    } else {
+        zero_kernel<<<64, 256, 0, st>>>(s.g_psi, a.n_nodes);
+        zero_kernel<<<64, 256, 0, st>>>(s.g_P, (int64_t)5 * a.n_nodes);
+    }
+    if (int rc = check_launch("zero")) return rc;
+    if (p.params.event_begin) (void)hipEventRecord((hipEvent_t)p.params.event_begin, st);
+    if (mode == 0) {
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void*)soft_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        soft_kernel<0><<<p.emit_grid, kSoftWaves * kWave, lds, st>>>(a, s);
+    } else {
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void*)soft_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        soft_kernel<1><<<p.emit_grid, kSoftWaves * kWave, lds, st>>>(a, s);
+    }
+    if (int rc = check_launch("soft")) return rc;
+    if (p.params.event_end) (void)hipEventRecord((hipEvent_t)p.params.event_end, st);
+    return CKV_OK;
 }
 
 int launch_count(const ckv_segments* segs, const ckv_params* prm, const ckv_atmo* atmo, double k_ft,

@@ -74,13 +74,13 @@ int build_atmo_tables(const double* alt, const double* eta, int64_t n, double h_
     return CKV_OK;
 }
 
-int build_array_grid(ckv_array* arr)
+int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ckv_grid* g)
 {
     const int32_t n = arr->n_tel;
     double rmax = 0, xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
     for (int32_t k = 0; k < n; ++k) {
-        double reach = arr->r[k] / kGridWLo;
-        rmax = std::max(rmax, arr->r[k]);
+        double reach = radius[k] / kGridWLo;
+        rmax = std::max(rmax, radius[k]);
         xmin = std::min(xmin, arr->x[k] - reach);
         xmax = std::max(xmax, arr->x[k] + reach);
         ymin = std::min(ymin, arr->y[k] - reach);
@@ -92,16 +92,16 @@ int build_array_grid(ckv_array* arr)
     xmin -= margin; ymin -= margin;
     int32_t nx = (int32_t)std::ceil((xmax + margin - xmin) / cell) + 1;
     int32_t ny = (int32_t)std::ceil((ymax + margin - ymin) / cell) + 1;
-    arr->gx0 = xmin;
-    arr->gy0 = ymin;
-    arr->cell = cell;
-    arr->inv_cell = 1.0 / cell;
-    arr->nx = nx;
-    arr->ny = ny;
-    arr->cell_off.assign((size_t)nx * ny + 1, 0);
+    g->gx0 = xmin;
+    g->gy0 = ymin;
+    g->cell = cell;
+    g->inv_cell = 1.0 / cell;
+    g->nx = nx;
+    g->ny = ny;
+    g->cell_off.assign((size_t)nx * ny + 1, 0);
     std::vector<std::vector<uint16_t>> lists((size_t)nx * ny);
     for (int32_t k = 0; k < n; ++k) {
-        double reach = arr->r[k] / kGridWLo + margin;
+        double reach = radius[k] / kGridWLo + margin;
         int32_t ix0 = std::max(0, (int32_t)std::floor((arr->x[k] - reach - xmin) / cell));
         int32_t ix1 = std::min(nx - 1, (int32_t)std::floor((arr->x[k] + reach - xmin) / cell));
         int32_t iy0 = std::max(0, (int32_t)std::floor((arr->y[k] - reach - ymin) / cell));
@@ -116,14 +116,144 @@ int build_array_grid(ckv_array* arr)
                     lists[(size_t)ix * ny + iy].push_back((uint16_t)k);
             }
     }
-    arr->cell_list.clear();
+    g->cell_list.clear();
     for (size_t c = 0; c < lists.size(); ++c) {
-        arr->cell_off[c] = (int32_t)arr->cell_list.size();
-        arr->cell_list.insert(arr->cell_list.end(), lists[c].begin(), lists[c].end());
+        g->cell_off[c] = (int32_t)g->cell_list.size();
+        g->cell_list.insert(g->cell_list.end(), lists[c].begin(), lists[c].end());
     }
-    arr->cell_off[lists.size()] = (int32_t)arr->cell_list.size();
-    if (arr->cell_list.empty()) arr->cell_list.push_back(0);
+    g->cell_off[lists.size()] = (int32_t)g->cell_list.size();
+    if (g->cell_list.empty()) g->cell_list.push_back(0);
     return CKV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Parameterised atmosphere (differentiation pattern):
+//   log eta(h) = log eta0 - sum_l overlap([0, h], layer l) / H_l + Lambda(h),
+// Lambda the linear interpolant of knot values at h_j = j*knot_top/(n_knots-1),
+// constant above knot_top; the last layer extends upward.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct KnotPos {
+    int32_t j;
+    double f;
+};
+
+KnotPos knot_pos(const ckv_atmo_param_spec* sp, double h)
+{
+#pragma clang fp contract(off)
+    double hc = h < sp->knot_top_m ? h : sp->knot_top_m;
+    double dk = sp->knot_top_m / (double)(sp->n_knots - 1);
+    double x = hc / dk;
+    int32_t j = (int32_t)std::floor(x);
+    if (j > sp->n_knots - 2) j = sp->n_knots - 2;
+    if (j < 0) j = 0;
+    return {j, x - (double)j};
+}
+
+double layer_overlap(const ckv_atmo_param_spec* sp, int32_t l, double h)
+{
+#pragma clang fp contract(off)
+    double top = (l + 1 < sp->n_layers) ? sp->layer_bounds_m[l + 1] : INFINITY;
+    double hi = h < top ? h : top;
+    double over = hi - sp->layer_bounds_m[l];
+    return over > 0.0 ? over : 0.0;
+}
+
+double log_eta_param(const ckv_atmo_param_spec* sp, const double* theta, double h)
+{
+#pragma clang fp contract(off)
+    const double* knots = theta;
+    const double* H = theta + sp->n_knots;
+    double depth = 0.0;
+    for (int32_t l = 0; l < sp->n_layers; ++l) {
+        double over = layer_overlap(sp, l, h);
+        if (over > 0.0) depth += over / H[l];
+    }
+    KnotPos kp = knot_pos(sp, h);
+    double lam = knots[kp.j] + kp.f * (knots[kp.j + 1] - knots[kp.j]);
+    return std::log(sp->eta0) - depth + lam;
+}
+
+}  // namespace
+
+int param_spec_check(const ckv_atmo_param_spec* sp, const double* theta)
+{
+    if (!sp || !theta || !sp->layer_bounds_m) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    if (sp->n_layers < 1 || sp->n_layers > 64 || sp->n_knots < 2 || sp->n_knots > 4096) {
+        set_error("need 1 <= n_layers <= 64 and 2 <= n_knots <= 4096"); return CKV_ERR_ARG;
+    }
+    if (!(sp->eta0 > 0.0) || !(sp->knot_top_m > 0.0) || !(sp->step_m > 0.0) ||
+        !(sp->top_m > sp->obs_level_m) || !(sp->obs_level_m >= sp->layer_bounds_m[0])) {
+        set_error("parameterised atmosphere: bad eta0, knot_top, step or altitude range");
+        return CKV_ERR_ARG;
+    }
+    for (int32_t l = 0; l < sp->n_layers; ++l) {
+        if (!(sp->layer_bounds_m[l + 1] > sp->layer_bounds_m[l])) {
+            set_error("layer bounds must increase"); return CKV_ERR_ARG;
+        }
+        if (!(theta[sp->n_knots + l] > 0.0)) { set_error("scale heights must be > 0"); return CKV_ERR_ARG; }
+    }
+    for (int32_t j = 0; j < sp->n_knots + sp->n_layers; ++j)
+        if (!std::isfinite(theta[j])) { set_error("non-finite parameter"); return CKV_ERR_ARG; }
+    return CKV_OK;
+}
+
+void param_profile(const ckv_atmo_param_spec* sp, const double* theta, std::vector<double>* alt,
+                   std::vector<double>* eta)
+{
+    int64_t m = (int64_t)std::floor((sp->top_m - sp->obs_level_m) / sp->step_m) + 1;
+    alt->resize(m);
+    eta->resize(m);
+    for (int64_t i = 0; i < m; ++i) {
+        double h = sp->obs_level_m + (double)i * sp->step_m;
+        (*alt)[i] = h;
+        (*eta)[i] = std::exp(log_eta_param(sp, theta, h));
+    }
+}
+
+// Reverse of theta -> eta_i -> psi_i -> P_j(h_i):
+//   P_j(h_i) = sum_{m<i} c_j(psi_m, psi_{m+1}),  c_j(a, b) = step/(j+1) h_j(a, b),
+// so dL/dpsi_m collects suffix sums of dL/dP_j over the nodes above m.
+void param_backward(const ckv_atmo_param_spec* sp, const double* theta, const ckv_atmo* a,
+                    const double* g_psi, const double* g_P, double* g_theta)
+{
+    const int64_t m = a->n_nodes;
+    const double step = a->step;
+    std::vector<double> gpsi(g_psi, g_psi + m);
+    for (int j = 1; j <= 5; ++j) {
+        const double* gp = g_P + (size_t)(j - 1) * m;
+        double suffix = 0.0;                       // sum of g_P over nodes i >= c + 1
+        for (int64_t c = m - 2; c >= 0; --c) {
+            suffix += gp[c + 1];
+            const double lo = a->psi[c], hi = a->psi[c + 1];
+            // d h_j / d lo and d h_j / d hi
+            double dlo = 0.0, dhi = 0.0;
+            for (int q = 0; q <= j; ++q) {
+                if (j - q >= 1) dlo += (double)(j - q) * std::pow(lo, j - q - 1) * std::pow(hi, q);
+                if (q >= 1) dhi += (double)q * std::pow(lo, j - q) * std::pow(hi, q - 1);
+            }
+            const double w = step / (double)(j + 1);
+            gpsi[c] += suffix * w * dlo;
+            gpsi[c + 1] += suffix * w * dhi;
+        }
+    }
+    const int32_t nk = sp->n_knots, nl = sp->n_layers;
+    for (int32_t q = 0; q < nk + nl; ++q) g_theta[q] = 0.0;
+    const double* H = theta + nk;
+    for (int64_t i = 0; i < m; ++i) {
+        const double h = a->h_obs + (double)i * step;
+        const double eta = std::exp(log_eta_param(sp, theta, h));
+        // psi = eta (2 + eta): d psi / d log eta = eta (2 + 2 eta)
+        const double g_log = gpsi[i] * eta * (2.0 + 2.0 * eta);
+        KnotPos kp = knot_pos(sp, h);
+        g_theta[kp.j] += g_log * (1.0 - kp.f);
+        g_theta[kp.j + 1] += g_log * kp.f;
+        for (int32_t l = 0; l < nl; ++l) {
+            const double over = layer_overlap(sp, l, h);
+            if (over > 0.0) g_theta[nk + l] += g_log * over / (H[l] * H[l]);
+        }
+    }
 }
 
 }  // namespace ckv

@@ -358,3 +358,57 @@ def hadron_like(zenith_deg: float, n_seg: int = 50_000_000, shower: int = 0) -> 
     segs = shower_segments(shower, n_seg, atmo, zenith_deg=zenith_deg, xmax=550.0,
                            lateral_mean=60.0, muon_fraction=0.1)
     return Workload(f"hadron_like_{int(zenith_deg)}deg", atmo, telescopes_disk(), segs)
+
+
+# ----------------------------------------------------------------------------
+# differentiation workload: parameterised atmosphere, target from perturbed
+# parameters (common random numbers: same steps, same seed)
+# ----------------------------------------------------------------------------
+
+DIFF_LAYER_BOUNDS_M = tuple(1000.0 * b for b in (0, 2, 4, 7, 10, 15, 25, 40, 120))
+DIFF_BASE_SCALE_M = tuple(1000.0 * h for h in (9.5, 9.5, 8.5, 8.5, 6.4, 6.4, 6.4, 7.2))
+DIFF_N_KNOTS = 64
+DIFF_KNOT_TOP_M = 60_000.0
+
+
+@dataclasses.dataclass
+class DiffWorkload:
+    name: str
+    segs: Segments
+    tels: Telescopes
+    eta0: float
+    layer_bounds: np.ndarray
+    n_knots: int
+    knot_top: float
+    obs_level: float
+    step: float
+    top: float
+    theta0: np.ndarray          # 64 knots (log n-1 offsets), then 8 scale heights [m]
+    theta_target: np.ndarray
+    sigma: float = 0.5          # soft sphere edge [m]
+    bunch_size: float = 5.0
+    lambda_min: float = 300.0
+    lambda_max: float = 600.0
+    seed: int = METHOD_SEED
+
+
+def diff_showers(n_showers: int = 64, n_seg: int = 500_000, seed: int = 4927) -> DiffWorkload:
+    """Gamma-like showers at 20 deg, Xmax 400, cores uniform within 300 m of the
+    array centre; theta0 = (knots 0, base scale heights), target theta* with
+    knots 0.05 sin(2 pi j/16 + 0.3) and scale heights x (1 + 0.02 (-1)^l)."""
+    place = layered_atmosphere()
+    rng = np.random.default_rng(seed)
+    rc = 300.0 * np.sqrt(rng.uniform(size=n_showers))
+    ac = rng.uniform(0.0, 2 * math.pi, size=n_showers)
+    parts = [shower_segments(s, n_seg, place, zenith_deg=20.0, azimuth_deg=0.0,
+                             core=(rc[s] * math.cos(ac[s]), rc[s] * math.sin(ac[s])), xmax=400.0)
+             for s in range(n_showers)]
+    j = np.arange(DIFF_N_KNOTS)
+    l = np.arange(len(DIFF_BASE_SCALE_M))
+    base = np.array(DIFF_BASE_SCALE_M)
+    theta0 = np.concatenate([np.zeros(DIFF_N_KNOTS), base])
+    target = np.concatenate([0.05 * np.sin(2 * math.pi * j / 16.0 + 0.3),
+                             base * (1.0 + 0.02 * (-1.0) ** l)])
+    return DiffWorkload(f"diff_{n_showers}x{n_seg}", Segments.concat(parts), telescopes_disk(),
+                        ETA_SEA, np.array(DIFF_LAYER_BOUNDS_M), DIFF_N_KNOTS, DIFF_KNOT_TOP_M,
+                        2200.0, 50.0, 120_000.0, theta0, target)

@@ -1,0 +1,135 @@
+"""Differentiation: the soft telescope response and its gradient with respect to
+the atmosphere parameters (64 log(n-1) knots + 8 layer scale heights), through
+torch.autograd, against FP64 central finite differences of the oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_14927_amd import ckv, synth
+from paper_2006_14927_amd.objective import telescope_loss
+
+from gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+def np_loss(S, A, St, At):
+    mask = St >= 100.0
+    rel = (S - St) / (St + 10.0)
+    M = A / np.where(S > 0, S, 1.0)
+    Mt = At / np.where(St > 0, St, 1.0)
+    return float(np.sum(rel * rel) + np.sum(mask * (M - Mt) ** 2))
+
+
+class Oracle:
+    def __init__(self, dw):
+        self.dw = dw
+        self.spec = oracle.AtmoParamSpec(dw.eta0, dw.layer_bounds, dw.n_knots, dw.knot_top,
+                                         dw.obs_level, dw.step, dw.top)
+        cfg0 = self.cfg(dw.theta0)
+        self.nb = oracle.segment_details(cfg0, dw.segs)["n_b"].astype(np.int64)
+
+    def cfg(self, theta):
+        t = oracle.tables_from_params(self.spec, theta)
+        return oracle.Config(t, self.dw.tels.x, self.dw.tels.y, self.dw.tels.r, seed=self.dw.seed)
+
+    def SA(self, theta):
+        return oracle.soft(self.cfg(theta), self.dw.segs, self.nb, self.dw.sigma, nthreads=16)
+
+
+def gpu_model(dw):
+    spec = ckv.ParamSpec(dw.eta0, dw.layer_bounds, dw.n_knots, dw.knot_top, dw.obs_level, dw.step,
+                         dw.top)
+    return ckv.SoftModel(dw.segs, dw.tels, spec, dw.theta0, dw.sigma, seed=dw.seed)
+
+
+@pytest.fixture(scope="module")
+def small():
+    dw = synth.diff_showers(2, 5000)
+    return dw, Oracle(dw), gpu_model(dw)
+
+
+def test_parameterised_tables_and_frozen_counts(small):
+    dw, orc, model = small
+    psi, P = model.atmo0.tables()
+    t = oracle.tables_from_params(orc.spec, dw.theta0)
+    np.testing.assert_array_equal(psi, t.psi)
+    np.testing.assert_allclose(P, t.P, rtol=1e-13, atol=0)
+    np.testing.assert_array_equal(model.n_b.cpu().numpy(), orc.nb)
+
+
+@pytest.mark.parametrize("which", ["theta0", "target"])
+def test_soft_forward_matches_oracle(small, which):
+    import torch
+    dw, orc, model = small
+    th = dw.theta0 if which == "theta0" else dw.theta_target
+    S, A = model.forward(th)
+    torch.cuda.synchronize()
+    So, Ao = orc.SA(th)
+    assert So.sum() > 1e3 and (So > 100).sum() >= 4
+    np.testing.assert_allclose(S.cpu().numpy(), So, rtol=1e-10, atol=1e-12 * So.max())
+    np.testing.assert_allclose(A.cpu().numpy(), Ao, rtol=1e-10, atol=1e-12 * np.abs(Ao).max())
+
+
+def test_gradient_matches_oracle_finite_differences(small):
+    """All 72 coordinates: Richardson-extrapolated central differences of the
+    FP64 oracle loss, (4 D(h) - D(2h)) / 3 (plain central differences at
+    h = 1e-4 still carry ~1e-4 relative truncation error here)."""
+    import torch
+    dw, orc, model = small
+    St_o, At_o = orc.SA(dw.theta_target)
+    St, At = model.forward(dw.theta_target)
+    theta = torch.tensor(dw.theta0, dtype=torch.float64, requires_grad=True)
+    S, A = ckv.soft_response(theta, model)
+    L = telescope_loss(S, A, St, At)
+    L.backward()
+    g = theta.grad.numpy().copy()
+    assert np.isfinite(g).all()
+    L_o0 = np_loss(*orc.SA(dw.theta0), St_o, At_o)
+    assert float(L.detach()) == pytest.approx(L_o0, rel=1e-9)
+
+    def central(j, step):
+        tp, tm = dw.theta0.copy(), dw.theta0.copy()
+        tp[j] += step
+        tm[j] -= step
+        return (np_loss(*orc.SA(tp), St_o, At_o) - np_loss(*orc.SA(tm), St_o, At_o)) / (2 * step)
+
+    fd = np.zeros_like(g)
+    for j in range(len(g)):
+        step = 1e-4 if j < dw.n_knots else 1e-4 * dw.theta0[j]
+        fd[j] = (4.0 * central(j, step) - central(j, 2 * step)) / 3.0
+    floor = 1e-3 * np.abs(fd).max()
+    err = np.abs(g - fd) / np.maximum(np.abs(fd), floor)
+    say(f"[gpu] grad vs oracle FD: max rel err {err.max():.2e} (|g|max {np.abs(g).max():.3e})")
+    assert np.abs(fd).max() > 0
+    assert err.max() <= 1e-5, (np.argsort(-err)[:5], err[np.argsort(-err)[:5]])
+
+
+def test_directional_derivative_larger_instance():
+    """8 showers x 2e4 steps: gradient . v against central differences of the
+    FP64 response along 4 random directions v."""
+    import torch
+    dw = synth.diff_showers(8, 20000)
+    model = gpu_model(dw)
+    St, At = model.forward(dw.theta_target)
+    theta = torch.tensor(dw.theta0, dtype=torch.float64, requires_grad=True)
+    S, A = ckv.soft_response(theta, model)
+    telescope_loss(S, A, St, At).backward()
+    g = theta.grad.numpy()
+    rng = np.random.default_rng(7)
+    scale = np.concatenate([np.full(dw.n_knots, 1.0), dw.theta0[dw.n_knots:]])
+    for _ in range(4):
+        v = rng.normal(size=g.shape) * scale
+        h = 1e-4
+
+        def L_at(th):
+            S_, A_ = model.forward(th)
+            return float(telescope_loss(S_, A_, St, At))
+
+        def central(hh):
+            return (L_at(dw.theta0 + hh * v) - L_at(dw.theta0 - hh * v)) / (2 * hh)
+
+        fd = (4.0 * central(h) - central(2 * h)) / 3.0
+        say(f"[gpu] directional: g.v={g @ v:.10e} fd={fd:.10e}")
+        assert g @ v == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(g * v).sum())
