@@ -168,6 +168,56 @@ def time_path(hip, ckv, dsegs, atmo, tels, params, capacity, steps, warmup, stre
     return total_ms / steps, sum(kern_ms) / len(kern_ms), out.result()
 
 
+def diff_timing(hip, reps: int, n_showers: int = 64, n_seg: int = 500_000):
+    """Forward + backward of the soft telescope response on the differentiation
+    workload (64 showers x 5e5 steps); returns ms per shower and kernel times."""
+    import torch
+
+    from paper_2006_14927_amd import ckv, synth
+    from paper_2006_14927_amd.objective import telescope_loss
+    dw = synth.diff_showers(n_showers, n_seg)
+    spec = ckv.ParamSpec(dw.eta0, dw.layer_bounds, dw.n_knots, dw.knot_top, dw.obs_level, dw.step,
+                         dw.top)
+    model = ckv.SoftModel(dw.segs, dw.tels, spec, dw.theta0, dw.sigma, seed=dw.seed)
+    St, At = model.forward(dw.theta_target)
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+
+    def step(events=None):
+        theta = torch.tensor(dw.theta0, dtype=torch.float64, requires_grad=True)
+        if events:
+            model.params.event_begin, model.params.event_end = events[0].value, events[1].value
+        S, A = ckv.soft_response(theta, model)
+        loss = telescope_loss(S, A, St, At)
+        if events:
+            model.params.event_begin, model.params.event_end = events[2].value, events[3].value
+        loss.backward()
+        model.params.event_begin = model.params.event_end = None
+        return theta.grad
+
+    step()
+    torch.cuda.synchronize()
+    walls, fwd, bwd = [], [], []
+    for _ in range(reps):
+        ev = [_event(hip) for _ in range(4)]
+        t0 = time.perf_counter()
+        g = step(ev)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+        fwd.append(_elapsed_ms(hip, ev[0], ev[1]))
+        bwd.append(_elapsed_ms(hip, ev[2], ev[3]))
+        for e in ev:
+            hip.hipEventDestroy(e)
+    nb = int(model.n_b.sum())
+    if not bool(torch.isfinite(g).all()):
+        raise RuntimeError("differentiation: non-finite gradient")
+    wall = sorted(walls)[len(walls) // 2]
+    return {"workload": dw.name, "showers": n_showers, "steps": dw.segs.n, "bunches": nb,
+            "ms_per_shower": wall / n_showers, "fwd_kernel_ms": sum(fwd) / len(fwd),
+            "bwd_kernel_ms": sum(bwd) / len(bwd), "wall_ms": wall,
+            "grad_norm": float(g.norm())}
+
+
 def cpu_baseline(wl, target_cpu_seconds: float = 20.0):
     """The FP64 oracle on an evenly spaced sample of the shower's steps."""
     import numpy as np
@@ -199,6 +249,9 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-diff", action="store_true",
+                    help="skip the forward+backward timing of the differentiation workload")
+    ap.add_argument("--diff-reps", type=int, default=3)
     ap.add_argument("--no-tune-cache", action="store_true",
                     help="re-run the launch-shape autotuner instead of using its cache")
     ap.add_argument("--segments", type=int, default=2_000_000,
@@ -307,6 +360,13 @@ def main(argv=None):
         "fwd_bwd_ms_per_shower": None,
         "cpu_baseline": None,
     }
+    if not args.no_diff:
+        del dsegs
+        torch.cuda.empty_cache()
+        d = diff_timing(hip, args.diff_reps)
+        print(f"# differentiation: {d}", file=sys.stderr, flush=True)
+        line["fwd_bwd_ms_per_shower"] = d["ms_per_shower"]
+        line["differentiation"] = d
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

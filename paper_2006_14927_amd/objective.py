@@ -12,8 +12,13 @@ the expensive part, (S, A) and their gradients, runs in the HIP library.
 def telescope_loss(S, A, S_target, A_target, count_floor=10.0, time_scale_ns=1.0,
                    min_photons=100.0):
     import torch
-    mask = (S_target >= min_photons).to(S.dtype)
     rel = (S - S_target) / (S_target + count_floor)
-    M = A / torch.where(S > 0, S, torch.ones_like(S))
-    Mt = A_target / torch.where(S_target > 0, S_target, torch.ones_like(S_target))
-    return (rel * rel).sum() + (mask * ((M - Mt) / time_scale_ns) ** 2).sum()
+    # mean times only where the target sees enough light; the divisions are
+    # masked before they happen, so a tiny S elsewhere cannot turn the gradient
+    # into 0 * inf
+    use = (S_target >= min_photons) & (S > 0)
+    one = torch.ones_like(S)
+    M = A / torch.where(use, S, one)
+    Mt = A_target / torch.where(use, S_target, one)
+    dt = torch.where(use, (M - Mt) / time_scale_ns, torch.zeros_like(S))
+    return (rel * rel).sum() + (dt * dt).sum()

@@ -15,11 +15,11 @@ pytestmark = pytest.mark.gpu
 
 
 def np_loss(S, A, St, At):
-    mask = St >= 100.0
+    use = (St >= 100.0) & (S > 0)
     rel = (S - St) / (St + 10.0)
-    M = A / np.where(S > 0, S, 1.0)
-    Mt = At / np.where(St > 0, St, 1.0)
-    return float(np.sum(rel * rel) + np.sum(mask * (M - Mt) ** 2))
+    M = A / np.where(use, S, 1.0)
+    Mt = At / np.where(use, St, 1.0)
+    return float(np.sum(rel * rel) + np.sum(np.where(use, M - Mt, 0.0) ** 2))
 
 
 class Oracle:
