@@ -511,28 +511,26 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                     }
                     const T psi_e = psi_i + f * dpsi;
                     const T dz = f * (T)a.step;
-                    // partial-cell moments: P_j += dz/(j+1) * sum_m psi_i^(j-m) psi_e^m
-                    const T b_2 = psi_e * psi_e, b_3 = b_2 * psi_e, b_4 = b_3 * psi_e, b_5 = b_4 * psi_e;
-                    const T h1 = psi_i + psi_e;
-                    const T h2 = psi_i * h1 + b_2;
-                    const T h3 = psi_i * h2 + b_3;
-                    const T h4 = psi_i * h3 + b_4;
-                    const T h5 = psi_i * h4 + b_5;
-                    const T Q1 = P1 + dz * h1 * (T)0.5;
-                    const T Q2 = P2 + dz * h2 * (T)(1.0 / 3.0);
-                    const T Q3 = P3 + dz * h3 * (T)0.25;
-                    const T Q4 = P4 + dz * h4 * (T)0.2;
-                    const T Q5 = P5 + dz * h5 * (T)(1.0 / 6.0);
-                    // D_k = int (psi - psi_e)^k dh = sum_j C(k,j) (-psi_e)^(k-j) P_j
+                    // D_k = int_{h_obs}^{h_e} (psi - psi_e)^k dh, k = 1..5, split at the
+                    // cell's lower node h_i: below it, the node moments shifted to psi_e,
+                    // sum_j C(k,j) (-psi_e)^(k-j) P_j(h_i) (Pascal-triangle shift);
+                    // inside the cell, psi is linear from psi_i to psi_e, so the rest
+                    // is dz (psi_i - psi_e)^k / (k+1).
                     const double dh = he - a.h_obs;
-                    const T dhT = (T)dh;
-                    const T c1 = -psi_e, c2 = c1 * c1, c3 = c2 * c1, c4 = c3 * c1, c5 = c4 * c1;
-                    const T D1 = Q1 + c1 * dhT;
-                    const T D2 = Q2 + (T)2 * c1 * Q1 + c2 * dhT;
-                    const T D3 = Q3 + (T)3 * c1 * Q2 + (T)3 * c2 * Q1 + c3 * dhT;
-                    const T D4 = Q4 + (T)4 * c1 * Q3 + (T)6 * c2 * Q2 + (T)4 * c3 * Q1 + c4 * dhT;
-                    const T D5 = Q5 + (T)5 * c1 * Q4 + (T)10 * c2 * Q3 + (T)10 * c3 * Q2 +
-                                 (T)5 * c4 * Q1 + c5 * dhT;
+                    const T c1 = -psi_e;
+                    T X0 = (T)((double)ci * a.step), X1 = P1, X2 = P2, X3 = P3, X4 = P4, X5 = P5;
+                    X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2; X2 += c1 * X1; X1 += c1 * X0;
+                    X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2; X2 += c1 * X1;
+                    X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2;
+                    X5 += c1 * X4; X4 += c1 * X3;
+                    X5 += c1 * X4;
+                    const T del = -f * dpsi;               // psi_i - psi_e
+                    const T del2 = del * del, del3 = del2 * del, del4 = del3 * del, del5 = del4 * del;
+                    const T D1 = X1 + dz * (T)0.5 * del;
+                    const T D2 = X2 + dz * (T)(1.0 / 3.0) * del2;
+                    const T D3 = X3 + dz * (T)0.25 * del3;
+                    const T D4 = X4 + dz * (T)0.2 * del4;
+                    const T D5 = X5 + dz * (T)(1.0 / 6.0) * del5;
                     // index at emission: n_e = 1 + delta_e
                     const T ne2 = (T)1 + psi_e;
                     double ne, inv_w;
@@ -544,7 +542,7 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                         q = (T)1 / (ne2 * (T)(pw * pw));
                         inv_ne = (T)(1.0 / ne);
                     } else {
-                        const float de = (float)psi_e * __builtin_amdgcn_rcpf(1.0f + __builtin_sqrtf(1.0f + (float)psi_e));
+                        const float de = (float)psi_e * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_sqrtf(1.0f + (float)psi_e));
                         ne = 1.0 + (double)de;
                         ratio = 1.0f + (de - d_obs) * inv_1pdobs;
                         // reciprocal of w with two Newton steps (FP64-accurate)
