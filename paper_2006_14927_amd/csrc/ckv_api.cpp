@@ -21,6 +21,14 @@ int hip_fail(const char* what, hipError_t e)
     return CKV_ERR_HIP;
 }
 
+int device_cu_count(int* n_cu)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    return e == hipSuccess ? CKV_OK : hip_fail("device query", e);
+}
+
 template <typename T>
 int upload(const T* host, size_t count, T** dev)
 {
@@ -207,8 +215,8 @@ int ckv_atmo_tables(const ckv_atmo* a, double* psi, double* P)
 int ckv_atmo_destroy(ckv_atmo* a)
 {
     if (!a) return CKV_OK;
-    if (a->d_node64) hipFree(a->d_node64);
-    if (a->d_cell32) hipFree(a->d_cell32);
+    if (a->d_node64) (void)hipFree(a->d_node64);
+    if (a->d_cell32) (void)hipFree(a->d_cell32);
     delete a;
     return CKV_OK;
 }
@@ -224,8 +232,8 @@ static int upload_grid(ckv_grid* g)
 
 static void free_grid(ckv_grid* g)
 {
-    if (g->d_cell_off) hipFree(g->d_cell_off);
-    if (g->d_cell_list) hipFree(g->d_cell_list);
+    if (g->d_cell_off) (void)hipFree(g->d_cell_off);
+    if (g->d_cell_list) (void)hipFree(g->d_cell_list);
     g->d_cell_off = nullptr;
     g->d_cell_list = nullptr;
 }
@@ -256,8 +264,11 @@ static int array_create(const double* x_m, const double* y_m, const double* r_m,
             reff[k] = std::sqrt(r_m[k] * r_m[k] + 2.0 * r_m[k] * sigma * kSoftZCut) * (1.0 + 1e-9);
         rc = build_array_grid(arr, reff, &arr->soft);
     }
-    if (rc) { delete arr; return rc; }
-    hipGetDevice(&arr->device);
+    if (!rc) {
+        const hipError_t e = hipGetDevice(&arr->device);
+        if (e != hipSuccess) rc = hip_fail("hipGetDevice", e);
+    }
+    if (rc) { ckv_array_destroy(arr); return rc; }
     std::vector<double> tel(4 * (size_t)n_tel);
     for (int32_t k = 0; k < n_tel; ++k) {
         tel[4 * k] = x_m[k];
@@ -290,7 +301,7 @@ int ckv_array_create_soft(const double* x_m, const double* y_m, const double* r_
 int ckv_array_destroy(ckv_array* arr)
 {
     if (!arr) return CKV_OK;
-    if (arr->d_tel) hipFree(arr->d_tel);
+    if (arr->d_tel) (void)hipFree(arr->d_tel);
     free_grid(&arr->hit);
     free_grid(&arr->soft);
     delete arr;
@@ -334,11 +345,7 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
     plan.stream = (hipStream_t)stream;
     plan.k_ft = frank_tamm_k(params->lambda_min_nm, params->lambda_max_nm);
     int n_cu = 256;
-    {
-        int dev = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    }
+    if (int rc = device_cu_count(&n_cu)) return rc;
     plan.emit_grid = params->grid > 0 ? params->grid : std::min(n_cu, kMaxEmitGrid);
     plan.emit_waves = params->waves_per_group > 0 ? params->waves_per_group : kMaxEmitWaves;
     return launch_run(plan);
@@ -371,11 +378,7 @@ static int soft_common(const ckv_segments* segs, const ckv_showers* showers,
     plan->stream = (hipStream_t)stream;
     plan->k_ft = frank_tamm_k(params->lambda_min_nm, params->lambda_max_nm);
     int n_cu = 256;
-    {
-        int dev = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    }
+    if (int rc = device_cu_count(&n_cu)) return rc;
     plan->emit_grid = params->grid > 0 ? params->grid : std::min(n_cu, kMaxEmitGrid);
     plan->emit_waves = 4;
     return CKV_OK;
@@ -439,7 +442,10 @@ static int atmo_create(const double* alt_m, const double* eta, int64_t n, double
     int rc = build_atmo_tables(alt_m, eta, n, obs_level_m, step_m, a);
     if (rc) { delete a; return rc; }
     if (a->n_nodes > (1 << 20)) { delete a; set_error("atmosphere table too fine"); return CKV_ERR_TABLE; }
-    hipGetDevice(&a->device);
+    {
+        const hipError_t e = hipGetDevice(&a->device);
+        if (e != hipSuccess) { delete a; return hip_fail("hipGetDevice", e); }
+    }
     const int64_t m = a->n_nodes;
     std::vector<double> node(m * kNode64);
     for (int64_t i = 0; i < m; ++i) {
@@ -452,7 +458,7 @@ static int atmo_create(const double* alt_m, const double* eta, int64_t n, double
         c[0] = (float)a->psi[i];
         c[1] = (float)(a->psi[i + 1] - a->psi[i]);
         for (int j = 0; j < 5; ++j) c[2 + j] = (float)a->P[j * m + i];
-        c[7] = 0.0f;
+        c[7] = (float)((double)i * a->step);   // node height above the observation level
     }
     if ((rc = upload(node.data(), node.size(), &a->d_node64)) ||
         (rc = upload(cell.data(), cell.size(), &a->d_cell32))) {

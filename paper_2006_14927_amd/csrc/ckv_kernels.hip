@@ -322,6 +322,8 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
     const double inv_c = 1.0 / kSpeedOfLight;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t le_mask = lt_mask | (1ull << lane);
+    const float step32 = __builtin_bit_cast(
+        float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, (float)a.step)));
     // n - 1 at the observation level, for the observed direction
     const float d_obs = (float)(a.n_obs - 1.0);
     const float inv_1pdobs = 1.0f / (1.0f + d_obs);
@@ -427,9 +429,10 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
 
             bool alive = false;
             int drop_why = -1;
-            double xg = 0, yg = 0, he = 0, tarr = 0;
-            float uo = 0, vo = 0, lam = 0, photons = 0, he_f = 0, t_f = 0;
-            int32_t k = 0, sidx = 0;
+            // read only in lanes that emit a live bunch: left undefined elsewhere
+            double xg, yg, he, tarr;
+            float uo, vo, lam, photons, he_f, t_f;
+            int32_t k, sidx;
             if (active) {
                 const Entry& e = stash[si];
                 k = j - e.boff;
@@ -497,28 +500,31 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                     int ci = (int)x;
                     ci = min(ci, a.n_nodes - 2);
                     const T f = (T)(x - (double)ci);
-                    T psi_i, dpsi, P1, P2, P3, P4, P5;
+                    T psi_i, dpsi, P0, P1, P2, P3, P4, P5;
                     if (PREC == 0) {
                         const double* nd = tab64 + (size_t)kNode64 * ci;
                         psi_i = nd[0];
                         dpsi = nd[kNode64] - nd[0];
+                        P0 = (double)ci * a.step;
                         P1 = nd[1]; P2 = nd[2]; P3 = nd[3]; P4 = nd[4]; P5 = nd[5];
                     } else {
                         const float4* cc = reinterpret_cast<const float4*>(tab32 + (size_t)kCell32 * ci);
                         const float4 c_a = cc[0], c_b = cc[1];
                         psi_i = c_a.x; dpsi = c_a.y; P1 = c_a.z; P2 = c_a.w;
                         P3 = c_b.x; P4 = c_b.y; P5 = c_b.z;
+                        P0 = c_b.w;
                     }
                     const T psi_e = psi_i + f * dpsi;
-                    const T dz = f * (T)a.step;
+                    const T dz = f * (PREC == 0 ? (T)a.step : (T)step32);
                     // D_k = int_{h_obs}^{h_e} (psi - psi_e)^k dh, k = 1..5, split at the
                     // cell's lower node h_i: below it, the node moments shifted to psi_e,
-                    // sum_j C(k,j) (-psi_e)^(k-j) P_j(h_i) (Pascal-triangle shift);
+                    // sum_j C(k,j) (-psi_e)^(k-j) P_j(h_i) with P_0(h_i) = h_i - h_obs
+                    // (Pascal-triangle shift);
                     // inside the cell, psi is linear from psi_i to psi_e, so the rest
                     // is dz (psi_i - psi_e)^k / (k+1).
                     const double dh = he - a.h_obs;
                     const T c1 = -psi_e;
-                    T X0 = (T)((double)ci * a.step), X1 = P1, X2 = P2, X3 = P3, X4 = P4, X5 = P5;
+                    T X0 = P0, X1 = P1, X2 = P2, X3 = P3, X4 = P4, X5 = P5;
                     X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2; X2 += c1 * X1; X1 += c1 * X0;
                     X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2; X2 += c1 * X1;
                     X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2;
@@ -583,11 +589,13 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                     wcnt[kWcDrop0 + CKV_DROP_GRAZING] += d3;
                 }
             }
-            const double uod = (double)uo, vod = (double)vo;
             // ---- candidate spheres (ascending telescope index)
             int cur = 0, cend = 0;
             bool brute = false;
+            double uod, vod;
             if (alive) {
+                uod = (double)uo;
+                vod = (double)vo;
                 const double wo2 = 1.0 - uod * uod - vod * vod;
                 if (wo2 >= kGridWLo * kGridWLo + 1e-6) {
                     const double fx = (xg - a.gx0) * a.inv_cell, fy = (yg - a.gy0) * a.inv_cell;
