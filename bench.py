@@ -42,8 +42,7 @@ OPS_MIXED = {
     "wavelength (inverse CDF, rcp)": 2,
     "drop tests": 4,
     "table index (FP64 -> cell, fraction)": 7,
-    "partial-cell moments P1..P5 (FP32)": 21,
-    "moment transform D1..D5 (FP32)": 34,
+    "moments about psi_e, D1..D5: node moments shifted (15 FMA) + in-cell closed form (16)": 31,
     "index at emission, n_e / n_obs": 9,
     "1/w (FP64 rcp + 2 Newton steps)": 5,
     "series variable q": 5,
@@ -63,8 +62,7 @@ OPS_FP64 = {
     "wavelength (FP64 divide)": 9,
     "drop tests": 4,
     "table index": 6,
-    "partial-cell moments P1..P5": 21,
-    "moment transform D1..D5": 34,
+    "moments about psi_e, D1..D5: node shift + in-cell closed form": 31,
     "index at emission (FP64 sqrt, divide)": 16,
     "1/w (FP64 divide)": 8,
     "series variable q (FP64 divide)": 11,

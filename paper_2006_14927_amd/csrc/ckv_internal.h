@@ -25,7 +25,11 @@ constexpr int kStageBlock = 256;       // staging slots a wave claims at once
 constexpr int kMaxEmitGrid = 512;      // bound on bunch-kernel workgroups (workspace sizing)
 constexpr int kMaxEmitWaves = 16;     // waves per bunch-kernel workgroup
 constexpr int kRowBlock = 64;          // tiles per block of the per-telescope scan
-constexpr double kGridWLo = 0.2;       // candidate grid valid for observed w >= this
+// Candidate grids are stacked in levels; level l lists, per cell, the spheres a
+// line through the cell with observed w >= kGridWLevel[l] can meet (reach R/w).
+constexpr int kGridLevels = 3;
+constexpr double kGridWLevel[kGridLevels] = {0.2, 0.5, 0.85};
+constexpr double kGridWLo = kGridWLevel[0];  // below it every sphere is tested
 
 // Layout of one cell of the FP32 table: psi_i, psi_{i+1}-psi_i, P1_i..P5_i, 0.
 constexpr int kCell32 = 8;
@@ -79,7 +83,8 @@ struct ckv_atmo {
 struct ckv_grid {
     double gx0 = 0, gy0 = 0, cell = 1, inv_cell = 1;
     int32_t nx = 0, ny = 0;
-    std::vector<int32_t> cell_off;   // nx*ny + 1
+    int32_t level_cells = 0;         // nx*ny
+    std::vector<int32_t> cell_off;   // kGridLevels*nx*ny + 1, level-major
     std::vector<uint16_t> cell_list;
     int32_t* d_cell_off = nullptr;
     uint16_t* d_cell_list = nullptr;

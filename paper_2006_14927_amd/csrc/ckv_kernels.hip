@@ -49,7 +49,7 @@ struct Args {
     int32_t n_tel;
     const double* tel;          // X, Y, R, R^2
     double gx0, gy0, inv_cell;
-    int32_t nx, ny;
+    int32_t nx, ny, level_cells;
     const int32_t* cell_off;
     const uint16_t* cell_list;
     // parameters
@@ -115,6 +115,19 @@ template <typename T>
 __device__ __forceinline__ T uniform(T x)
 {
     return __shfl(x, 0);
+}
+
+// Candidate-grid level for a line with observed w^2 = wo2 (>= kLevelW2[0]):
+// the deepest level whose w floor the line clears, with a 1e-6 margin that
+// covers the rounding of wo2.
+constexpr double kLevelW2[kGridLevels] = {
+    kGridWLevel[0] * kGridWLevel[0] + 1e-6, kGridWLevel[1] * kGridWLevel[1] + 1e-6,
+    kGridWLevel[2] * kGridWLevel[2] + 1e-6};
+static_assert(kGridLevels == 3, "grid_level selects among three levels");
+
+__device__ __forceinline__ int grid_level(double wo2)
+{
+    return wo2 >= kLevelW2[2] ? 2 : (wo2 >= kLevelW2[1] ? 1 : 0);
 }
 
 // --------------------------------------------------------------------------
@@ -597,10 +610,10 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                 uod = (double)uo;
                 vod = (double)vo;
                 const double wo2 = 1.0 - uod * uod - vod * vod;
-                if (wo2 >= kGridWLo * kGridWLo + 1e-6) {
+                if (wo2 >= kLevelW2[0]) {
                     const double fx = (xg - a.gx0) * a.inv_cell, fy = (yg - a.gy0) * a.inv_cell;
                     if (fx >= 0.0 && fy >= 0.0 && fx < (double)a.nx && fy < (double)a.ny) {
-                        const int cidx = (int)fx * a.ny + (int)fy;
+                        const int cidx = grid_level(wo2) * a.level_cells + (int)fx * a.ny + (int)fy;
                         cur = a.cell_off[cidx];
                         cend = a.cell_off[cidx + 1];
                     }
@@ -929,7 +942,7 @@ struct SoftArgs {
     double* g_psi;
     double* g_P;
     double gx0, gy0, inv_cell;
-    int32_t nx, ny;
+    int32_t nx, ny, level_cells;
     const int32_t* cell_off;
     const uint16_t* cell_list;
 };
@@ -1165,10 +1178,10 @@ __global__ void __launch_bounds__(256) soft_kernel(Args a, SoftArgs sa)
             int cur = 0, cend = 0;
             bool brute = false;
             const double wo2 = 1.0 - uo * uo - vo * vo;
-            if (wo2 >= kGridWLo * kGridWLo + 1e-6) {
+            if (wo2 >= kLevelW2[0]) {
                 const double fx = (xg - sa.gx0) * sa.inv_cell, fy = (yg - sa.gy0) * sa.inv_cell;
                 if (fx >= 0.0 && fy >= 0.0 && fx < (double)sa.nx && fy < (double)sa.ny) {
-                    const int cidx = (int)fx * sa.ny + (int)fy;
+                    const int cidx = grid_level(wo2) * sa.level_cells + (int)fx * sa.ny + (int)fy;
                     cur = sa.cell_off[cidx];
                     cend = sa.cell_off[cidx + 1];
                 }
@@ -1330,7 +1343,7 @@ Args make_args(const RunPlan& p)
         a.n_tel = ar->n_tel;
         a.tel = ar->d_tel;
         a.gx0 = ar->hit.gx0; a.gy0 = ar->hit.gy0; a.inv_cell = ar->hit.inv_cell;
-        a.nx = ar->hit.nx; a.ny = ar->hit.ny;
+        a.nx = ar->hit.nx; a.ny = ar->hit.ny; a.level_cells = ar->hit.level_cells;
         a.cell_off = ar->hit.d_cell_off;
         a.cell_list = ar->hit.d_cell_list;
     }
@@ -1474,6 +1487,7 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     s.inv_cell = ar->soft.inv_cell;
     s.nx = ar->soft.nx;
     s.ny = ar->soft.ny;
+    s.level_cells = ar->soft.level_cells;
     s.cell_off = ar->soft.d_cell_off;
     s.cell_list = ar->soft.d_cell_list;
     const size_t lds = soft_bin_bytes(mode, a.n_nodes) + (size_t)kSoftWaves * soft_wave_bytes(a.n_tel);

@@ -79,7 +79,7 @@ int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ck
     const int32_t n = arr->n_tel;
     double rmax = 0, xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
     for (int32_t k = 0; k < n; ++k) {
-        double reach = radius[k] / kGridWLo;
+        double reach = radius[k] / kGridWLevel[0];
         rmax = std::max(rmax, radius[k]);
         xmin = std::min(xmin, arr->x[k] - reach);
         xmax = std::max(xmax, arr->x[k] + reach);
@@ -88,7 +88,7 @@ int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ck
     }
     double extent = std::max(xmax - xmin, ymax - ymin);
     double margin = 0.01 + 1e-9 * extent;
-    double cell = std::max(2.0 * rmax, extent / 1024.0);
+    double cell = std::max(rmax, extent / 512.0);
     xmin -= margin; ymin -= margin;
     int32_t nx = (int32_t)std::ceil((xmax + margin - xmin) / cell) + 1;
     int32_t ny = (int32_t)std::ceil((ymax + margin - ymin) / cell) + 1;
@@ -98,24 +98,27 @@ int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ck
     g->inv_cell = 1.0 / cell;
     g->nx = nx;
     g->ny = ny;
-    g->cell_off.assign((size_t)nx * ny + 1, 0);
-    std::vector<std::vector<uint16_t>> lists((size_t)nx * ny);
-    for (int32_t k = 0; k < n; ++k) {
-        double reach = radius[k] / kGridWLo + margin;
-        int32_t ix0 = std::max(0, (int32_t)std::floor((arr->x[k] - reach - xmin) / cell));
-        int32_t ix1 = std::min(nx - 1, (int32_t)std::floor((arr->x[k] + reach - xmin) / cell));
-        int32_t iy0 = std::max(0, (int32_t)std::floor((arr->y[k] - reach - ymin) / cell));
-        int32_t iy1 = std::min(ny - 1, (int32_t)std::floor((arr->y[k] + reach - ymin) / cell));
-        for (int32_t ix = ix0; ix <= ix1; ++ix)
-            for (int32_t iy = iy0; iy <= iy1; ++iy) {
-                // distance from the centre to the cell rectangle
-                double cx0 = xmin + ix * cell, cy0 = ymin + iy * cell;
-                double dx = std::max({cx0 - arr->x[k], 0.0, arr->x[k] - (cx0 + cell)});
-                double dy = std::max({cy0 - arr->y[k], 0.0, arr->y[k] - (cy0 + cell)});
-                if (dx * dx + dy * dy <= reach * reach)
-                    lists[(size_t)ix * ny + iy].push_back((uint16_t)k);
-            }
-    }
+    g->level_cells = nx * ny;
+    const size_t n_cells = (size_t)nx * ny;
+    g->cell_off.assign(kGridLevels * n_cells + 1, 0);
+    std::vector<std::vector<uint16_t>> lists(kGridLevels * n_cells);
+    for (int lv = 0; lv < kGridLevels; ++lv)
+        for (int32_t k = 0; k < n; ++k) {
+            double reach = radius[k] / kGridWLevel[lv] + margin;
+            int32_t ix0 = std::max(0, (int32_t)std::floor((arr->x[k] - reach - xmin) / cell));
+            int32_t ix1 = std::min(nx - 1, (int32_t)std::floor((arr->x[k] + reach - xmin) / cell));
+            int32_t iy0 = std::max(0, (int32_t)std::floor((arr->y[k] - reach - ymin) / cell));
+            int32_t iy1 = std::min(ny - 1, (int32_t)std::floor((arr->y[k] + reach - ymin) / cell));
+            for (int32_t ix = ix0; ix <= ix1; ++ix)
+                for (int32_t iy = iy0; iy <= iy1; ++iy) {
+                    // distance from the centre to the cell rectangle
+                    double cx0 = xmin + ix * cell, cy0 = ymin + iy * cell;
+                    double dx = std::max({cx0 - arr->x[k], 0.0, arr->x[k] - (cx0 + cell)});
+                    double dy = std::max({cy0 - arr->y[k], 0.0, arr->y[k] - (cy0 + cell)});
+                    if (dx * dx + dy * dy <= reach * reach)
+                        lists[lv * n_cells + (size_t)ix * ny + iy].push_back((uint16_t)k);
+                }
+        }
     g->cell_list.clear();
     for (size_t c = 0; c < lists.size(); ++c) {
         g->cell_off[c] = (int32_t)g->cell_list.size();
