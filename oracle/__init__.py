@@ -362,9 +362,11 @@ def tables_from_params(spec: AtmoParamSpec, theta) -> Tables:
     return build_tables(g, eta_from_params(spec, theta, g), spec.obs_level, spec.step)
 
 
-def soft(cfg: Config, segs, n_b_frozen, sigma: float, nthreads: int = 1):
-    """(S, A), each (n_showers, n_tel): soft photon counts and photon-weighted times."""
-    sv = SegView(segs)
+def soft(cfg: Config, segs, n_b_frozen, sigma: float, nthreads: int = 1, seg_id_base=None,
+         seg_id=None):
+    """(S, A), each (n_showers, n_tel): soft photon counts and photon-weighted times.
+    seg_id_base / seg_id as in run()."""
+    sv = SegView(segs, seg_id_base=seg_id_base, seg_id=seg_id)
     nb = np.ascontiguousarray(n_b_frozen, dtype=np.int64)
     S = np.zeros(sv.n_showers * cfg.n_tel)
     A = np.zeros(sv.n_showers * cfg.n_tel)

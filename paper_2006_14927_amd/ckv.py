@@ -205,6 +205,34 @@ class DeviceSegments:
             np.asarray(seg_id_base, dtype=np.int64), device=device)
         self.n = segs.n
         self.n_showers = segs.n_showers
+        self.offsets_host = np.asarray(segs.seg_offsets, dtype=np.int64).copy()
+        self.base_host = (np.zeros(self.n_showers, dtype=np.int64) if seg_id_base is None
+                          else np.asarray(seg_id_base, dtype=np.int64).copy())
+
+    def view(self, a: int, b: int) -> "DeviceSegments":
+        """Steps [a, b) as their own input, without copying the step arrays: the
+        showers they touch keep their ids and t_ref, and each shower's first step
+        in the range keeps its step index (seg_id_base), so every bunch keeps its
+        random numbers."""
+        import torch
+        off = self.offsets_host
+        s0 = int(np.searchsorted(off, a, side="right") - 1)
+        s1 = int(np.searchsorted(off, b, side="left"))          # exclusive
+        s1 = max(s1, s0 + 1)
+        v = DeviceSegments.__new__(DeviceSegments)
+        v.t = {f: t[a:b] for f, t in self.t.items()}
+        sub_off = np.clip(off[s0:s1 + 1], a, b) - a
+        sub_off[0], sub_off[-1] = 0, b - a
+        dev = self.t["x0"].device
+        v.seg_offsets = torch.as_tensor(sub_off, device=dev)
+        v.t_ref = self.t_ref[s0:s1]
+        v.shower_ids = self.shower_ids[s0:s1]
+        base = self.base_host[s0:s1] + np.maximum(a - off[s0:s1], 0)
+        v.seg_id_base = torch.as_tensor(base, device=dev)
+        v.n, v.n_showers = b - a, s1 - s0
+        v.offsets_host, v.base_host = sub_off, base
+        v.shower_range = (s0, s1)
+        return v
 
     def c_segments(self) -> _Segments:
         t = self.t
@@ -293,6 +321,101 @@ def run(segs, atmo: Atmosphere, tels: TelescopeArray, *, capacity: int, want_ids
     """One-shot convenience: segments (synth.Segments or DeviceSegments) -> records."""
     d = segs if isinstance(segs, DeviceSegments) else DeviceSegments(segs)
     return Runner(d, atmo, tels, make_params(**param_kw), capacity, want_ids).run(stream)
+
+
+@dataclass
+class Chunk:
+    """One range of a streamed run: steps [begin, end) of the input, showers
+    [shower_begin, shower_end), and its n_records records grouped per
+    (shower, telescope) through tel_offsets."""
+    begin: int
+    end: int
+    shower_begin: int
+    shower_end: int
+    records: "object"
+    ids: "object"
+    tel_offsets: "object"
+    result: dict
+
+
+class Streamer:
+    """ckv_run over consecutive step ranges of a large input, each sized so that
+    its records fit one output chunk (8 388 608 records = 256 MB by default).
+
+    Ranges are planned from the exact bunch count of every step (ckv_count) and
+    the largest crossings-per-bunch ratio seen so far; a range whose crossings
+    overflow the chunk is rerun smaller (ckv_run reports the required count and
+    writes nothing).  Per (shower, telescope), the records of consecutive ranges
+    concatenate in the one-shot (step, bunch) order."""
+
+    def __init__(self, dsegs: DeviceSegments, atmo: Atmosphere, tels: TelescopeArray,
+                 params: _Params, chunk_records: int = 8_388_608, want_ids: bool = True,
+                 first_ratio: float = 0.05, max_range: Optional[int] = None, device="cuda"):
+        import torch
+        self.dsegs, self.atmo, self.tels, self.params = dsegs, atmo, tels, params
+        self.capacity = int(chunk_records)
+        n_b = count(dsegs, atmo, params)
+        self.cum = np.zeros(dsegs.n + 1, dtype=np.int64)
+        self.cum[1:] = torch.cumsum(n_b, 0).cpu().numpy()
+        self.ratio = float(first_ratio)     # crossings per bunch assumed for planning
+        self.max_seen = 0.0
+        self.max_range = dsegs.n if max_range is None else int(max_range)
+        ws = workspace_size(max(self.max_range, 1), dsegs.n_showers, tels.n, self.capacity, params)
+        self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+        self.records = torch.empty((max(self.capacity, 1), 8), dtype=torch.float32, device=device)
+        self.ids = torch.empty((max(self.capacity, 1), 2), dtype=torch.int64, device=device) \
+            if want_ids else None
+        self.tel_offsets = torch.empty(dsegs.n_showers * tels.n + 1, dtype=torch.int64, device=device)
+        self.result_raw = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
+        self.n_reruns = 0
+
+    @property
+    def total_bunches(self) -> int:
+        return int(self.cum[-1])
+
+    def _range_end(self, a: int) -> int:
+        budget = 0.8 * self.capacity / max(self.ratio, 1e-12)
+        b = int(np.searchsorted(self.cum, self.cum[a] + budget, side="right")) - 1
+        return int(min(max(b, a + 1), self.dsegs.n, a + self.max_range))
+
+    def _run_range(self, a: int, b: int, stream=None) -> Chunk:
+        import torch
+        v = self.dsegs.view(a, b)
+        out = _Output(self.records.data_ptr(), self.ids.data_ptr() if self.ids is not None else None,
+                      self.capacity, self.tel_offsets.data_ptr(), self.result_raw.data_ptr())
+        segs, showers = v.c_segments(), v.c_showers()
+        _check(lib().ckv_run(C.byref(segs), C.byref(showers), C.byref(self.params), self.atmo.handle,
+                             self.tels.handle, C.c_void_p(self.workspace.data_ptr()),
+                             self.workspace.numel(), C.byref(out), _stream_ptr(stream)))
+        torch.cuda.synchronize()
+        res = RunOutput(self.records, self.ids, self.tel_offsets, self.result_raw).result()
+        n = int(res["n_records"])
+        return Chunk(a, b, *v.shower_range, self.records[:n], self.ids[:n] if self.ids is not None else None,
+                     self.tel_offsets[:v.n_showers * self.tels.n + 1], res)
+
+    def chunks(self, stream=None):
+        """Yields Chunk objects in step order; the buffers are reused by the next chunk."""
+        a, n = 0, self.dsegs.n
+        while a < n:
+            b = self._range_end(a)
+            ch = self._run_range(a, b, stream)
+            res = ch.result
+            if res["error"]:
+                raise CkvError(f"device reported error flags {res['error']} on steps [{a}, {b})")
+            bunches = int(self.cum[b] - self.cum[a])
+            seen = res["n_hits"] / max(bunches, 1)
+            if res["overflow"]:
+                if b == a + 1:
+                    raise CkvError(f"step {a} alone has {res['n_hits']} crossings > chunk capacity")
+                self.max_seen = max(self.max_seen, seen * 1.25)
+                self.ratio = self.max_seen
+                self.n_reruns += 1
+                continue
+            self.max_seen = max(self.max_seen, seen)
+            if self.max_seen > 0:
+                self.ratio = 1.1 * self.max_seen
+            yield ch
+            a = b
 
 
 class GraphRunner:

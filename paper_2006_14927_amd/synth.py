@@ -27,7 +27,9 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional, Sequence
+import os
+from concurrent.futures import ThreadPoolExecutor
+from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
@@ -187,17 +189,47 @@ class Segments:
                         seg_offsets=np.array([0, len(idx)], dtype=np.int64),
                         t_ref=self.t_ref[:1].copy(), shower_ids=self.shower_ids[:1].copy())
 
+    def take_shower(self, shower: int, local_idx: np.ndarray) -> "Segments":
+        """Steps local_idx (indices inside the shower) of one shower, as a one-shower input."""
+        base = int(self.seg_offsets[shower])
+        idx = base + np.asarray(local_idx, dtype=np.int64)
+        out = {f: getattr(self, f)[idx] for f in self.FIELDS}
+        return Segments(**out, ptype=self.ptype[idx],
+                        seg_offsets=np.array([0, len(idx)], dtype=np.int64),
+                        t_ref=self.t_ref[shower:shower + 1].copy(),
+                        shower_ids=self.shower_ids[shower:shower + 1].copy())
+
     @staticmethod
-    def concat(parts: List["Segments"]) -> "Segments":
-        out = {f: np.concatenate([getattr(p, f) for p in parts]) for f in Segments.FIELDS}
-        offs = [0]
-        for p in parts:
+    def concat(parts: List["Segments"], consume: bool = False) -> "Segments":
+        """Showers of all parts in order.  consume=True empties `parts` while
+        copying, so that large inputs are not held twice."""
+        total = sum(p.n for p in parts)
+        out = {f: np.empty(total, dtype=np.float64) for f in Segments.FIELDS}
+        ptype = np.empty(total, dtype=np.uint8)
+        offs, t_ref, sids = [0], [], []
+        at = 0
+        for i in range(len(parts)):
+            p = parts[i]
+            for f in Segments.FIELDS:
+                out[f][at:at + p.n] = getattr(p, f)
+            ptype[at:at + p.n] = p.ptype
+            at += p.n
             for s in range(p.n_showers):
                 offs.append(offs[-1] + int(p.seg_offsets[s + 1] - p.seg_offsets[s]))
-        return Segments(**out, ptype=np.concatenate([p.ptype for p in parts]),
-                        seg_offsets=np.array(offs, dtype=np.int64),
-                        t_ref=np.concatenate([p.t_ref for p in parts]),
-                        shower_ids=np.concatenate([p.shower_ids for p in parts]).astype(np.uint32))
+            t_ref.append(p.t_ref)
+            sids.append(p.shower_ids)
+            if consume:
+                parts[i] = None
+        return Segments(**out, ptype=ptype, seg_offsets=np.array(offs, dtype=np.int64),
+                        t_ref=np.concatenate(t_ref), shower_ids=np.concatenate(sids).astype(np.uint32))
+
+    @staticmethod
+    def join_blocks(blocks: List["Segments"]) -> "Segments":
+        """Blocks of one shower (same t_ref and shower id) as a single shower."""
+        one = Segments.concat(blocks, consume=True)
+        return Segments(**{f: getattr(one, f) for f in Segments.FIELDS}, ptype=one.ptype,
+                        seg_offsets=np.array([0, one.n], dtype=np.int64),
+                        t_ref=one.t_ref[:1].copy(), shower_ids=one.shower_ids[:1].copy())
 
 
 def _orthonormal_pair(ax: np.ndarray):
@@ -229,9 +261,11 @@ def shower_segments(shower: int, n_seg: int, atmo: Atmosphere, *, zenith_deg: fl
                     len_range=(1.0, 100.0), muon_fraction: float = 0.0,
                     muon_e_range_mev=(1000.0, 100000.0), muon_cone_deg: float = 15.0,
                     muon_xmax: float = 450.0, muon_lateral_mean: float = 150.0,
-                    shower_id: Optional[int] = None) -> Segments:
-    """Segments of one synthetic shower, seeded by SeedSequence(2006, spawn_key=(shower,))."""
-    rng = np.random.default_rng(np.random.SeedSequence(2006, spawn_key=(shower,)))
+                    shower_id: Optional[int] = None, block: Optional[int] = None) -> Segments:
+    """Segments of one synthetic shower, seeded by SeedSequence(2006, spawn_key=(shower,)),
+    or, for one block of a large shower, spawn_key=(shower, block)."""
+    key = (shower,) if block is None else (shower, block)
+    rng = np.random.default_rng(np.random.SeedSequence(2006, spawn_key=key))
     h_obs = atmo.obs_level
     th, ph = math.radians(zenith_deg), math.radians(azimuth_deg)
     axis = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), -math.cos(th)])
@@ -301,6 +335,36 @@ def shower_segments(shower: int, n_seg: int, atmo: Atmosphere, *, zenith_deg: fl
 # the workloads
 # ----------------------------------------------------------------------------
 
+# showers above this many steps are generated as independently seeded blocks
+BLOCK_SEGMENTS = 4_000_000
+
+
+def default_workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _pmap(fn: Callable, items, workers: Optional[int]):
+    """Map in threads (numpy releases the GIL in the bulk of the generator);
+    results in input order."""
+    items = list(items)
+    w = default_workers() if workers is None else workers
+    if w <= 1 or len(items) <= 1:
+        return [fn(x) for x in items]
+    with ThreadPoolExecutor(min(w, len(items))) as ex:
+        return list(ex.map(fn, items))
+
+
+def large_shower(shower: int, n_seg: int, atmo: Atmosphere, workers: Optional[int] = None,
+                 **kw) -> Segments:
+    """One shower; above BLOCK_SEGMENTS steps it is the concatenation of blocks of
+    BLOCK_SEGMENTS steps, block b seeded by spawn_key=(shower, b)."""
+    if n_seg <= BLOCK_SEGMENTS:
+        return shower_segments(shower, n_seg, atmo, **kw)
+    sizes = [min(BLOCK_SEGMENTS, n_seg - b0) for b0 in range(0, n_seg, BLOCK_SEGMENTS)]
+    blocks = _pmap(lambda b: shower_segments(shower, sizes[b], atmo, block=b, **kw),
+                   range(len(sizes)), workers)
+    return Segments.join_blocks(blocks)
+
 @dataclasses.dataclass
 class Workload:
     name: str
@@ -331,7 +395,8 @@ def single_tev(n_seg: int = 2_000_000) -> Workload:
                     telescopes_disk(), segs)
 
 
-def batched_showers(n_showers: int = 256, seg_scale: float = 1.0, seed: int = 2006) -> Workload:
+def batched_showers(n_showers: int = 256, seg_scale: float = 1.0, seed: int = 2006,
+                    workers: Optional[int] = None) -> Workload:
     """Many showers of uneven size: E log-uniform 30 GeV..30 TeV,
     n_seg = min(4e6, 1e4 E/30 GeV) x seg_scale, zenith U[0,60], cores in the 1 km disk."""
     atmo = layered_atmosphere()
@@ -341,22 +406,24 @@ def batched_showers(n_showers: int = 256, seg_scale: float = 1.0, seed: int = 20
     az = rng.uniform(0.0, 360.0, size=n_showers)
     rc = 1000.0 * np.sqrt(rng.uniform(size=n_showers))
     ac = rng.uniform(0.0, 2 * math.pi, size=n_showers)
-    parts = []
-    for s in range(n_showers):
+
+    def one(s):
         n_seg = max(1, int(round(min(4e6, 1e4 * energy[s] / 30.0) * seg_scale)))
         xm = 400.0 + 80.0 * math.log10(energy[s] / 1000.0)
-        parts.append(shower_segments(s, n_seg, atmo, zenith_deg=float(zen[s]),
-                                     azimuth_deg=float(az[s]),
-                                     core=(rc[s] * math.cos(ac[s]), rc[s] * math.sin(ac[s])),
-                                     xmax=xm))
-    return Workload(f"batched_{n_showers}", atmo, telescopes_disk(), Segments.concat(parts))
+        return shower_segments(s, n_seg, atmo, zenith_deg=float(zen[s]), azimuth_deg=float(az[s]),
+                               core=(rc[s] * math.cos(ac[s]), rc[s] * math.sin(ac[s])), xmax=xm)
+
+    parts = _pmap(one, range(n_showers), workers)
+    return Workload(f"batched_{n_showers}", atmo, telescopes_disk(),
+                    Segments.concat(parts, consume=True))
 
 
-def hadron_like(zenith_deg: float, n_seg: int = 50_000_000, shower: int = 0) -> Workload:
+def hadron_like(zenith_deg: float, n_seg: int = 50_000_000, shower: int = 0,
+                workers: Optional[int] = None) -> Workload:
     """90% e+- (Xmax 550, lateral mean 60 m) + 10% muons (1-100 GeV, 15 deg cone)."""
     atmo = layered_atmosphere()
-    segs = shower_segments(shower, n_seg, atmo, zenith_deg=zenith_deg, xmax=550.0,
-                           lateral_mean=60.0, muon_fraction=0.1)
+    segs = large_shower(shower, n_seg, atmo, workers, zenith_deg=zenith_deg, xmax=550.0,
+                        lateral_mean=60.0, muon_fraction=0.1)
     return Workload(f"hadron_like_{int(zenith_deg)}deg", atmo, telescopes_disk(), segs)
 
 
@@ -400,15 +467,17 @@ def diff_showers(n_showers: int = 64, n_seg: int = 500_000, seed: int = 4927) ->
     rng = np.random.default_rng(seed)
     rc = 300.0 * np.sqrt(rng.uniform(size=n_showers))
     ac = rng.uniform(0.0, 2 * math.pi, size=n_showers)
-    parts = [shower_segments(s, n_seg, place, zenith_deg=20.0, azimuth_deg=0.0,
-                             core=(rc[s] * math.cos(ac[s]), rc[s] * math.sin(ac[s])), xmax=400.0)
-             for s in range(n_showers)]
+    parts = _pmap(lambda s: shower_segments(s, n_seg, place, zenith_deg=20.0, azimuth_deg=0.0,
+                                            core=(rc[s] * math.cos(ac[s]), rc[s] * math.sin(ac[s])),
+                                            xmax=400.0),
+                  range(n_showers), None)
     j = np.arange(DIFF_N_KNOTS)
     l = np.arange(len(DIFF_BASE_SCALE_M))
     base = np.array(DIFF_BASE_SCALE_M)
     theta0 = np.concatenate([np.zeros(DIFF_N_KNOTS), base])
     target = np.concatenate([0.05 * np.sin(2 * math.pi * j / 16.0 + 0.3),
                              base * (1.0 + 0.02 * (-1.0) ** l)])
-    return DiffWorkload(f"diff_{n_showers}x{n_seg}", Segments.concat(parts), telescopes_disk(),
+    return DiffWorkload(f"diff_{n_showers}x{n_seg}", Segments.concat(parts, consume=True),
+                        telescopes_disk(),
                         ETA_SEA, np.array(DIFF_LAYER_BOUNDS_M), DIFF_N_KNOTS, DIFF_KNOT_TOP_M,
                         2200.0, 50.0, 120_000.0, theta0, target)

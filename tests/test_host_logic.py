@@ -1,0 +1,65 @@
+"""Host-side bookkeeping of the binding and the input generators (no GPU)."""
+
+import numpy as np
+
+from paper_2006_14927_amd import ckv, synth
+
+
+def _three_showers():
+    atmo = synth.layered_atmosphere()
+    parts = [synth.shower_segments(s, n, atmo, zenith_deg=20.0) for s, n in ((0, 50), (1, 7), (2, 40))]
+    return synth.Segments.concat(parts)
+
+
+def test_segment_view_keeps_shower_ids_and_step_indices():
+    segs = _three_showers()
+    d = ckv.DeviceSegments(segs, device="cpu", seg_id_base=[0, 3, 0])
+    for a, b in ((0, 97), (10, 55), (50, 57), (52, 53), (56, 90), (57, 97), (0, 1)):
+        v = d.view(a, b)
+        s0, s1 = v.shower_range
+        off = segs.seg_offsets
+        assert off[s0] <= a < off[s0 + 1] and off[s1 - 1] < b <= off[s1]
+        assert v.n == b - a and v.n_showers == s1 - s0
+        so = v.seg_offsets.numpy()
+        assert so[0] == 0 and so[-1] == b - a and np.all(np.diff(so) >= 0)
+        # global step index of every step in the view -> (shower, index in shower + base)
+        for j in range(v.n):
+            loc = int(np.searchsorted(so, j, side="right") - 1)
+            s = s0 + loc
+            want = (a + j) - off[s] + [0, 3, 0][s]
+            assert v.base_host[loc] + (j - so[loc]) == want
+        np.testing.assert_array_equal(v.t["x0"].numpy(), segs.x0[a:b])
+        np.testing.assert_array_equal(v.shower_ids.numpy(), segs.shower_ids[s0:s1].view(np.int32))
+
+
+def test_take_shower_and_concat():
+    segs = _three_showers()
+    one = segs.take_shower(2, np.array([0, 5, 39]))
+    assert one.n == 3 and one.t_ref[0] == segs.t_ref[2] and one.shower_ids[0] == 2
+    np.testing.assert_array_equal(one.h0, segs.h0[[57, 62, 96]])
+    parts = [segs.take_shower(s, np.arange(n)) for s, n in enumerate((50, 7, 40))]
+    back = synth.Segments.concat(parts, consume=True)
+    assert all(p is None for p in parts)
+    for f in segs.FIELDS + ("ptype", "seg_offsets", "t_ref", "shower_ids"):
+        np.testing.assert_array_equal(getattr(back, f), getattr(segs, f))
+
+
+def test_threaded_generation_is_deterministic():
+    a = synth.batched_showers(12, seg_scale=2e-3, workers=1)
+    b = synth.batched_showers(12, seg_scale=2e-3, workers=4)
+    for f in a.segs.FIELDS + ("ptype", "seg_offsets", "t_ref", "shower_ids"):
+        np.testing.assert_array_equal(getattr(a.segs, f), getattr(b.segs, f))
+
+
+def test_large_shower_blocks():
+    atmo = synth.layered_atmosphere()
+    old = synth.BLOCK_SEGMENTS
+    try:
+        synth.BLOCK_SEGMENTS = 1000
+        big = synth.large_shower(3, 2500, atmo, workers=3, zenith_deg=40.0, muon_fraction=0.1)
+    finally:
+        synth.BLOCK_SEGMENTS = old
+    assert big.n == 2500 and big.n_showers == 1 and big.shower_ids[0] == 3
+    blk = synth.shower_segments(3, 1000, atmo, block=1, zenith_deg=40.0, muon_fraction=0.1)
+    np.testing.assert_array_equal(big.x0[1000:2000], blk.x0)
+    assert np.all(np.isfinite(big.h0))
