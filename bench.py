@@ -216,6 +216,94 @@ def diff_timing(hip, reps: int, n_showers: int = 64, n_seg: int = 500_000):
             "grad_norm": float(g.norm())}
 
 
+def batched_timing(hip, reps: int, use_cache: bool = True):
+    """256 showers (~3e8 steps, ~2e10 bunches) in one persistent launch, the whole
+    run captured into a HIP graph and replayed; mixed precision, autotuned shape."""
+    import torch
+
+    from paper_2006_14927_amd import autotune, ckv, synth
+    wl = synth.batched_showers(256)
+    atmo = ckv.Atmosphere(wl.atmo.alt, wl.atmo.eta, wl.atmo.obs_level, wl.fine_step)
+    tels = ckv.TelescopeArray(wl.tels.x, wl.tels.y, wl.tels.r)
+    d = ckv.DeviceSegments(wl.segs)
+    p = ckv.make_params(precision=ckv.CKV_MIXED, bunch_size=wl.bunch_size, lambda_min=wl.lambda_min,
+                        lambda_max=wl.lambda_max, seed=wl.seed)
+    total = int(ckv.count(d, atmo, p).sum())
+    cap = int(0.02 * total)
+    probe = ckv.Runner(d, atmo, tels, p, cap, want_ids=False).run()
+    torch.cuda.synchronize()
+    res = probe.result()
+    if res["overflow"]:
+        cap = int(res["n_hits"]) + 1024
+    del probe
+    torch.cuda.empty_cache()
+    tuned = autotune.tune(d, atmo, tels, p, cap, candidates=[(32, 16), (64, 16), (32, 8), (16, 16)],
+                          reps=1, use_cache=use_cache)
+    q = autotune.apply(p, tuned)
+    gr = ckv.GraphRunner(ckv.Runner(d, atmo, tels, q, cap, want_ids=False))
+    gr.replay()
+    torch.cuda.synchronize()
+    sp = C.c_void_p(gr.stream.cuda_stream)
+    t0, t1 = _event(hip), _event(hip)
+    hip.hipEventRecord(t0, sp)
+    for _ in range(reps):
+        with torch.cuda.stream(gr.stream):
+            out = gr.replay()
+    hip.hipEventRecord(t1, sp)
+    hip.hipEventSynchronize(t1)
+    torch.cuda.synchronize()
+    ms = _elapsed_ms(hip, t0, t1) / reps
+    hip.hipEventDestroy(t0)
+    hip.hipEventDestroy(t1)
+    res = out.result()
+    if res["overflow"] or res["error"] or res["n_bunches"] != total:
+        raise RuntimeError(f"batched run reported a problem: {res}")
+    return {"workload": wl.name, "showers": wl.segs.n_showers, "steps": wl.segs.n,
+            "bunches": total, "records": res["n_hits"], "ms_per_launch": ms,
+            "bunches_per_s": total / (ms * 1e-3), "graph_replays": reps,
+            "launch": {"tile_segments": tuned["tile_segments"],
+                       "waves_per_group": tuned["waves_per_group"]}}
+
+
+def streamed_timing(hip, zeniths=(0.0, 20.0, 40.0, 60.0)):
+    """One 5e7-step hadron-like shower per zenith, mixed precision, output streamed
+    to pinned host memory in chunks of 8 388 608 records (256 MB); timed from the
+    bunch counts to the last chunk on the host."""
+    import torch
+
+    from paper_2006_14927_amd import ckv, synth
+    out = []
+    for z in zeniths:
+        wl = synth.hadron_like(z)
+        atmo = ckv.Atmosphere(wl.atmo.alt, wl.atmo.eta, wl.atmo.obs_level, wl.fine_step)
+        tels = ckv.TelescopeArray(wl.tels.x, wl.tels.y, wl.tels.r)
+        d = ckv.DeviceSegments(wl.segs)
+        p = ckv.make_params(precision=ckv.CKV_MIXED, bunch_size=wl.bunch_size,
+                            lambda_min=wl.lambda_min, lambda_max=wl.lambda_max, seed=wl.seed)
+        ckv.Streamer(d, atmo, tels, p, want_ids=False)        # warm: allocations, first launch
+        torch.cuda.synchronize()
+        agg = dict(chunks=0, records=0, bunches=0)
+
+        def sink(ch):
+            agg["chunks"] += 1
+            agg["records"] += int(ch.records.shape[0])
+            agg["bunches"] += ch.result["n_bunches"]
+
+        t0 = time.perf_counter()
+        st = ckv.Streamer(d, atmo, tels, p, want_ids=False)
+        st.to_host(sink)
+        dt = time.perf_counter() - t0
+        n_chunks, n_rec, n_b = agg["chunks"], agg["records"], agg["bunches"]
+        if n_b != st.total_bunches:
+            raise RuntimeError("streamed bunch count mismatch")
+        out.append({"zenith_deg": z, "steps": wl.segs.n, "bunches": n_b, "records": n_rec,
+                    "chunks": n_chunks, "reruns": st.n_reruns, "s": dt, "bunches_per_s": n_b / dt})
+        print(f"# streamed {wl.name}: {out[-1]}", file=sys.stderr, flush=True)
+        del st, d
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, target_cpu_seconds: float = 20.0):
     """The FP64 oracle on an evenly spaced sample of the shower's steps."""
     import numpy as np
@@ -250,6 +338,10 @@ def main(argv=None):
     ap.add_argument("--no-diff", action="store_true",
                     help="skip the forward+backward timing of the differentiation workload")
     ap.add_argument("--diff-reps", type=int, default=3)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 256-shower batched launch (~3e8 steps)")
+    ap.add_argument("--no-streamed", action="store_true",
+                    help="skip the 5e7-step hadron-like showers streamed in 256 MB chunks")
     ap.add_argument("--no-tune-cache", action="store_true",
                     help="re-run the launch-shape autotuner instead of using its cache")
     ap.add_argument("--segments", type=int, default=2_000_000,
@@ -365,6 +457,14 @@ def main(argv=None):
         print(f"# differentiation: {d}", file=sys.stderr, flush=True)
         line["fwd_bwd_ms_per_shower"] = d["ms_per_shower"]
         line["differentiation"] = d
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        b = batched_timing(hip, 3, use_cache=not args.no_tune_cache)
+        print(f"# batched: {b}", file=sys.stderr, flush=True)
+        line["batched"] = b
+        torch.cuda.empty_cache()
+    if not args.no_streamed:
+        line["streamed"] = streamed_timing(hip)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

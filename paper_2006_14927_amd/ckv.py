@@ -338,84 +338,185 @@ class Chunk:
     result: dict
 
 
+class _OutBuf:
+    """Device output of one ckv_run: records, ids, CSR offsets, result."""
+
+    def __init__(self, capacity: int, n_groups: int, want_ids: bool, device):
+        import torch
+        self.records = torch.empty((max(capacity, 1), 8), dtype=torch.float32, device=device)
+        self.ids = torch.empty((max(capacity, 1), 2), dtype=torch.int64, device=device) \
+            if want_ids else None
+        self.tel_offsets = torch.empty(n_groups + 1, dtype=torch.int64, device=device)
+        self.result_raw = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
+
+    def c_output(self, capacity: int) -> _Output:
+        return _Output(self.records.data_ptr(), self.ids.data_ptr() if self.ids is not None else None,
+                       capacity, self.tel_offsets.data_ptr(), self.result_raw.data_ptr())
+
+    def result(self) -> dict:
+        return RunOutput(self.records, self.ids, self.tel_offsets, self.result_raw).result()
+
+
 class Streamer:
     """ckv_run over consecutive step ranges of a large input, each sized so that
     its records fit one output chunk (8 388 608 records = 256 MB by default).
 
-    Ranges are planned from the exact bunch count of every step (ckv_count) and
-    the largest crossings-per-bunch ratio seen so far; a range whose crossings
+    Ranges are planned from the bunch counts of the steps (ckv_count, summed on
+    the device into one prefix value per block of `plan_block` steps) and the
+    largest crossings-per-bunch ratio seen so far; a range whose crossings
     overflow the chunk is rerun smaller (ckv_run reports the required count and
     writes nothing).  Per (shower, telescope), the records of consecutive ranges
-    concatenate in the one-shot (step, bunch) order."""
+    concatenate in the one-shot (step, bunch) order.
+
+    chunks() yields each range's output on the device; to_host() copies every
+    chunk to pinned host memory while the next range is computed."""
 
     def __init__(self, dsegs: DeviceSegments, atmo: Atmosphere, tels: TelescopeArray,
                  params: _Params, chunk_records: int = 8_388_608, want_ids: bool = True,
-                 first_ratio: float = 0.05, max_range: Optional[int] = None, device="cuda"):
+                 first_ratio: float = 0.05, max_range: Optional[int] = None,
+                 plan_block: int = 4096, device="cuda"):
         import torch
         self.dsegs, self.atmo, self.tels, self.params = dsegs, atmo, tels, params
         self.capacity = int(chunk_records)
+        self.want_ids = want_ids
+        self.device = device
+        n = dsegs.n
+        self.block = int(plan_block)
         n_b = count(dsegs, atmo, params)
-        self.cum = np.zeros(dsegs.n + 1, dtype=np.int64)
-        self.cum[1:] = torch.cumsum(n_b, 0).cpu().numpy()
+        cum = torch.cumsum(n_b, 0)
+        ends = torch.arange(self.block, n + self.block, self.block, device=cum.device).clamp_(max=n)
+        self.plan_at = np.concatenate([[0], ends.cpu().numpy()]).astype(np.int64)
+        self.plan_cum = np.zeros(len(self.plan_at), dtype=np.int64)
+        if n:
+            self.plan_cum[1:] = cum[ends - 1].cpu().numpy()
         self.ratio = float(first_ratio)     # crossings per bunch assumed for planning
         self.max_seen = 0.0
-        self.max_range = dsegs.n if max_range is None else int(max_range)
+        self.max_range = n if max_range is None else int(max_range)
         ws = workspace_size(max(self.max_range, 1), dsegs.n_showers, tels.n, self.capacity, params)
         self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
-        self.records = torch.empty((max(self.capacity, 1), 8), dtype=torch.float32, device=device)
-        self.ids = torch.empty((max(self.capacity, 1), 2), dtype=torch.int64, device=device) \
-            if want_ids else None
-        self.tel_offsets = torch.empty(dsegs.n_showers * tels.n + 1, dtype=torch.int64, device=device)
-        self.result_raw = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
+        self.out = _OutBuf(self.capacity, dsegs.n_showers * tels.n, want_ids, device)
         self.n_reruns = 0
 
     @property
     def total_bunches(self) -> int:
-        return int(self.cum[-1])
+        return int(self.plan_cum[-1])
+
+    def _cum_at(self, x: int) -> float:
+        return float(np.interp(x, self.plan_at, self.plan_cum))
 
     def _range_end(self, a: int) -> int:
         budget = 0.8 * self.capacity / max(self.ratio, 1e-12)
-        b = int(np.searchsorted(self.cum, self.cum[a] + budget, side="right")) - 1
+        target = self._cum_at(a) + budget
+        j = int(np.searchsorted(self.plan_cum, target, side="right")) - 1
+        b = int(self.plan_at[max(j, 0)])
+        if b <= a:                          # less than one block fits: interpolate inside it
+            b = int(np.interp(target, self.plan_cum, self.plan_at))
         return int(min(max(b, a + 1), self.dsegs.n, a + self.max_range))
 
-    def _run_range(self, a: int, b: int, stream=None) -> Chunk:
-        import torch
+    def _launch(self, a: int, b: int, out: _OutBuf, stream=None):
         v = self.dsegs.view(a, b)
-        out = _Output(self.records.data_ptr(), self.ids.data_ptr() if self.ids is not None else None,
-                      self.capacity, self.tel_offsets.data_ptr(), self.result_raw.data_ptr())
-        segs, showers = v.c_segments(), v.c_showers()
+        segs, showers, o = v.c_segments(), v.c_showers(), out.c_output(self.capacity)
         _check(lib().ckv_run(C.byref(segs), C.byref(showers), C.byref(self.params), self.atmo.handle,
                              self.tels.handle, C.c_void_p(self.workspace.data_ptr()),
-                             self.workspace.numel(), C.byref(out), _stream_ptr(stream)))
-        torch.cuda.synchronize()
-        res = RunOutput(self.records, self.ids, self.tel_offsets, self.result_raw).result()
-        n = int(res["n_records"])
-        return Chunk(a, b, *v.shower_range, self.records[:n], self.ids[:n] if self.ids is not None else None,
-                     self.tel_offsets[:v.n_showers * self.tels.n + 1], res)
+                             self.workspace.numel(), C.byref(o), _stream_ptr(stream)))
+        return v
+
+    def _accept(self, a: int, b: int, res: dict) -> bool:
+        """Updates the planning ratio; False when the range has to be rerun smaller."""
+        if res["error"]:
+            raise CkvError(f"device reported error flags {res['error']} on steps [{a}, {b})")
+        seen = res["n_hits"] / max(res["n_bunches"], 1)
+        if res["overflow"]:
+            if b == a + 1:
+                raise CkvError(f"step {a} alone has {res['n_hits']} crossings > chunk capacity")
+            self.max_seen = max(self.max_seen, seen * 1.25)
+            self.ratio = self.max_seen
+            self.n_reruns += 1
+            return False
+        self.max_seen = max(self.max_seen, seen)
+        if self.max_seen > 0:
+            self.ratio = 1.1 * self.max_seen
+        return True
 
     def chunks(self, stream=None):
-        """Yields Chunk objects in step order; the buffers are reused by the next chunk."""
+        """Yields Chunk objects (device buffers, reused by the next chunk) in step order."""
+        import torch
         a, n = 0, self.dsegs.n
         while a < n:
             b = self._range_end(a)
-            ch = self._run_range(a, b, stream)
-            res = ch.result
-            if res["error"]:
-                raise CkvError(f"device reported error flags {res['error']} on steps [{a}, {b})")
-            bunches = int(self.cum[b] - self.cum[a])
-            seen = res["n_hits"] / max(bunches, 1)
-            if res["overflow"]:
-                if b == a + 1:
-                    raise CkvError(f"step {a} alone has {res['n_hits']} crossings > chunk capacity")
-                self.max_seen = max(self.max_seen, seen * 1.25)
-                self.ratio = self.max_seen
-                self.n_reruns += 1
+            v = self._launch(a, b, self.out, stream)
+            torch.cuda.synchronize()
+            res = self.out.result()
+            if not self._accept(a, b, res):
                 continue
-            self.max_seen = max(self.max_seen, seen)
-            if self.max_seen > 0:
-                self.ratio = 1.1 * self.max_seen
-            yield ch
+            k = int(res["n_records"])
+            yield Chunk(a, b, *v.shower_range, self.out.records[:k],
+                        self.out.ids[:k] if self.out.ids is not None else None,
+                        self.out.tel_offsets[:v.n_showers * self.tels.n + 1], res)
             a = b
+
+    def to_host(self, sink):
+        """Streams every chunk to pinned host memory: sink(chunk) receives a Chunk
+        whose records, ids and tel_offsets are host tensors (valid during the
+        call).  The device-to-host copy of a chunk runs on its own stream while
+        the next range is computed into a second output buffer."""
+        import torch
+        comp = torch.cuda.current_stream()
+        copy = torch.cuda.Stream()
+        outs = [self.out, _OutBuf(self.capacity, self.dsegs.n_showers * self.tels.n, self.want_ids,
+                                  self.device)]
+        n_groups = self.dsegs.n_showers * self.tels.n + 1
+        host = [dict(records=torch.empty((self.capacity, 8), dtype=torch.float32, pin_memory=True),
+                     ids=torch.empty((self.capacity, 2), dtype=torch.int64, pin_memory=True)
+                     if self.want_ids else None,
+                     off=torch.empty(n_groups, dtype=torch.int64, pin_memory=True))
+                for _ in range(2)]
+        copied = [None, None]          # event: copy out of buffer i finished
+        pending = None
+
+        def deliver(p):
+            ev, slot, meta = p
+            ev.synchronize()
+            h = host[slot]
+            k = int(meta["res"]["n_records"])
+            sink(Chunk(meta["a"], meta["b"], *meta["showers"], h["records"][:k],
+                       h["ids"][:k] if h["ids"] is not None else None, h["off"][:meta["ng"]],
+                       meta["res"]))
+
+        a, n, i = 0, self.dsegs.n, 0
+        while a < n:
+            b = self._range_end(a)
+            slot = i % 2
+            out = outs[slot]
+            if copied[slot] is not None:
+                comp.wait_event(copied[slot])      # its last copy must be done before reuse
+            v = self._launch(a, b, out, comp)
+            ran = torch.cuda.Event()
+            ran.record(comp)
+            if pending is not None:                # hand over the previous chunk meanwhile
+                deliver(pending)
+                pending = None
+            ran.synchronize()
+            res = out.result()
+            if not self._accept(a, b, res):
+                continue
+            k = int(res["n_records"])
+            ng = v.n_showers * self.tels.n + 1
+            copy.wait_event(ran)
+            with torch.cuda.stream(copy):
+                h = host[slot]
+                h["records"][:k].copy_(out.records[:k], non_blocking=True)
+                if h["ids"] is not None:
+                    h["ids"][:k].copy_(out.ids[:k], non_blocking=True)
+                h["off"][:ng].copy_(out.tel_offsets[:ng], non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(copy)
+            copied[slot] = ev
+            pending = (ev, slot, dict(a=a, b=b, showers=v.shower_range, res=res, ng=ng))
+            a, i = b, i + 1
+        if pending is not None:
+            deliver(pending)
+        torch.cuda.synchronize()
 
 
 class GraphRunner:

@@ -89,3 +89,48 @@ def test_autotune_candidates_identical_and_cached(tmp_path, monkeypatch):
     for off, rec in outs[1:]:
         np.testing.assert_array_equal(off, outs[0][0])
         np.testing.assert_array_equal(rec, outs[0][1])
+
+
+@pytest.mark.parametrize("mode", ["device", "host"])
+def test_streamed_chunks_equal_one_shot(batched, mode):
+    """Small output chunks force many ranges, some of them inside one shower and
+    some spanning several; per (shower, telescope) the chunks concatenate to the
+    one-shot output, bit for bit (ids shifted by each range's first step)."""
+    import torch
+    wl, cfg, r = batched
+    atmo, tels = handles(wl)
+    d = ckv.DeviceSegments(wl.segs)
+    p = params(wl, ckv.CKV_MIXED)
+    one = gpu_run(wl, ckv.CKV_MIXED, handles_=(atmo, tels))
+    n_tel, n_sh = tels.n, wl.segs.n_showers
+    st = ckv.Streamer(d, atmo, tels, p, chunk_records=max(1000, len(r.seg) // 12), first_ratio=0.002,
+                      plan_block=64)
+    got = [[] for _ in range(n_sh * n_tel)]
+    n_chunks = [0]
+
+    def take(ch):
+        n_chunks[0] += 1
+        off = np.asarray(ch.tel_offsets.cpu() if mode == "device" else ch.tel_offsets)
+        rec = (ch.records.cpu() if mode == "device" else ch.records).numpy().copy()
+        ids = (ch.ids.cpu() if mode == "device" else ch.ids).numpy().copy()
+        ids[:, 0] += ch.begin
+        for loc in range(ch.shower_end - ch.shower_begin):
+            for t in range(n_tel):
+                gi = loc * n_tel + t
+                got[(ch.shower_begin + loc) * n_tel + t].append(
+                    (rec[off[gi]:off[gi + 1]], ids[off[gi]:off[gi + 1]]))
+
+    if mode == "device":
+        for ch in st.chunks():
+            take(ch)
+    else:
+        st.to_host(take)
+    torch.cuda.synchronize()
+    say(f"[gpu] streamed ({mode}): {n_chunks[0]} chunks, {st.n_reruns} reruns")
+    assert n_chunks[0] >= 8
+    o = one["offsets"]
+    for gi in range(n_sh * n_tel):
+        rec = np.concatenate([x[0] for x in got[gi]]) if got[gi] else np.zeros((0, 8), np.float32)
+        ids = np.concatenate([x[1] for x in got[gi]]) if got[gi] else np.zeros((0, 2), np.int64)
+        np.testing.assert_array_equal(rec.view(np.uint32), one["rec"][o[gi]:o[gi + 1]].view(np.uint32))
+        np.testing.assert_array_equal(ids, one["ids"][o[gi]:o[gi + 1]])

@@ -63,3 +63,32 @@ def test_large_shower_blocks():
     blk = synth.shower_segments(3, 1000, atmo, block=1, zenith_deg=40.0, muon_fraction=0.1)
     np.testing.assert_array_equal(big.x0[1000:2000], blk.x0)
     assert np.all(np.isfinite(big.h0))
+
+
+def test_stream_range_planning():
+    """Ranges respect the crossing budget at block granularity, always advance,
+    and stay inside the input."""
+    st = ckv.Streamer.__new__(ckv.Streamer)
+    rng = np.random.default_rng(3)
+    n = 100_003
+    nb = rng.integers(0, 200, size=n)
+    nb[5000:9000] = 0
+    cum = np.concatenate([[0], np.cumsum(nb)])
+    st.block = 4096
+    st.plan_at = np.concatenate([[0], np.minimum(np.arange(4096, n + 4096, 4096), n)])
+    st.plan_cum = cum[st.plan_at]
+    st.capacity, st.max_range = 50_000, n
+
+    class D:
+        pass
+    st.dsegs = D()
+    st.dsegs.n = n
+    for ratio in (1e-3, 0.05, 0.5, 20.0):
+        st.ratio = ratio
+        a = 0
+        while a < n:
+            b = st._range_end(a)
+            assert a < b <= n
+            if b - a > 1 and b % 4096 == 0:
+                assert (cum[b] - cum[a]) * ratio <= 0.8 * st.capacity + 1e-9
+            a = b
