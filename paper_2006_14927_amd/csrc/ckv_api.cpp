@@ -380,7 +380,7 @@ static int soft_common(const ckv_segments* segs, const ckv_showers* showers,
     int n_cu = 256;
     if (int rc = device_cu_count(&n_cu)) return rc;
     plan->emit_grid = params->grid > 0 ? params->grid : std::min(n_cu, kMaxEmitGrid);
-    plan->emit_waves = 4;
+    plan->emit_waves = 0;            // as many as the LDS holds
     return CKV_OK;
 }
 

@@ -958,16 +958,30 @@ struct alignas(16) SoftStep {
 static_assert(sizeof(SoftStep) % 16 == 0, "soft step entry alignment");
 
 constexpr int kSoftTS = 32;
-constexpr int kSoftWaves = 4;
+// forward: 8 waves (<= 256 VGPRs, two waves per SIMD); adjoint: 4 waves, whose
+// reverse sweep needs more registers than two waves per SIMD leave
+__host__ __device__ constexpr int soft_max_waves(int mode) { return mode == 0 ? 8 : 4; }
+// adjoint bins (dL/dpsi_i, dL/dP_j(h_i)) of the lowest kSoftBinNodes nodes live in
+// LDS (h_obs + 51 km on a 50 m grid); the rare contributions above go to HBM
+constexpr int kSoftBinNodes = 1024;
 
-__host__ __device__ inline size_t soft_wave_bytes(int n_tel)
+__host__ __device__ inline int soft_bin_nodes(int n_nodes)
 {
-    return kSoftTS * sizeof(SoftStep) + kWave * sizeof(int32_t) + (size_t)2 * n_tel * sizeof(double);
+    return n_nodes < kSoftBinNodes ? n_nodes : kSoftBinNodes;
 }
 
-__host__ __device__ inline size_t soft_bin_bytes(int mode, int n_nodes)
+// per wave: step stash, flag row and (forward only) S, A per telescope
+__host__ __device__ inline size_t soft_wave_bytes(int mode, int n_tel)
 {
-    return mode == 1 ? (size_t)6 * n_nodes * sizeof(double) : 0;
+    return kSoftTS * sizeof(SoftStep) + kWave * sizeof(int32_t) +
+           (mode == 0 ? (size_t)2 * n_tel * sizeof(double) : 0);
+}
+
+// per workgroup: adjoint bins, then 1 / (2 R sigma) per telescope, then the waves
+__host__ __device__ inline size_t soft_lds_bytes(int mode, int n_nodes, int n_tel, int waves)
+{
+    const size_t bins = mode == 1 ? (size_t)6 * soft_bin_nodes(n_nodes) * sizeof(double) : 0;
+    return bins + (size_t)n_tel * sizeof(double) + (size_t)waves * soft_wave_bytes(mode, n_tel);
 }
 
 // step setup with a frozen bunch count; false when the step emits nothing
@@ -1022,23 +1036,33 @@ __device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, Sof
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(256) soft_kernel(Args a, SoftArgs sa)
+__global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args a, SoftArgs sa)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     const int N = a.n_nodes;
-    double* gpsi_l = reinterpret_cast<double*>(lds);
-    double* gP_l = gpsi_l + N;
-    unsigned char* wbase = lds + soft_bin_bytes(MODE, N) + (size_t)wave * soft_wave_bytes(a.n_tel);
+    const int NB = soft_bin_nodes(N);
+    double* bins = reinterpret_cast<double*>(lds);                 // MODE 1: 6 x NB
+    double* inv_2rs = bins + (MODE == 1 ? 6 * NB : 0);               // n_tel
+    unsigned char* wbase = reinterpret_cast<unsigned char*>(inv_2rs + a.n_tel) +
+                           (size_t)wave * soft_wave_bytes(MODE, a.n_tel);
     SoftStep* stash = reinterpret_cast<SoftStep*>(wbase);
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + kSoftTS * sizeof(SoftStep));
     double* acc = reinterpret_cast<double*>(flags + kWave);     // MODE 0: S then A per telescope
     if (MODE == 1)
-        for (int q = threadIdx.x; q < 6 * N; q += blockDim.x) gpsi_l[q] = 0.0;
-    for (int q = lane; q < 2 * a.n_tel; q += kWave) acc[q] = 0.0;
+        for (int q = threadIdx.x; q < 6 * NB; q += blockDim.x) bins[q] = 0.0;
+    for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x)
+        inv_2rs[q] = 1.0 / (2.0 * a.tel[4 * q + 2] * sa.sigma);
+    if (MODE == 0)
+        for (int q = lane; q < 2 * a.n_tel; q += kWave) acc[q] = 0.0;
     flags[lane] = 0;
     __syncthreads();
+    // j = 0: dL/dpsi_i, j = 1..5: dL/dP_j(h_i)
+    auto add_bin = [&](int j, int i, double v) {
+        if (i < NB) atomicAdd(&bins[j * NB + i], v);
+        else atomicAdd(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
+    };
 
     const double a1 = -0.5, a2 = 0.375, a3 = -0.3125, a4 = 0.2734375;
     const double ak[5] = {1.0, a1, a2, a3, a4};
@@ -1047,7 +1071,8 @@ __global__ void __launch_bounds__(256) soft_kernel(Args a, SoftArgs sa)
     const double inv_sqrt2pi = 0.39894228040143267794;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t le_mask = lt_mask | (1ull << lane);
-    const double nobs = a.n_obs;
+    const double inv_nobs = 1.0 / a.n_obs;
+    const double half_inv_nobs3 = 0.5 * inv_nobs * inv_nobs * inv_nobs;
     double g_psi0 = 0.0;
     const int64_t n_tiles = a.ctrl[kNumTiles];
 
@@ -1132,45 +1157,42 @@ __global__ void __launch_bounds__(256) soft_kernel(Args a, SoftArgs sa)
             const double pa = nd[0], pb = nd[kNode64];
             const double psi_e = pa + fe * (pb - pa);
             const double dz = fe * a.step;
-            double P[6], D[6];
-            double pow_a[6], pow_b[6];
-            pow_a[0] = pow_b[0] = 1.0;
-            for (int q = 1; q <= 5; ++q) { pow_a[q] = pow_a[q - 1] * pa; pow_b[q] = pow_b[q - 1] * psi_e; }
             const double dh = he - a.h_obs;
-            P[0] = dh;
-            for (int jj = 1; jj <= 5; ++jj) {
-                double hs = 0.0;
-                for (int q = 0; q <= jj; ++q) hs += pow_a[jj - q] * pow_b[q];
-                P[jj] = nd[jj] + dz / (double)(jj + 1) * hs;
-            }
-            const double cneg = -psi_e;
-            for (int kk = 0; kk <= 5; ++kk) {
-                // D_k = sum_j C(k,j) (-psi_e)^(k-j) P_j
-                double sum = 0.0, binom = 1.0, cp_pow = 1.0;
-                for (int q = kk; q >= 0; --q) {
-                    sum += binom * cp_pow * P[q];
-                    binom = binom * (double)q / (double)(kk - q + 1);
-                    cp_pow *= cneg;
-                }
-                D[kk] = sum;
-            }
+            // D_k = int (psi - psi_e)^k dh: node moments shifted to psi_e (Pascal
+            // triangle, P_0(h_i) = h_i - h_obs) plus the in-cell part of the linear
+            // profile, dz (psi_i - psi_e)^k / (k+1)
+            const double c = -psi_e, del = pa - psi_e;
+            double X1 = nd[1], X2 = nd[2], X3 = nd[3], X4 = nd[4], X5 = nd[5];
+            const double X0 = (double)ie * a.step;
+            X5 += c * X4; X4 += c * X3; X3 += c * X2; X2 += c * X1; X1 += c * X0;
+            X5 += c * X4; X4 += c * X3; X3 += c * X2; X2 += c * X1;
+            X5 += c * X4; X4 += c * X3; X3 += c * X2;
+            X5 += c * X4; X4 += c * X3;
+            X5 += c * X4;
+            const double dl2 = del * del, dl3 = dl2 * del, dl4 = dl3 * del;
+            double D[6];
+            D[0] = dh;
+            D[1] = X1 + dz * 0.5 * del;
+            D[2] = X2 + dz * (1.0 / 3.0) * dl2;
+            D[3] = X3 + dz * 0.25 * dl3;
+            D[4] = X4 + dz * 0.2 * dl4;
+            D[5] = X5 + dz * (1.0 / 6.0) * (dl4 * del);
             const double ne2 = 1.0 + psi_e;
             const double ne = sqrt(ne2);
-            const double q = 1.0 / (ne2 * pw * pw);
-            double qk[5];
-            qk[0] = 1.0;
-            for (int kk = 1; kk < 5; ++kk) qk[kk] = qk[kk - 1] * q;
-            double Sser = 0.0, U = 0.0;
-            for (int kk = 0; kk < 5; ++kk) {
-                Sser += ak[kk] * qk[kk] * D[kk];
-                U += ak[kk] * qk[kk] * (ne2 * D[kk] + D[kk + 1]);
-            }
-            const double T = U / (ne * pw) * inv_c;
-            const double xg = xe + pu * Sser / pw;
-            const double yg = ye + pv * Sser / pw;
+            const double inv_ne = 1.0 / ne, inv_pw = 1.0 / pw;
+            const double q = (inv_pw * inv_pw) * (inv_ne * inv_ne);
+            const double Sser = D[0] + q * (a1 * D[1] + q * (a2 * D[2] + q * (a3 * D[3] + q * a4 * D[4])));
+            const double U = (ne2 * D[0] + D[1]) +
+                             q * (a1 * (ne2 * D[1] + D[2]) +
+                                  q * (a2 * (ne2 * D[2] + D[3]) +
+                                       q * (a3 * (ne2 * D[3] + D[4]) + q * a4 * (ne2 * D[4] + D[5]))));
+            const double T = U * inv_ne * inv_pw * inv_c;
+            const double adv = Sser * inv_pw;
+            const double xg = xe + pu * adv;
+            const double yg = ye + pv * adv;
             const double tt = te + T - t_ref;
-            const double uo = pu * ne / nobs;
-            const double vo = pv * ne / nobs;
+            const double uo = pu * ne * inv_nobs;
+            const double vo = pv * ne * inv_nobs;
             const double p = e.photons;
 
             // soft weights over candidate spheres
@@ -1195,8 +1217,7 @@ __global__ void __launch_bounds__(256) soft_kernel(Args a, SoftArgs sa)
                 const double dx = xg - tp[0], dy = yg - tp[1];
                 const double b = dx * uo + dy * vo;
                 const double rho2 = dx * dx + dy * dy - b * b;
-                const double R = tp[2];
-                const double z = (tp[3] - rho2) / (2.0 * R * sa.sigma);
+                const double z = (tp[3] - rho2) * inv_2rs[kt];
                 if (z < -kSoftZCut) continue;
                 const double W = 0.5 * erfc(-z * inv_sqrt2);
                 if (MODE == 0) {
@@ -1208,7 +1229,7 @@ __global__ void __launch_bounds__(256) soft_kernel(Args a, SoftArgs sa)
                     g_p += gSk * W + gAk * W * tt;
                     g_t += gAk * p * W;
                     const double g_z = (gSk * p + gAk * p * tt) * inv_sqrt2pi * exp(-0.5 * z * z);
-                    const double g_r2 = -g_z / (2.0 * R * sa.sigma);
+                    const double g_r2 = -g_z * inv_2rs[kt];
                     g_xg += g_r2 * (2.0 * dx - 2.0 * b * uo);
                     g_yg += g_r2 * (2.0 * dy - 2.0 * b * vo);
                     g_uo += g_r2 * (-2.0 * b * dx);
@@ -1218,17 +1239,18 @@ __global__ void __launch_bounds__(256) soft_kernel(Args a, SoftArgs sa)
             if (MODE == 1 && (g_xg != 0.0 || g_yg != 0.0 || g_uo != 0.0 || g_vo != 0.0 || g_t != 0.0 ||
                               g_p != 0.0)) {
                 // ---- reverse through propagation
-                double g_pu = g_uo * ne / nobs + g_xg * Sser / pw;
-                double g_pv = g_vo * ne / nobs + g_yg * Sser / pw;
-                double g_ne = (g_uo * pu + g_vo * pv) / nobs;
-                g_psi0 += -(g_uo * pu + g_vo * pv) * ne / (nobs * nobs) / (2.0 * nobs);
-                const double g_T = g_t;
-                const double g_U = g_T * inv_c / (ne * pw);
-                g_ne += -g_T * T / ne;
-                double g_pw = -g_T * T / pw;
+                double g_pu = g_uo * ne * inv_nobs + g_xg * adv;
+                double g_pv = g_vo * ne * inv_nobs + g_yg * adv;
+                double g_ne = (g_uo * pu + g_vo * pv) * inv_nobs;
+                // n_obs = sqrt(1 + psi_0): d(1/n_obs)/d psi_0 = -1 / (2 n_obs^3)
+                g_psi0 -= (g_uo * pu + g_vo * pv) * ne * half_inv_nobs3;
+                const double g_U = g_t * inv_c * inv_ne * inv_pw;
+                g_ne -= g_t * T * inv_ne;
+                double g_pw = -g_t * T * inv_pw;
                 const double XS = g_xg * pu + g_yg * pv;
-                const double g_S = XS / pw;
-                g_pw += -XS * Sser / (pw * pw);
+                const double g_S = XS * inv_pw;
+                g_pw -= XS * adv * inv_pw;
+                const double qk[5] = {1.0, q, q * q, q * q * q, q * q * q * q};
                 double gD[6] = {0, 0, 0, 0, 0, 0};
                 double g_q = 0.0;
                 for (int kk = 0; kk < 5; ++kk) {
@@ -1239,33 +1261,34 @@ __global__ void __launch_bounds__(256) soft_kernel(Args a, SoftArgs sa)
                         g_q += (g_S * D[kk] + g_U * (ne2 * D[kk] + D[kk + 1])) * (double)kk * ak[kk] * qk[kk - 1];
                 }
                 double g_ne2 = g_U * Sser;
-                g_ne2 += -g_q * q / ne2;
-                g_pw += -2.0 * g_q * q / pw;
-                g_ne2 += g_ne / (2.0 * ne);
-                double g_psie = g_ne2;
-                for (int kk = 1; kk <= 5; ++kk) g_psie += -(double)kk * gD[kk] * D[kk - 1];
-                // dL/dP_j = sum_{k>=j} gD_k C(k,j) (-psi_e)^(k-j)
-                double g_pa = 0.0;
-                for (int jj = 1; jj <= 5; ++jj) {
-                    double gP = 0.0, binom = 1.0, cp_pow = 1.0;
-                    for (int kk = jj; kk <= 5; ++kk) {
-                        gP += gD[kk] * binom * cp_pow;
-                        binom = binom * (double)(kk + 1) / (double)(kk + 1 - jj);
-                        cp_pow *= cneg;
-                    }
-                    atomicAdd(&gP_l[(size_t)(jj - 1) * N + ie], gP);
-                    // partial-cell moment: dz/(j+1) h_j(pa, psi_e)
-                    double dha = 0.0, dhb = 0.0;
-                    for (int qq = 0; qq <= jj; ++qq) {
-                        if (jj - qq >= 1) dha += (double)(jj - qq) * pow_a[jj - qq - 1] * pow_b[qq];
-                        if (qq >= 1) dhb += (double)qq * pow_a[jj - qq] * pow_b[qq - 1];
-                    }
-                    const double wgt = dz / (double)(jj + 1);
-                    g_pa += gP * wgt * dha;
-                    g_psie += gP * wgt * dhb;
+                g_ne2 -= g_q * q * inv_ne * inv_ne;
+                g_pw -= 2.0 * g_q * q * inv_pw;
+                g_ne2 += g_ne * 0.5 * inv_ne;
+                // D_k as a function of (P_j(h_i), psi_i, psi_e):
+                //   dD_k/dpsi_e = -k D_{k-1} + dz del^(k-1) / (k+1)
+                //   dD_k/dpsi_i = dz k del^(k-1) / (k+1)
+                const double dpow[5] = {1.0, del, dl2, dl3, dl4};
+                double g_psie = g_ne2, g_pa = 0.0;
+#pragma unroll
+                for (int kk = 1; kk <= 5; ++kk) {
+                    const double inc = dz * dpow[kk - 1] * (1.0 / (double)(kk + 1));
+                    g_psie += gD[kk] * (inc - (double)kk * D[kk - 1]);
+                    g_pa += gD[kk] * ((double)kk * inc);
                 }
-                atomicAdd(&gpsi_l[ie], g_pa + (1.0 - fe) * g_psie);
-                atomicAdd(&gpsi_l[ie + 1], fe * g_psie);
+                // dL/dP_j(h_i): the Pascal shift transposed
+                double G1 = gD[1], G2 = gD[2], G3 = gD[3], G4 = gD[4], G5 = gD[5];
+                G4 += c * G5;
+                G3 += c * G4; G4 += c * G5;
+                G2 += c * G3; G3 += c * G4; G4 += c * G5;
+                G1 += c * G2; G2 += c * G3; G3 += c * G4; G4 += c * G5;
+                G1 += c * G2; G2 += c * G3; G3 += c * G4; G4 += c * G5;
+                add_bin(1, ie, G1);
+                add_bin(2, ie, G2);
+                add_bin(3, ie, G3);
+                add_bin(4, ie, G4);
+                add_bin(5, ie, G5);
+                add_bin(0, ie, g_pa + (1.0 - fe) * g_psie);
+                add_bin(0, ie + 1, fe * g_psie);
                 // ---- reverse through the direction on the cone and the yield
                 const double g_cos = g_pu * e.u + g_pv * e.v + g_pw * e.w;
                 const double g_sin = g_pu * Ex + g_pv * Ey - g_pw * Ez;
@@ -1293,18 +1316,19 @@ __global__ void __launch_bounds__(256) soft_kernel(Args a, SoftArgs sa)
             const double g_g1 = -0.5 * es.g_cos * es.cos_t * es.cos_t * es.cos_t + g_sin2 / (es.g1 * es.g1);
             const double g_psim = g_g1 * (1.0 - es.r2);
             if (g_psim != 0.0) {
-                atomicAdd(&gpsi_l[es.i_m], (1.0 - es.f_m) * g_psim);
-                atomicAdd(&gpsi_l[es.i_m + 1], es.f_m * g_psim);
+                add_bin(0, es.i_m, (1.0 - es.f_m) * g_psim);
+                add_bin(0, es.i_m + 1, es.f_m * g_psim);
             }
         }
         wave_lds_sync();
     }
     if (MODE == 1) {
-        if (g_psi0 != 0.0) atomicAdd(&gpsi_l[0], g_psi0);
+        if (g_psi0 != 0.0) add_bin(0, 0, g_psi0);
         __syncthreads();
-        for (int qq = threadIdx.x; qq < 6 * N; qq += blockDim.x) {
-            const double v = gpsi_l[qq];
-            if (v != 0.0) atomicAdd(qq < N ? &sa.g_psi[qq] : &sa.g_P[qq - N], v);
+        for (int qq = threadIdx.x; qq < 6 * NB; qq += blockDim.x) {
+            const double v = bins[qq];
+            const int j = qq / NB, i = qq - j * NB;
+            if (v != 0.0) atomicAdd(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
         }
     }
 }
@@ -1490,9 +1514,13 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     s.level_cells = ar->soft.level_cells;
     s.cell_off = ar->soft.d_cell_off;
     s.cell_list = ar->soft.d_cell_list;
-    const size_t lds = soft_bin_bytes(mode, a.n_nodes) + (size_t)kSoftWaves * soft_wave_bytes(a.n_tel);
+    // as many waves as the kernel's launch bounds allow and the LDS holds
+    const int wmax = soft_max_waves(mode);
+    int waves = p.emit_waves > 0 && p.emit_waves < wmax ? p.emit_waves : wmax;
+    while (waves > 1 && soft_lds_bytes(mode, a.n_nodes, a.n_tel, waves) > 160 * 1024) waves >>= 1;
+    const size_t lds = soft_lds_bytes(mode, a.n_nodes, a.n_tel, waves);
     if (lds > 160 * 1024) {
-        set_error("soft response: atmosphere table or telescope count too large for LDS");
+        set_error("soft response: telescope count too large for LDS");
         return CKV_ERR_TABLE;
     }
     init_kernel<<<1, 1024, 0, st>>>(a);
@@ -1513,14 +1541,14 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
             (void)hipFuncSetAttribute((const void*)soft_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
-        soft_kernel<0><<<p.emit_grid, kSoftWaves * kWave, lds, st>>>(a, s);
+        soft_kernel<0><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
     } else {
         static bool attr = false;
         if (!attr) {
             (void)hipFuncSetAttribute((const void*)soft_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
-        soft_kernel<1><<<p.emit_grid, kSoftWaves * kWave, lds, st>>>(a, s);
+        soft_kernel<1><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
     }
     if (int rc = check_launch("soft")) return rc;
     if (p.params.event_end) (void)hipEventRecord((hipEvent_t)p.params.event_end, st);
