@@ -91,6 +91,9 @@ def _declare(L):
     L.or_frank_tamm_k.argtypes = [D, D]
     L.or_soft.argtypes = [C.POINTER(_Config), C.POINTER(_Segments), P, D, C.c_int32, C.c_int, P, P]
     L.or_eta_param_many.argtypes = [D, C.c_int32, P, C.c_int32, D, P, I64, P, P]
+    L.or_build_depth.argtypes = [P, P, I64, D, D, I64, P]
+    L.or_profile.argtypes = [C.POINTER(_Config), C.POINTER(_Segments), P, D, C.c_int32, C.c_int32,
+                             C.c_int, P, P]
 
 
 def _p(a: np.ndarray):
@@ -115,6 +118,34 @@ class Tables:
     @property
     def h_top(self) -> float:
         return self.h_obs + (self.n_nodes - 1) * self.step
+
+
+def build_depth(alt, depth, t: Tables) -> np.ndarray:
+    """Vertical depth [g/cm^2] at the uniform nodes of t (linear in altitude)."""
+    alt = np.ascontiguousarray(alt, dtype=np.float64)
+    depth = np.ascontiguousarray(depth, dtype=np.float64)
+    T = np.empty(t.n_nodes)
+    lib().or_build_depth(_p(alt), _p(depth), alt.shape[0], t.h_obs, t.step, t.n_nodes, _p(T))
+    return T
+
+
+def profile_bins(T: np.ndarray, width: float) -> int:
+    """Number of depth bins of the given width that cover [0, X(h_obs)]."""
+    return int(np.floor(T[0] * (1.0 / width))) + 1
+
+
+def profile(cfg: "Config", segs, T: np.ndarray, width: float, nthreads: int = 1, seg_id_base=None,
+            seg_id=None):
+    """Longitudinal photon-production profile: (photons, bunches), each
+    (n_showers, n_bins), binned in vertical depth of the emission point."""
+    sv = SegView(segs, seg_id_base=seg_id_base, seg_id=seg_id)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    nb = profile_bins(T, width)
+    ph = np.zeros(sv.n_showers * nb)
+    bu = np.zeros(sv.n_showers * nb, dtype=np.int64)
+    lib().or_profile(C.byref(cfg.c), C.byref(sv.c), _p(T), float(width), nb, sv.n_showers,
+                     int(nthreads), _p(ph), _p(bu))
+    return ph.reshape(sv.n_showers, nb), bu.reshape(sv.n_showers, nb)
 
 
 def build_tables(alt, eta, h_obs: float, step: float = 0.0) -> Tables:

@@ -181,6 +181,18 @@ void or_lookup(const or_config* cf, double h, double* psi_out, double P_out[5])
     }
 }
 
+/* Vertical depth (atmospheric thickness, g/cm^2) on the same uniform grid: the
+   tabulated thickness interpolated linearly in altitude, as the index is
+   (sec. 3.3.1: one search per altitude serves density, thickness and index;
+   sec. 3.3.2: fine uniform tables built once). */
+int or_build_depth(const double* alt, const double* depth, int64_t n, double h_obs, double step,
+                   int64_t n_nodes, double* T)
+{
+    for (int64_t i = 0; i < n_nodes; ++i)
+        T[i] = or_eta_at(alt, depth, n, h_obs + (double)i * step);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Per-step setup (App. A: for each step the number of emitted photons is     */
 /* computed; the step is cut into sub-steps with one bunch of about 5 photons */
@@ -421,6 +433,72 @@ static void or_run_range(const or_config* cf, const or_segments* sg, int64_t lo,
    telescope order.  Grouping by (bucket, telescope) is left to the caller.
    Threads split the segments into contiguous ranges; results are joined in
    range order, so the output does not depend on the thread count. */
+/* ------------------------------------------------------------------------- */
+/* Longitudinal profile of Cherenkov photon production (the CERLDE output,     */
+/* sec. 4.3.3 and 5.2.2): for every shower, the photons and bunches emitted in  */
+/* bins of vertical depth X of the emission point, bin b = floor(X / width)    */
+/* (multiplied by 1/width), counting every bunch emitted inside the tables,    */
+/* h_obs <= h_e < h_top, whatever its direction.  X(h_e) is read from the depth */
+/* table exactly as psi is: x = (h - h_obs) / step, i = floor(x), linear in f.  */
+/* ------------------------------------------------------------------------- */
+static void or_profile_range(const or_config* cf, const or_segments* sg, const double* T,
+                             double inv_width, int32_t n_bins, int64_t lo, int64_t hi,
+                             double* photons, int64_t* bunches)
+{
+    int64_t N = cf->n_nodes;
+    double h_top = cf->h_obs + (double)(N - 1) * cf->step;
+    uint32_t key[2] = {(uint32_t)cf->seed, (uint32_t)(cf->seed >> 32)};
+    for (int64_t i = lo; i < hi; ++i) {
+        or_setup st;
+        or_segment_setup(cf, sg, i, &st);
+        if (st.status >= 0) continue;
+        for (int64_t k = 0; k < st.n_b; ++k) {
+            uint32_t ctr[4] = {(uint32_t)k, sg->seg_id[i], sg->shower_id[i], 0u}, r[4];
+            or_philox4x32_10(ctr, key, r);
+            double s = ((double)k + or_uniform(r[0])) * st.ds;
+            double h_e = sg->h0[i] - s * sg->w[i];
+            if (h_e < cf->h_obs || h_e >= h_top) continue;
+            double x = (h_e - cf->h_obs) * (1.0 / cf->step);
+            int64_t c = (int64_t)floor(x);
+            if (c > N - 2) c = N - 2;
+            double f = x - (double)c;
+            double X = T[c] + f * (T[c + 1] - T[c]);
+            int64_t b = (int64_t)floor(X * inv_width);
+            if (b < 0) b = 0;
+            if (b > n_bins - 1) b = n_bins - 1;
+            int64_t g = (int64_t)sg->bucket[i] * n_bins + b;
+            photons[g] += st.photons;
+            bunches[g] += 1;
+        }
+    }
+}
+
+/* photons and bunches: n_groups x n_bins each, zeroed here */
+int or_profile(const or_config* cf, const or_segments* sg, const double* T, double width,
+               int32_t n_bins, int32_t n_groups, int nthreads, double* photons, int64_t* bunches)
+{
+    if (nthreads < 1) nthreads = 1;
+    size_t m = (size_t)n_groups * n_bins;
+    double* ph = (double*)calloc((size_t)nthreads * m, sizeof(double));
+    int64_t* bu = (int64_t*)calloc((size_t)nthreads * m, sizeof(int64_t));
+    double inv_width = 1.0 / width;
+#pragma omp parallel for schedule(static, 1) num_threads(nthreads)
+    for (int t = 0; t < nthreads; ++t) {
+        int64_t lo = sg->n * t / nthreads, hi = sg->n * (t + 1) / nthreads;
+        or_profile_range(cf, sg, T, inv_width, n_bins, lo, hi, ph + (size_t)t * m, bu + (size_t)t * m);
+    }
+    for (size_t q = 0; q < m; ++q) {
+        double a = 0.0;
+        int64_t c = 0;
+        for (int t = 0; t < nthreads; ++t) { a += ph[(size_t)t * m + q]; c += bu[(size_t)t * m + q]; }
+        photons[q] = a;
+        bunches[q] = c;
+    }
+    free(ph);
+    free(bu);
+    return 0;
+}
+
 or_result* or_run(const or_config* cf, const or_segments* sg, int nthreads, int64_t* n_b_out)
 {
     or_result* res = (or_result*)calloc(1, sizeof(or_result));
