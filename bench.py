@@ -78,6 +78,7 @@ PEAK_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 SEG_BYTES = 9 * 8 + 1            # SoA step record read once
 STAGE_BYTES = 64                 # staging entry written and read back
+PROFILE_BIN_GCM2 = 20.0          # depth bin of the longitudinal profile run
 RECORD_BYTES = 32                # output record
 
 
@@ -393,7 +394,16 @@ def main(argv=None):
                                             capacity, args.steps, args.warmup, stream)
     print(f"# fp64: {ms_fp64:.3f} ms/step, bunch kernel {kms_fp64:.3f} ms", file=sys.stderr,
           flush=True)
-    for res in (res_mixed, res_fp64):
+    # the same run with the longitudinal photon-production profile (20 g/cm^2 bins)
+    atmo_d = ckv.Atmosphere(wl.atmo.alt, wl.atmo.eta, wl.atmo.obs_level, wl.fine_step,
+                            depth=wl.atmo.vertical_depth())
+    p_prof = autotune.apply(mk(ckv.CKV_MIXED), tuned[ckv.CKV_MIXED])
+    p_prof.depth_bin_gcm2 = PROFILE_BIN_GCM2
+    ms_prof, kms_prof, res_prof = time_path(hip, ckv, dsegs, atmo_d, tels, p_prof, capacity,
+                                            args.steps, args.warmup, stream)
+    print(f"# mixed + profile: {ms_prof:.3f} ms/step, bunch kernel {kms_prof:.3f} ms", file=sys.stderr,
+          flush=True)
+    for res in (res_mixed, res_fp64, res_prof):
         if res["error"] or res["overflow"]:
             raise RuntimeError(f"run reported a problem: {res}")
     nb = res_mixed["n_bunches"]
@@ -440,6 +450,9 @@ def main(argv=None):
                        "roofline_frac": sum(OPS_FP64.values()) * nb / (kms_fp64 * 1e-3)
                        / PEAK_OPS_PER_S},
         "mixed_over_fp64": ms_fp64 / ms_mixed,
+        "with_profile": {"bin_gcm2": PROFILE_BIN_GCM2, "bins": atmo_d.profile_bins(PROFILE_BIN_GCM2),
+                         "ms_per_step": ms_prof, "bunch_kernel_ms": kms_prof,
+                         "value": nb / (ms_prof * 1e-3), "overhead": ms_prof / ms_mixed - 1.0},
         "bunch_kernel_ms": kms_mixed,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak,

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define CKV_VERSION 100
+#define CKV_VERSION 110
 
 enum {
     CKV_OK = 0,
@@ -93,6 +93,24 @@ int ckv_version(void);
  * ------------------------------------------------------------------------- */
 int ckv_atmo_create(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
                     double step_m, ckv_atmo** out);
+/* As ckv_atmo_create, with the vertical depth (atmospheric thickness, g/cm^2)
+   tabulated at the same altitudes: depth_gcm2[n], finite, non-increasing with
+   altitude, host memory, copied.  The library samples it onto the same uniform
+   grid the same way as eta (sec. 3.3.1: one search per altitude serves the
+   thickness and the index; sec. 3.3.2: fine uniform tables built once), which
+   enables the longitudinal profile of ckv_run (depth_bin_gcm2 > 0).
+   Errors: as ckv_atmo_create; CKV_ERR_TABLE also for a depth that increases
+   with altitude or is not finite. */
+int ckv_atmo_create_with_depth(const double* alt_m, const double* eta, const double* depth_gcm2,
+                               int64_t n, double obs_level_m, double step_m, ckv_atmo** out);
+/* Host copy of the depth at the grid nodes, depth[n_nodes].  CKV_ERR_ARG if
+   the handle has no depth table. */
+int ckv_atmo_depth(const ckv_atmo* atmo, double* depth);
+/* Bins of width bin_gcm2 that cover depths [0, X(h_obs)]: floor(X(h_obs) /
+   bin_gcm2) + 1 (X(h_obs) times 1/bin_gcm2).  CKV_ERR_ARG without a depth
+   table, for bin_gcm2 <= 0, or above CKV_MAX_PROFILE_BINS bins. */
+#define CKV_MAX_PROFILE_BINS 128
+int ckv_profile_bins(const ckv_atmo* atmo, double bin_gcm2, int32_t* n_bins);
 /* Grid of the handle: node count, observation level, step. */
 int ckv_atmo_info(const ckv_atmo* atmo, int64_t* n_nodes, double* obs_level_m, double* step_m);
 /* Host copies of the tables: psi[n_nodes], P[5*n_nodes] with
@@ -157,6 +175,9 @@ typedef struct {
                               fit is lowered to one that does */
     void* event_begin;     /* optional hipEvent_t recorded on the stream just before */
     void* event_end;       /* and just after the bunch kernel (profiling); NULL = none */
+    double depth_bin_gcm2; /* > 0: also accumulate the longitudinal photon-production
+                              profile in bins of this width (needs an atmosphere with a
+                              depth table); 0 = no profile */
 } ckv_params;
 
 /* Device-side report, written by ckv_run (the caller syncs the stream before
@@ -180,13 +201,23 @@ typedef struct {
    [m, m, -, -, ns, m, photons, nm].  Records of shower s and telescope k are
    records[tel_offsets[s*n_tel + k] .. tel_offsets[s*n_tel + k + 1]), in
    ascending (step, bunch) order.  ids (optional, NULL to skip): capacity x 2
-   int64 per record = (index of the step in the segment arrays, bunch k). */
+   int64 per record = (index of the step in the segment arrays, bunch k).
+   Longitudinal profile (the CERLDE output, sec. 4.3.3 and 5.2.2; only when
+   params->depth_bin_gcm2 > 0): n_showers x n_bins each (ckv_profile_bins),
+   photons and bunches emitted per shower in bins of vertical depth X of the
+   emission point, bin floor(X * (1/width)), counting every bunch emitted at
+   h_obs <= h < h_top whatever its direction; X is the depth table read like
+   the index, in FP64 without contraction, so bins match the FP64 definition
+   exactly.  Overwritten by each run (photon sums in FP64 by atomics: their
+   rounding order varies). */
 typedef struct {
     float* records;
     int64_t* ids;
     int64_t capacity;
     int64_t* tel_offsets;    /* n_showers * n_tel + 1 */
     ckv_result* result;
+    double* profile_photons;   /* n_showers * n_bins, or NULL without a profile */
+    int64_t* profile_bunches;  /* n_showers * n_bins, or NULL without a profile */
 } ckv_output;
 
 /* Bytes of device workspace ckv_run needs for these sizes. */
@@ -199,8 +230,9 @@ size_t ckv_workspace_size(int64_t n_segments, int32_t n_showers, int32_t n_tel,
    enqueues kernels only, so it can be captured into a HIP graph.
    workspace: device memory of ws_bytes >= ckv_workspace_size(...), any
    content.  Errors (synchronous): CKV_ERR_ARG for null pointers, n < 0,
-   n_showers < 1, bad params; CKV_ERR_CAPACITY for a small workspace;
-   CKV_ERR_HIP if a launch fails. */
+   n_showers < 1, bad params, a profile asked for without a depth table, with
+   too many bins or without its output arrays; CKV_ERR_CAPACITY for a small
+   workspace; CKV_ERR_HIP if a launch fails. */
 int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
             const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
             ckv_output* out, void* stream);

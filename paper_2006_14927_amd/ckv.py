@@ -25,7 +25,8 @@ RECORD_FIELDS = ("dx", "dy", "u_obs", "v_obs", "t", "h_emit", "photons", "lambda
 EXPORTED = ("ckv_last_error", "ckv_version", "ckv_atmo_create", "ckv_atmo_info", "ckv_atmo_tables",
             "ckv_atmo_destroy", "ckv_array_create", "ckv_array_destroy", "ckv_workspace_size",
             "ckv_run", "ckv_count", "ckv_atmo_from_params", "ckv_atmo_params_backward",
-            "ckv_array_create_soft", "ckv_soft_forward", "ckv_soft_backward")
+            "ckv_array_create_soft", "ckv_soft_forward", "ckv_soft_backward",
+            "ckv_atmo_create_with_depth", "ckv_atmo_depth", "ckv_profile_bins")
 
 
 class CkvError(RuntimeError):
@@ -47,7 +48,7 @@ class _Params(C.Structure):
                 ("lambda_max_nm", C.c_double), ("w_min", C.c_double), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("tile_segments", C.c_int32), ("grid", C.c_int32),
                 ("waves_per_group", C.c_int32), ("event_begin", C.c_void_p),
-                ("event_end", C.c_void_p)]
+                ("event_end", C.c_void_p), ("depth_bin_gcm2", C.c_double)]
 
 
 class _Result(C.Structure):
@@ -64,7 +65,8 @@ class _ParamSpec(C.Structure):
 
 class _Output(C.Structure):
     _fields_ = [("records", C.c_void_p), ("ids", C.c_void_p), ("capacity", C.c_int64),
-                ("tel_offsets", C.c_void_p), ("result", C.c_void_p)]
+                ("tel_offsets", C.c_void_p), ("result", C.c_void_p),
+                ("profile_photons", C.c_void_p), ("profile_bunches", C.c_void_p)]
 
 
 RESULT_BYTES = C.sizeof(_Result)
@@ -82,6 +84,9 @@ def lib():
         L.ckv_last_error.restype = C.c_char_p
         L.ckv_version.restype = C.c_int
         L.ckv_atmo_create.argtypes = [P, P, I64, D, D, C.POINTER(P)]
+        L.ckv_atmo_create_with_depth.argtypes = [P, P, P, I64, D, D, C.POINTER(P)]
+        L.ckv_atmo_depth.argtypes = [P, P]
+        L.ckv_profile_bins.argtypes = [P, D, P]
         L.ckv_atmo_info.argtypes = [P, P, P, P]
         L.ckv_atmo_tables.argtypes = [P, P, P]
         L.ckv_atmo_destroy.argtypes = [P]
@@ -119,16 +124,35 @@ def _np_ptr(a: np.ndarray):
 class Atmosphere:
     """ckv_atmo: uniform fine tables built from a tabulated n-1 profile."""
 
-    def __init__(self, alt=None, eta=None, obs_level: float = 0.0, step: float = 0.0, handle=None):
+    def __init__(self, alt=None, eta=None, obs_level: float = 0.0, step: float = 0.0, handle=None,
+                 depth=None):
         if handle is not None:          # adopt a handle made by another constructor
             self.handle = handle
             return
         self._alt = np.ascontiguousarray(alt, dtype=np.float64)
         self._eta = np.ascontiguousarray(eta, dtype=np.float64)
         h = C.c_void_p()
-        _check(lib().ckv_atmo_create(_np_ptr(self._alt), _np_ptr(self._eta), self._alt.shape[0],
-                                     float(obs_level), float(step), C.byref(h)))
+        if depth is None:
+            _check(lib().ckv_atmo_create(_np_ptr(self._alt), _np_ptr(self._eta), self._alt.shape[0],
+                                         float(obs_level), float(step), C.byref(h)))
+        else:
+            self._depth = np.ascontiguousarray(depth, dtype=np.float64)
+            _check(lib().ckv_atmo_create_with_depth(_np_ptr(self._alt), _np_ptr(self._eta),
+                                                    _np_ptr(self._depth), self._alt.shape[0],
+                                                    float(obs_level), float(step), C.byref(h)))
         self.handle = h
+
+    def depth(self) -> np.ndarray:
+        """Vertical depth [g/cm^2] at the grid nodes."""
+        n, _, _ = self.info()
+        out = np.empty(n)
+        _check(lib().ckv_atmo_depth(self.handle, _np_ptr(out)))
+        return out
+
+    def profile_bins(self, width_gcm2: float) -> int:
+        nb = C.c_int32()
+        _check(lib().ckv_profile_bins(self.handle, float(width_gcm2), C.byref(nb)))
+        return nb.value
 
     def info(self):
         n = C.c_int64()
@@ -247,10 +271,11 @@ class DeviceSegments:
 
 def make_params(*, precision=CKV_MIXED, bunch_size=5.0, lambda_min=300.0, lambda_max=600.0,
                 w_min=0.1, seed=0x14927, tile_segments=0, grid=0, waves_per_group=0,
-                event_begin=None, event_end=None) -> _Params:
+                event_begin=None, event_end=None, depth_bin=0.0) -> _Params:
+    """depth_bin > 0 [g/cm^2]: also the longitudinal photon-production profile."""
     return _Params(bunch_size, lambda_min, lambda_max, w_min, int(seed) & (2**64 - 1),
                    int(precision), int(tile_segments), int(grid), int(waves_per_group),
-                   event_begin, event_end)
+                   event_begin, event_end, float(depth_bin))
 
 
 def workspace_size(n_segments, n_showers, n_tel, capacity, params: _Params) -> int:
@@ -269,6 +294,8 @@ class RunOutput:
     ids: "object"           # torch int64 (capacity, 2) or None
     tel_offsets: "object"   # torch int64 (n_showers*n_tel + 1)
     result_raw: "object"    # torch uint8 (RESULT_BYTES)
+    profile_photons: "object" = None   # torch float64 (n_showers, n_bins) or None
+    profile_bunches: "object" = None   # torch int64 (n_showers, n_bins) or None
 
     def result(self) -> dict:
         r = _Result.from_buffer_copy(self.result_raw.cpu().numpy().tobytes())
@@ -293,17 +320,25 @@ class Runner:
             if want_ids else None
         self.tel_offsets = torch.empty(dsegs.n_showers * tels.n + 1, dtype=torch.int64, device=device)
         self.result_raw = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
+        self.profile_photons = self.profile_bunches = None
+        if params.depth_bin_gcm2 > 0:
+            nb = atmo.profile_bins(params.depth_bin_gcm2)
+            self.profile_photons = torch.empty((dsegs.n_showers, nb), dtype=torch.float64, device=device)
+            self.profile_bunches = torch.empty((dsegs.n_showers, nb), dtype=torch.int64, device=device)
         self._segs = dsegs.c_segments()
         self._showers = dsegs.c_showers()
         self._out = _Output(self.records.data_ptr(),
                             self.ids.data_ptr() if self.ids is not None else None,
-                            self.capacity, self.tel_offsets.data_ptr(), self.result_raw.data_ptr())
+                            self.capacity, self.tel_offsets.data_ptr(), self.result_raw.data_ptr(),
+                            self.profile_photons.data_ptr() if self.profile_photons is not None else None,
+                            self.profile_bunches.data_ptr() if self.profile_bunches is not None else None)
 
     def run(self, stream=None) -> RunOutput:
         _check(lib().ckv_run(C.byref(self._segs), C.byref(self._showers), C.byref(self.params),
                              self.atmo.handle, self.tels.handle, C.c_void_p(self.workspace.data_ptr()),
                              self.workspace.numel(), C.byref(self._out), _stream_ptr(stream)))
-        return RunOutput(self.records, self.ids, self.tel_offsets, self.result_raw)
+        return RunOutput(self.records, self.ids, self.tel_offsets, self.result_raw,
+                         self.profile_photons, self.profile_bunches)
 
 
 def count(dsegs: DeviceSegments, atmo: Atmosphere, params: _Params, stream=None):
@@ -376,6 +411,8 @@ class Streamer:
                  first_ratio: float = 0.05, max_range: Optional[int] = None,
                  plan_block: int = 4096, device="cuda"):
         import torch
+        if params.depth_bin_gcm2 > 0:
+            raise CkvError("Streamer: run the longitudinal profile with Runner (one launch)")
         self.dsegs, self.atmo, self.tels, self.params = dsegs, atmo, tels, params
         self.capacity = int(chunk_records)
         self.want_ids = want_ids

@@ -21,6 +21,20 @@ int hip_fail(const char* what, hipError_t e)
     return CKV_ERR_HIP;
 }
 
+int profile_bins(const ckv_atmo* atmo, double bin_gcm2, int32_t* n_bins)
+{
+    if (atmo->depth.empty()) { set_error("the atmosphere has no depth table"); return CKV_ERR_ARG; }
+    if (!(bin_gcm2 > 0.0) || !std::isfinite(bin_gcm2)) {
+        set_error("depth bin width must be > 0"); return CKV_ERR_ARG;
+    }
+    const double nb = std::floor(atmo->depth[0] * (1.0 / bin_gcm2)) + 1.0;
+    if (!(nb <= (double)CKV_MAX_PROFILE_BINS)) {
+        set_error("more than CKV_MAX_PROFILE_BINS depth bins"); return CKV_ERR_ARG;
+    }
+    *n_bins = (int32_t)nb;
+    return CKV_OK;
+}
+
 int device_cu_count(int* n_cu)
 {
     int dev = 0;
@@ -67,6 +81,9 @@ int check_params(const ckv_params* p)
     if (p->waves_per_group != 0 && p->waves_per_group != 1 && p->waves_per_group != 2 &&
         p->waves_per_group != 4 && p->waves_per_group != 8 && p->waves_per_group != 16) {
         set_error("waves_per_group must be 0, 1, 2, 4, 8 or 16"); return CKV_ERR_ARG;
+    }
+    if (!(p->depth_bin_gcm2 >= 0.0) || !std::isfinite(p->depth_bin_gcm2)) {
+        set_error("depth_bin_gcm2 must be >= 0"); return CKV_ERR_ARG;
     }
     return CKV_OK;
 }
@@ -143,8 +160,8 @@ size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, in
 
 using namespace ckv;
 
-static int atmo_create(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
-                       double step_m, ckv_atmo** out);
+static int atmo_create(const double* alt_m, const double* eta, const double* depth, int64_t n,
+                       double obs_level_m, double step_m, ckv_atmo** out);
 
 extern "C" {
 
@@ -152,8 +169,8 @@ const char* ckv_last_error(void) { return g_error.c_str(); }
 
 int ckv_version(void) { return CKV_VERSION; }
 
-int ckv_atmo_create(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
-                    double step_m, ckv_atmo** out)
+int ckv_atmo_create_with_depth(const double* alt_m, const double* eta, const double* depth_gcm2,
+                               int64_t n, double obs_level_m, double step_m, ckv_atmo** out)
 {
     if (!alt_m || !eta || !out) { set_error("NULL argument"); return CKV_ERR_ARG; }
     *out = nullptr;
@@ -167,8 +184,32 @@ int ckv_atmo_create(const double* alt_m, const double* eta, int64_t n, double ob
         if (i > 0 && !(alt_m[i] > alt_m[i - 1])) {
             set_error("atmosphere: altitudes must increase strictly"); return CKV_ERR_TABLE;
         }
+        if (depth_gcm2 && (!std::isfinite(depth_gcm2[i]) || (i > 0 && depth_gcm2[i] > depth_gcm2[i - 1]))) {
+            set_error("atmosphere: depth must be finite and non-increasing with altitude");
+            return CKV_ERR_TABLE;
+        }
     }
-    return atmo_create(alt_m, eta, n, obs_level_m, step_m, out);
+    return atmo_create(alt_m, eta, depth_gcm2, n, obs_level_m, step_m, out);
+}
+
+int ckv_atmo_create(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
+                    double step_m, ckv_atmo** out)
+{
+    return ckv_atmo_create_with_depth(alt_m, eta, nullptr, n, obs_level_m, step_m, out);
+}
+
+int ckv_atmo_depth(const ckv_atmo* atmo, double* depth)
+{
+    if (!atmo || !depth) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    if (atmo->depth.empty()) { set_error("the atmosphere has no depth table"); return CKV_ERR_ARG; }
+    std::memcpy(depth, atmo->depth.data(), sizeof(double) * atmo->depth.size());
+    return CKV_OK;
+}
+
+int ckv_profile_bins(const ckv_atmo* atmo, double bin_gcm2, int32_t* n_bins)
+{
+    if (!atmo || !n_bins) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    return profile_bins(atmo, bin_gcm2, n_bins);
 }
 
 
@@ -181,7 +222,8 @@ int ckv_atmo_from_params(const ckv_atmo_param_spec* spec, const double* theta, c
     std::vector<double> alt, eta;
     param_profile(spec, theta, &alt, &eta);
     if (alt.size() < 2) { set_error("fewer than two nodes"); return CKV_ERR_ARG; }
-    return atmo_create(alt.data(), eta.data(), (int64_t)alt.size(), spec->obs_level_m, spec->step_m, out);
+    return atmo_create(alt.data(), eta.data(), nullptr, (int64_t)alt.size(), spec->obs_level_m,
+                       spec->step_m, out);
 }
 
 int ckv_atmo_params_backward(const ckv_atmo_param_spec* spec, const double* theta,
@@ -217,6 +259,7 @@ int ckv_atmo_destroy(ckv_atmo* a)
     if (!a) return CKV_OK;
     if (a->d_node64) (void)hipFree(a->d_node64);
     if (a->d_cell32) (void)hipFree(a->d_cell32);
+    if (a->d_depth) (void)hipFree(a->d_depth);
     delete a;
     return CKV_OK;
 }
@@ -329,8 +372,17 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
         set_error("output: tel_offsets, result and records (capacity > 0) are required");
         return CKV_ERR_ARG;
     }
+    int32_t prof_bins = 0;
+    if (params->depth_bin_gcm2 > 0.0) {
+        if ((rc = profile_bins(atmo, params->depth_bin_gcm2, &prof_bins))) return rc;
+        if (!out->profile_photons || !out->profile_bunches) {
+            set_error("output: profile_photons and profile_bunches are required for a profile");
+            return CKV_ERR_ARG;
+        }
+    }
     if ((rc = current_device(atmo->device)) || (rc = current_device(arr->device))) return rc;
     RunPlan plan{};
+    plan.prof_bins = prof_bins;
     size_t need = workspace_layout(segs->n, showers->n_showers, arr->n_tel, out->capacity, params,
                                    &plan, workspace);
     if (ws_bytes < need) {
@@ -434,13 +486,14 @@ int ckv_count(const ckv_segments* segs, const ckv_params* params, const ckv_atmo
 
 }  // extern "C"
 
-static int atmo_create(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
-                       double step_m, ckv_atmo** out)
+static int atmo_create(const double* alt_m, const double* eta, const double* depth, int64_t n,
+                       double obs_level_m, double step_m, ckv_atmo** out)
 {
     ckv_atmo* a = new (std::nothrow) ckv_atmo();
     if (!a) { set_error("out of host memory"); return CKV_ERR_NOMEM; }
     int rc = build_atmo_tables(alt_m, eta, n, obs_level_m, step_m, a);
     if (rc) { delete a; return rc; }
+    if (depth) build_depth_table(alt_m, depth, n, a);
     if (a->n_nodes > (1 << 20)) { delete a; set_error("atmosphere table too fine"); return CKV_ERR_TABLE; }
     {
         const hipError_t e = hipGetDevice(&a->device);
@@ -461,7 +514,8 @@ static int atmo_create(const double* alt_m, const double* eta, int64_t n, double
         c[7] = (float)((double)i * a->step);   // node height above the observation level
     }
     if ((rc = upload(node.data(), node.size(), &a->d_node64)) ||
-        (rc = upload(cell.data(), cell.size(), &a->d_cell32))) {
+        (rc = upload(cell.data(), cell.size(), &a->d_cell32)) ||
+        (!a->depth.empty() && (rc = upload(a->depth.data(), a->depth.size(), &a->d_depth)))) {
         ckv_atmo_destroy(a);
         return rc;
     }

@@ -75,6 +75,8 @@ struct ckv_atmo {
     std::vector<double> P;           // host, 5 x n_nodes
     double* d_node64 = nullptr;      // device, n_nodes x kNode64
     float* d_cell32 = nullptr;       // device, (n_nodes - 1) x kCell32
+    std::vector<double> depth;       // host, n_nodes, vertical depth [g/cm^2]; empty: none
+    double* d_depth = nullptr;       // device copy of depth
 };
 
 // Candidate grid: cells of size `cell` starting at (gx0, gy0); the list of
@@ -107,6 +109,8 @@ void set_error(const std::string& msg);
 // host builders (ckv_tables.cpp)
 int build_atmo_tables(const double* alt, const double* eta, int64_t n, double h_obs, double step,
                       ckv_atmo* a);
+// depth at the nodes of a (after build_atmo_tables), the same interpolation as eta
+void build_depth_table(const double* alt, const double* depth, int64_t n, ckv_atmo* a);
 int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ckv_grid* g);
 constexpr double kSoftZCut = 40.0;   // Phi(-40) underflows to exactly 0 in FP64
 int param_spec_check(const ckv_atmo_param_spec* sp, const double* theta);
@@ -131,6 +135,7 @@ struct RunPlan {
     int32_t tile_segs;
     int64_t max_tiles, max_row_blocks, stage_slots;
     int32_t emit_grid, emit_waves;
+    int32_t prof_bins;          // longitudinal-profile bins, 0 = no profile
     double k_ft;
     // workspace carve-out
     int64_t* ctrl;
@@ -148,7 +153,7 @@ size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, in
 int launch_run(RunPlan& plan);
 int launch_count(const ckv_segments* segs, const ckv_params* p, const ckv_atmo* atmo, double k_ft,
                  int64_t* n_b, hipStream_t stream);
-int emit_config(int precision, int n_tel, const ckv_atmo* atmo, int tile_segs, int* waves,
+int emit_config(int precision, int n_tel, int prof_bins, const ckv_atmo* atmo, int tile_segs, int* waves,
                 size_t* lds_bytes);
 
 struct SoftPlan {

@@ -45,6 +45,13 @@ struct Args {
     double h_obs, step, inv_step, h_top, n_obs;
     const double* node64;
     const float* cell32;
+    int32_t lds_entries;        // table entries staged in LDS (the rest read from HBM)
+    // longitudinal profile (prof_bins = 0: none)
+    const double* depth;        // n_nodes, vertical depth [g/cm^2]
+    double* prof_ph;            // n_showers x prof_bins
+    int64_t* prof_bu;
+    double inv_bin;
+    int32_t prof_bins;
     // telescopes and candidate grid
     int32_t n_tel;
     const double* tel;          // X, Y, R, R^2
@@ -255,6 +262,19 @@ __device__ __forceinline__ void sincos_turns(uint32_t r, float& s, float& c)
 // compacted), a 64-entry flag row used to map bunches to steps, the per-
 // telescope crossing counters of the tile, and the wave's run counters.
 // --------------------------------------------------------------------------
+// Depth bin of an emission altitude h_obs <= h < h_top, given its table cell c
+// and fraction f (x = (h - h_obs) / step, c = floor(x), f = x - c): the depth
+// table read like the index and binned by floor(X * (1/width)), in FP64
+// without contraction, so the bin is the one the FP64 definition gives.
+__device__ __forceinline__ int profile_bin(const Args& a, int c, double f)
+{
+#pragma clang fp contract(off)
+    const double X = a.depth[c] + f * (a.depth[c + 1] - a.depth[c]);
+    int b = (int)floor(X * a.inv_bin);
+    b = max(0, min(b, a.prof_bins - 1));
+    return b;
+}
+
 template <int PREC>
 struct StepEntry;
 
@@ -262,10 +282,11 @@ struct StepEntry;
 template <>
 struct alignas(16) StepEntry<1> {
     double x0, y0, h0, t0, u, v, w, cos_t, ds, inv_bc;
-    float sb1x, sb1y, sb1z, sb2x, sb2y, sb2z, photons;
+    double photons;  // FP64: the longitudinal profile sums it
+    float sb1x, sb1y, sb1z, sb2x, sb2y, sb2z;
     int32_t boff;   // first bunch of the step inside the tile
     int32_t sidx;   // index of the step inside the tile
-    int32_t pad[3];
+    int32_t pad[2];
 };
 static_assert(sizeof(StepEntry<1>) == 128, "step entry size");
 
@@ -281,25 +302,38 @@ static_assert(sizeof(StepEntry<0>) == 144, "step entry size");
 // per-wave counters kept in LDS (wave-uniform increments by lane 0)
 enum WaveCounter { kWcBunches = 0, kWcEmitting, kWcHits, kWcDrop0, kWcCount = kWcDrop0 + CKV_N_DROP };
 
-__host__ __device__ inline size_t table_bytes(int prec, int n_nodes)
+// Without the profile the whole table is staged in LDS.  With it, only the
+// lowest kLdsTableEntries entries (nodes for FP64, cells for mixed, i.e. up to
+// 76.8 km above the observation level on a 50 m grid) are, to leave room for
+// the per-wave histograms; lookups above them read the same entries from HBM.
+constexpr int kLdsTableEntries = 1536;
+
+__host__ __device__ inline int lds_entries(int prec, int n_nodes, bool prof)
 {
-    return prec == 0 ? (size_t)n_nodes * kNode64 * sizeof(double)
-                     : (size_t)(n_nodes - 1) * kCell32 * sizeof(float);
+    const int n = prec == 0 ? n_nodes : n_nodes - 1;
+    return prof && n > kLdsTableEntries ? kLdsTableEntries : n;
 }
 
-__host__ __device__ inline size_t wave_bytes(int prec, int tile_segs, int n_tel)
+__host__ __device__ inline size_t table_bytes(int prec, int n_nodes, bool prof)
+{
+    return (size_t)lds_entries(prec, n_nodes, prof) *
+           (prec == 0 ? kNode64 * sizeof(double) : kCell32 * sizeof(float));
+}
+
+__host__ __device__ inline size_t wave_bytes(int prec, int tile_segs, int n_tel, int prof_bins)
 {
     size_t b = (size_t)tile_segs * (prec == 0 ? sizeof(StepEntry<0>) : sizeof(StepEntry<1>));
     b += kWave * sizeof(int32_t);                       // flag row
     b += (size_t)kWcCount * sizeof(int64_t);            // counters
     b += ((size_t)n_tel * sizeof(int32_t) + 15) & ~(size_t)15;   // telescope counters
+    b += (size_t)prof_bins * (sizeof(double) + sizeof(uint32_t));  // profile of the tile
     return (b + 15) & ~(size_t)15;
 }
 
 // --------------------------------------------------------------------------
 // the bunch kernel
 // --------------------------------------------------------------------------
-template <int PREC, int TS>
+template <int PREC, int TS, bool PROF>
 __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
 {
     using T = typename std::conditional<PREC == 0, double, float>::type;
@@ -310,7 +344,7 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
     const int wave = threadIdx.x / kWave;
 
     // ---- stage the atmosphere table once per workgroup
-    const size_t tab_bytes = table_bytes(PREC, a.n_nodes);
+    const size_t tab_bytes = table_bytes(PREC, a.n_nodes, PROF);
     {
         const uint4* src = reinterpret_cast<const uint4*>(PREC == 0 ? (const void*)a.node64
                                                                     : (const void*)a.cell32);
@@ -319,12 +353,18 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
         for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
     }
     unsigned char* wbase = lds + ((tab_bytes + 15) & ~(size_t)15) +
-                           (size_t)wave * wave_bytes(PREC, TS, a.n_tel);
+                           (size_t)wave * wave_bytes(PREC, TS, a.n_tel, PROF ? a.prof_bins : 0);
     Entry* stash = reinterpret_cast<Entry*>(wbase);
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + TS * sizeof(Entry));
     int64_t* wcnt = reinterpret_cast<int64_t*>(flags + kWave);
     int32_t* tcount = reinterpret_cast<int32_t*>(wcnt + kWcCount);
+    // profile of the current tile: photons (FP64) and bunches per depth bin
+    double* hph = reinterpret_cast<double*>(
+        reinterpret_cast<unsigned char*>(tcount) + (((size_t)a.n_tel * sizeof(int32_t) + 15) & ~(size_t)15));
+    uint32_t* hbu = reinterpret_cast<uint32_t*>(hph + a.prof_bins);
     for (int k = lane; k < a.n_tel; k += kWave) tcount[k] = 0;
+    if (PROF)
+        for (int k = lane; k < a.prof_bins; k += kWave) { hph[k] = 0.0; hbu[k] = 0u; }
     if (lane < kWcCount) wcnt[lane] = 0;
     flags[lane] = 0;
     __syncthreads();
@@ -406,7 +446,7 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
             e.sb2x = (T)(st.sin_t * st.b2x);
             e.sb2y = (T)(st.sin_t * st.b2y);
             e.sb2z = (T)(st.sin_t * st.b2z);
-            e.photons = (T)st.photons;
+            e.photons = st.photons;
             e.boff = excl;
             e.sidx = lane;
         }
@@ -446,6 +486,9 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
             double xg, yg, he, tarr;
             float uo, vo, lam, photons, he_f, t_f;
             int32_t k, sidx;
+            int pbin = -1;     // depth bin of the bunch for the profile, -1: not counted
+            double xcell;
+            int ci;
             if (active) {
                 const Entry& e = stash[si];
                 k = j - e.boff;
@@ -472,8 +515,17 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                 const double tu = e.u, tv = e.v, tw = e.w;
                 const double xe = fma(s_along, tu, e.x0);
                 const double ye = fma(s_along, tv, e.y0);
-                he = fma(-s_along, tw, e.h0);
+                {
+                    // rounded as the FP64 definition rounds it: the drop tests and the
+                    // profile bin take their decisions on this value
+#pragma clang fp contract(off)
+                    he = e.h0 - s_along * tw;
+                }
                 const double te = fma(s_along, e.inv_bc, e.t0);
+                // table cell and fraction of the emission altitude (index and depth)
+                xcell = (he - a.h_obs) * a.inv_step;
+                ci = min((int)xcell, a.n_nodes - 2);
+                if (PROF && he >= a.h_obs && he < a.h_top) pbin = profile_bin(a, ci, xcell - (double)ci);
                 const double ct = e.cos_t;
                 // direction on the Cherenkov cone
                 double pu, pv, pw;
@@ -509,20 +561,46 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                 if (drop_why < 0) {
                     alive = true;
                     // ---- atmosphere at the emission altitude (uniform table, no search)
-                    const double x = (he - a.h_obs) * a.inv_step;
-                    int ci = (int)x;
-                    ci = min(ci, a.n_nodes - 2);
-                    const T f = (T)(x - (double)ci);
+                    const T f = (T)(xcell - (double)ci);
                     T psi_i, dpsi, P0, P1, P2, P3, P4, P5;
+                    // LDS read always (index clamped into the staged part); the rare
+                    // lookups above it are replaced by a read from HBM
                     if (PREC == 0) {
-                        const double* nd = tab64 + (size_t)kNode64 * ci;
-                        psi_i = nd[0];
-                        dpsi = nd[kNode64] - nd[0];
+                        double n0[6], n1;
+                        {
+                            const int cl = PROF ? min(ci, a.lds_entries - 2) : ci;
+                            const double* nd = tab64 + (size_t)kNode64 * cl;
+                            for (int q = 0; q < 6; ++q) n0[q] = nd[q];
+                            n1 = nd[kNode64];
+                        }
+                        if (PROF && ci + 1 >= a.lds_entries) {
+                            // a distinct load kind keeps the compiler from fusing the two
+                            // reads into one generic (flat) load of a selected address
+                            const double* nd = a.node64 + (size_t)kNode64 * ci;
+                            for (int q = 0; q < 6; ++q) n0[q] = __builtin_nontemporal_load(nd + q);
+                            n1 = __builtin_nontemporal_load(nd + kNode64);
+                        }
+                        psi_i = n0[0];
+                        dpsi = n1 - n0[0];
                         P0 = (double)ci * a.step;
-                        P1 = nd[1]; P2 = nd[2]; P3 = nd[3]; P4 = nd[4]; P5 = nd[5];
+                        P1 = n0[1]; P2 = n0[2]; P3 = n0[3]; P4 = n0[4]; P5 = n0[5];
                     } else {
-                        const float4* cc = reinterpret_cast<const float4*>(tab32 + (size_t)kCell32 * ci);
-                        const float4 c_a = cc[0], c_b = cc[1];
+                        float4 c_a, c_b;
+                        {
+                            const int cl = PROF ? min(ci, a.lds_entries - 1) : ci;
+                            const float4* cc = reinterpret_cast<const float4*>(tab32 + (size_t)kCell32 * cl);
+                            c_a = cc[0];
+                            c_b = cc[1];
+                        }
+                        if (PROF && ci >= a.lds_entries) {
+                            // a distinct load kind keeps the compiler from fusing the two
+                            // reads into one generic (flat) load of a selected address
+                            const float* cg = a.cell32 + (size_t)kCell32 * ci;
+                            c_a = make_float4(__builtin_nontemporal_load(cg), __builtin_nontemporal_load(cg + 1),
+                                              __builtin_nontemporal_load(cg + 2), __builtin_nontemporal_load(cg + 3));
+                            c_b = make_float4(__builtin_nontemporal_load(cg + 4), __builtin_nontemporal_load(cg + 5),
+                                              __builtin_nontemporal_load(cg + 6), __builtin_nontemporal_load(cg + 7));
+                        }
                         psi_i = c_a.x; dpsi = c_a.y; P1 = c_a.z; P2 = c_a.w;
                         P3 = c_b.x; P4 = c_b.y; P5 = c_b.z;
                         P0 = c_b.w;
@@ -600,6 +678,24 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                     wcnt[kWcDrop0 + CKV_DROP_ABOVE_TOP] += d1;
                     wcnt[kWcDrop0 + CKV_DROP_UPWARD] += d2;
                     wcnt[kWcDrop0 + CKV_DROP_GRAZING] += d3;
+                }
+            }
+            if (PROF) {
+                // runs of lanes with the same step and bin (bunches of a step are
+                // consecutive lanes and their depth is monotonic in k): the first lane
+                // of each run adds the whole run, so LDS atomics do not collide
+                const bool member = pbin >= 0;
+                const int key = member ? (si << 8) | pbin : -1;     // pbin < 256
+                // the previous lane's key (DPP wave shift right by one; lane 0 gets -2)
+                const int key_prev = __builtin_amdgcn_update_dpp(-2, key, 0x138, 0xf, 0xf, false);
+                const bool head = member && key_prev != key;
+                const uint64_t mem_mask = __ballot(member), head_mask = __ballot(head);
+                if (head) {
+                    const uint64_t after = lane == kWave - 1 ? 0ull : (~0ull << (lane + 1));
+                    const uint64_t ends = (~mem_mask | head_mask) & after;
+                    const int len = (ends ? __builtin_ctzll(ends) : kWave) - lane;
+                    atomicAdd(&hph[pbin], (double)len * stash[si].photons);
+                    atomicAdd(&hbu[pbin], (uint32_t)len);
                 }
             }
             // ---- candidate spheres (ascending telescope index)
@@ -695,6 +791,17 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
             for (int kk = lane; kk < a.n_tel; kk += kWave) {
                 row[kk] = tcount[kk];
                 tcount[kk] = 0;
+            }
+        }
+        // ---- profile of this tile into its shower's row
+        for (int kk = lane; PROF && kk < a.prof_bins; kk += kWave) {
+            const uint32_t c = hbu[kk];
+            if (c) {
+                const int64_t g = (int64_t)s * a.prof_bins + kk;
+                atomicAdd(&a.prof_ph[g], hph[kk]);
+                atomicAdd((unsigned long long*)&a.prof_bu[g], (unsigned long long)c);
+                hph[kk] = 0.0;
+                hbu[kk] = 0u;
             }
         }
         wave_lds_sync();
@@ -1362,6 +1469,14 @@ Args make_args(const RunPlan& p)
     a.n_obs = at->n_obs;
     a.node64 = at->d_node64;
     a.cell32 = at->d_cell32;
+    a.lds_entries = lds_entries(p.params.precision, a.n_nodes, p.prof_bins > 0);
+    a.depth = at->d_depth;
+    if (p.prof_bins > 0) {
+        a.prof_ph = p.out.profile_photons;
+        a.prof_bu = p.out.profile_bunches;
+        a.inv_bin = 1.0 / p.params.depth_bin_gcm2;
+        a.prof_bins = p.prof_bins;
+    }
     const ckv_array* ar = p.arr;
     if (ar) {
         a.n_tel = ar->n_tel;
@@ -1410,12 +1525,12 @@ int check_launch(const char* what)
 
 }  // namespace
 
-int emit_config(int precision, int n_tel, const ckv_atmo* atmo, int tile_segs, int* waves,
-                size_t* lds_bytes)
+int emit_config(int precision, int n_tel, int prof_bins, const ckv_atmo* atmo, int tile_segs,
+                int* waves, size_t* lds_bytes)
 {
-    const size_t tab = (table_bytes(precision, (int)atmo->n_nodes) + 15) & ~(size_t)15;
+    const size_t tab = (table_bytes(precision, (int)atmo->n_nodes, prof_bins > 0) + 15) & ~(size_t)15;
     const size_t cap = 160 * 1024;
-    const size_t per = wave_bytes(precision, tile_segs, n_tel);
+    const size_t per = wave_bytes(precision, tile_segs, n_tel, prof_bins);
     const int max_waves = precision == 0 ? kMaxEmitWaves / 2 : kMaxEmitWaves;
     for (int wv = max_waves; wv >= 1; wv /= 2) {
         const size_t tot = tab + (size_t)wv * per;
@@ -1431,16 +1546,16 @@ int emit_config(int precision, int n_tel, const ckv_atmo* atmo, int tile_segs, i
 
 namespace {
 
-template <int PREC, int TS>
+template <int PREC, int TS, bool PROF>
 int launch_emit(const Args& a, int grid, int waves, size_t lds, hipStream_t st)
 {
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)emit_kernel<PREC, TS>,
+        (void)hipFuncSetAttribute((const void*)emit_kernel<PREC, TS, PROF>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    emit_kernel<PREC, TS><<<grid, waves * kWave, lds, st>>>(a);
+    emit_kernel<PREC, TS, PROF><<<grid, waves * kWave, lds, st>>>(a);
     return check_launch("emit");
 }
 
@@ -1448,10 +1563,14 @@ template <int PREC>
 int launch_emit_ts(const Args& a, int ts, int grid, int waves, size_t lds, hipStream_t st)
 {
     switch (ts) {
-        case 8: return launch_emit<PREC, 8>(a, grid, waves, lds, st);
-        case 16: return launch_emit<PREC, 16>(a, grid, waves, lds, st);
-        case 32: return launch_emit<PREC, 32>(a, grid, waves, lds, st);
-        case 64: return launch_emit<PREC, 64>(a, grid, waves, lds, st);
+        case 8: return a.prof_bins ? launch_emit<PREC, 8, true>(a, grid, waves, lds, st)
+                                   : launch_emit<PREC, 8, false>(a, grid, waves, lds, st);
+        case 16: return a.prof_bins ? launch_emit<PREC, 16, true>(a, grid, waves, lds, st)
+                                    : launch_emit<PREC, 16, false>(a, grid, waves, lds, st);
+        case 32: return a.prof_bins ? launch_emit<PREC, 32, true>(a, grid, waves, lds, st)
+                                    : launch_emit<PREC, 32, false>(a, grid, waves, lds, st);
+        case 64: return a.prof_bins ? launch_emit<PREC, 64, true>(a, grid, waves, lds, st)
+                                    : launch_emit<PREC, 64, false>(a, grid, waves, lds, st);
     }
     set_error("tile_segments must be 8, 16, 32 or 64");
     return CKV_ERR_ARG;
@@ -1467,11 +1586,20 @@ int launch_run(RunPlan& p)
     if (int rc = check_launch("init")) return rc;
     int waves = 0;
     size_t lds = 0;
-    if (int rc = emit_config(p.params.precision, a.n_tel, p.atmo, p.tile_segs, &waves, &lds)) return rc;
+    if (int rc = emit_config(p.params.precision, a.n_tel, p.prof_bins, p.atmo, p.tile_segs, &waves,
+                             &lds))
+        return rc;
     if (p.emit_waves < waves) {
         waves = p.emit_waves;
-        lds = ((table_bytes(p.params.precision, a.n_nodes) + 15) & ~(size_t)15) +
-              (size_t)waves * wave_bytes(p.params.precision, p.tile_segs, a.n_tel);
+        lds = ((table_bytes(p.params.precision, a.n_nodes, p.prof_bins > 0) + 15) & ~(size_t)15) +
+              (size_t)waves * wave_bytes(p.params.precision, p.tile_segs, a.n_tel, p.prof_bins);
+    }
+    if (p.prof_bins > 0) {
+        // the profile accumulates by atomics: clear it (a kernel, so the run stays capturable)
+        const int64_t m = (int64_t)a.n_showers * p.prof_bins;
+        zero_kernel<<<64, 256, 0, st>>>(a.prof_ph, m);
+        zero_kernel<<<64, 256, 0, st>>>(reinterpret_cast<double*>(a.prof_bu), m);
+        if (int rc = check_launch("zero")) return rc;
     }
     if (p.params.event_begin) (void)hipEventRecord((hipEvent_t)p.params.event_begin, st);
     int rc = p.params.precision == 0

@@ -74,6 +74,14 @@ int build_atmo_tables(const double* alt, const double* eta, int64_t n, double h_
     return CKV_OK;
 }
 
+void build_depth_table(const double* alt, const double* depth, int64_t n, ckv_atmo* a)
+{
+#pragma clang fp contract(off)
+    a->depth.assign(a->n_nodes, 0.0);
+    for (int64_t i = 0; i < a->n_nodes; ++i)
+        a->depth[i] = profile_at(alt, depth, n, a->h_obs + (double)i * a->step);
+}
+
 int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ckv_grid* g)
 {
     const int32_t n = arr->n_tel;

@@ -36,14 +36,14 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_version(L):
-    assert L.ckv_version() == 100
+    assert L.ckv_version() == 110
 
 
 def test_struct_sizes_match_header_layout():
     assert C.sizeof(ckv._Segments) == 11 * 8
-    assert C.sizeof(ckv._Params) == 4 * 8 + 8 + 4 * 4 + 2 * 8
+    assert C.sizeof(ckv._Params) == 4 * 8 + 8 + 4 * 4 + 2 * 8 + 8
     assert C.sizeof(ckv._Result) == 5 * 8 + 8 * 8 + 2 * 4
-    assert C.sizeof(ckv._Output) == 5 * 8
+    assert C.sizeof(ckv._Output) == 7 * 8
 
 
 def _atmo_create(L, alt, eta, obs=2200.0, step=0.0):
@@ -68,6 +68,21 @@ def test_atmosphere_validation(L, alt, eta, obs, step, code):
     assert rc == code
     assert not h.value
     assert L.ckv_last_error()
+
+
+def test_depth_table_validation(L):
+    alt = np.array([0.0, 100.0, 200.0])
+    eta = np.array([3e-4, 2e-4, 1e-4])
+    h = C.c_void_p()
+    for depth in (np.array([1000.0, 1001.0, 900.0]), np.array([1000.0, np.inf, 900.0])):
+        rc = L.ckv_atmo_create_with_depth(ckv._np_ptr(alt), ckv._np_ptr(eta), ckv._np_ptr(depth), 3,
+                                          0.0, 0.0, C.byref(h))
+        assert rc == -2 and not h.value and L.ckv_last_error()
+    nb = C.c_int32()
+    assert L.ckv_profile_bins(None, 10.0, C.byref(nb)) == -1
+    assert L.ckv_atmo_depth(None, None) == -1
+    with pytest.raises(ckv.CkvError):
+        ckv.Streamer(None, None, None, ckv.make_params(depth_bin=10.0))
 
 
 def test_array_validation(L):
@@ -97,7 +112,7 @@ def test_run_argument_validation(L):
     assert rc == -1
     for bad in (ckv.make_params(bunch_size=0.0), ckv.make_params(lambda_min=600.0),
                 ckv.make_params(precision=7), ckv.make_params(w_min=1.5),
-                ckv.make_params(tile_segments=65)):
+                ckv.make_params(tile_segments=65), ckv.make_params(depth_bin=-1.0)):
         empty = ckv._Segments(*([None] * 10), 0)
         assert L.ckv_run(C.byref(empty), C.byref(sh), C.byref(bad), None, None, None, 0,
                          C.byref(out), None) == -1
