@@ -178,6 +178,11 @@ typedef struct {
     double depth_bin_gcm2; /* > 0: also accumulate the longitudinal photon-production
                               profile in bins of this width (needs an atmosphere with a
                               depth table); 0 = no profile */
+    int32_t grazing_exact; /* 0: bunches with 0 < w <= w_min are dropped (counted);
+                              1: they are propagated exactly, cell by cell in FP64 through
+                              the index table, instead of by the moment series (the slow
+                              path for rare bunches, sec. 4.3.1 and App. C) */
+    int32_t reserved;      /* must be 0 */
 } ckv_params;
 
 /* Device-side report, written by ckv_run (the caller syncs the stream before

@@ -59,7 +59,8 @@ class _Config(C.Structure):
                 ("psi", C.c_void_p), ("P", C.c_void_p),
                 ("n_tel", C.c_int32), ("tx", C.c_void_p), ("ty", C.c_void_p), ("tr", C.c_void_p),
                 ("bunch_size", C.c_double), ("lambda_min", C.c_double),
-                ("lambda_max", C.c_double), ("w_min", C.c_double), ("seed", C.c_uint64)]
+                ("lambda_max", C.c_double), ("w_min", C.c_double), ("seed", C.c_uint64),
+                ("grazing_exact", C.c_int32)]
 
 
 class _Segments(C.Structure):
@@ -85,6 +86,7 @@ def _declare(L):
     L.or_segment_details.argtypes = [C.POINTER(_Config), C.POINTER(_Segments), P]
     L.or_lookup_many.argtypes = [C.POINTER(_Config), I64, P, P]
     L.or_propagate_many.argtypes = [C.POINTER(_Config), I64, P, P]
+    L.or_propagate_exact_many.argtypes = [C.POINTER(_Config), I64, P, P]
     L.or_sphere_disc.restype = D
     L.or_sphere_disc.argtypes = [D] * 7
     L.or_frank_tamm_k.restype = D
@@ -170,7 +172,8 @@ class Config:
     """Tables + telescopes + parameters, kept alive for the C structure."""
 
     def __init__(self, tables: Tables, tel_x, tel_y, tel_r, *, bunch_size=5.0,
-                 lambda_min=300.0, lambda_max=600.0, seed=0x14927, w_min=W_MIN):
+                 lambda_min=300.0, lambda_max=600.0, seed=0x14927, w_min=W_MIN,
+                 grazing_exact=False):
         self.tables = tables
         self.tx = np.ascontiguousarray(tel_x, dtype=np.float64)
         self.ty = np.ascontiguousarray(tel_y, dtype=np.float64)
@@ -182,7 +185,7 @@ class Config:
         self.c = _Config(tables.n_nodes, tables.h_obs, tables.step, _p(self.psi).value,
                          _p(self.P).value, self.tx.shape[0], _p(self.tx).value,
                          _p(self.ty).value, _p(self.tr).value, bunch_size, lambda_min,
-                         lambda_max, w_min, self.seed)
+                         lambda_max, w_min, self.seed, int(bool(grazing_exact)))
 
     @property
     def n_tel(self) -> int:
@@ -329,6 +332,16 @@ def propagate(cfg: Config, x_e, y_e, h_e, u, v, w) -> dict:
         axis=1))
     out = np.empty((inp.shape[0], 9))
     lib().or_propagate_many(C.byref(cfg.c), inp.shape[0], _p(inp), _p(out))
+    return {f: out[:, i] for i, f in enumerate(PROP_FIELDS)}
+
+
+def propagate_exact(cfg: Config, x_e, y_e, h_e, u, v, w) -> dict:
+    """Cell-by-cell exact propagation (the slow path for grazing bunches)."""
+    inp = np.ascontiguousarray(np.stack(np.broadcast_arrays(
+        *[np.atleast_1d(np.asarray(a, dtype=np.float64)) for a in (x_e, y_e, h_e, u, v, w)]),
+        axis=1))
+    out = np.empty((inp.shape[0], 9))
+    lib().or_propagate_exact_many(C.byref(cfg.c), inp.shape[0], _p(inp), _p(out))
     return {f: out[:, i] for i, f in enumerate(PROP_FIELDS)}
 
 

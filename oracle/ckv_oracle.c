@@ -61,6 +61,7 @@ typedef struct {
     /* parameters */
     double bunch_size, lambda_min, lambda_max, w_min;
     uint64_t seed;
+    int32_t grazing_exact;   /* 1: bunches with 0 < w <= w_min are traced exactly, not dropped */
 } or_config;
 
 typedef struct {
@@ -307,6 +308,68 @@ void or_propagate(const or_config* cf, double x_e, double y_e, double h_e, doubl
     pr->psi_e = psi_e;
 }
 
+/* Exact propagation, cell by cell (the rare-bunch slow path of sec. 4.3.1 and
+   App. C, done exactly instead of by the series): with Snell's invariant
+   p = n_e sin(theta_e) and psi linear in each cell, s = n cos(theta) satisfies
+   s^2 = n_e^2 w^2 + psi - psi_e, linear in altitude, and over a cell of
+   height dz between s_t (top) and s_b (bottom)
+     horizontal advance   int p / s dh        = 2 p dz / (s_t + s_b),
+     c * travel time      int (s^2 + p^2) / s dh
+                          = (2/3) dz (s_t^2 + s_t s_b + s_b^2) / (s_t + s_b) + 2 p^2 dz / (s_t + s_b).
+   The ray goes down from h_e through the partial cell and then every full cell
+   to h_obs; a downward ray never turns (n grows downward). */
+void or_propagate_exact(const or_config* cf, double x_e, double y_e, double h_e, double u,
+                        double v, double w, or_prop* pr)
+{
+    int64_t N = cf->n_nodes;
+    double psi_e;
+    or_lookup(cf, h_e, &psi_e, NULL);
+    double ne2 = 1.0 + psi_e, ne = sqrt(ne2);
+    double sin_e = sqrt(u * u + v * v);
+    double p = ne * sin_e;
+    double s0sq = ne2 * w * w;            /* s^2 at emission */
+    double x = (h_e - cf->h_obs) * (1.0 / cf->step);
+    int64_t c = (int64_t)floor(x);
+    if (c > N - 2) c = N - 2;
+    double X = 0.0, cT = 0.0;
+    double h_top = h_e, s_t = sqrt(s0sq);
+    for (int64_t i = c; i >= 0; --i) {
+        double h_b = cf->h_obs + (double)i * cf->step;
+        double dz = h_top - h_b;
+        double s_b = sqrt(s0sq + (cf->psi[i] - psi_e));
+        if (dz > 0.0) {
+            double den = s_t + s_b;
+            X += 2.0 * p * dz / den;
+            cT += (2.0 / 3.0) * dz * (s_t * s_t + s_t * s_b + s_b * s_b) / den + 2.0 * p * p * dz / den;
+        }
+        h_top = h_b;
+        s_t = s_b;
+    }
+    double n_obs = sqrt(1.0 + cf->psi[0]);
+    pr->S = X;
+    pr->x_g = sin_e > 0.0 ? x_e + (u / sin_e) * X : x_e;
+    pr->y_g = sin_e > 0.0 ? y_e + (v / sin_e) * X : y_e;
+    pr->T = cT / OR_C_M_PER_NS;
+    pr->u_o = u * ne / n_obs;
+    pr->v_o = v * ne / n_obs;
+    pr->w_o = sqrt(1.0 - pr->u_o * pr->u_o - pr->v_o * pr->v_o);
+    pr->n_e = ne;
+    pr->psi_e = psi_e;
+}
+
+void or_propagate_exact_many(const or_config* cf, int64_t m, const double* in, double* out)
+{
+    for (int64_t q = 0; q < m; ++q) {
+        const double* pp = in + 6 * q;
+        or_prop pr;
+        or_propagate_exact(cf, pp[0], pp[1], pp[2], pp[3], pp[4], pp[5], &pr);
+        double* o = out + 9 * q;
+        o[0] = pr.x_g; o[1] = pr.y_g; o[2] = pr.T; o[3] = pr.u_o; o[4] = pr.v_o;
+        o[5] = pr.w_o; o[6] = pr.n_e; o[7] = pr.psi_e; o[8] = pr.S;
+    }
+}
+
+
 /* ------------------------------------------------------------------------- */
 /* One bunch k of a step: sub-step emission point, direction on the Cherenkov */
 /* cone, wavelength, drop rules, propagation.                                 */
@@ -348,9 +411,13 @@ void or_make_bunch(const or_config* cf, const or_segments* sg, int64_t i, const 
     if (bn->h_e < cf->h_obs) { bn->status = OR_DROP_BELOW_OBS; return; }
     if (bn->h_e >= h_top) { bn->status = OR_DROP_ABOVE_TOP; return; }
     if (bn->w <= 0.0) { bn->status = OR_DROP_UPWARD; return; }
-    if (bn->w <= cf->w_min) { bn->status = OR_DROP_GRAZING; return; }
+    int grazing = bn->w <= cf->w_min;
+    if (grazing && !cf->grazing_exact) { bn->status = OR_DROP_GRAZING; return; }
     bn->status = -1;
-    or_propagate(cf, bn->x_e, bn->y_e, bn->h_e, bn->u, bn->v, bn->w, &bn->pr);
+    if (grazing)
+        or_propagate_exact(cf, bn->x_e, bn->y_e, bn->h_e, bn->u, bn->v, bn->w, &bn->pr);
+    else
+        or_propagate(cf, bn->x_e, bn->y_e, bn->h_e, bn->u, bn->v, bn->w, &bn->pr);
     bn->t = bn->t_e + bn->pr.T - sg->t_ref[i];
 }
 

@@ -48,7 +48,8 @@ class _Params(C.Structure):
                 ("lambda_max_nm", C.c_double), ("w_min", C.c_double), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("tile_segments", C.c_int32), ("grid", C.c_int32),
                 ("waves_per_group", C.c_int32), ("event_begin", C.c_void_p),
-                ("event_end", C.c_void_p), ("depth_bin_gcm2", C.c_double)]
+                ("event_end", C.c_void_p), ("depth_bin_gcm2", C.c_double),
+                ("grazing_exact", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -271,11 +272,12 @@ class DeviceSegments:
 
 def make_params(*, precision=CKV_MIXED, bunch_size=5.0, lambda_min=300.0, lambda_max=600.0,
                 w_min=0.1, seed=0x14927, tile_segments=0, grid=0, waves_per_group=0,
-                event_begin=None, event_end=None, depth_bin=0.0) -> _Params:
-    """depth_bin > 0 [g/cm^2]: also the longitudinal photon-production profile."""
+                event_begin=None, event_end=None, depth_bin=0.0, grazing_exact=False) -> _Params:
+    """depth_bin > 0 [g/cm^2]: also the longitudinal photon-production profile;
+    grazing_exact: trace bunches with 0 < w <= w_min exactly instead of dropping them."""
     return _Params(bunch_size, lambda_min, lambda_max, w_min, int(seed) & (2**64 - 1),
                    int(precision), int(tile_segments), int(grid), int(waves_per_group),
-                   event_begin, event_end, float(depth_bin))
+                   event_begin, event_end, float(depth_bin), int(bool(grazing_exact)), 0)
 
 
 def workspace_size(n_segments, n_showers, n_tel, capacity, params: _Params) -> int:

@@ -85,6 +85,9 @@ int check_params(const ckv_params* p)
     if (!(p->depth_bin_gcm2 >= 0.0) || !std::isfinite(p->depth_bin_gcm2)) {
         set_error("depth_bin_gcm2 must be >= 0"); return CKV_ERR_ARG;
     }
+    if ((p->grazing_exact != 0 && p->grazing_exact != 1) || p->reserved != 0) {
+        set_error("grazing_exact must be 0 or 1, reserved 0"); return CKV_ERR_ARG;
+    }
     return CKV_OK;
 }
 

@@ -61,6 +61,7 @@ struct Args {
     const uint16_t* cell_list;
     // parameters
     double bunch_size, k_ft, inv_l1, dl, w_min;
+    int32_t grazing_exact;      // 1: bunches with 0 < w <= w_min take propagate_exact
     uint32_t key0, key1;
     int32_t tile_segs;
     // workspace and output
@@ -262,6 +263,46 @@ __device__ __forceinline__ void sincos_turns(uint32_t r, float& s, float& c)
 // compacted), a 64-entry flag row used to map bunches to steps, the per-
 // telescope crossing counters of the tile, and the wave's run counters.
 // --------------------------------------------------------------------------
+// Exact propagation of a grazing bunch (0 < w <= w_min), cell by cell in FP64
+// from the FP64 node table, where the moment series is not used (sec. 4.3.1 and
+// App. C: rare bunches take a slow path).  With Snell's invariant
+// p = n_e sin(theta_e), s = n cos(theta) obeys s^2 = n_e^2 w^2 + psi - psi_e,
+// linear inside a cell, and a cell of height dz between s_t (top) and s_b
+// (bottom) adds 2 p dz / (s_t + s_b) to the horizontal advance and
+// (2/3) dz (s_t^2 + s_t s_b + s_b^2) / (s_t + s_b) + 2 p^2 dz / (s_t + s_b)
+// to c times the travel time; a downward ray never turns.
+__device__ __forceinline__ void propagate_exact(const Args& a, double xe, double ye, double he,
+                                             double u, double v, double w, double& xg, double& yg,
+                                             double& T, double& ne)
+{
+    const double* nd = a.node64;
+    const double x = (he - a.h_obs) * a.inv_step;
+    int c = min((int)x, a.n_nodes - 2);
+    const double f = x - (double)c;
+    const double psi_e = nd[kNode64 * c] + f * (nd[kNode64 * (c + 1)] - nd[kNode64 * c]);
+    const double ne2 = 1.0 + psi_e;
+    ne = sqrt(ne2);
+    const double sin_e = sqrt(u * u + v * v);
+    const double p = ne * sin_e;
+    const double s0sq = ne2 * w * w;
+    double X = 0.0, cT = 0.0, h_top = he, s_t = sqrt(s0sq);
+    for (int i = c; i >= 0; --i) {
+        const double h_b = a.h_obs + (double)i * a.step;
+        const double dz = h_top - h_b;
+        const double s_b = sqrt(s0sq + (nd[kNode64 * i] - psi_e));
+        if (dz > 0.0) {
+            const double inv = 1.0 / (s_t + s_b);
+            X += 2.0 * p * dz * inv;
+            cT += (2.0 / 3.0) * dz * (s_t * s_t + s_t * s_b + s_b * s_b) * inv + 2.0 * p * p * dz * inv;
+        }
+        h_top = h_b;
+        s_t = s_b;
+    }
+    xg = sin_e > 0.0 ? xe + (u / sin_e) * X : xe;
+    yg = sin_e > 0.0 ? ye + (v / sin_e) * X : ye;
+    T = cT / kSpeedOfLight;
+}
+
 // Depth bin of an emission altitude h_obs <= h < h_top, given its table cell c
 // and fraction f (x = (h - h_obs) / step, c = floor(x), f = x - c): the depth
 // table read like the index and binned by floor(X * (1/width)), in FP64
@@ -333,9 +374,17 @@ __host__ __device__ inline size_t wave_bytes(int prec, int tile_segs, int n_tel,
 // --------------------------------------------------------------------------
 // the bunch kernel
 // --------------------------------------------------------------------------
-template <int PREC, int TS, bool PROF>
+// FEAT bits: kFeatProfile (longitudinal profile), kFeatExact (grazing bunches
+// traced exactly); each combination is its own kernel, so runs without them
+// carry none of their code or registers.
+constexpr int kFeatProfile = 1;
+constexpr int kFeatExact = 2;
+
+template <int PREC, int TS, int FEAT>
 __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
 {
+    constexpr bool PROF = (FEAT & kFeatProfile) != 0;
+    constexpr bool EXACT = (FEAT & kFeatExact) != 0;
     using T = typename std::conditional<PREC == 0, double, float>::type;
     using Entry = StepEntry<PREC>;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -486,6 +535,7 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
             double xg, yg, he, tarr;
             float uo, vo, lam, photons, he_f, t_f;
             int32_t k, sidx;
+            double uod, vod;   // observed direction for the sphere test (live bunches)
             int pbin = -1;     // depth bin of the bunch for the profile, -1: not counted
             double xcell;
             int ci;
@@ -557,8 +607,41 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                 if (he < a.h_obs) drop_why = CKV_DROP_BELOW_OBS;
                 else if (he >= a.h_top) drop_why = CKV_DROP_ABOVE_TOP;
                 else if (pw <= 0.0) drop_why = CKV_DROP_UPWARD;
-                else if (pw <= a.w_min) drop_why = CKV_DROP_GRAZING;
-                if (drop_why < 0) {
+                bool slow = false;     // grazing bunch traced exactly, cell by cell
+                if (drop_why < 0 && pw <= a.w_min) {
+                    if (EXACT) slow = true;
+                    else drop_why = CKV_DROP_GRAZING;
+                }
+                if (EXACT && slow) {
+                    alive = true;
+                    if (PREC == 1) {
+                        // a grazing ray magnifies a direction error by 1/w^2 on the
+                        // ground: redo the direction in FP64 (frame of the step, FP64
+                        // azimuth), as the FP64 path has it
+                        const double Dz = -tw, sgn = copysign(1.0, Dz);
+                        const double ia = -1.0 / (sgn + Dz), ib = tu * tv * ia;
+                        const double b1x = 1.0 + sgn * tu * tu * ia, b1y = sgn * ib, b1z = -sgn * tu;
+                        const double b2x = ib, b2y = sgn + tv * tv * ia, b2z = -tv;
+                        const double st_ = sqrt((1.0 - ct) * (1.0 + ct));
+                        const double phi = 6.283185307179586 *
+                                           fma((double)r1, 2.3283064365386963e-10, 1.1641532182693481e-10);
+                        double sp, cp;
+                        sincos(phi, &sp, &cp);
+                        pu = ct * tu + st_ * (cp * b1x + sp * b2x);
+                        pv = ct * tv + st_ * (cp * b1y + sp * b2y);
+                        pw = ct * tw - st_ * (cp * b1z + sp * b2z);
+                    }
+                    double T_x, ne_x;
+                    propagate_exact(a, xe, ye, he, pu, pv, pw, xg, yg, T_x, ne_x);
+                    tarr = (te - t_ref) + T_x;
+                    uod = pu * ne_x / a.n_obs;
+                    vod = pv * ne_x / a.n_obs;
+                    uo = (float)uod;
+                    vo = (float)vod;
+                    t_f = (float)tarr;
+                    he_f = (float)he;
+                }
+                if (drop_why < 0 && !slow) {
                     alive = true;
                     // ---- atmosphere at the emission altitude (uniform table, no search)
                     const T f = (T)(xcell - (double)ci);
@@ -662,8 +745,13 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                     xg = fma(pu, adv, xe);
                     yg = fma(pv, adv, ye);
                     tarr = (te - t_ref) + T_travel;
-                    uo = (float)((T)pu * ratio);
-                    vo = (float)((T)pv * ratio);
+                    // the sphere test takes the observed direction at the path's
+                    // precision (FP64 path: before the record's FP32 rounding)
+                    const T uT = (T)pu * ratio, vT = (T)pv * ratio;
+                    uo = (float)uT;
+                    vo = (float)vT;
+                    uod = (double)uT;
+                    vod = (double)vT;
                     t_f = (float)tarr;
                     he_f = (float)he;
                 }
@@ -701,10 +789,7 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
             // ---- candidate spheres (ascending telescope index)
             int cur = 0, cend = 0;
             bool brute = false;
-            double uod, vod;
             if (alive) {
-                uod = (double)uo;
-                vod = (double)vo;
                 const double wo2 = 1.0 - uod * uod - vod * vod;
                 if (wo2 >= kLevelW2[0]) {
                     const double fx = (xg - a.gx0) * a.inv_cell, fy = (yg - a.gy0) * a.inv_cell;
@@ -1491,6 +1576,7 @@ Args make_args(const RunPlan& p)
     a.inv_l1 = 1.0 / p.params.lambda_min_nm;
     a.dl = 1.0 / p.params.lambda_min_nm - 1.0 / p.params.lambda_max_nm;
     a.w_min = p.params.w_min;
+    a.grazing_exact = p.params.grazing_exact;
     a.key0 = (uint32_t)p.params.seed;
     a.key1 = (uint32_t)(p.params.seed >> 32);
     a.tile_segs = p.tile_segs;
@@ -1546,31 +1632,39 @@ int emit_config(int precision, int n_tel, int prof_bins, const ckv_atmo* atmo, i
 
 namespace {
 
-template <int PREC, int TS, bool PROF>
+template <int PREC, int TS, int FEAT>
 int launch_emit(const Args& a, int grid, int waves, size_t lds, hipStream_t st)
 {
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)emit_kernel<PREC, TS, PROF>,
+        (void)hipFuncSetAttribute((const void*)emit_kernel<PREC, TS, FEAT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    emit_kernel<PREC, TS, PROF><<<grid, waves * kWave, lds, st>>>(a);
+    emit_kernel<PREC, TS, FEAT><<<grid, waves * kWave, lds, st>>>(a);
     return check_launch("emit");
+}
+
+template <int PREC, int TS>
+int launch_emit_feat(const Args& a, int grid, int waves, size_t lds, hipStream_t st)
+{
+    const int feat = (a.prof_bins > 0 ? kFeatProfile : 0) | (a.grazing_exact ? kFeatExact : 0);
+    switch (feat) {
+        case 0: return launch_emit<PREC, TS, 0>(a, grid, waves, lds, st);
+        case kFeatProfile: return launch_emit<PREC, TS, kFeatProfile>(a, grid, waves, lds, st);
+        case kFeatExact: return launch_emit<PREC, TS, kFeatExact>(a, grid, waves, lds, st);
+        default: return launch_emit<PREC, TS, kFeatProfile | kFeatExact>(a, grid, waves, lds, st);
+    }
 }
 
 template <int PREC>
 int launch_emit_ts(const Args& a, int ts, int grid, int waves, size_t lds, hipStream_t st)
 {
     switch (ts) {
-        case 8: return a.prof_bins ? launch_emit<PREC, 8, true>(a, grid, waves, lds, st)
-                                   : launch_emit<PREC, 8, false>(a, grid, waves, lds, st);
-        case 16: return a.prof_bins ? launch_emit<PREC, 16, true>(a, grid, waves, lds, st)
-                                    : launch_emit<PREC, 16, false>(a, grid, waves, lds, st);
-        case 32: return a.prof_bins ? launch_emit<PREC, 32, true>(a, grid, waves, lds, st)
-                                    : launch_emit<PREC, 32, false>(a, grid, waves, lds, st);
-        case 64: return a.prof_bins ? launch_emit<PREC, 64, true>(a, grid, waves, lds, st)
-                                    : launch_emit<PREC, 64, false>(a, grid, waves, lds, st);
+        case 8: return launch_emit_feat<PREC, 8>(a, grid, waves, lds, st);
+        case 16: return launch_emit_feat<PREC, 16>(a, grid, waves, lds, st);
+        case 32: return launch_emit_feat<PREC, 32>(a, grid, waves, lds, st);
+        case 64: return launch_emit_feat<PREC, 64>(a, grid, waves, lds, st);
     }
     set_error("tile_segments must be 8, 16, 32 or 64");
     return CKV_ERR_ARG;

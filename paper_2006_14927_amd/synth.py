@@ -427,6 +427,31 @@ def hadron_like(zenith_deg: float, n_seg: int = 50_000_000, shower: int = 0,
     return Workload(f"hadron_like_{int(zenith_deg)}deg", atmo, telescopes_disk(), segs)
 
 
+def grazing_tracks(n_seg: int = 20_000, seed: int = 86) -> Workload:
+    """Near-horizontal electron steps low above the observation level (step w
+    0.02-0.14, heading +x, 30-400 m up), so their photons arrive with w on both
+    sides of 0.1 (and some upward); 400 spheres of 12 m on a line along +x
+    (100 m - 10.1 km, 25 m apart) catch them."""
+    atmo = layered_atmosphere()
+    rng = np.random.default_rng(seed)
+    h_obs = atmo.obs_level
+    w = rng.uniform(0.02, 0.14, n_seg)
+    az = rng.normal(0.0, 0.002, n_seg)
+    s = np.sqrt(1.0 - w * w)
+    u, v = s * np.cos(az), s * np.sin(az)
+    h0 = h_obs + rng.uniform(30.0, 400.0, n_seg)
+    x0 = rng.uniform(-200.0, 200.0, n_seg)
+    y0 = rng.normal(0.0, 4.0, n_seg)
+    length = np.minimum(np.exp(rng.uniform(math.log(1.0), math.log(100.0), n_seg)), (h0 - h_obs) / w)
+    energy = np.exp(rng.uniform(math.log(100.0), math.log(2000.0), n_seg))
+    t0 = rng.uniform(0.0, 100.0, n_seg)
+    segs = Segments(x0, y0, h0, u, v, w, length, t0, energy, np.zeros(n_seg, np.uint8),
+                    np.array([0, n_seg], dtype=np.int64), np.zeros(1), np.zeros(1, np.uint32))
+    xs = 100.0 + 25.0 * np.arange(400)
+    tels = Telescopes(xs, np.zeros(400), np.full(400, 12.0))
+    return Workload("grazing_tracks", atmo, tels, segs)
+
+
 # ----------------------------------------------------------------------------
 # differentiation workload: parameterised atmosphere, target from perturbed
 # parameters (common random numbers: same steps, same seed)
