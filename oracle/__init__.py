@@ -60,7 +60,7 @@ class _Config(C.Structure):
                 ("n_tel", C.c_int32), ("tx", C.c_void_p), ("ty", C.c_void_p), ("tr", C.c_void_p),
                 ("bunch_size", C.c_double), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("w_min", C.c_double), ("seed", C.c_uint64),
-                ("grazing_exact", C.c_int32)]
+                ("grazing_exact", C.c_int32), ("h_nodes", C.c_void_p)]
 
 
 class _Segments(C.Structure):
@@ -94,6 +94,8 @@ def _declare(L):
     L.or_soft.argtypes = [C.POINTER(_Config), C.POINTER(_Segments), P, D, C.c_int32, C.c_int, P, P]
     L.or_eta_param_many.argtypes = [D, C.c_int32, P, C.c_int32, D, P, I64, P, P]
     L.or_build_depth.argtypes = [P, P, I64, D, D, I64, P]
+    L.or_build_node_tables.restype = I64
+    L.or_build_node_tables.argtypes = [P, P, I64, D, P, P, P, I64]
     L.or_profile.argtypes = [C.POINTER(_Config), C.POINTER(_Segments), P, D, C.c_int32, C.c_int32,
                              C.c_int, P, P]
 
@@ -112,6 +114,7 @@ class Tables:
     step: float
     psi: np.ndarray      # n_nodes
     P: np.ndarray        # (5, n_nodes)
+    h_nodes: Optional[np.ndarray] = None   # node altitudes of a non-uniform (search) table
 
     @property
     def n_nodes(self) -> int:
@@ -119,7 +122,14 @@ class Tables:
 
     @property
     def h_top(self) -> float:
+        if self.h_nodes is not None:
+            return float(self.h_nodes[-1])
         return self.h_obs + (self.n_nodes - 1) * self.step
+
+    def grid(self) -> np.ndarray:
+        if self.h_nodes is not None:
+            return self.h_nodes.copy()
+        return self.h_obs + np.arange(self.n_nodes) * self.step
 
 
 def build_depth(alt, depth, t: Tables) -> np.ndarray:
@@ -148,6 +158,21 @@ def profile(cfg: "Config", segs, T: np.ndarray, width: float, nthreads: int = 1,
     lib().or_profile(C.byref(cfg.c), C.byref(sv.c), _p(T), float(width), nb, sv.n_showers,
                      int(nthreads), _p(ph), _p(bu))
     return ph.reshape(sv.n_showers, nb), bu.reshape(sv.n_showers, nb)
+
+
+def build_node_tables(alt, eta, h_obs: float) -> Tables:
+    """Tables on the input's own altitudes above h_obs (binary-search lookups)."""
+    alt = np.ascontiguousarray(alt, dtype=np.float64)
+    eta = np.ascontiguousarray(eta, dtype=np.float64)
+    cap = alt.shape[0] + 1
+    hn = np.empty(cap)
+    psi = np.empty(cap)
+    P = np.empty(5 * cap)
+    m = lib().or_build_node_tables(_p(alt), _p(eta), alt.shape[0], h_obs, _p(hn), _p(psi), _p(P), cap)
+    if m < 2:
+        raise ValueError("observation level outside the atmosphere table")
+    P = P[:5 * m].reshape(5, m).copy()
+    return Tables(h_obs, float("nan"), psi[:m].copy(), P, hn[:m].copy())
 
 
 def build_tables(alt, eta, h_obs: float, step: float = 0.0) -> Tables:
@@ -180,12 +205,14 @@ class Config:
         self.tr = np.ascontiguousarray(tel_r, dtype=np.float64)
         self.psi = np.ascontiguousarray(tables.psi)
         self.P = np.ascontiguousarray(tables.P)
+        self.h_nodes = None if tables.h_nodes is None else np.ascontiguousarray(tables.h_nodes)
         self.bunch_size, self.lambda_min, self.lambda_max = bunch_size, lambda_min, lambda_max
         self.seed, self.w_min = int(seed), w_min
         self.c = _Config(tables.n_nodes, tables.h_obs, tables.step, _p(self.psi).value,
                          _p(self.P).value, self.tx.shape[0], _p(self.tx).value,
                          _p(self.ty).value, _p(self.tr).value, bunch_size, lambda_min,
-                         lambda_max, w_min, self.seed, int(bool(grazing_exact)))
+                         lambda_max, w_min, self.seed, int(bool(grazing_exact)),
+                         None if self.h_nodes is None else _p(self.h_nodes).value)
 
     @property
     def n_tel(self) -> int:

@@ -62,6 +62,8 @@ typedef struct {
     double bunch_size, lambda_min, lambda_max, w_min;
     uint64_t seed;
     int32_t grazing_exact;   /* 1: bunches with 0 < w <= w_min are traced exactly, not dropped */
+    const double* h_nodes;   /* NULL: uniform nodes h_obs + i*step; else node altitudes
+                                (ascending, h_nodes[0] = h_obs), found by binary search */
 } or_config;
 
 typedef struct {
@@ -160,20 +162,53 @@ int or_build_tables(const double* alt, const double* eta, int64_t n, double h_ob
 
 /* psi(h) and P_1..P_5(h): locate the cell directly from the uniform step (no
    search), interpolate psi linearly, and add the partial-cell integral. */
+/* altitude of node i, the table top, and the cell holding h (clamped into the
+   table): c with h_c <= h < h_{c+1}, fraction f = (h - h_c)/(h_{c+1} - h_c) and
+   dz = f * (h_{c+1} - h_c).  Uniform tables: x = (h - h_obs) / step, c = floor(x),
+   f = x - c (sec. 3.3.2, no search); node tables: binary search for the
+   bracketing pair (sec. 3.3.1, as RPOL does), then the same linear fraction. */
+static double or_node_h(const or_config* cf, int64_t i)
+{
+    return cf->h_nodes ? cf->h_nodes[i] : cf->h_obs + (double)i * cf->step;
+}
+
+static double or_h_top(const or_config* cf) { return or_node_h(cf, cf->n_nodes - 1); }
+
+static void or_cell(const or_config* cf, double h, int64_t* c_out, double* f_out, double* dz_out)
+{
+    int64_t N = cf->n_nodes;
+    double h_top = or_h_top(cf);
+    double hc = h < cf->h_obs ? cf->h_obs : (h > h_top ? h_top : h);
+    if (!cf->h_nodes) {
+        double x = (hc - cf->h_obs) * (1.0 / cf->step);
+        int64_t i = (int64_t)floor(x);
+        if (i > N - 2) i = N - 2;
+        *c_out = i;
+        *f_out = x - (double)i;
+        *dz_out = *f_out * cf->step;
+        return;
+    }
+    int64_t lo = 0, hi = N - 1;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) / 2;
+        if (cf->h_nodes[mid] <= hc) lo = mid; else hi = mid;
+    }
+    double width = cf->h_nodes[lo + 1] - cf->h_nodes[lo];
+    *c_out = lo;
+    *dz_out = hc - cf->h_nodes[lo];
+    *f_out = *dz_out / width;
+}
+
 void or_lookup(const or_config* cf, double h, double* psi_out, double P_out[5])
 {
     int64_t N = cf->n_nodes;
-    double h_top = cf->h_obs + (double)(N - 1) * cf->step;
-    double hc = h < cf->h_obs ? cf->h_obs : (h > h_top ? h_top : h);
-    double x = (hc - cf->h_obs) * (1.0 / cf->step);
-    int64_t i = (int64_t)floor(x);
-    if (i > N - 2) i = N - 2;
-    double f = x - (double)i;
+    int64_t i;
+    double f, dz;
+    or_cell(cf, h, &i, &f, &dz);
     double a = cf->psi[i], b = cf->psi[i + 1];
     double p = a + f * (b - a);
     *psi_out = p;
     if (P_out) {
-        double dz = f * cf->step;
         for (int j = 1; j <= 5; ++j) {
             double sum = 0.0;
             for (int m = 0; m <= j; ++m) sum += pow(a, j - m) * pow(p, m);
@@ -192,6 +227,34 @@ int or_build_depth(const double* alt, const double* depth, int64_t n, double h_o
     for (int64_t i = 0; i < n_nodes; ++i)
         T[i] = or_eta_at(alt, depth, n, h_obs + (double)i * step);
     return 0;
+}
+
+/* Tables on the input's own nodes (the standard interpolation of sec. 3.3.1,
+   without resampling): the observation level, then every input altitude above
+   it.  psi and the cumulative moments as for the uniform grid, with the width
+   of each cell.  Returns the node count, or -1 (obs level outside the table). */
+int64_t or_build_node_tables(const double* alt, const double* eta, int64_t n, double h_obs,
+                             double* h_nodes, double* psi, double* P, int64_t cap)
+{
+    if (n < 2 || h_obs < alt[0] || h_obs >= alt[n - 1]) return -1;
+    int64_t m = 0;
+    h_nodes[m++] = h_obs;
+    for (int64_t i = 0; i < n; ++i)
+        if (alt[i] > h_obs && m < cap) h_nodes[m++] = alt[i];
+    for (int64_t i = 0; i < m; ++i) {
+        double e = or_eta_at(alt, eta, n, h_nodes[i]);
+        psi[i] = e * (2.0 + e);
+    }
+    for (int j = 1; j <= 5; ++j) P[(j - 1) * m + 0] = 0.0;
+    for (int64_t i = 0; i + 1 < m; ++i) {
+        double a = psi[i], b = psi[i + 1], width = h_nodes[i + 1] - h_nodes[i];
+        for (int j = 1; j <= 5; ++j) {
+            double sum = 0.0;
+            for (int q = 0; q <= j; ++q) sum += pow(a, j - q) * pow(b, q);
+            P[(j - 1) * m + i + 1] = P[(j - 1) * m + i] + width / (j + 1) * sum;
+        }
+    }
+    return m;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -328,13 +391,13 @@ void or_propagate_exact(const or_config* cf, double x_e, double y_e, double h_e,
     double sin_e = sqrt(u * u + v * v);
     double p = ne * sin_e;
     double s0sq = ne2 * w * w;            /* s^2 at emission */
-    double x = (h_e - cf->h_obs) * (1.0 / cf->step);
-    int64_t c = (int64_t)floor(x);
-    if (c > N - 2) c = N - 2;
+    int64_t c;
+    double f_c, dz_c;
+    or_cell(cf, h_e, &c, &f_c, &dz_c);
     double X = 0.0, cT = 0.0;
     double h_top = h_e, s_t = sqrt(s0sq);
     for (int64_t i = c; i >= 0; --i) {
-        double h_b = cf->h_obs + (double)i * cf->step;
+        double h_b = or_node_h(cf, i);
         double dz = h_top - h_b;
         double s_b = sqrt(s0sq + (cf->psi[i] - psi_e));
         if (dz > 0.0) {
@@ -407,7 +470,7 @@ void or_make_bunch(const or_config* cf, const or_segments* sg, int64_t i, const 
     double il1 = 1.0 / cf->lambda_min, il2 = 1.0 / cf->lambda_max;
     bn->lambda = 1.0 / (il1 - u2 * (il1 - il2));
     bn->photons = st->photons;
-    double h_top = cf->h_obs + (double)(cf->n_nodes - 1) * cf->step;
+    double h_top = or_h_top(cf);
     if (bn->h_e < cf->h_obs) { bn->status = OR_DROP_BELOW_OBS; return; }
     if (bn->h_e >= h_top) { bn->status = OR_DROP_ABOVE_TOP; return; }
     if (bn->w <= 0.0) { bn->status = OR_DROP_UPWARD; return; }
@@ -513,7 +576,7 @@ static void or_profile_range(const or_config* cf, const or_segments* sg, const d
                              double* photons, int64_t* bunches)
 {
     int64_t N = cf->n_nodes;
-    double h_top = cf->h_obs + (double)(N - 1) * cf->step;
+    double h_top = or_h_top(cf);
     uint32_t key[2] = {(uint32_t)cf->seed, (uint32_t)(cf->seed >> 32)};
     for (int64_t i = lo; i < hi; ++i) {
         or_setup st;
@@ -525,10 +588,9 @@ static void or_profile_range(const or_config* cf, const or_segments* sg, const d
             double s = ((double)k + or_uniform(r[0])) * st.ds;
             double h_e = sg->h0[i] - s * sg->w[i];
             if (h_e < cf->h_obs || h_e >= h_top) continue;
-            double x = (h_e - cf->h_obs) * (1.0 / cf->step);
-            int64_t c = (int64_t)floor(x);
-            if (c > N - 2) c = N - 2;
-            double f = x - (double)c;
+            int64_t c;
+            double f, dz;
+            or_cell(cf, h_e, &c, &f, &dz);
             double X = T[c] + f * (T[c + 1] - T[c]);
             int64_t b = (int64_t)floor(X * inv_width);
             if (b < 0) b = 0;

@@ -116,6 +116,18 @@ def layered_atmosphere(bounds_km: Sequence[float] = (0, 4, 10, 40, 100, 120),
 # telescopes
 # ----------------------------------------------------------------------------
 
+def sparse_atmosphere(obs_level: float = 2200.0) -> Atmosphere:
+    """The 5-layer profile tabulated at 57 non-uniform altitudes, the way
+    atmospheric-profile files give it (about 55 points, denser low down):
+    every 0.5 km to 10 km, every 1 km to 30 km, every 3 km to 60 km, every
+    10 km to 120 km."""
+    fine = layered_atmosphere(step=50.0, obs_level=obs_level)
+    alt = np.concatenate([np.arange(0.0, 10000.0, 500.0), np.arange(10000.0, 30000.0, 1000.0),
+                          np.arange(30000.0, 60000.0, 3000.0), np.arange(60000.0, 120001.0, 10000.0)])
+    eta = np.interp(alt, fine.alt, fine.eta)
+    return Atmosphere(alt, eta, obs_level)
+
+
 @dataclasses.dataclass
 class Telescopes:
     x: np.ndarray
