@@ -355,6 +355,7 @@ def main(argv=None):
               "(showers and step ranges shard independently; see the design notes).",
               file=sys.stderr)
         return 2
+    import numpy as np
     import torch
 
     from paper_2006_14927_amd import ckv, synth
@@ -403,7 +404,21 @@ def main(argv=None):
                                             args.steps, args.warmup, stream)
     print(f"# mixed + profile: {ms_prof:.3f} ms/step, bunch kernel {kms_prof:.3f} ms", file=sys.stderr,
           flush=True)
-    for res in (res_mixed, res_fp64, res_prof):
+    # table-lookup ablation: the 57-point profile on its own nodes (binary search per
+    # bunch) against the same profile resampled on the 50 m uniform grid
+    sp = synth.sparse_atmosphere(wl.atmo.obs_level)
+    atmo_n = ckv.Atmosphere(sp.alt, sp.eta, sp.obs_level, nodes=True)
+    fine_alt = np.arange(0.0, sp.alt[-1] + 1.0, 50.0)
+    atmo_u = ckv.Atmosphere(fine_alt, np.interp(fine_alt, sp.alt, sp.eta), sp.obs_level, 50.0)
+    p32 = mk(ckv.CKV_MIXED)
+    p32.tile_segments, p32.waves_per_group = 32, tuned[ckv.CKV_MIXED]["waves_per_group"]
+    ms_nodes, kms_nodes, res_nodes = time_path(hip, ckv, dsegs, atmo_n, tels, p32, capacity,
+                                               args.steps, args.warmup, stream)
+    ms_unif, kms_unif, res_unif = time_path(hip, ckv, dsegs, atmo_u, tels, p32, capacity,
+                                            args.steps, args.warmup, stream)
+    print(f"# node tables (binary search): {ms_nodes:.3f} ms/step; resampled 50 m: {ms_unif:.3f}",
+          file=sys.stderr, flush=True)
+    for res in (res_mixed, res_fp64, res_prof, res_nodes, res_unif):
         if res["error"] or res["overflow"]:
             raise RuntimeError(f"run reported a problem: {res}")
     nb = res_mixed["n_bunches"]
@@ -450,6 +465,13 @@ def main(argv=None):
                        "roofline_frac": sum(OPS_FP64.values()) * nb / (kms_fp64 * 1e-3)
                        / PEAK_OPS_PER_S},
         "mixed_over_fp64": ms_fp64 / ms_mixed,
+        "table_ablation": {"profile": "5-layer, 57 tabulated altitudes",
+                           "node_tables_binary_search": {"nodes": int(atmo_n.info()[0]),
+                                                         "ms_per_step": ms_nodes,
+                                                         "bunch_kernel_ms": kms_nodes},
+                           "uniform_50m": {"nodes": int(atmo_u.info()[0]), "ms_per_step": ms_unif,
+                                           "bunch_kernel_ms": kms_unif},
+                           "uniform_over_search": ms_nodes / ms_unif},
         "with_profile": {"bin_gcm2": PROFILE_BIN_GCM2, "bins": atmo_d.profile_bins(PROFILE_BIN_GCM2),
                          "ms_per_step": ms_prof, "bunch_kernel_ms": kms_prof,
                          "value": nb / (ms_prof * 1e-3), "overhead": ms_prof / ms_mixed - 1.0},

@@ -111,6 +111,19 @@ int ckv_atmo_depth(const ckv_atmo* atmo, double* depth);
    table, for bin_gcm2 <= 0, or above CKV_MAX_PROFILE_BINS bins. */
 #define CKV_MAX_PROFILE_BINS 128
 int ckv_profile_bins(const ckv_atmo* atmo, double bin_gcm2, int32_t* n_bins);
+/* Node tables: the same tables on the profile's own altitudes (the observation
+   level, then every alt_m[i] above it), looked up by a binary search for the
+   bracketing pair and linear interpolation (sec. 3.3.1, the standard RPOL
+   interpolation), instead of resampling onto a uniform grid (sec. 3.3.2).
+   2 <= n <= CKV_MAX_NODE_TABLE.  For the table-lookup ablation: ckv_run takes
+   such a handle with tile_segments 0 or 32 and neither the profile nor the
+   exact grazing path; ckv_atmo_info reports step 0.  Errors: as
+   ckv_atmo_create. */
+#define CKV_MAX_NODE_TABLE 4096
+int ckv_atmo_create_nodes(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
+                          ckv_atmo** out);
+/* Node altitudes of the handle, h_nodes[n_nodes] (uniform grids too). */
+int ckv_atmo_nodes(const ckv_atmo* atmo, double* h_nodes);
 /* Grid of the handle: node count, observation level, step. */
 int ckv_atmo_info(const ckv_atmo* atmo, int64_t* n_nodes, double* obs_level_m, double* step_m);
 /* Host copies of the tables: psi[n_nodes], P[5*n_nodes] with

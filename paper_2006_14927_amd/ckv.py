@@ -26,7 +26,8 @@ EXPORTED = ("ckv_last_error", "ckv_version", "ckv_atmo_create", "ckv_atmo_info",
             "ckv_atmo_destroy", "ckv_array_create", "ckv_array_destroy", "ckv_workspace_size",
             "ckv_run", "ckv_count", "ckv_atmo_from_params", "ckv_atmo_params_backward",
             "ckv_array_create_soft", "ckv_soft_forward", "ckv_soft_backward",
-            "ckv_atmo_create_with_depth", "ckv_atmo_depth", "ckv_profile_bins")
+            "ckv_atmo_create_with_depth", "ckv_atmo_depth", "ckv_profile_bins",
+            "ckv_atmo_create_nodes", "ckv_atmo_nodes")
 
 
 class CkvError(RuntimeError):
@@ -88,6 +89,8 @@ def lib():
         L.ckv_atmo_create_with_depth.argtypes = [P, P, P, I64, D, D, C.POINTER(P)]
         L.ckv_atmo_depth.argtypes = [P, P]
         L.ckv_profile_bins.argtypes = [P, D, P]
+        L.ckv_atmo_create_nodes.argtypes = [P, P, I64, D, C.POINTER(P)]
+        L.ckv_atmo_nodes.argtypes = [P, P]
         L.ckv_atmo_info.argtypes = [P, P, P, P]
         L.ckv_atmo_tables.argtypes = [P, P, P]
         L.ckv_atmo_destroy.argtypes = [P]
@@ -126,14 +129,18 @@ class Atmosphere:
     """ckv_atmo: uniform fine tables built from a tabulated n-1 profile."""
 
     def __init__(self, alt=None, eta=None, obs_level: float = 0.0, step: float = 0.0, handle=None,
-                 depth=None):
+                 depth=None, nodes: bool = False):
+        """nodes=True: tables on the profile's own altitudes, binary-search lookups."""
         if handle is not None:          # adopt a handle made by another constructor
             self.handle = handle
             return
         self._alt = np.ascontiguousarray(alt, dtype=np.float64)
         self._eta = np.ascontiguousarray(eta, dtype=np.float64)
         h = C.c_void_p()
-        if depth is None:
+        if nodes:
+            _check(lib().ckv_atmo_create_nodes(_np_ptr(self._alt), _np_ptr(self._eta),
+                                               self._alt.shape[0], float(obs_level), C.byref(h)))
+        elif depth is None:
             _check(lib().ckv_atmo_create(_np_ptr(self._alt), _np_ptr(self._eta), self._alt.shape[0],
                                          float(obs_level), float(step), C.byref(h)))
         else:
@@ -142,6 +149,13 @@ class Atmosphere:
                                                     _np_ptr(self._depth), self._alt.shape[0],
                                                     float(obs_level), float(step), C.byref(h)))
         self.handle = h
+
+    def nodes(self) -> np.ndarray:
+        """Node altitudes [m]."""
+        n, _, _ = self.info()
+        out = np.empty(n)
+        _check(lib().ckv_atmo_nodes(self.handle, _np_ptr(out)))
+        return out
 
     def depth(self) -> np.ndarray:
         """Vertical depth [g/cm^2] at the grid nodes."""

@@ -201,6 +201,37 @@ int ckv_atmo_create(const double* alt_m, const double* eta, int64_t n, double ob
     return ckv_atmo_create_with_depth(alt_m, eta, nullptr, n, obs_level_m, step_m, out);
 }
 
+int ckv_atmo_create_nodes(const double* alt_m, const double* eta, int64_t n, double obs_level_m,
+                          ckv_atmo** out)
+{
+    if (!alt_m || !eta || !out) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    *out = nullptr;
+    if (n < 2 || n > CKV_MAX_NODE_TABLE) {
+        set_error("node tables need 2 .. CKV_MAX_NODE_TABLE points"); return CKV_ERR_ARG;
+    }
+    if (!std::isfinite(obs_level_m)) { set_error("observation level not finite"); return CKV_ERR_ARG; }
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(alt_m[i]) || !std::isfinite(eta[i]) || eta[i] < 0.0) {
+            set_error("atmosphere: non-finite altitude or eta < 0"); return CKV_ERR_TABLE;
+        }
+        if (i > 0 && !(alt_m[i] > alt_m[i - 1])) {
+            set_error("atmosphere: altitudes must increase strictly"); return CKV_ERR_TABLE;
+        }
+    }
+    return atmo_create(alt_m, eta, nullptr, n, obs_level_m, -1.0, out);
+}
+
+int ckv_atmo_nodes(const ckv_atmo* atmo, double* h_nodes)
+{
+    if (!atmo || !h_nodes) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    if (atmo->h_nodes.empty()) {
+        for (int64_t i = 0; i < atmo->n_nodes; ++i) h_nodes[i] = atmo->h_obs + (double)i * atmo->step;
+    } else {
+        std::memcpy(h_nodes, atmo->h_nodes.data(), sizeof(double) * atmo->h_nodes.size());
+    }
+    return CKV_OK;
+}
+
 int ckv_atmo_depth(const ckv_atmo* atmo, double* depth)
 {
     if (!atmo || !depth) { set_error("NULL argument"); return CKV_ERR_ARG; }
@@ -263,6 +294,7 @@ int ckv_atmo_destroy(ckv_atmo* a)
     if (a->d_node64) (void)hipFree(a->d_node64);
     if (a->d_cell32) (void)hipFree(a->d_cell32);
     if (a->d_depth) (void)hipFree(a->d_depth);
+    if (a->d_hnodes) (void)hipFree(a->d_hnodes);
     delete a;
     return CKV_OK;
 }
@@ -375,6 +407,12 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
         set_error("output: tel_offsets, result and records (capacity > 0) are required");
         return CKV_ERR_ARG;
     }
+    if (!atmo->h_nodes.empty() &&
+        ((params->tile_segments != 0 && params->tile_segments != 32) || params->depth_bin_gcm2 > 0.0 ||
+         params->grazing_exact)) {
+        set_error("node tables run with tile_segments 0 or 32, without profile or exact grazing path");
+        return CKV_ERR_ARG;
+    }
     int32_t prof_bins = 0;
     if (params->depth_bin_gcm2 > 0.0) {
         if ((rc = profile_bins(atmo, params->depth_bin_gcm2, &prof_bins))) return rc;
@@ -421,6 +459,9 @@ static int soft_common(const ckv_segments* segs, const ckv_showers* showers,
     }
     if (!(arr->soft_sigma > 0.0)) {
         set_error("telescope handle has no soft grid (use ckv_array_create_soft)"); return CKV_ERR_ARG;
+    }
+    if (!atmo->h_nodes.empty()) {
+        set_error("the soft response needs a uniform-grid atmosphere"); return CKV_ERR_ARG;
     }
     if ((rc = current_device(atmo->device)) || (rc = current_device(arr->device))) return rc;
     size_t need = workspace_layout(segs->n, showers->n_showers, arr->n_tel, 0, params, plan, workspace);
@@ -494,7 +535,9 @@ static int atmo_create(const double* alt_m, const double* eta, const double* dep
 {
     ckv_atmo* a = new (std::nothrow) ckv_atmo();
     if (!a) { set_error("out of host memory"); return CKV_ERR_NOMEM; }
-    int rc = build_atmo_tables(alt_m, eta, n, obs_level_m, step_m, a);
+    // step_m < 0 asks for node tables on the input's own altitudes
+    int rc = step_m < 0.0 ? build_node_tables(alt_m, eta, n, obs_level_m, a)
+                          : build_atmo_tables(alt_m, eta, n, obs_level_m, step_m, a);
     if (rc) { delete a; return rc; }
     if (depth) build_depth_table(alt_m, depth, n, a);
     if (a->n_nodes > (1 << 20)) { delete a; set_error("atmosphere table too fine"); return CKV_ERR_TABLE; }
@@ -514,11 +557,18 @@ static int atmo_create(const double* alt_m, const double* eta, const double* dep
         c[0] = (float)a->psi[i];
         c[1] = (float)(a->psi[i + 1] - a->psi[i]);
         for (int j = 0; j < 5; ++j) c[2 + j] = (float)a->P[j * m + i];
-        c[7] = (float)((double)i * a->step);   // node height above the observation level
+        // node height above the observation level
+        c[7] = (float)(a->h_nodes.empty() ? (double)i * a->step : a->h_nodes[i] - a->h_obs);
+    }
+    std::vector<double> hinfo;   // node tables: altitudes, then inverse cell widths
+    if (!a->h_nodes.empty()) {
+        hinfo = a->h_nodes;
+        for (int64_t i = 0; i + 1 < m; ++i) hinfo.push_back(1.0 / (a->h_nodes[i + 1] - a->h_nodes[i]));
     }
     if ((rc = upload(node.data(), node.size(), &a->d_node64)) ||
         (rc = upload(cell.data(), cell.size(), &a->d_cell32)) ||
-        (!a->depth.empty() && (rc = upload(a->depth.data(), a->depth.size(), &a->d_depth)))) {
+        (!a->depth.empty() && (rc = upload(a->depth.data(), a->depth.size(), &a->d_depth))) ||
+        (!hinfo.empty() && (rc = upload(hinfo.data(), hinfo.size(), &a->d_hnodes)))) {
         ckv_atmo_destroy(a);
         return rc;
     }

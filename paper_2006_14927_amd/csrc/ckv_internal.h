@@ -77,6 +77,9 @@ struct ckv_atmo {
     float* d_cell32 = nullptr;       // device, (n_nodes - 1) x kCell32
     std::vector<double> depth;       // host, n_nodes, vertical depth [g/cm^2]; empty: none
     double* d_depth = nullptr;       // device copy of depth
+    // node tables (non-uniform altitudes, binary-search lookups); empty: uniform grid
+    std::vector<double> h_nodes;     // host, n_nodes
+    double* d_hnodes = nullptr;      // device: n_nodes altitudes, then n_nodes-1 inverse widths
 };
 
 // Candidate grid: cells of size `cell` starting at (gx0, gy0); the list of
@@ -109,6 +112,8 @@ void set_error(const std::string& msg);
 // host builders (ckv_tables.cpp)
 int build_atmo_tables(const double* alt, const double* eta, int64_t n, double h_obs, double step,
                       ckv_atmo* a);
+// tables on the input's own altitudes above h_obs (node tables)
+int build_node_tables(const double* alt, const double* eta, int64_t n, double h_obs, ckv_atmo* a);
 // depth at the nodes of a (after build_atmo_tables), the same interpolation as eta
 void build_depth_table(const double* alt, const double* depth, int64_t n, ckv_atmo* a);
 int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ckv_grid* g);

@@ -46,6 +46,10 @@ struct Args {
     const double* node64;
     const float* cell32;
     int32_t lds_entries;        // table entries staged in LDS (the rest read from HBM)
+    // node tables (binary-search lookups): n_nodes altitudes then n_nodes-1 inverse
+    // widths; NULL for the uniform grid
+    const double* hnodes;
+    int32_t search_pow2;        // largest power of two below n_nodes - 1
     // longitudinal profile (prof_bins = 0: none)
     const double* depth;        // n_nodes, vertical depth [g/cm^2]
     double* prof_ph;            // n_showers x prof_bins
@@ -177,10 +181,23 @@ __device__ __forceinline__ double psi_fp64(const Args& a, double h)
 {
 #pragma clang fp contract(off)
     double hc = h < a.h_obs ? a.h_obs : (h > a.h_top ? a.h_top : h);
-    double x = (hc - a.h_obs) * a.inv_step;
-    int64_t i = (int64_t)floor(x);
-    if (i > a.n_nodes - 2) i = a.n_nodes - 2;
-    double f = x - (double)i;
+    int64_t i;
+    double f;
+    if (a.hnodes) {
+        // node tables: binary search for the bracketing pair, then the fraction
+        int lo = 0, hi = a.n_nodes - 1;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.hnodes[mid] <= hc) lo = mid; else hi = mid;
+        }
+        i = lo;
+        f = (hc - a.hnodes[lo]) / (a.hnodes[lo + 1] - a.hnodes[lo]);
+    } else {
+        double x = (hc - a.h_obs) * a.inv_step;
+        i = (int64_t)floor(x);
+        if (i > a.n_nodes - 2) i = a.n_nodes - 2;
+        f = x - (double)i;
+    }
     double lo = a.node64[kNode64 * i], hi = a.node64[kNode64 * (i + 1)];
     return lo + f * (hi - lo);
 }
@@ -379,12 +396,19 @@ __host__ __device__ inline size_t wave_bytes(int prec, int tile_segs, int n_tel,
 // carry none of their code or registers.
 constexpr int kFeatProfile = 1;
 constexpr int kFeatExact = 2;
+constexpr int kFeatSearch = 4;   // node tables: binary search per bunch (alone, 32-step tiles)
+
+__host__ __device__ inline size_t search_bytes(int n_nodes)
+{
+    return ((size_t)(2 * n_nodes - 1) * sizeof(double) + 15) & ~(size_t)15;
+}
 
 template <int PREC, int TS, int FEAT>
 __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
 {
     constexpr bool PROF = (FEAT & kFeatProfile) != 0;
     constexpr bool EXACT = (FEAT & kFeatExact) != 0;
+    constexpr bool SEARCH = (FEAT & kFeatSearch) != 0;
     using T = typename std::conditional<PREC == 0, double, float>::type;
     using Entry = StepEntry<PREC>;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -401,7 +425,12 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
         const int n16 = (int)(tab_bytes / 16);
         for (int q = threadIdx.x; q < n16; q += blockDim.x) dst[q] = src[q];
     }
-    unsigned char* wbase = lds + ((tab_bytes + 15) & ~(size_t)15) +
+    // node tables: altitudes and inverse widths after the table
+    double* hn_lds = reinterpret_cast<double*>(lds + ((tab_bytes + 15) & ~(size_t)15));
+    const size_t srch_bytes = SEARCH ? search_bytes(a.n_nodes) : 0;
+    if (SEARCH)
+        for (int q = threadIdx.x; q < 2 * a.n_nodes - 1; q += blockDim.x) hn_lds[q] = a.hnodes[q];
+    unsigned char* wbase = lds + ((tab_bytes + 15) & ~(size_t)15) + srch_bytes +
                            (size_t)wave * wave_bytes(PREC, TS, a.n_tel, PROF ? a.prof_bins : 0);
     Entry* stash = reinterpret_cast<Entry*>(wbase);
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + TS * sizeof(Entry));
@@ -537,7 +566,7 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
             int32_t k, sidx;
             double uod, vod;   // observed direction for the sphere test (live bunches)
             int pbin = -1;     // depth bin of the bunch for the profile, -1: not counted
-            double xcell;
+            double fcell, dcell;   // fraction and height of the emission point in its cell
             int ci;
             if (active) {
                 const Entry& e = stash[si];
@@ -573,9 +602,22 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                 }
                 const double te = fma(s_along, e.inv_bc, e.t0);
                 // table cell and fraction of the emission altitude (index and depth)
-                xcell = (he - a.h_obs) * a.inv_step;
-                ci = min((int)xcell, a.n_nodes - 2);
-                if (PROF && he >= a.h_obs && he < a.h_top) pbin = profile_bin(a, ci, xcell - (double)ci);
+                if (SEARCH) {
+                    // node tables: branch-free binary search in LDS (sec. 3.3.1)
+                    int lo = 0;
+                    for (int stp = a.search_pow2; stp > 0; stp >>= 1) {
+                        const int c = lo + stp;
+                        if (c < a.n_nodes - 1 && hn_lds[c] <= he) lo = c;
+                    }
+                    ci = lo;
+                    dcell = he - hn_lds[ci];
+                    fcell = dcell * hn_lds[a.n_nodes + ci];
+                } else {
+                    const double xcell = (he - a.h_obs) * a.inv_step;
+                    ci = min((int)xcell, a.n_nodes - 2);
+                    fcell = xcell - (double)ci;
+                }
+                if (PROF && he >= a.h_obs && he < a.h_top) pbin = profile_bin(a, ci, fcell);
                 const double ct = e.cos_t;
                 // direction on the Cherenkov cone
                 double pu, pv, pw;
@@ -644,7 +686,7 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                 if (drop_why < 0 && !slow) {
                     alive = true;
                     // ---- atmosphere at the emission altitude (uniform table, no search)
-                    const T f = (T)(xcell - (double)ci);
+                    const T f = (T)fcell;
                     T psi_i, dpsi, P0, P1, P2, P3, P4, P5;
                     // LDS read always (index clamped into the staged part); the rare
                     // lookups above it are replaced by a read from HBM
@@ -665,7 +707,7 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                         }
                         psi_i = n0[0];
                         dpsi = n1 - n0[0];
-                        P0 = (double)ci * a.step;
+                        P0 = SEARCH ? hn_lds[ci] - a.h_obs : (double)ci * a.step;
                         P1 = n0[1]; P2 = n0[2]; P3 = n0[3]; P4 = n0[4]; P5 = n0[5];
                     } else {
                         float4 c_a, c_b;
@@ -689,7 +731,7 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                         P0 = c_b.w;
                     }
                     const T psi_e = psi_i + f * dpsi;
-                    const T dz = f * (PREC == 0 ? (T)a.step : (T)step32);
+                    const T dz = SEARCH ? (T)dcell : f * (PREC == 0 ? (T)a.step : (T)step32);
                     // D_k = int_{h_obs}^{h_e} (psi - psi_e)^k dh, k = 1..5, split at the
                     // cell's lower node h_i: below it, the node moments shifted to psi_e,
                     // sum_j C(k,j) (-psi_e)^(k-j) P_j(h_i) with P_0(h_i) = h_i - h_obs
@@ -1555,6 +1597,10 @@ Args make_args(const RunPlan& p)
     a.node64 = at->d_node64;
     a.cell32 = at->d_cell32;
     a.lds_entries = lds_entries(p.params.precision, a.n_nodes, p.prof_bins > 0);
+    a.hnodes = at->d_hnodes;
+    a.search_pow2 = 0;
+    while ((a.search_pow2 ? 2 * a.search_pow2 : 1) < a.n_nodes - 1)
+        a.search_pow2 = a.search_pow2 ? 2 * a.search_pow2 : 1;
     a.depth = at->d_depth;
     if (p.prof_bins > 0) {
         a.prof_ph = p.out.profile_photons;
@@ -1614,7 +1660,8 @@ int check_launch(const char* what)
 int emit_config(int precision, int n_tel, int prof_bins, const ckv_atmo* atmo, int tile_segs,
                 int* waves, size_t* lds_bytes)
 {
-    const size_t tab = (table_bytes(precision, (int)atmo->n_nodes, prof_bins > 0) + 15) & ~(size_t)15;
+    const size_t tab = ((table_bytes(precision, (int)atmo->n_nodes, prof_bins > 0) + 15) & ~(size_t)15) +
+                       (atmo->h_nodes.empty() ? 0 : search_bytes((int)atmo->n_nodes));
     const size_t cap = 160 * 1024;
     const size_t per = wave_bytes(precision, tile_segs, n_tel, prof_bins);
     const int max_waves = precision == 0 ? kMaxEmitWaves / 2 : kMaxEmitWaves;
@@ -1648,6 +1695,12 @@ int launch_emit(const Args& a, int grid, int waves, size_t lds, hipStream_t st)
 template <int PREC, int TS>
 int launch_emit_feat(const Args& a, int grid, int waves, size_t lds, hipStream_t st)
 {
+    if (a.hnodes) {
+        // node tables run alone (checked by the caller) and with 32-step tiles
+        if (TS == 32) return launch_emit<PREC, 32, kFeatSearch>(a, grid, waves, lds, st);
+        set_error("node tables need tile_segments 32");
+        return CKV_ERR_ARG;
+    }
     const int feat = (a.prof_bins > 0 ? kFeatProfile : 0) | (a.grazing_exact ? kFeatExact : 0);
     switch (feat) {
         case 0: return launch_emit<PREC, TS, 0>(a, grid, waves, lds, st);
@@ -1686,6 +1739,7 @@ int launch_run(RunPlan& p)
     if (p.emit_waves < waves) {
         waves = p.emit_waves;
         lds = ((table_bytes(p.params.precision, a.n_nodes, p.prof_bins > 0) + 15) & ~(size_t)15) +
+              (a.hnodes ? search_bytes(a.n_nodes) : 0) +
               (size_t)waves * wave_bytes(p.params.precision, p.tile_segs, a.n_tel, p.prof_bins);
     }
     if (p.prof_bins > 0) {

@@ -74,6 +74,43 @@ int build_atmo_tables(const double* alt, const double* eta, int64_t n, double h_
     return CKV_OK;
 }
 
+int build_node_tables(const double* alt, const double* eta, int64_t n, double h_obs, ckv_atmo* a)
+{
+#pragma clang fp contract(off)
+    if (!(h_obs >= alt[0]) || !(h_obs < alt[n - 1])) {
+        set_error("atmosphere: observation level outside the profile");
+        return CKV_ERR_TABLE;
+    }
+    a->h_nodes.clear();
+    a->h_nodes.push_back(h_obs);
+    for (int64_t i = 0; i < n; ++i)
+        if (alt[i] > h_obs) a->h_nodes.push_back(alt[i]);
+    const int64_t m = (int64_t)a->h_nodes.size();
+    a->n_nodes = m;
+    a->h_obs = h_obs;
+    a->step = 0.0;               // not a uniform grid
+    a->inv_step = 0.0;
+    a->h_top = a->h_nodes[m - 1];
+    a->psi.assign(m, 0.0);
+    a->P.assign(5 * m, 0.0);
+    for (int64_t i = 0; i < m; ++i) {
+        double e = profile_at(alt, eta, n, a->h_nodes[i]);
+        a->psi[i] = e * (2.0 + e);
+    }
+    // the cell integral of psi^j for psi linear over a cell of width h_{i+1} - h_i
+    for (int64_t i = 0; i + 1 < m; ++i) {
+        double lo = a->psi[i], hi = a->psi[i + 1], width = a->h_nodes[i + 1] - a->h_nodes[i];
+        double hs = 1.0, hp = 1.0;
+        for (int j = 1; j <= 5; ++j) {
+            hp = hp * hi;
+            hs = lo * hs + hp;
+            a->P[(j - 1) * m + i + 1] = a->P[(j - 1) * m + i] + width * hs / (double)(j + 1);
+        }
+    }
+    a->n_obs = std::sqrt(1.0 + a->psi[0]);
+    return CKV_OK;
+}
+
 void build_depth_table(const double* alt, const double* depth, int64_t n, ckv_atmo* a)
 {
 #pragma clang fp contract(off)
