@@ -131,6 +131,7 @@ class Atmosphere:
     def __init__(self, alt=None, eta=None, obs_level: float = 0.0, step: float = 0.0, handle=None,
                  depth=None, nodes: bool = False):
         """nodes=True: tables on the profile's own altitudes, binary-search lookups."""
+        self._L = lib()
         if handle is not None:          # adopt a handle made by another constructor
             self.handle = handle
             return
@@ -184,8 +185,10 @@ class Atmosphere:
         return psi, P
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().ckv_atmo_destroy(self.handle)
+        # the library is held by the object: module globals may be gone at exit
+        L = getattr(self, "_L", None)
+        if getattr(self, "handle", None) and L is not None:
+            L.ckv_atmo_destroy(self.handle)
             self.handle = None
 
     __del__ = close
@@ -196,6 +199,7 @@ class TelescopeArray:
     soft_sigma > 0, the grid of the soft response)."""
 
     def __init__(self, x, y, r, soft_sigma: float = 0.0):
+        self._L = lib()
         self.x = np.ascontiguousarray(x, dtype=np.float64)
         self.y = np.ascontiguousarray(y, dtype=np.float64)
         self.r = np.ascontiguousarray(r, dtype=np.float64)
@@ -214,8 +218,9 @@ class TelescopeArray:
         return int(self.x.shape[0])
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().ckv_array_destroy(self.handle)
+        L = getattr(self, "_L", None)
+        if getattr(self, "handle", None) and L is not None:
+            L.ckv_array_destroy(self.handle)
             self.handle = None
 
     __del__ = close
