@@ -305,6 +305,31 @@ def streamed_timing(hip, zeniths=(0.0, 20.0, 40.0, 60.0)):
     return out
 
 
+def order_study(hip, wl, atmo, tels, stream, steps: int, warmup: int):
+    """Bunch-kernel time with the shower's steps in generator order, sorted by
+    start altitude (neighbouring lanes then read neighbouring table cells), and
+    shuffled: the memory-layout study of the step input."""
+    import numpy as np
+    import torch
+
+    from paper_2006_14927_amd import ckv
+    orders = {"generator": np.arange(wl.segs.n),
+              "by_altitude": np.argsort(-wl.segs.h0, kind="stable"),
+              "shuffled": np.random.default_rng(1).permutation(wl.segs.n)}
+    out = {}
+    for name, idx in orders.items():
+        d = ckv.DeviceSegments(wl.segs.take(idx))
+        p = ckv.make_params(precision=ckv.CKV_MIXED, bunch_size=wl.bunch_size, lambda_min=wl.lambda_min,
+                            lambda_max=wl.lambda_max, seed=wl.seed, tile_segments=32, waves_per_group=16)
+        ms, kms, res = time_path(hip, ckv, d, atmo, tels, p, max(1 << 16, 2 * wl.segs.n), steps, warmup,
+                                 stream)
+        out[name] = {"ms_per_step": ms, "bunch_kernel_ms": kms, "bunches": res["n_bunches"]}
+        print(f"# step order {name}: {out[name]}", file=sys.stderr, flush=True)
+        del d
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, target_cpu_seconds: float = 20.0):
     """The FP64 oracle on an evenly spaced sample of the shower's steps."""
     import numpy as np
@@ -343,6 +368,8 @@ def main(argv=None):
                     help="skip the 256-shower batched launch (~3e8 steps)")
     ap.add_argument("--no-streamed", action="store_true",
                     help="skip the 5e7-step hadron-like showers streamed in 256 MB chunks")
+    ap.add_argument("--order-study", action="store_true",
+                    help="also time the shower with its steps sorted by altitude and shuffled")
     ap.add_argument("--no-tune-cache", action="store_true",
                     help="re-run the launch-shape autotuner instead of using its cache")
     ap.add_argument("--segments", type=int, default=2_000_000,
@@ -500,6 +527,8 @@ def main(argv=None):
         torch.cuda.empty_cache()
     if not args.no_streamed:
         line["streamed"] = streamed_timing(hip)
+    if args.order_study:
+        line["step_order_study"] = order_study(hip, wl, atmo, tels, stream, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)
