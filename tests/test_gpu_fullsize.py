@@ -3,8 +3,8 @@ benchmark uses, checked where the oracle can follow: exact bunch counts for ever
 step (or every step of sampled showers), oracle records for sampled steps with
 their original random numbers, and properties that hold at any size.
 
-* hadron-like shower, 60 deg zenith, 5e7 steps (~2.5e9 bunches), mixed precision,
-  output streamed in chunks of 8 388 608 records (256 MB);
+* hadron-like showers at 0, 20, 40 and 60 deg zenith, 5e7 steps each (2.5-4.3e9
+  bunches), mixed precision, output streamed in chunks of 8 388 608 records (256 MB);
 * 256 showers of 30 GeV - 30 TeV (~3e8 steps, ~1.6e10 bunches) in one persistent
   launch;
 * differentiation workload, 64 showers x 5e5 steps: forward against the oracle on
@@ -32,15 +32,16 @@ def _sampled_view(g_off, g_rec, g_ids, keep, n_groups):
     return dict(offsets=off, rec=g_rec[keep], ids=g_ids[keep])
 
 
-def test_hadron_like_60deg_full_size_streamed():
+@pytest.mark.parametrize("zenith", [0.0, 20.0, 40.0, 60.0])
+def test_hadron_like_full_size_streamed(zenith):
     import torch
-    wl = synth.hadron_like(60.0)
+    wl = synth.hadron_like(zenith)
     assert wl.segs.n == 50_000_000 and wl.segs.n_showers == 1
     cfg = oracle.Config.from_workload(wl)
     atmo, tels = handles(wl)
     d = ckv.DeviceSegments(wl.segs)
     st = ckv.Streamer(d, atmo, tels, params(wl, ckv.CKV_MIXED))
-    say(f"[gpu] hadron 60 deg full: {st.total_bunches} bunches")
+    say(f"[gpu] hadron {zenith} deg full: {st.total_bunches} bunches")
     # exact bunch counts of every step against the oracle, in slices
     n_b_gpu = ckv.count(d, atmo, params(wl, ckv.CKV_MIXED)).cpu().numpy()
     total = 0
@@ -80,7 +81,7 @@ def test_hadron_like_60deg_full_size_streamed():
     ores = oracle.run(cfg, sub, nthreads=16, seg_id=idx)
     rep = compare_records(wl, cfg, ores, dict(offsets=off, rec=rec, ids=ids), ckv.CKV_MIXED,
                           segs=sub, seg_map=idx)
-    say(f"[gpu] hadron 60 deg full, sampled steps: {rep}")
+    say(f"[gpu] hadron {zenith} deg full, sampled steps: {rep}")
 
 
 def test_batched_256_showers_full_size():
