@@ -245,3 +245,22 @@ def test_bad_shower_offsets_flagged_on_device():
                          np.array([0, 150], dtype=np.int64), segs.t_ref, segs.shower_ids)
     g = gpu_run(wl, ckv.CKV_MIXED, segs=bad)
     assert g["result"]["error"] == 1 and g["result"]["n_bunches"] == 0
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_maximum_telescope_count(precision):
+    """CKV_MAX_TEL = 1024 spheres (the per-wave crossing counters then take 4 KB of
+    LDS each, so the bunch kernel runs fewer waves per workgroup)."""
+    wl = synth.vertical_gamma(6000)
+    wl.tels = synth.telescopes_disk(n=1024, disk_radius=550.0, seed=1024)
+    assert wl.tels.n == 1024
+    cfg = oracle.Config.from_workload(wl)
+    ores = oracle.run(cfg, wl.segs, nthreads=16)
+    g = gpu_run(wl, precision)
+    res = g["result"]
+    assert res["error"] == 0 and res["overflow"] == 0 and res["n_bunches"] == ores.n_bunches
+    if precision == ckv.CKV_FP64:
+        np.testing.assert_array_equal(g["offsets"], ores.offsets)
+    rep = compare_records(wl, cfg, ores, g, precision)
+    assert rep["matched"] > 10_000
+    say(f"[gpu] 1024 telescopes prec={precision}: {rep}")

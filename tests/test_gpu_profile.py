@@ -117,3 +117,15 @@ def test_profile_requires_depth_table():
     atmo2, _ = _handles(wl)
     with pytest.raises(ckv.CkvError):
         atmo2.profile_bins(1.0)          # more than CKV_MAX_PROFILE_BINS bins
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_profile_near_maximum_bins(precision):
+    """6.25 g/cm^2 bins: 127 of the CKV_MAX_PROFILE_BINS = 128 histogram slots."""
+    wl = synth.vertical_gamma(4000)
+    atmo, tels = _handles(wl)
+    assert atmo.profile_bins(6.25) == 127
+    _, _, ph_o, bu_o = _oracle(wl, 6.25)
+    ph, bu, _, _, _ = _run(wl, atmo, tels, precision, 6.25)
+    np.testing.assert_array_equal(bu, bu_o)
+    np.testing.assert_allclose(ph, ph_o, rtol=1e-12, atol=1e-9)
