@@ -55,19 +55,19 @@ OPS_MIXED = {
 }
 OPS_FP64 = {
     "philox4x32-10": 60,
-    "uniforms u0, u1, u2": 6,
+    "uniforms u0, u2": 4,
     "emission point and time": 7,
-    "azimuth sincos (FP64 range reduction + polynomials)": 40,
+    "azimuth sin/cos: quadrant fold + Taylor polynomials to a^17 (FP64)": 32,
     "direction on the cone": 9,
-    "wavelength (FP64 divide)": 9,
+    "wavelength (rcp + 2 Newton)": 7,
     "drop tests": 4,
     "table index": 6,
     "moments about psi_e, D1..D5: node shift + in-cell closed form": 31,
-    "index at emission (FP64 sqrt, divide)": 16,
-    "1/w (FP64 divide)": 8,
-    "series variable q (FP64 divide)": 11,
+    "index at emission (sqrt, 1/n_e by rcp + 2 Newton, n_e / n_obs)": 8,
+    "1/w (rcp + 2 Newton)": 5,
+    "series variable q": 3,
     "advance series S": 9,
-    "time series T (+ divide by n_e)": 27,
+    "time series T": 20,
     "ground point, arrival time": 5,
     "observed direction, record conversions": 6,
     "candidate cell + sphere tests": 16,

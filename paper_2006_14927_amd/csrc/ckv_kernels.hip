@@ -273,6 +273,49 @@ __device__ __forceinline__ void sincos_turns(uint32_t r, float& s, float& c)
     s = (q == 0) ? sq : (q == 1) ? cq : (q == 2) ? -sq : -cq;
 }
 
+// The same in FP64 for the FP64 path: quadrant and half-quadrant fold from the
+// integer draw, then Taylor series of sin and cos on |a| <= pi/4 to a^17 and a^16
+// (next terms below 1e-17).
+__device__ __forceinline__ void sincos_turns64(uint32_t r, double& s, double& c)
+{
+    const uint32_t q = r >> 30;
+    const uint32_t low = r & 0x3FFFFFFFu;
+    const bool upper = low >= 0x20000000u;
+    const uint32_t m = upper ? (0x3FFFFFFFu - low) : low;
+    const double kq = 1.4629180792671596e-09;          // (pi/2) / 2^30
+    const double a = fma((double)m, kq, 0.5 * kq);
+    const double a2 = a * a;
+    double sa = fma(a2, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0);
+    sa = fma(a2, sa, 1.0 / 6227020800.0);
+    sa = fma(a2, sa, -1.0 / 39916800.0);
+    sa = fma(a2, sa, 1.0 / 362880.0);
+    sa = fma(a2, sa, -1.0 / 5040.0);
+    sa = fma(a2, sa, 1.0 / 120.0);
+    sa = fma(a2, sa, -1.0 / 6.0);
+    sa = a * fma(a2, sa, 1.0);
+    double ca = fma(a2, 1.0 / 20922789888000.0, -1.0 / 87178291200.0);
+    ca = fma(a2, ca, 1.0 / 479001600.0);
+    ca = fma(a2, ca, -1.0 / 3628800.0);
+    ca = fma(a2, ca, 1.0 / 40320.0);
+    ca = fma(a2, ca, -1.0 / 720.0);
+    ca = fma(a2, ca, 1.0 / 24.0);
+    ca = fma(a2, ca, -0.5);
+    ca = fma(a2, ca, 1.0);
+    const double cq = upper ? sa : ca;
+    const double sq = upper ? ca : sa;
+    c = (q == 0) ? cq : (q == 1) ? -sq : (q == 2) ? -cq : sq;
+    s = (q == 0) ? sq : (q == 1) ? cq : (q == 2) ? -sq : -cq;
+}
+
+// 1/x in FP64 from the hardware reciprocal and two Newton steps (to an ulp or so,
+// without the correctly rounded division's scaling sequence)
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // --------------------------------------------------------------------------
 // LDS layout of the bunch kernel
 //   [atmosphere table][wave 0 area][wave 1 area]...
@@ -456,6 +499,7 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
     const float step32 = __builtin_bit_cast(
         float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, (float)a.step)));
     // n - 1 at the observation level, for the observed direction
+    const double inv_nobs64 = 1.0 / a.n_obs;
     const float d_obs = (float)(a.n_obs - 1.0);
     const float inv_1pdobs = 1.0f / (1.0f + d_obs);
 
@@ -622,16 +666,14 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                 // direction on the Cherenkov cone
                 double pu, pv, pw;
                 if (PREC == 0) {
-                    const double phi = 6.283185307179586 * fma((double)r1, 2.3283064365386963e-10,
-                                                               1.1641532182693481e-10);
                     double sp, cp;
-                    sincos(phi, &sp, &cp);
+                    sincos_turns64(r1, sp, cp);
                     pu = ct * tu + (cp * (double)e.sb1x + sp * (double)e.sb2x);
                     pv = ct * tv + (cp * (double)e.sb1y + sp * (double)e.sb2y);
                     pw = ct * tw - (cp * (double)e.sb1z + sp * (double)e.sb2z);
                     photons = (float)e.photons;
-                    lam = (float)(1.0 / (a.inv_l1 - fma((double)r2, 2.3283064365386963e-10,
-                                                        1.1641532182693481e-10) * a.dl));
+                    lam = (float)rcp64(a.inv_l1 - fma((double)r2, 2.3283064365386963e-10,
+                                                      1.1641532182693481e-10) * a.dl);
                 } else {
                     float sp, cp;
                     sincos_turns(r1, sp, cp);
@@ -665,10 +707,8 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                         const double b1x = 1.0 + sgn * tu * tu * ia, b1y = sgn * ib, b1z = -sgn * tu;
                         const double b2x = ib, b2y = sgn + tv * tv * ia, b2z = -tv;
                         const double st_ = sqrt((1.0 - ct) * (1.0 + ct));
-                        const double phi = 6.283185307179586 *
-                                           fma((double)r1, 2.3283064365386963e-10, 1.1641532182693481e-10);
                         double sp, cp;
-                        sincos(phi, &sp, &cp);
+                        sincos_turns64(r1, sp, cp);
                         pu = ct * tu + st_ * (cp * b1x + sp * b2x);
                         pv = ct * tv + st_ * (cp * b1y + sp * b2y);
                         pw = ct * tw - st_ * (cp * b1z + sp * b2z);
@@ -759,10 +799,10 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                     T ratio, q, inv_ne;
                     if (PREC == 0) {
                         ne = sqrt(1.0 + (double)psi_e);
-                        ratio = (T)(ne / a.n_obs);
-                        inv_w = 1.0 / pw;
-                        q = (T)1 / (ne2 * (T)(pw * pw));
-                        inv_ne = (T)(1.0 / ne);
+                        ratio = (T)(ne * inv_nobs64);
+                        inv_w = rcp64(pw);
+                        inv_ne = (T)rcp64(ne);
+                        q = (T)(inv_w * inv_w) * (inv_ne * inv_ne);
                     } else {
                         const float de = (float)psi_e * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_sqrtf(1.0f + (float)psi_e));
                         ne = 1.0 + (double)de;
@@ -1372,9 +1412,8 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
             const double ye = e.y0 + s_along * e.v;
             const double he = e.h0 - s_along * e.w;
             const double te = e.t0 + s_along * e.inv_bc;
-            const double phi = 6.283185307179586 * (((double)r[1] + 0.5) * 2.3283064365386963e-10);
             double sp, cp;
-            sincos(phi, &sp, &cp);
+            sincos_turns64(r[1], sp, cp);
             const double Ex = cp * e.b1x + sp * e.b2x;
             const double Ey = cp * e.b1y + sp * e.b2y;
             const double Ez = cp * e.b1z + sp * e.b2z;
@@ -1413,7 +1452,7 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
             D[5] = X5 + dz * (1.0 / 6.0) * (dl4 * del);
             const double ne2 = 1.0 + psi_e;
             const double ne = sqrt(ne2);
-            const double inv_ne = 1.0 / ne, inv_pw = 1.0 / pw;
+            const double inv_ne = rcp64(ne), inv_pw = rcp64(pw);
             const double q = (inv_pw * inv_pw) * (inv_ne * inv_ne);
             const double Sser = D[0] + q * (a1 * D[1] + q * (a2 * D[2] + q * (a3 * D[3] + q * a4 * D[4])));
             const double U = (ne2 * D[0] + D[1]) +
