@@ -60,7 +60,8 @@ class _Config(C.Structure):
                 ("n_tel", C.c_int32), ("tx", C.c_void_p), ("ty", C.c_void_p), ("tr", C.c_void_p),
                 ("bunch_size", C.c_double), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("w_min", C.c_double), ("seed", C.c_uint64),
-                ("grazing_exact", C.c_int32), ("h_nodes", C.c_void_p)]
+                ("grazing_exact", C.c_int32), ("h_nodes", C.c_void_p),
+                ("earth_radius", C.c_double)]
 
 
 class _Segments(C.Structure):
@@ -87,6 +88,9 @@ def _declare(L):
     L.or_lookup_many.argtypes = [C.POINTER(_Config), I64, P, P]
     L.or_propagate_many.argtypes = [C.POINTER(_Config), I64, P, P]
     L.or_propagate_exact_many.argtypes = [C.POINTER(_Config), I64, P, P]
+    L.or_propagate_curved_many.argtypes = [C.POINTER(_Config), I64, P, P]
+    L.or_curved_altitude.restype = D
+    L.or_curved_altitude.argtypes = [D, D, D, D]
     L.or_sphere_disc.restype = D
     L.or_sphere_disc.argtypes = [D] * 7
     L.or_frank_tamm_k.restype = D
@@ -150,6 +154,8 @@ def profile(cfg: "Config", segs, T: np.ndarray, width: float, nthreads: int = 1,
             seg_id=None):
     """Longitudinal photon-production profile: (photons, bunches), each
     (n_showers, n_bins), binned in vertical depth of the emission point."""
+    if cfg.earth_radius > 0.0:
+        raise ValueError("the profile is defined for the plane-parallel atmosphere")
     sv = SegView(segs, seg_id_base=seg_id_base, seg_id=seg_id)
     T = np.ascontiguousarray(T, dtype=np.float64)
     nb = profile_bins(T, width)
@@ -198,7 +204,7 @@ class Config:
 
     def __init__(self, tables: Tables, tel_x, tel_y, tel_r, *, bunch_size=5.0,
                  lambda_min=300.0, lambda_max=600.0, seed=0x14927, w_min=W_MIN,
-                 grazing_exact=False):
+                 grazing_exact=False, earth_radius=0.0):
         self.tables = tables
         self.tx = np.ascontiguousarray(tel_x, dtype=np.float64)
         self.ty = np.ascontiguousarray(tel_y, dtype=np.float64)
@@ -208,11 +214,13 @@ class Config:
         self.h_nodes = None if tables.h_nodes is None else np.ascontiguousarray(tables.h_nodes)
         self.bunch_size, self.lambda_min, self.lambda_max = bunch_size, lambda_min, lambda_max
         self.seed, self.w_min = int(seed), w_min
+        self.earth_radius = float(earth_radius)
         self.c = _Config(tables.n_nodes, tables.h_obs, tables.step, _p(self.psi).value,
                          _p(self.P).value, self.tx.shape[0], _p(self.tx).value,
                          _p(self.ty).value, _p(self.tr).value, bunch_size, lambda_min,
                          lambda_max, w_min, self.seed, int(bool(grazing_exact)),
-                         None if self.h_nodes is None else _p(self.h_nodes).value)
+                         None if self.h_nodes is None else _p(self.h_nodes).value,
+                         self.earth_radius)
 
     @property
     def n_tel(self) -> int:
@@ -372,6 +380,27 @@ def propagate_exact(cfg: Config, x_e, y_e, h_e, u, v, w) -> dict:
     return {f: out[:, i] for i, f in enumerate(PROP_FIELDS)}
 
 
+def propagate_curved(cfg: Config, x_e, y_e, z_e, u, v, w) -> dict:
+    """Exact propagation through spherical shells of radius cfg.earth_radius
+    (the curved variant); (x_e, y_e, z_e) Cartesian with z along the array
+    origin's vertical.  Adds 'status' (-1 reached the ground, else the drop
+    reason index: upward or grazing)."""
+    if not cfg.earth_radius > 0.0:
+        raise ValueError("propagate_curved needs earth_radius > 0")
+    inp = np.ascontiguousarray(np.stack(np.broadcast_arrays(
+        *[np.atleast_1d(np.asarray(a, dtype=np.float64)) for a in (x_e, y_e, z_e, u, v, w)]),
+        axis=1))
+    out = np.empty((inp.shape[0], 10))
+    lib().or_propagate_curved_many(C.byref(cfg.c), inp.shape[0], _p(inp), _p(out))
+    d = {f: out[:, i + 1] for i, f in enumerate(PROP_FIELDS)}
+    d["status"] = out[:, 0].astype(np.int64)
+    return d
+
+
+def curved_altitude(R: float, x: float, y: float, z: float) -> float:
+    return lib().or_curved_altitude(float(R), float(x), float(y), float(z))
+
+
 def philox(ctr, key) -> np.ndarray:
     ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(4)
     key = np.ascontiguousarray(key, dtype=np.uint32).reshape(2)
@@ -437,6 +466,8 @@ def soft(cfg: Config, segs, n_b_frozen, sigma: float, nthreads: int = 1, seg_id_
          seg_id=None):
     """(S, A), each (n_showers, n_tel): soft photon counts and photon-weighted times.
     seg_id_base / seg_id as in run()."""
+    if cfg.earth_radius > 0.0:
+        raise ValueError("the soft response is defined for the plane-parallel atmosphere")
     sv = SegView(segs, seg_id_base=seg_id_base, seg_id=seg_id)
     nb = np.ascontiguousarray(n_b_frozen, dtype=np.int64)
     S = np.zeros(sv.n_showers * cfg.n_tel)

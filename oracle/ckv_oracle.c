@@ -64,6 +64,8 @@ typedef struct {
     int32_t grazing_exact;   /* 1: bunches with 0 < w <= w_min are traced exactly, not dropped */
     const double* h_nodes;   /* NULL: uniform nodes h_obs + i*step; else node altitudes
                                 (ascending, h_nodes[0] = h_obs), found by binary search */
+    double earth_radius;     /* 0: plane-parallel atmosphere; > 0: spherical shells of this
+                                radius (curved variant, every bunch traced exactly) */
 } or_config;
 
 typedef struct {
@@ -269,6 +271,18 @@ typedef struct {
     double D[3], b1[3], b2[3];   /* physical direction (u, v, -w) and its frame */
 } or_setup;
 
+/* Curved variant: x, y horizontal at the array origin, z along the origin's
+   vertical from sea level, the Earth's centre at (0, 0, -R).  The altitude of
+   a point is its distance from the centre minus R, written without the
+   cancellation of sqrt(...) - R. */
+double or_curved_altitude(double R, double x, double y, double z)
+{
+    double q = x * x + y * y;
+    double rz = R + z;
+    double r = sqrt(q + rz * rz);
+    return (q + z * (2.0 * R + z)) / (r + R);
+}
+
 double or_frank_tamm_k(double lambda_min_nm, double lambda_max_nm)
 {
     /* 2 pi alpha (1/l1 - 1/l2), in photons per metre for sin^2(theta) = 1 */
@@ -289,7 +303,15 @@ void or_segment_setup(const or_config* cf, const or_segments* sg, int64_t i, or_
     double r = m / E;
     double r2 = r * r;                       /* 1/gamma^2 = 1 - beta^2 */
     if (!(r2 < 1.0)) { st->status = OR_DROP_MASS; return; }
-    double h_mid = sg->h0[i] - (0.5 * L) * sg->w[i];
+    double h_mid;
+    if (cf->earth_radius > 0.0) {
+        /* curved: the altitude of the step's midpoint above the spherical shells */
+        double hl = 0.5 * L;
+        h_mid = or_curved_altitude(cf->earth_radius, sg->x0[i] + hl * sg->u[i],
+                                   sg->y0[i] + hl * sg->v[i], sg->h0[i] - hl * sg->w[i]);
+    } else {
+        h_mid = sg->h0[i] - (0.5 * L) * sg->w[i];
+    }
     double psi;
     or_lookup(cf, h_mid, &psi, NULL);
     double n2 = 1.0 + psi;
@@ -434,6 +456,136 @@ void or_propagate_exact_many(const or_config* cf, int64_t m, const double* in, d
 
 
 /* ------------------------------------------------------------------------- */
+/* Curved atmosphere (spherical shells of radius R; the large-zenith variant). */
+/* The index depends on the altitude h = r - R only (r the distance from the  */
+/* Earth's centre C), so a ray stays in the plane of C, its emission point and */
+/* its direction, and keeps the Bouguer invariant K = n r sin(zeta), zeta the  */
+/* angle from the local vertical.  With s = sqrt(n^2 r^2 - K^2) the polar      */
+/* angle swept about C and the optical path down to the observation sphere    */
+/* r_obs = R + h_obs are                                                      */
+/*   theta = int K / (r s) dr,     c T = int n^2 r / s dr.                    */
+/* s^2 is taken relative to the emission point, s^2 = s_e^2 + M(h) - M(h_e)   */
+/* with M = n^2 r^2, M(h) - M(h_e) = (h - h_e)(r + r_e) + psi r^2 - psi_e r_e^2 */
+/* and s_e = n_e (r_e cos zeta_e), which keeps it accurate for grazing rays.   */
+/* psi is linear in h inside each table cell; over a cell, s^2 is nearly      */
+/* linear in h, so the substitution h = h_b + dh (u^2 - s_b^2)/(s_t^2 - s_b^2) */
+/* (u from s_b to s_t) removes the 1/s behaviour:                             */
+/*   int F / s dh = 2 dh / (s_t^2 - s_b^2) int F(h(u)) u / s(h(u)) du,        */
+/* evaluated with 8-point Gauss-Legendre in u.  The ray reaches the ground iff */
+/* s^2 > 0 there; a ray with cos zeta_e <= 0 moves outward for good.          */
+/* The array is treated as planar: the ground point's x, y and the arrival    */
+/* direction's x, y components enter the same sphere test as the flat path.   */
+/* Returns -1, OR_DROP_UPWARD or OR_DROP_GRAZING (the ray turns above ground). */
+/* ------------------------------------------------------------------------- */
+static const double or_gl8_x[4] = {0.18343464249564980493947614236018,
+                                   0.52553240991632898581773904918925,
+                                   0.79666647741362673959155393647583,
+                                   0.96028985649753623168356086856947};
+static const double or_gl8_w[4] = {0.36268378337836198296515044927720,
+                                   0.31370664587788728733796220198660,
+                                   0.22238103445337447054435599442624,
+                                   0.10122853629037625915253135430996};
+
+int or_propagate_curved(const or_config* cf, double x_e, double y_e, double z_e, double u,
+                        double v, double w, or_prop* pr)
+{
+    double R = cf->earth_radius;
+    double rz = R + z_e;
+    double r_e = sqrt(x_e * x_e + y_e * y_e + rz * rz);
+    double h_e = or_curved_altitude(R, x_e, y_e, z_e);
+    /* r_e cos(zeta_e) with zeta_e measured from the downward local vertical */
+    double mu_num = w * rz - u * x_e - v * y_e;
+    memset(pr, 0, sizeof(*pr));
+    if (!(mu_num > 0.0)) return OR_DROP_UPWARD;
+    double psi_e;
+    or_lookup(cf, h_e, &psi_e, NULL);
+    double ne2 = 1.0 + psi_e, ne = sqrt(ne2);
+    /* r_e sin(zeta_e) = |(P_e - C) x D|, D = (u, v, -w) */
+    double Lx = -y_e * w - rz * v, Ly = rz * u + x_e * w, Lz = x_e * v - y_e * u;
+    double K = ne * sqrt(Lx * Lx + Ly * Ly + Lz * Lz);
+    double s2e = ne2 * (mu_num * mu_num);
+    double Mr_e = psi_e * r_e * r_e;
+    double r_obs = R + cf->h_obs;
+    double s2g = s2e + ((cf->h_obs - h_e) * (r_obs + r_e) + cf->psi[0] * r_obs * r_obs - Mr_e);
+    if (!(s2g > 0.0)) return OR_DROP_GRAZING;
+    int64_t c;
+    double f_c, dz_c;
+    or_cell(cf, h_e, &c, &f_c, &dz_c);
+    double theta = 0.0, opt = 0.0;
+    double h_t = h_e, psi_t = psi_e, s2t = s2e, s_t = sqrt(s2e);
+    for (int64_t i = c; i >= 0; --i) {
+        double h_b = or_node_h(cf, i);
+        double psi_b = cf->psi[i];
+        double r_b = R + h_b;
+        double s2b = i == 0 ? s2g : s2e + ((h_b - h_e) * (r_b + r_e) + psi_b * r_b * r_b - Mr_e);
+        double s_b = sqrt(s2b);
+        double dh = h_t - h_b;
+        if (dh > 0.0) {
+            double g = (psi_t - psi_b) / dh;
+            double mid = 0.5 * (s_t + s_b), half = 0.5 * (s_t - s_b);
+            double a_th = 0.0, a_op = 0.0;
+            for (int q = 0; q < 8; ++q) {
+                double xq = q < 4 ? -or_gl8_x[3 - q] : or_gl8_x[q - 4];
+                double wq = q < 4 ? or_gl8_w[3 - q] : or_gl8_w[q - 4];
+                double uq = mid + half * xq;
+                double hq = h_b + dh * ((uq * uq - s2b) / (s2t - s2b));
+                double psq = psi_b + g * (hq - h_b);
+                double rq = R + hq;
+                double s2q = s2e + ((hq - h_e) * (rq + r_e) + psq * rq * rq - Mr_e);
+                double ratio = uq / sqrt(s2q);
+                a_th += wq * (K / rq) * ratio;
+                a_op += wq * ((1.0 + psq) * rq) * ratio;
+            }
+            theta += dh / (s_t + s_b) * a_th;
+            opt += dh / (s_t + s_b) * a_op;
+        }
+        h_t = h_b;
+        psi_t = psi_b;
+        s2t = s2b;
+        s_t = s_b;
+    }
+    /* ground point: rotate the emission point's radial direction by theta
+       towards the ray's tangential direction, at radius r_obs */
+    double rho[3] = {x_e / r_e, y_e / r_e, rz / r_e};
+    double mu = mu_num / r_e;
+    double tp[3] = {u + mu * rho[0], v + mu * rho[1], -w + mu * rho[2]};
+    double sz = sqrt(tp[0] * tp[0] + tp[1] * tp[1] + tp[2] * tp[2]);
+    for (int a = 0; a < 3; ++a) tp[a] = sz > 0.0 ? tp[a] / sz : 0.0;
+    double ct = cos(theta), sn = sin(theta);
+    double rg[3], tg[3];
+    for (int a = 0; a < 3; ++a) {
+        rg[a] = ct * rho[a] + sn * tp[a];
+        tg[a] = -sn * rho[a] + ct * tp[a];
+    }
+    double n_obs = sqrt(1.0 + cf->psi[0]);
+    double sin_g = K / (n_obs * r_obs), cos_g = sqrt(s2g) / (n_obs * r_obs);
+    pr->x_g = r_obs * rg[0];
+    pr->y_g = r_obs * rg[1];
+    pr->u_o = -cos_g * rg[0] + sin_g * tg[0];
+    pr->v_o = -cos_g * rg[1] + sin_g * tg[1];
+    pr->w_o = sqrt(1.0 - pr->u_o * pr->u_o - pr->v_o * pr->v_o);
+    pr->T = opt / OR_C_M_PER_NS;
+    pr->n_e = ne;
+    pr->psi_e = psi_e;
+    pr->S = r_obs * theta;
+    return -1;
+}
+
+/* rows of 10: status, then the 9 fields of or_propagate_many */
+void or_propagate_curved_many(const or_config* cf, int64_t m, const double* in, double* out)
+{
+    for (int64_t q = 0; q < m; ++q) {
+        const double* pp = in + 6 * q;
+        or_prop pr;
+        int st = or_propagate_curved(cf, pp[0], pp[1], pp[2], pp[3], pp[4], pp[5], &pr);
+        double* o = out + 10 * q;
+        o[0] = st;
+        o[1] = pr.x_g; o[2] = pr.y_g; o[3] = pr.T; o[4] = pr.u_o; o[5] = pr.v_o;
+        o[6] = pr.w_o; o[7] = pr.n_e; o[8] = pr.psi_e; o[9] = pr.S;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* One bunch k of a step: sub-step emission point, direction on the Cherenkov */
 /* cone, wavelength, drop rules, propagation.                                 */
 /* ------------------------------------------------------------------------- */
@@ -471,6 +623,16 @@ void or_make_bunch(const or_config* cf, const or_segments* sg, int64_t i, const 
     bn->lambda = 1.0 / (il1 - u2 * (il1 - il2));
     bn->photons = st->photons;
     double h_top = or_h_top(cf);
+    if (cf->earth_radius > 0.0) {
+        /* curved: drops on the true altitude; every bunch traced exactly */
+        double z_e = bn->h_e;
+        bn->h_e = or_curved_altitude(cf->earth_radius, bn->x_e, bn->y_e, z_e);
+        if (bn->h_e < cf->h_obs) { bn->status = OR_DROP_BELOW_OBS; return; }
+        if (bn->h_e >= h_top) { bn->status = OR_DROP_ABOVE_TOP; return; }
+        bn->status = or_propagate_curved(cf, bn->x_e, bn->y_e, z_e, bn->u, bn->v, bn->w, &bn->pr);
+        if (bn->status < 0) bn->t = bn->t_e + bn->pr.T - sg->t_ref[i];
+        return;
+    }
     if (bn->h_e < cf->h_obs) { bn->status = OR_DROP_BELOW_OBS; return; }
     if (bn->h_e >= h_top) { bn->status = OR_DROP_ABOVE_TOP; return; }
     if (bn->w <= 0.0) { bn->status = OR_DROP_UPWARD; return; }
