@@ -13,7 +13,10 @@
  *
  * Conventions: units m, ns, MeV, nm.  x, y horizontal, h altitude.  Directions
  * are (u, v, w) = (dx/ds, dy/ds, -dh/ds): w > 0 is downward.  The atmosphere
- * is plane-parallel.
+ * is plane-parallel, or (params->earth_radius_m > 0) made of spherical shells
+ * around the Earth's centre (0, 0, -R): then h is the Cartesian height along
+ * the array origin's vertical and the altitude of a point is its distance from
+ * the centre minus R.
  *
  * Errors: every call returns CKV_OK (0) or a negative code; no exception
  * crosses the ABI.  ckv_last_error() gives a message for the calling thread.
@@ -37,7 +40,7 @@
 extern "C" {
 #endif
 
-#define CKV_VERSION 110
+#define CKV_VERSION 111
 
 enum {
     CKV_OK = 0,
@@ -196,6 +199,19 @@ typedef struct {
                               the index table, instead of by the moment series (the slow
                               path for rare bunches, sec. 4.3.1 and App. C) */
     int32_t reserved;      /* must be 0 */
+    double earth_radius_m; /* 0: plane-parallel atmosphere.  > 0: curved variant for large
+                              zenith angles: spherical shells of this radius (Earth: 6.371e6);
+                              step midpoints and emission points take their true altitude,
+                              and every bunch is traced exactly (Bouguer's invariant
+                              n r sin(zeta), cell by cell through the index table, FP64)
+                              down to the observation sphere h = h_obs, where the ground
+                              point's x, y and the arrival direction's x, y components enter
+                              the sphere test (the array is taken as planar).  Drops: below
+                              the observation level or above the table on the true altitude;
+                              upward = moving away from the centre; grazing = the ray turns
+                              above the observation sphere.  Needs uniform tables,
+                              tile_segments 0 or 32, no profile, grazing_exact 0; not for the
+                              soft response. */
 } ckv_params;
 
 /* Device-side report, written by ckv_run (the caller syncs the stream before

@@ -520,7 +520,7 @@ int or_propagate_curved(const or_config* cf, double x_e, double y_e, double z_e,
         double s2b = i == 0 ? s2g : s2e + ((h_b - h_e) * (r_b + r_e) + psi_b * r_b * r_b - Mr_e);
         double s_b = sqrt(s2b);
         double dh = h_t - h_b;
-        if (dh > 0.0) {
+        if (dh > 0.0 && s2t != s2b) {   /* (a cell of zero s^2 span adds ~dh/s: nothing) */
             double g = (psi_t - psi_b) / dh;
             double mid = 0.5 * (s_t + s_b), half = 0.5 * (s_t - s_b);
             double a_th = 0.0, a_op = 0.0;

@@ -50,7 +50,8 @@ class _Params(C.Structure):
                 ("precision", C.c_int32), ("tile_segments", C.c_int32), ("grid", C.c_int32),
                 ("waves_per_group", C.c_int32), ("event_begin", C.c_void_p),
                 ("event_end", C.c_void_p), ("depth_bin_gcm2", C.c_double),
-                ("grazing_exact", C.c_int32), ("reserved", C.c_int32)]
+                ("grazing_exact", C.c_int32), ("reserved", C.c_int32),
+                ("earth_radius_m", C.c_double)]
 
 
 class _Result(C.Structure):
@@ -291,12 +292,15 @@ class DeviceSegments:
 
 def make_params(*, precision=CKV_MIXED, bunch_size=5.0, lambda_min=300.0, lambda_max=600.0,
                 w_min=0.1, seed=0x14927, tile_segments=0, grid=0, waves_per_group=0,
-                event_begin=None, event_end=None, depth_bin=0.0, grazing_exact=False) -> _Params:
+                event_begin=None, event_end=None, depth_bin=0.0, grazing_exact=False,
+                earth_radius=0.0) -> _Params:
     """depth_bin > 0 [g/cm^2]: also the longitudinal photon-production profile;
-    grazing_exact: trace bunches with 0 < w <= w_min exactly instead of dropping them."""
+    grazing_exact: trace bunches with 0 < w <= w_min exactly instead of dropping them;
+    earth_radius > 0 [m]: curved atmosphere (spherical shells), every bunch traced exactly."""
     return _Params(bunch_size, lambda_min, lambda_max, w_min, int(seed) & (2**64 - 1),
                    int(precision), int(tile_segments), int(grid), int(waves_per_group),
-                   event_begin, event_end, float(depth_bin), int(bool(grazing_exact)), 0)
+                   event_begin, event_end, float(depth_bin), int(bool(grazing_exact)), 0,
+                   float(earth_radius))
 
 
 def workspace_size(n_segments, n_showers, n_tel, capacity, params: _Params) -> int:

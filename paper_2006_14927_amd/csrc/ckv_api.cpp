@@ -88,6 +88,16 @@ int check_params(const ckv_params* p)
     if ((p->grazing_exact != 0 && p->grazing_exact != 1) || p->reserved != 0) {
         set_error("grazing_exact must be 0 or 1, reserved 0"); return CKV_ERR_ARG;
     }
+    if (!(p->earth_radius_m >= 0.0) || !std::isfinite(p->earth_radius_m)) {
+        set_error("earth_radius_m must be >= 0"); return CKV_ERR_ARG;
+    }
+    if (p->earth_radius_m > 0.0 &&
+        ((p->tile_segments != 0 && p->tile_segments != 32) || p->depth_bin_gcm2 > 0.0 ||
+         p->grazing_exact)) {
+        set_error("the curved atmosphere runs with tile_segments 0 or 32, without profile or "
+                  "grazing_exact (every bunch is traced exactly)");
+        return CKV_ERR_ARG;
+    }
     return CKV_OK;
 }
 
@@ -409,8 +419,9 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
     }
     if (!atmo->h_nodes.empty() &&
         ((params->tile_segments != 0 && params->tile_segments != 32) || params->depth_bin_gcm2 > 0.0 ||
-         params->grazing_exact)) {
-        set_error("node tables run with tile_segments 0 or 32, without profile or exact grazing path");
+         params->grazing_exact || params->earth_radius_m > 0.0)) {
+        set_error("node tables run with tile_segments 0 or 32, without profile, exact grazing "
+                  "path or curved atmosphere");
         return CKV_ERR_ARG;
     }
     int32_t prof_bins = 0;
@@ -462,6 +473,9 @@ static int soft_common(const ckv_segments* segs, const ckv_showers* showers,
     }
     if (!atmo->h_nodes.empty()) {
         set_error("the soft response needs a uniform-grid atmosphere"); return CKV_ERR_ARG;
+    }
+    if (params->earth_radius_m > 0.0) {
+        set_error("the soft response is defined for the plane-parallel atmosphere"); return CKV_ERR_ARG;
     }
     if ((rc = current_device(atmo->device)) || (rc = current_device(arr->device))) return rc;
     size_t need = workspace_layout(segs->n, showers->n_showers, arr->n_tel, 0, params, plan, workspace);

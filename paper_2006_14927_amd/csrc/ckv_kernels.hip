@@ -66,6 +66,8 @@ struct Args {
     // parameters
     double bunch_size, k_ft, inv_l1, dl, w_min;
     int32_t grazing_exact;      // 1: bunches with 0 < w <= w_min take propagate_exact
+    double earth_r;             // > 0: spherical shells of this radius (curved variant)
+    double r_obs;               // earth_r + h_obs
     uint32_t key0, key1;
     int32_t tile_segs;
     // workspace and output
@@ -202,6 +204,20 @@ __device__ __forceinline__ double psi_fp64(const Args& a, double h)
     return lo + f * (hi - lo);
 }
 
+// Curved variant: x, y horizontal at the array origin, z along the origin's
+// vertical from sea level, the Earth's centre at (0, 0, -R).  The altitude of a
+// point is its distance from the centre minus R, written without the
+// cancellation of sqrt(...) - R; no contraction, so drop decisions and table
+// cells match the FP64 definition's operations.
+__device__ __forceinline__ double curved_altitude(double R, double x, double y, double z)
+{
+#pragma clang fp contract(off)
+    const double q = x * x + y * y;
+    const double rz = R + z;
+    const double r = sqrt(q + rz * rz);
+    return (q + z * (2.0 * R + z)) / (r + R);
+}
+
 __device__ __forceinline__ void step_setup(const Args& a, int64_t i, Setup& st)
 {
 #pragma clang fp contract(off)
@@ -217,7 +233,13 @@ __device__ __forceinline__ void step_setup(const Args& a, int64_t i, Setup& st)
     const double r = m / E;
     const double r2 = r * r;                           // 1 - beta^2
     if (!(r2 < 1.0)) { st.status = CKV_DROP_MASS; return; }
-    const double h_mid = h0 - (0.5 * L) * w;           // index at the step midpoint
+    double h_mid;                                      // index at the step midpoint
+    if (a.earth_r > 0.0) {
+        const double hl = 0.5 * L;
+        h_mid = curved_altitude(a.earth_r, x0 + hl * u, y0 + hl * v, h0 - hl * w);
+    } else {
+        h_mid = h0 - (0.5 * L) * w;
+    }
     const double psi = psi_fp64(a, h_mid);
     const double n2 = 1.0 + psi;
     const double num = psi - n2 * r2;                  // beta^2 n^2 - 1
@@ -363,6 +385,116 @@ __device__ __forceinline__ void propagate_exact(const Args& a, double xe, double
     T = cT / kSpeedOfLight;
 }
 
+// FP64 reciprocal square root: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsqrt64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+// Curved atmosphere: exact propagation through spherical shells (radius R =
+// a.earth_r, centre (0, 0, -R)).  n depends on the altitude h = r - R only, so
+// the ray stays in the plane of the centre, its emission point and direction,
+// and keeps Bouguer's invariant K = n r sin(zeta) (zeta from the local
+// vertical).  With s = sqrt(n^2 r^2 - K^2), the polar angle about the centre
+// and the optical path down to the observation sphere r_obs are
+//   theta = int K / (r s) dr,    c T = int n^2 r / s dr,
+// integrated cell by cell (psi linear in h inside a cell).  s^2 is written
+// relative to the emission point, s^2 = s_e^2 + (h - h_e)(r + r_e) + psi r^2 -
+// psi_e r_e^2 with s_e = n_e r_e cos(zeta_e), which stays accurate for grazing
+// rays.  Over a cell s^2 is nearly linear in h, so the substitution
+// h = h_b + dh (u^2 - s_b^2) / (s_t^2 - s_b^2), u from s_b to s_t, turns
+//   int F / s dh  into  dh / (s_t + s_b) * sum of F u / s at the 2-point
+// Gauss-Legendre nodes of [s_b, s_t] (u / s is 1 up to the cell's curvature of
+// s^2, ~1e-9, so two nodes reach FP64 rounding).  The ground point is the
+// emission point's radial direction turned by theta towards the ray's tangential
+// direction, at r_obs; the arrival direction has sin(zeta_g) = K / (n_obs r_obs).
+// The upward and turning decisions use the FP64 definition's operations.
+// Returns -1 (reached the ground), CKV_DROP_UPWARD or CKV_DROP_GRAZING.
+__device__ __forceinline__ int propagate_curved(const Args& a, double xe, double ye, double ze,
+                                                double he, double u, double v, double w,
+                                                double& xg, double& yg, double& T, double& uo,
+                                                double& vo)
+{
+    const double R = a.earth_r;
+    const double* nd = a.node64;
+    double rz, r_e, mu_num, psi_e, ne2, K, s2e, Mre, s2g;
+    {
+#pragma clang fp contract(off)
+        rz = R + ze;
+        r_e = sqrt(xe * xe + ye * ye + rz * rz);
+        mu_num = w * rz - u * xe - v * ye;          // r_e cos(zeta_e), zeta_e from the downward vertical
+        if (!(mu_num > 0.0)) return CKV_DROP_UPWARD;
+        psi_e = psi_fp64(a, he);
+        ne2 = 1.0 + psi_e;
+        const double Lx = -ye * w - rz * v, Ly = rz * u + xe * w, Lz = xe * v - ye * u;
+        K = sqrt(ne2) * sqrt(Lx * Lx + Ly * Ly + Lz * Lz);   // n_e |(P_e - C) x D|
+        s2e = ne2 * (mu_num * mu_num);
+        Mre = psi_e * r_e * r_e;
+        s2g = s2e + ((a.h_obs - he) * (a.r_obs + r_e) + nd[0] * a.r_obs * a.r_obs - Mre);
+        if (!(s2g > 0.0)) return CKV_DROP_GRAZING;
+    }
+    const double x = (he - a.h_obs) * a.inv_step;
+    const int c = min((int)x, a.n_nodes - 2);
+    constexpr double kg = 0.57735026918962576451;   // 1/sqrt(3)
+    double theta = 0.0, opt = 0.0;
+    double h_t = he, s2t = s2e, s_t = s2e * rsqrt64(s2e);
+    for (int i = c; i >= 0; --i) {
+        const double h_b = a.h_obs + (double)i * a.step;
+        const double psi_b = nd[kNode64 * i];
+        const double r_b = R + h_b;
+        const double s2b = i == 0 ? s2g : s2e + ((h_b - he) * (r_b + r_e) + psi_b * r_b * r_b - Mre);
+        const double s_b = s2b * rsqrt64(s2b);
+        const double dh = h_t - h_b;
+        if (dh > 0.0 && s2t != s2b) {    // (a cell of zero s^2 span adds ~dh/s: nothing)
+            const double g = (nd[kNode64 * (i + 1)] - psi_b) * a.inv_step;   // dpsi/dh in the cell
+            const double inv_ds2 = rcp64(s2t - s2b);
+            const double inv_rb = rcp64(r_b);
+            const double mid = 0.5 * (s_t + s_b), half = (0.5 * kg) * (s_t - s_b);
+            double a_th = 0.0, a_op = 0.0;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const double uq = q ? mid + half : mid - half;
+                const double xq = dh * ((uq * uq - s2b) * inv_ds2);     // h_q - h_b
+                const double psq = fma(g, xq, psi_b);
+                const double rq = r_b + xq;
+                const double s2q = s2e + ((h_b + xq - he) * (rq + r_e) + psq * rq * rq - Mre);
+                const double ratio = uq * rsqrt64(s2q);
+                const double e = xq * inv_rb;                            // 1/r_q = (1 - e + e^2) / r_b
+                a_th += ratio * (inv_rb * fma(e, e - 1.0, 1.0));
+                a_op += ((1.0 + psq) * rq) * ratio;
+            }
+            const double scale = dh * rcp64(s_t + s_b);
+            theta = fma(scale, K * a_th, theta);
+            opt = fma(scale, a_op, opt);
+        }
+        h_t = h_b;
+        s2t = s2b;
+        s_t = s_b;
+    }
+    // ground point and arrival direction in the ray plane
+    const double inv_re = rcp64(r_e);
+    const double rho0 = xe * inv_re, rho1 = ye * inv_re, rho2 = rz * inv_re;
+    const double mu = mu_num * inv_re;
+    double t0 = fma(mu, rho0, u), t1 = fma(mu, rho1, v), t2 = fma(mu, rho2, -w);
+    const double sz2 = t0 * t0 + t1 * t1 + t2 * t2;
+    const double isz = sz2 > 0.0 ? rsqrt64(sz2) : 0.0;
+    t0 *= isz; t1 *= isz; t2 *= isz;
+    double sth, cth;
+    sincos(theta, &sth, &cth);
+    const double rg0 = cth * rho0 + sth * t0, rg1 = cth * rho1 + sth * t1;
+    const double tg0 = cth * t0 - sth * rho0, tg1 = cth * t1 - sth * rho1;
+    const double inv_nr = rcp64(a.n_obs * a.r_obs);
+    const double sin_g = K * inv_nr, cos_g = s2g * rsqrt64(s2g) * inv_nr;
+    xg = a.r_obs * rg0;
+    yg = a.r_obs * rg1;
+    uo = sin_g * tg0 - cos_g * rg0;
+    vo = sin_g * tg1 - cos_g * rg1;
+    T = opt * (1.0 / kSpeedOfLight);
+    return -1;
+}
+
 // Depth bin of an emission altitude h_obs <= h < h_top, given its table cell c
 // and fraction f (x = (h - h_obs) / step, c = floor(x), f = x - c): the depth
 // table read like the index and binned by floor(X * (1/width)), in FP64
@@ -440,18 +572,29 @@ __host__ __device__ inline size_t wave_bytes(int prec, int tile_segs, int n_tel,
 constexpr int kFeatProfile = 1;
 constexpr int kFeatExact = 2;
 constexpr int kFeatSearch = 4;   // node tables: binary search per bunch (alone, 32-step tiles)
+constexpr int kFeatCurved = 8;   // spherical shells, every bunch traced exactly (alone, 32-step tiles)
 
 __host__ __device__ inline size_t search_bytes(int n_nodes)
 {
     return ((size_t)(2 * n_nodes - 1) * sizeof(double) + 15) & ~(size_t)15;
 }
 
+// Workgroup size the variant is compiled for: the FP64 kernel and the exact-path
+// variants (grazing, curved) carry FP64 tracing state and get the registers of
+// 8 waves; the plain mixed kernel runs 16.
+constexpr int emit_threads(int prec, int feat)
+{
+    return (prec == 0 || (feat & (kFeatExact | kFeatCurved)) != 0) ? 512 : 1024;
+}
+
 template <int PREC, int TS, int FEAT>
-__global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
+__global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
 {
     constexpr bool PROF = (FEAT & kFeatProfile) != 0;
     constexpr bool EXACT = (FEAT & kFeatExact) != 0;
     constexpr bool SEARCH = (FEAT & kFeatSearch) != 0;
+    constexpr bool CURVED = (FEAT & kFeatCurved) != 0;
+    constexpr bool SLOWPATH = EXACT || CURVED;    // lanes that leave the moment series
     using T = typename std::conditional<PREC == 0, double, float>::type;
     using Entry = StepEntry<PREC>;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -636,14 +779,24 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                 const double u0 = fma((double)r0, 2.3283064365386963e-10, 1.1641532182693481e-10);
                 const double s_along = ((double)k + u0) * e.ds;
                 const double tu = e.u, tv = e.v, tw = e.w;
-                const double xe = fma(s_along, tu, e.x0);
-                const double ye = fma(s_along, tv, e.y0);
+                double xe, ye, ze;
                 {
                     // rounded as the FP64 definition rounds it: the drop tests and the
-                    // profile bin take their decisions on this value
+                    // profile bin take their decisions on this value (and, curved, on
+                    // the altitude of (x, y, z))
 #pragma clang fp contract(off)
                     he = e.h0 - s_along * tw;
+                    if (CURVED) {
+                        xe = e.x0 + s_along * tu;
+                        ye = e.y0 + s_along * tv;
+                    }
                 }
+                if (!CURVED) {
+                    xe = fma(s_along, tu, e.x0);
+                    ye = fma(s_along, tv, e.y0);
+                }
+                ze = he;
+                if (CURVED) he = curved_altitude(a.earth_r, xe, ye, ze);
                 const double te = fma(s_along, e.inv_bc, e.t0);
                 // table cell and fraction of the emission altitude (index and depth)
                 if (SEARCH) {
@@ -690,13 +843,15 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                 // drop rules
                 if (he < a.h_obs) drop_why = CKV_DROP_BELOW_OBS;
                 else if (he >= a.h_top) drop_why = CKV_DROP_ABOVE_TOP;
-                else if (pw <= 0.0) drop_why = CKV_DROP_UPWARD;
-                bool slow = false;     // grazing bunch traced exactly, cell by cell
-                if (drop_why < 0 && pw <= a.w_min) {
+                else if (!CURVED && pw <= 0.0) drop_why = CKV_DROP_UPWARD;
+                // slow: traced exactly, cell by cell (grazing bunches; every bunch when curved,
+                // whose upward and turning drops the tracer decides)
+                bool slow = CURVED && drop_why < 0;
+                if (!CURVED && drop_why < 0 && pw <= a.w_min) {
                     if (EXACT) slow = true;
                     else drop_why = CKV_DROP_GRAZING;
                 }
-                if (EXACT && slow) {
+                if (SLOWPATH && slow) {
                     alive = true;
                     if (PREC == 1) {
                         // a grazing ray magnifies a direction error by 1/w^2 on the
@@ -713,11 +868,21 @@ __global__ void __launch_bounds__(PREC == 0 ? 512 : 1024) emit_kernel(Args a)
                         pv = ct * tv + st_ * (cp * b1y + sp * b2y);
                         pw = ct * tw - st_ * (cp * b1z + sp * b2z);
                     }
-                    double T_x, ne_x;
-                    propagate_exact(a, xe, ye, he, pu, pv, pw, xg, yg, T_x, ne_x);
+                    double T_x = 0.0;
+                    if (CURVED) {
+                        const int stc = propagate_curved(a, xe, ye, ze, he, pu, pv, pw, xg, yg, T_x,
+                                                         uod, vod);
+                        if (stc >= 0) {
+                            drop_why = stc;
+                            alive = false;
+                        }
+                    } else {
+                        double ne_x;
+                        propagate_exact(a, xe, ye, he, pu, pv, pw, xg, yg, T_x, ne_x);
+                        uod = pu * ne_x / a.n_obs;
+                        vod = pv * ne_x / a.n_obs;
+                    }
                     tarr = (te - t_ref) + T_x;
-                    uod = pu * ne_x / a.n_obs;
-                    vod = pv * ne_x / a.n_obs;
                     uo = (float)uod;
                     vo = (float)vod;
                     t_f = (float)tarr;
@@ -1662,6 +1827,8 @@ Args make_args(const RunPlan& p)
     a.dl = 1.0 / p.params.lambda_min_nm - 1.0 / p.params.lambda_max_nm;
     a.w_min = p.params.w_min;
     a.grazing_exact = p.params.grazing_exact;
+    a.earth_r = p.params.earth_radius_m;
+    a.r_obs = a.earth_r + a.h_obs;
     a.key0 = (uint32_t)p.params.seed;
     a.key1 = (uint32_t)(p.params.seed >> 32);
     a.tile_segs = p.tile_segs;
@@ -1740,6 +1907,12 @@ int launch_emit_feat(const Args& a, int grid, int waves, size_t lds, hipStream_t
         set_error("node tables need tile_segments 32");
         return CKV_ERR_ARG;
     }
+    if (a.earth_r > 0.0) {
+        // the curved atmosphere runs alone (checked by the caller) and with 32-step tiles
+        if (TS == 32) return launch_emit<PREC, 32, kFeatCurved>(a, grid, waves, lds, st);
+        set_error("the curved atmosphere needs tile_segments 32");
+        return CKV_ERR_ARG;
+    }
     const int feat = (a.prof_bins > 0 ? kFeatProfile : 0) | (a.grazing_exact ? kFeatExact : 0);
     switch (feat) {
         case 0: return launch_emit<PREC, TS, 0>(a, grid, waves, lds, st);
@@ -1775,8 +1948,11 @@ int launch_run(RunPlan& p)
     if (int rc = emit_config(p.params.precision, a.n_tel, p.prof_bins, p.atmo, p.tile_segs, &waves,
                              &lds))
         return rc;
-    if (p.emit_waves < waves) {
-        waves = p.emit_waves;
+    int cap = p.emit_waves;
+    if (p.params.precision == 1 && (p.params.grazing_exact || p.params.earth_radius_m > 0.0))
+        cap = std::min(cap, emit_threads(1, kFeatExact) / kWave);
+    if (cap < waves) {
+        waves = cap;
         lds = ((table_bytes(p.params.precision, a.n_nodes, p.prof_bins > 0) + 15) & ~(size_t)15) +
               (a.hnodes ? search_bytes(a.n_nodes) : 0) +
               (size_t)waves * wave_bytes(p.params.precision, p.tile_segs, a.n_tel, p.prof_bins);

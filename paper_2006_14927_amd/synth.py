@@ -407,6 +407,16 @@ def single_tev(n_seg: int = 2_000_000) -> Workload:
                     telescopes_disk(), segs)
 
 
+def inclined(zenith_deg: float, n_seg: int = 2_000_000) -> Workload:
+    """The TeV gamma-like shower of single_tev at a large zenith angle (core at
+    the array centre, Xmax 400 g/cm^2 along the axis), for the curved
+    atmosphere: at 70 deg its light is emitted 10-60 km from the array."""
+    atmo = layered_atmosphere()
+    segs = shower_segments(0, n_seg, atmo, zenith_deg=zenith_deg, azimuth_deg=0.0, xmax=400.0)
+    return Workload(f"inclined_{int(zenith_deg)}deg_{n_seg:.0e}".replace("+0", ""), atmo,
+                    telescopes_disk(), segs)
+
+
 def batched_showers(n_showers: int = 256, seg_scale: float = 1.0, seed: int = 2006,
                     workers: Optional[int] = None) -> Workload:
     """Many showers of uneven size: E log-uniform 30 GeV..30 TeV,

@@ -36,12 +36,12 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_version(L):
-    assert L.ckv_version() == 110
+    assert L.ckv_version() == 111
 
 
 def test_struct_sizes_match_header_layout():
     assert C.sizeof(ckv._Segments) == 11 * 8
-    assert C.sizeof(ckv._Params) == 4 * 8 + 8 + 4 * 4 + 2 * 8 + 8 + 2 * 4
+    assert C.sizeof(ckv._Params) == 4 * 8 + 8 + 4 * 4 + 2 * 8 + 8 + 2 * 4 + 8
     assert C.sizeof(ckv._Result) == 5 * 8 + 8 * 8 + 2 * 4
     assert C.sizeof(ckv._Output) == 7 * 8
 
@@ -114,7 +114,11 @@ def test_run_argument_validation(L):
     bad_reserved.reserved = 1
     for bad in (ckv.make_params(bunch_size=0.0), ckv.make_params(lambda_min=600.0),
                 ckv.make_params(precision=7), ckv.make_params(w_min=1.5),
-                ckv.make_params(tile_segments=65), ckv.make_params(depth_bin=-1.0), bad_reserved):
+                ckv.make_params(tile_segments=65), ckv.make_params(depth_bin=-1.0), bad_reserved,
+                ckv.make_params(earth_radius=-1.0), ckv.make_params(earth_radius=float("inf")),
+                ckv.make_params(earth_radius=6.371e6, tile_segments=16),
+                ckv.make_params(earth_radius=6.371e6, depth_bin=10.0),
+                ckv.make_params(earth_radius=6.371e6, grazing_exact=True)):
         empty = ckv._Segments(*([None] * 10), 0)
         assert L.ckv_run(C.byref(empty), C.byref(sh), C.byref(bad), None, None, None, 0,
                          C.byref(out), None) == -1
