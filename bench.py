@@ -167,6 +167,38 @@ def time_path(hip, ckv, dsegs, atmo, tels, params, capacity, steps, warmup, stre
     return total_ms / steps, sum(kern_ms) / len(kern_ms), out.result()
 
 
+EARTH_RADIUS_M = 6.371e6
+
+
+def curved_timing(hip, stream, reps: int = 3, zenith: float = 70.0, n_seg: int = 2_000_000):
+    """The TeV shower at a large zenith angle, three ways, mixed precision:
+    plane-parallel with the moment series (grazing bunches dropped), the same with
+    the exact grazing path, and the curved atmosphere (spherical shells of the
+    Earth's radius, every bunch traced exactly in FP64)."""
+    from paper_2006_14927_amd import ckv, synth
+    wl = synth.inclined(zenith, n_seg)
+    atmo = ckv.Atmosphere(wl.atmo.alt, wl.atmo.eta, wl.atmo.obs_level, wl.fine_step)
+    tels = ckv.TelescopeArray(wl.tels.x, wl.tels.y, wl.tels.r)
+    d = ckv.DeviceSegments(wl.segs)
+    cap = max(1 << 16, wl.segs.n)
+    out = {"workload": wl.name, "zenith_deg": zenith, "earth_radius_m": EARTH_RADIUS_M}
+    for name, kw in (("flat_series", {}), ("flat_exact_grazing", dict(grazing_exact=True)),
+                     ("curved_exact", dict(earth_radius=EARTH_RADIUS_M))):
+        p = ckv.make_params(precision=ckv.CKV_MIXED, bunch_size=wl.bunch_size,
+                            lambda_min=wl.lambda_min, lambda_max=wl.lambda_max, seed=wl.seed,
+                            tile_segments=32, **kw)
+        ms, kms, res = time_path(hip, ckv, d, atmo, tels, p, cap, reps, 1, stream)
+        if res["error"] or res["overflow"]:
+            raise RuntimeError(f"{name} run reported a problem: {res}")
+        out[name] = {"ms_per_step": ms, "bunch_kernel_ms": kms, "bunches": res["n_bunches"],
+                     "records": res["n_hits"], "bunches_per_s": res["n_bunches"] / (ms * 1e-3),
+                     "drops_grazing": res["drops"]["grazing"], "drops_upward": res["drops"]["upward"]}
+        print(f"# {wl.name} {name}: {ms:.3f} ms/step, {res['n_bunches']} bunches, "
+              f"{res['n_hits']} records", file=sys.stderr, flush=True)
+    out["curved_over_flat"] = out["curved_exact"]["ms_per_step"] / out["flat_series"]["ms_per_step"]
+    return out
+
+
 def diff_timing(hip, reps: int, n_showers: int = 64, n_seg: int = 500_000):
     """Forward + backward of the soft telescope response on the differentiation
     workload (64 showers x 5e5 steps); returns ms per shower and kernel times."""
@@ -368,6 +400,8 @@ def main(argv=None):
                     help="skip the 256-shower batched launch (~3e8 steps)")
     ap.add_argument("--no-streamed", action="store_true",
                     help="skip the 5e7-step hadron-like showers streamed in 256 MB chunks")
+    ap.add_argument("--no-curved", action="store_true",
+                    help="skip the curved-atmosphere timing (70 deg shower)")
     ap.add_argument("--order-study", action="store_true",
                     help="also time the shower with its steps sorted by altitude and shuffled")
     ap.add_argument("--no-tune-cache", action="store_true",
@@ -512,6 +546,9 @@ def main(argv=None):
         "fwd_bwd_ms_per_shower": None,
         "cpu_baseline": None,
     }
+    if not args.no_curved:
+        line["curved"] = curved_timing(hip, stream)
+        torch.cuda.empty_cache()
     if not args.no_diff:
         del dsegs
         torch.cuda.empty_cache()

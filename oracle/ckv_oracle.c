@@ -471,8 +471,9 @@ void or_propagate_exact_many(const or_config* cf, int64_t m, const double* in, d
 /* linear in h, so the substitution h = h_b + dh (u^2 - s_b^2)/(s_t^2 - s_b^2) */
 /* (u from s_b to s_t) removes the 1/s behaviour:                             */
 /*   int F / s dh = 2 dh / (s_t^2 - s_b^2) int F(h(u)) u / s(h(u)) du,        */
-/* evaluated with 8-point Gauss-Legendre in u.  The ray reaches the ground iff */
-/* s^2 > 0 there; a ray with cos zeta_e <= 0 moves outward for good.          */
+/* evaluated with 8-point Gauss-Legendre in u.  While n r grows with r (air   */
+/* at the Earth's radius: no ducting) the ray reaches the ground iff s^2 > 0  */
+/* there, and a ray with cos zeta_e <= 0 moves outward for good.              */
 /* The array is treated as planar: the ground point's x, y and the arrival    */
 /* direction's x, y components enter the same sphere test as the flat path.   */
 /* Returns -1, OR_DROP_UPWARD or OR_DROP_GRAZING (the ray turns above ground). */

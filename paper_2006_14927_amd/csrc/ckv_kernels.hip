@@ -410,6 +410,8 @@ __device__ __forceinline__ double rsqrt64(double x)
 // s^2, ~1e-9, so two nodes reach FP64 rounding).  The ground point is the
 // emission point's radial direction turned by theta towards the ray's tangential
 // direction, at r_obs; the arrival direction has sin(zeta_g) = K / (n_obs r_obs).
+// While n r grows with r (air at the Earth's radius: no ducting) the ray reaches
+// the ground iff s^2 > 0 there, and one with cos(zeta_e) <= 0 never comes down.
 // The upward and turning decisions use the FP64 definition's operations.
 // Returns -1 (reached the ground), CKV_DROP_UPWARD or CKV_DROP_GRAZING.
 __device__ __forceinline__ int propagate_curved(const Args& a, double xe, double ye, double ze,
