@@ -313,7 +313,8 @@ static int upload_grid(ckv_grid* g)
 {
     int rc;
     if ((rc = upload(g->cell_off.data(), g->cell_off.size(), &g->d_cell_off)) ||
-        (rc = upload(g->cell_list.data(), g->cell_list.size(), &g->d_cell_list)))
+        (rc = upload(g->cell_list.data(), g->cell_list.size(), &g->d_cell_list)) ||
+        (rc = upload(g->cell_ent.data(), g->cell_ent.size(), &g->d_cell_ent)))
         return rc;
     return CKV_OK;
 }
@@ -322,8 +323,10 @@ static void free_grid(ckv_grid* g)
 {
     if (g->d_cell_off) (void)hipFree(g->d_cell_off);
     if (g->d_cell_list) (void)hipFree(g->d_cell_list);
+    if (g->d_cell_ent) (void)hipFree(g->d_cell_ent);
     g->d_cell_off = nullptr;
     g->d_cell_list = nullptr;
+    g->d_cell_ent = nullptr;
 }
 
 static int array_create(const double* x_m, const double* y_m, const double* r_m, int32_t n_tel,

@@ -91,8 +91,12 @@ struct ckv_grid {
     int32_t level_cells = 0;         // nx*ny
     std::vector<int32_t> cell_off;   // kGridLevels*nx*ny + 1, level-major
     std::vector<uint16_t> cell_list;
+    // per cell, packed: {offset into cell_list, count | first listed sphere << 16},
+    // so a bunch learns its first candidate with the one load that finds its cell
+    std::vector<uint32_t> cell_ent;  // 2 x kGridLevels*nx*ny
     int32_t* d_cell_off = nullptr;
     uint16_t* d_cell_list = nullptr;
+    uint32_t* d_cell_ent = nullptr;
 };
 
 struct ckv_array {
@@ -158,8 +162,9 @@ size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, in
 int launch_run(RunPlan& plan);
 int launch_count(const ckv_segments* segs, const ckv_params* p, const ckv_atmo* atmo, double k_ft,
                  int64_t* n_b, hipStream_t stream);
-int emit_config(int precision, int n_tel, int prof_bins, const ckv_atmo* atmo, int tile_segs, int* waves,
-                size_t* lds_bytes);
+// waves per bunch-kernel workgroup (at most max_waves) and its LDS bytes
+int emit_config(int precision, int n_tel, int prof_bins, const ckv_atmo* atmo, int tile_segs,
+                int max_waves, int* waves, size_t* lds_bytes);
 
 struct SoftPlan {
     const int64_t* n_b_frozen;

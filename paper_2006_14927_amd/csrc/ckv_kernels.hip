@@ -63,6 +63,7 @@ struct Args {
     int32_t nx, ny, level_cells;
     const int32_t* cell_off;
     const uint16_t* cell_list;
+    const uint2* cell_ent;      // per cell: {offset, count | first sphere << 16}
     // parameters
     double bunch_size, k_ft, inv_l1, dl, w_min;
     int32_t grazing_exact;      // 1: bunches with 0 < w <= w_min take propagate_exact
@@ -581,6 +582,12 @@ __host__ __device__ inline size_t search_bytes(int n_nodes)
     return ((size_t)(2 * n_nodes - 1) * sizeof(double) + 15) & ~(size_t)15;
 }
 
+// sphere table in LDS: {X, Y, R^2} per sphere (at most CKV_MAX_TEL: 24 KB)
+__host__ __device__ inline size_t tel_bytes(int n_tel)
+{
+    return ((size_t)n_tel * 3 * sizeof(double) + 15) & ~(size_t)15;
+}
+
 // Workgroup size the variant is compiled for: the FP64 kernel and the exact-path
 // variants (grazing, curved) carry FP64 tracing state and get the registers of
 // 8 waves; the plain mixed kernel runs 16.
@@ -618,7 +625,14 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
     const size_t srch_bytes = SEARCH ? search_bytes(a.n_nodes) : 0;
     if (SEARCH)
         for (int q = threadIdx.x; q < 2 * a.n_nodes - 1; q += blockDim.x) hn_lds[q] = a.hnodes[q];
-    unsigned char* wbase = lds + ((tab_bytes + 15) & ~(size_t)15) + srch_bytes +
+    // sphere table {X, Y, R^2} after them
+    double* tel_sh = reinterpret_cast<double*>(lds + ((tab_bytes + 15) & ~(size_t)15) + srch_bytes);
+    for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x) {
+        tel_sh[3 * q] = a.tel[4 * q];
+        tel_sh[3 * q + 1] = a.tel[4 * q + 1];
+        tel_sh[3 * q + 2] = a.tel[4 * q + 3];
+    }
+    unsigned char* wbase = lds + ((tab_bytes + 15) & ~(size_t)15) + srch_bytes + tel_bytes(a.n_tel) +
                            (size_t)wave * wave_bytes(PREC, TS, a.n_tel, PROF ? a.prof_bins : 0);
     Entry* stash = reinterpret_cast<Entry*>(wbase);
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + TS * sizeof(Entry));
@@ -1037,6 +1051,7 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
             }
             // ---- candidate spheres (ascending telescope index)
             int cur = 0, cend = 0;
+            int first = -1;          // the cell's first sphere, known without a list read
             bool brute = false;
             if (alive) {
                 const double wo2 = 1.0 - uod * uod - vod * vod;
@@ -1044,8 +1059,10 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     const double fx = (xg - a.gx0) * a.inv_cell, fy = (yg - a.gy0) * a.inv_cell;
                     if (fx >= 0.0 && fy >= 0.0 && fx < (double)a.nx && fy < (double)a.ny) {
                         const int cidx = grid_level(wo2) * a.level_cells + (int)fx * a.ny + (int)fy;
-                        cur = a.cell_off[cidx];
-                        cend = a.cell_off[cidx + 1];
+                        const uint2 ce = a.cell_ent[cidx];
+                        cur = (int)ce.x;
+                        cend = cur + (int)(ce.y & 0xFFFFu);
+                        first = (int)(ce.y >> 16);
                     }
                 } else {
                     brute = true;
@@ -1056,12 +1073,14 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
             auto advance = [&]() {
                 my_next = INT_MAX;
                 while (cur < cend) {
-                    const int kt = brute ? cur : (int)a.cell_list[cur];
+                    const int kt = brute ? cur : (first >= 0 ? first : (int)a.cell_list[cur]);
+                    first = -1;
                     ++cur;
-                    const double* tp = a.tel + 4 * kt;
-                    const double dx = xg - tp[0], dy = yg - tp[1];
+                    const double* tq = tel_sh + 3 * kt;     // sphere table in LDS
+                    const double tX = tq[0], tY = tq[1], tR2 = tq[2];
+                    const double dx = xg - tX, dy = yg - tY;
                     const double b = dx * uod + dy * vod;
-                    const double disc = b * b - (dx * dx + dy * dy - tp[3]);
+                    const double disc = b * b - (dx * dx + dy * dy - tR2);
                     if (disc >= 0.0) { my_next = kt; break; }
                 }
             };
@@ -1822,6 +1841,7 @@ Args make_args(const RunPlan& p)
         a.nx = ar->hit.nx; a.ny = ar->hit.ny; a.level_cells = ar->hit.level_cells;
         a.cell_off = ar->hit.d_cell_off;
         a.cell_list = ar->hit.d_cell_list;
+        a.cell_ent = reinterpret_cast<const uint2*>(ar->hit.d_cell_ent);
     }
     a.bunch_size = p.params.bunch_size;
     a.k_ft = p.k_ft;
@@ -1866,15 +1886,16 @@ int check_launch(const char* what)
 }  // namespace
 
 int emit_config(int precision, int n_tel, int prof_bins, const ckv_atmo* atmo, int tile_segs,
-                int* waves, size_t* lds_bytes)
+                int max_waves, int* waves, size_t* lds_bytes)
 {
     const size_t tab = ((table_bytes(precision, (int)atmo->n_nodes, prof_bins > 0) + 15) & ~(size_t)15) +
                        (atmo->h_nodes.empty() ? 0 : search_bytes((int)atmo->n_nodes));
     const size_t cap = 160 * 1024;
     const size_t per = wave_bytes(precision, tile_segs, n_tel, prof_bins);
-    const int max_waves = precision == 0 ? kMaxEmitWaves / 2 : kMaxEmitWaves;
-    for (int wv = max_waves; wv >= 1; wv /= 2) {
-        const size_t tot = tab + (size_t)wv * per;
+    if (precision == 0) max_waves = std::min(max_waves, kMaxEmitWaves / 2);
+    for (int wv = kMaxEmitWaves; wv >= 1; wv /= 2) {
+        if (wv > max_waves) continue;
+        const size_t tot = tab + tel_bytes(n_tel) + (size_t)wv * per;
         if (tot <= cap) {
             *waves = wv;
             *lds_bytes = tot;
@@ -1947,18 +1968,12 @@ int launch_run(RunPlan& p)
     if (int rc = check_launch("init")) return rc;
     int waves = 0;
     size_t lds = 0;
-    if (int rc = emit_config(p.params.precision, a.n_tel, p.prof_bins, p.atmo, p.tile_segs, &waves,
-                             &lds))
-        return rc;
     int cap = p.emit_waves;
     if (p.params.precision == 1 && (p.params.grazing_exact || p.params.earth_radius_m > 0.0))
         cap = std::min(cap, emit_threads(1, kFeatExact) / kWave);
-    if (cap < waves) {
-        waves = cap;
-        lds = ((table_bytes(p.params.precision, a.n_nodes, p.prof_bins > 0) + 15) & ~(size_t)15) +
-              (a.hnodes ? search_bytes(a.n_nodes) : 0) +
-              (size_t)waves * wave_bytes(p.params.precision, p.tile_segs, a.n_tel, p.prof_bins);
-    }
+    if (int rc = emit_config(p.params.precision, a.n_tel, p.prof_bins, p.atmo, p.tile_segs, cap, &waves,
+                             &lds))
+        return rc;
     if (p.prof_bins > 0) {
         // the profile accumulates by atomics: clear it (a kernel, so the run stays capturable)
         const int64_t m = (int64_t)a.n_showers * p.prof_bins;

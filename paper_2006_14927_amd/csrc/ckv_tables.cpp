@@ -170,6 +170,12 @@ int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ck
         g->cell_list.insert(g->cell_list.end(), lists[c].begin(), lists[c].end());
     }
     g->cell_off[lists.size()] = (int32_t)g->cell_list.size();
+    g->cell_ent.assign(2 * lists.size(), 0u);
+    for (size_t c = 0; c < lists.size(); ++c) {
+        const uint32_t cnt = (uint32_t)lists[c].size();
+        g->cell_ent[2 * c] = (uint32_t)g->cell_off[c];
+        g->cell_ent[2 * c + 1] = cnt | ((cnt ? (uint32_t)lists[c][0] : 0u) << 16);
+    }
     if (g->cell_list.empty()) g->cell_list.push_back(0);
     return CKV_OK;
 }
