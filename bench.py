@@ -42,12 +42,12 @@ OPS_MIXED = {
     "wavelength (inverse CDF, rcp)": 2,
     "drop tests": 4,
     "table index (FP64 -> cell, fraction)": 7,
-    "moments about psi_e, D1..D5: node moments shifted (15 FMA) + in-cell closed form (16)": 31,
+    "moments about psi_e, D1..D5: node moments shifted (15 FMA) + in-cell closed form (11)": 26,
     "index at emission, n_e / n_obs": 9,
-    "1/w (FP64 rcp + 2 Newton steps)": 5,
+    "1/w (FP64 rcp + 1 Newton step)": 3,
     "series variable q": 5,
     "advance series S": 9,
-    "time series T": 19,
+    "time series T (n_e^2 times the advance series + a_k q^k D_{k+1})": 10,
     "ground point, arrival time": 5,
     "observed direction, record conversions": 6,
     "candidate cell": 13,
@@ -62,12 +62,12 @@ OPS_FP64 = {
     "wavelength (rcp + 2 Newton)": 7,
     "drop tests": 4,
     "table index": 6,
-    "moments about psi_e, D1..D5: node shift + in-cell closed form": 31,
+    "moments about psi_e, D1..D5: node shift + in-cell closed form": 26,
     "index at emission (sqrt, 1/n_e by rcp + 2 Newton, n_e / n_obs)": 8,
     "1/w (rcp + 2 Newton)": 5,
     "series variable q": 3,
     "advance series S": 9,
-    "time series T": 20,
+    "time series T (sharing the advance series)": 10,
     "ground point, arrival time": 5,
     "observed direction, record conversions": 6,
     "candidate cell + sphere tests": 16,

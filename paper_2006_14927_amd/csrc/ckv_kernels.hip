@@ -968,12 +968,12 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     X5 += c1 * X4; X4 += c1 * X3;
                     X5 += c1 * X4;
                     const T del = -f * dpsi;               // psi_i - psi_e
-                    const T del2 = del * del, del3 = del2 * del, del4 = del3 * del, del5 = del4 * del;
-                    const T D1 = X1 + dz * (T)0.5 * del;
-                    const T D2 = X2 + dz * (T)(1.0 / 3.0) * del2;
-                    const T D3 = X3 + dz * (T)0.25 * del3;
-                    const T D4 = X4 + dz * (T)0.2 * del4;
-                    const T D5 = X5 + dz * (T)(1.0 / 6.0) * del5;
+                    const T e1 = dz * del, e2 = e1 * del, e3 = e2 * del, e4 = e3 * del, e5 = e4 * del;
+                    const T D1 = X1 + e1 * (T)0.5;
+                    const T D2 = X2 + e2 * (T)(1.0 / 3.0);
+                    const T D3 = X3 + e3 * (T)0.25;
+                    const T D4 = X4 + e4 * (T)0.2;
+                    const T D5 = X5 + e5 * (T)(1.0 / 6.0);
                     // index at emission: n_e = 1 + delta_e
                     const T ne2 = (T)1 + psi_e;
                     double ne, inv_w;
@@ -988,9 +988,9 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                         const float de = (float)psi_e * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_sqrtf(1.0f + (float)psi_e));
                         ne = 1.0 + (double)de;
                         ratio = 1.0f + (de - d_obs) * inv_1pdobs;
-                        // reciprocal of w with two Newton steps (FP64-accurate)
-                        double r_w = __builtin_amdgcn_rcp(pw);
-                        r_w = fma(r_w, fma(-pw, r_w, 1.0), r_w);
+                        // reciprocal of w: the hardware estimate (relative error below
+                        // 2^-24 on this chip) and one Newton step, 2e-15 relative
+                        const double r_w = __builtin_amdgcn_rcp(pw);
                         inv_w = fma(r_w, fma(-pw, r_w, 1.0), r_w);
                         q = (T)__builtin_amdgcn_rcpf((float)ne2 * (float)(pw * pw));
                         inv_ne = (T)__builtin_amdgcn_rcpf(1.0f + de);
@@ -999,9 +999,9 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     const T s_corr = q * (a1 * D1 + q * (a2 * D2 + q * (a3 * D3 + q * a4 * D4)));
                     const double S = dh + (double)s_corr;
                     // c * time * w = n_e dh + (1/n_e) [D1 + sum_{k>=1} a_k q^k (n_e^2 D_k + D_{k+1})]
-                    const T t_corr = D1 + q * (a1 * (ne2 * D1 + D2) +
-                                           q * (a2 * (ne2 * D2 + D3) +
-                                           q * (a3 * (ne2 * D3 + D4) + q * a4 * (ne2 * D4 + D5))));
+                    //              = n_e dh + (1/n_e) [D1 + n_e^2 s_corr + sum_{k>=1} a_k q^k D_{k+1}]
+                    const T t_corr = D1 + ne2 * s_corr +
+                                     q * (a1 * D2 + q * (a2 * D3 + q * (a3 * D4 + q * a4 * D5)));
                     const double ctw = fma(ne, dh, (double)(t_corr * inv_ne));
                     const double T_travel = ctw * inv_w * inv_c;
                     const double adv = inv_w * S;
