@@ -576,6 +576,7 @@ constexpr int kFeatProfile = 1;
 constexpr int kFeatExact = 2;
 constexpr int kFeatSearch = 4;   // node tables: binary search per bunch (alone, 32-step tiles)
 constexpr int kFeatCurved = 8;   // spherical shells, every bunch traced exactly (alone, 32-step tiles)
+constexpr int kFeatWide = 16;    // mixed kernel built for <= 8 waves per workgroup (twice the registers)
 
 __host__ __device__ inline size_t search_bytes(int n_nodes)
 {
@@ -590,10 +591,13 @@ __host__ __device__ inline size_t tel_bytes(int n_tel)
 
 // Workgroup size the variant is compiled for: the FP64 kernel and the exact-path
 // variants (grazing, curved) carry FP64 tracing state and get the registers of
-// 8 waves; the plain mixed kernel runs 16.
+// 8 waves; the mixed kernel is built for 16 waves (128 registers, the most
+// waves per SIMD) and, as the wide variant, for up to 8 (256 registers: no
+// spills, faster where step setup weighs more than bunches, e.g. at large
+// zenith angles); the launch's wave count picks the build.
 constexpr int emit_threads(int prec, int feat)
 {
-    return (prec == 0 || (feat & (kFeatExact | kFeatCurved)) != 0) ? 512 : 1024;
+    return (prec == 0 || (feat & (kFeatExact | kFeatCurved | kFeatWide)) != 0) ? 512 : 1024;
 }
 
 template <int PREC, int TS, int FEAT>
@@ -1937,6 +1941,13 @@ int launch_emit_feat(const Args& a, int grid, int waves, size_t lds, hipStream_t
         return CKV_ERR_ARG;
     }
     const int feat = (a.prof_bins > 0 ? kFeatProfile : 0) | (a.grazing_exact ? kFeatExact : 0);
+    if constexpr (PREC == 1) {
+        if (waves <= emit_threads(1, kFeatWide) / kWave) {
+            if (feat == 0) return launch_emit<PREC, TS, kFeatWide>(a, grid, waves, lds, st);
+            if (feat == kFeatProfile)
+                return launch_emit<PREC, TS, kFeatProfile | kFeatWide>(a, grid, waves, lds, st);
+        }
+    }
     switch (feat) {
         case 0: return launch_emit<PREC, TS, 0>(a, grid, waves, lds, st);
         case kFeatProfile: return launch_emit<PREC, TS, kFeatProfile>(a, grid, waves, lds, st);
