@@ -1279,11 +1279,25 @@ __global__ void __launch_bounds__(256) rowblock_scan_kernel(Args a)
         if (have_tiles) {
             int32_t* col = a.block_sums + (int64_t)k * a.max_row_blocks;
             const int64_t b_end = a.blocks_before[s + 1];
-            for (int64_t b0 = a.blocks_before[s]; b0 < b_end; b0 += kWave) {
-                const int64_t b = b0 + lane;
-                const int64_t x = b < b_end ? col[b] : 0;
-                const int64_t incl = wave_incl_scan(x);
-                if (b < b_end) col[b] = (int32_t)(run + incl - x);
+            // 8 x 64 blocks per round, 8 consecutive ones per lane: the loads issue
+            // before the first store and one wave scan of the lane sums serves all
+            constexpr int G = 8;
+            for (int64_t b0 = a.blocks_before[s]; b0 < b_end; b0 += G * kWave) {
+                const int64_t bl = b0 + (int64_t)G * lane;
+                int32_t x[G];
+                int64_t lsum = 0;
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    x[j] = bl + j < b_end ? col[bl + j] : 0;
+                    lsum += x[j];
+                }
+                const int64_t incl = wave_incl_scan(lsum);
+                int64_t pre = run + incl - lsum;
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    if (bl + j < b_end) col[bl + j] = (int32_t)pre;
+                    pre += x[j];
+                }
                 run += __shfl(incl, kWave - 1);
             }
         }
@@ -1301,10 +1315,17 @@ __global__ void __launch_bounds__(256) tile_prefix_kernel(Args a)
         const int64_t t1 = min(t0 + kRowBlock, a.tiles_before[s + 1]);
         for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x) {
             int32_t run = a.block_sums[k * a.max_row_blocks + b];
-            for (int64_t t = t0; t < t1; ++t) {
-                const int32_t x = a.counts[t * a.n_tel + k];
-                a.counts[t * a.n_tel + k] = run;
-                run += x;
+            // 16 tiles per round: all loads issue before the first store
+            constexpr int G = 16;
+            for (int64_t tg = t0; tg < t1; tg += G) {
+                int32_t x[G];
+#pragma unroll
+                for (int j = 0; j < G; ++j) x[j] = tg + j < t1 ? a.counts[(tg + j) * a.n_tel + k] : 0;
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    if (tg + j < t1) a.counts[(tg + j) * a.n_tel + k] = run;
+                    run += x[j];
+                }
             }
         }
     }
