@@ -1430,6 +1430,7 @@ struct SoftArgs {
     int32_t nx, ny, level_cells;
     const int32_t* cell_off;
     const uint16_t* cell_list;
+    const uint2* cell_ent;      // per cell: {offset, count | first sphere << 16}
 };
 
 struct alignas(16) SoftStep {
@@ -1462,11 +1463,11 @@ __host__ __device__ inline size_t soft_wave_bytes(int mode, int n_tel)
            (mode == 0 ? (size_t)2 * n_tel * sizeof(double) : 0);
 }
 
-// per workgroup: adjoint bins, then 1 / (2 R sigma) per telescope, then the waves
+// per workgroup: adjoint bins, then {X, Y, R^2, 1 / (2 R sigma)} per telescope, then the waves
 __host__ __device__ inline size_t soft_lds_bytes(int mode, int n_nodes, int n_tel, int waves)
 {
     const size_t bins = mode == 1 ? (size_t)6 * soft_bin_nodes(n_nodes) * sizeof(double) : 0;
-    return bins + (size_t)n_tel * sizeof(double) + (size_t)waves * soft_wave_bytes(mode, n_tel);
+    return bins + (size_t)n_tel * 4 * sizeof(double) + (size_t)waves * soft_wave_bytes(mode, n_tel);
 }
 
 // step setup with a frozen bunch count; false when the step emits nothing
@@ -1529,16 +1530,20 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
     const int N = a.n_nodes;
     const int NB = soft_bin_nodes(N);
     double* bins = reinterpret_cast<double*>(lds);                 // MODE 1: 6 x NB
-    double* inv_2rs = bins + (MODE == 1 ? 6 * NB : 0);               // n_tel
-    unsigned char* wbase = reinterpret_cast<unsigned char*>(inv_2rs + a.n_tel) +
+    double* tsh = bins + (MODE == 1 ? 6 * NB : 0);     // n_tel x {X, Y, R^2, 1 / (2 R sigma)}
+    unsigned char* wbase = reinterpret_cast<unsigned char*>(tsh + 4 * a.n_tel) +
                            (size_t)wave * soft_wave_bytes(MODE, a.n_tel);
     SoftStep* stash = reinterpret_cast<SoftStep*>(wbase);
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + kSoftTS * sizeof(SoftStep));
     double* acc = reinterpret_cast<double*>(flags + kWave);     // MODE 0: S then A per telescope
     if (MODE == 1)
         for (int q = threadIdx.x; q < 6 * NB; q += blockDim.x) bins[q] = 0.0;
-    for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x)
-        inv_2rs[q] = 1.0 / (2.0 * a.tel[4 * q + 2] * sa.sigma);
+    for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x) {
+        tsh[4 * q] = a.tel[4 * q];
+        tsh[4 * q + 1] = a.tel[4 * q + 1];
+        tsh[4 * q + 2] = a.tel[4 * q + 3];
+        tsh[4 * q + 3] = 1.0 / (2.0 * a.tel[4 * q + 2] * sa.sigma);
+    }
     if (MODE == 0)
         for (int q = lane; q < 2 * a.n_tel; q += kWave) acc[q] = 0.0;
     flags[lane] = 0;
@@ -1682,26 +1687,30 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
             // soft weights over candidate spheres
             double g_xg = 0, g_yg = 0, g_uo = 0, g_vo = 0, g_t = 0, g_p = 0;
             int cur = 0, cend = 0;
+            int first = -1;          // the cell's first sphere, known without a list read
             bool brute = false;
             const double wo2 = 1.0 - uo * uo - vo * vo;
             if (wo2 >= kLevelW2[0]) {
                 const double fx = (xg - sa.gx0) * sa.inv_cell, fy = (yg - sa.gy0) * sa.inv_cell;
                 if (fx >= 0.0 && fy >= 0.0 && fx < (double)sa.nx && fy < (double)sa.ny) {
                     const int cidx = grid_level(wo2) * sa.level_cells + (int)fx * sa.ny + (int)fy;
-                    cur = sa.cell_off[cidx];
-                    cend = sa.cell_off[cidx + 1];
+                    const uint2 ce = sa.cell_ent[cidx];
+                    cur = (int)ce.x;
+                    cend = cur + (int)(ce.y & 0xFFFFu);
+                    first = (int)(ce.y >> 16);
                 }
             } else {
                 brute = true;
                 cend = a.n_tel;
             }
             for (; cur < cend; ++cur) {
-                const int kt = brute ? cur : (int)sa.cell_list[cur];
-                const double* tp = a.tel + 4 * kt;
+                const int kt = brute ? cur : (first >= 0 ? first : (int)sa.cell_list[cur]);
+                first = -1;
+                const double* tp = tsh + 4 * kt;                  // LDS
                 const double dx = xg - tp[0], dy = yg - tp[1];
                 const double b = dx * uo + dy * vo;
                 const double rho2 = dx * dx + dy * dy - b * b;
-                const double z = (tp[3] - rho2) * inv_2rs[kt];
+                const double z = (tp[2] - rho2) * tp[3];
                 if (z < -kSoftZCut) continue;
                 const double W = 0.5 * erfc(-z * inv_sqrt2);
                 if (MODE == 0) {
@@ -1713,7 +1722,7 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
                     g_p += gSk * W + gAk * W * tt;
                     g_t += gAk * p * W;
                     const double g_z = (gSk * p + gAk * p * tt) * inv_sqrt2pi * exp(-0.5 * z * z);
-                    const double g_r2 = -g_z * inv_2rs[kt];
+                    const double g_r2 = -g_z * tp[3];
                     g_xg += g_r2 * (2.0 * dx - 2.0 * b * uo);
                     g_yg += g_r2 * (2.0 * dy - 2.0 * b * vo);
                     g_uo += g_r2 * (-2.0 * b * dx);
@@ -2054,6 +2063,7 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     s.level_cells = ar->soft.level_cells;
     s.cell_off = ar->soft.d_cell_off;
     s.cell_list = ar->soft.d_cell_list;
+    s.cell_ent = reinterpret_cast<const uint2*>(ar->soft.d_cell_ent);
     // as many waves as the kernel's launch bounds allow and the LDS holds
     const int wmax = soft_max_waves(mode);
     int waves = p.emit_waves > 0 && p.emit_waves < wmax ? p.emit_waves : wmax;
