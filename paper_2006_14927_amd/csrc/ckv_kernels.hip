@@ -113,6 +113,21 @@ __device__ __forceinline__ int wave_min(int x)
     return x;
 }
 
+// Smallest x over the lanes where it is below `none` (at least one lane is):
+// take the first such lane's value and repeat while a lane holds a smaller one.
+// Passes = distinct values below the result + 1, usually one or two; ballots
+// and lane reads only, no LDS round trips.
+__device__ __forceinline__ int wave_min_sparse(int x, int none)
+{
+    uint64_t below = __ballot(x < none);
+    int m = none;
+    while (below) {
+        m = __builtin_amdgcn_readlane(x, __builtin_ctzll(below));
+        below = __ballot(x < m);
+    }
+    return m;
+}
+
 __device__ __forceinline__ int64_t wave_sum(int64_t x)
 {
 #pragma unroll
@@ -1091,7 +1106,7 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
             advance();
             // ---- record crossings; telescopes in ascending order, lanes (bunches) in order
             while (__ballot(my_next != INT_MAX)) {
-                const int kmin = wave_min(my_next);
+                const int kmin = wave_min_sparse(my_next, INT_MAX);
                 const bool mine = my_next == kmin;
                 const uint64_t mask = __ballot(mine);
                 const int nmine = __popcll(mask);
