@@ -125,3 +125,26 @@ def test_curved_streamed_chunks_equal_one_shot():
         ids = np.concatenate([x[1] for x in got[t]])
         np.testing.assert_array_equal(rec.view(np.uint32), one["rec"][o[t]:o[t + 1]].view(np.uint32))
         np.testing.assert_array_equal(ids, one["ids"][o[t]:o[t + 1]])
+
+
+@pytest.mark.parametrize("precision", [ckv.CKV_FP64, ckv.CKV_MIXED])
+def test_curved_several_showers_one_launch(precision):
+    """Three inclined showers of different sizes, zeniths, azimuths and cores in one
+    curved launch: per (shower, telescope) lists, counts and drops as the oracle."""
+    atmo = synth.layered_atmosphere()
+    parts = [synth.shower_segments(s, n, atmo, zenith_deg=z, azimuth_deg=az, core=c, xmax=400.0)
+             for s, n, z, az, c in ((0, 5000, 60.0, 0.0, (0.0, 0.0)),
+                                    (1, 12000, 72.0, 135.0, (300.0, -200.0)),
+                                    (2, 3000, 80.0, 250.0, (-500.0, 400.0)))]
+    segs = synth.Segments.concat(parts)
+    wl = synth.Workload("curved_mix", atmo, synth.telescopes_disk(), segs)
+    cfg = oracle.Config.from_workload(wl, earth_radius=R_EARTH)
+    r = oracle.run(cfg, segs, nthreads=16)
+    g = gpu_run(wl, precision, earth_radius=R_EARTH, capacity=4 * len(r.seg) + 4096)
+    res = g["result"]
+    assert res["error"] == 0 and res["overflow"] == 0, res
+    assert res["n_bunches"] == r.n_bunches and res["drops"] == r.drops, (res, r.drops)
+    if precision == ckv.CKV_FP64:
+        np.testing.assert_array_equal(g["offsets"], r.offsets)
+    rep = compare_records(wl, cfg, r, g, precision)
+    say(f"[gpu] curved 3 showers prec={precision}: hits={res['n_hits']} {rep}")
