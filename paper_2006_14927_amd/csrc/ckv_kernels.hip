@@ -409,6 +409,21 @@ __device__ __forceinline__ double rsqrt64(double x)
     return fma(0.5 * y, fma(-x * y, y, 1.0), y);
 }
 
+// One Newton step on the hardware estimates (relative errors below 2^-23 for rsq
+// and 2^-24 for rcp on this chip): ~1e-14 relative, for the per-cell factors of
+// the curved tracer, where such errors stay far below the result's rounding.
+__device__ __forceinline__ double rsqrt64_1(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+__device__ __forceinline__ double rcp64_1(double x)
+{
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
 // Curved atmosphere: exact propagation through spherical shells (radius R =
 // a.earth_r, centre (0, 0, -R)).  n depends on the altitude h = r - R only, so
 // the ray stays in the plane of the centre, its emission point and direction,
@@ -457,18 +472,18 @@ __device__ __forceinline__ int propagate_curved(const Args& a, double xe, double
     const int c = min((int)x, a.n_nodes - 2);
     constexpr double kg = 0.57735026918962576451;   // 1/sqrt(3)
     double theta = 0.0, opt = 0.0;
-    double h_t = he, s2t = s2e, s_t = s2e * rsqrt64(s2e);
+    double h_t = he, s2t = s2e, s_t = s2e * rsqrt64_1(s2e);
     for (int i = c; i >= 0; --i) {
         const double h_b = a.h_obs + (double)i * a.step;
         const double psi_b = nd[kNode64 * i];
         const double r_b = R + h_b;
         const double s2b = i == 0 ? s2g : s2e + ((h_b - he) * (r_b + r_e) + psi_b * r_b * r_b - Mre);
-        const double s_b = s2b * rsqrt64(s2b);
+        const double s_b = s2b * rsqrt64_1(s2b);
         const double dh = h_t - h_b;
         if (dh > 0.0 && s2t != s2b) {    // (a cell of zero s^2 span adds ~dh/s: nothing)
             const double g = (nd[kNode64 * (i + 1)] - psi_b) * a.inv_step;   // dpsi/dh in the cell
-            const double inv_ds2 = rcp64(s2t - s2b);
-            const double inv_rb = rcp64(r_b);
+            const double inv_ds2 = rcp64_1(s2t - s2b);
+            const double inv_rb = rcp64_1(r_b);
             const double mid = 0.5 * (s_t + s_b), half = (0.5 * kg) * (s_t - s_b);
             double a_th = 0.0, a_op = 0.0;
 #pragma unroll
@@ -478,12 +493,12 @@ __device__ __forceinline__ int propagate_curved(const Args& a, double xe, double
                 const double psq = fma(g, xq, psi_b);
                 const double rq = r_b + xq;
                 const double s2q = s2e + ((h_b + xq - he) * (rq + r_e) + psq * rq * rq - Mre);
-                const double ratio = uq * rsqrt64(s2q);
+                const double ratio = uq * rsqrt64_1(s2q);
                 const double e = xq * inv_rb;                            // 1/r_q = (1 - e + e^2) / r_b
                 a_th += ratio * (inv_rb * fma(e, e - 1.0, 1.0));
                 a_op += ((1.0 + psq) * rq) * ratio;
             }
-            const double scale = dh * rcp64(s_t + s_b);
+            const double scale = dh * rcp64_1(s_t + s_b);
             theta = fma(scale, K * a_th, theta);
             opt = fma(scale, a_op, opt);
         }
