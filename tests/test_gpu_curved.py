@@ -148,3 +148,40 @@ def test_curved_several_showers_one_launch(precision):
         np.testing.assert_array_equal(g["offsets"], r.offsets)
     rep = compare_records(wl, cfg, r, g, precision)
     say(f"[gpu] curved 3 showers prec={precision}: hits={res['n_hits']} {rep}")
+
+
+def test_curved_full_size_sampled():
+    """The 70-degree TeV shower at the benchmark's size (2e6 steps, 5.2e7 bunches),
+    curved, mixed, in the benchmark's launch shape: every step's bunch count
+    against the oracle, and the records of every 97th step (with their original
+    random numbers) against the oracle's curved run of those steps."""
+    import torch
+    wl = synth.inclined(70.0)
+    assert wl.segs.n == 2_000_000
+    cfg = oracle.Config.from_workload(wl, earth_radius=R_EARTH)
+    atmo, tels = handles(wl)
+    d = ckv.DeviceSegments(wl.segs)
+    p = params(wl, ckv.CKV_MIXED, earth_radius=R_EARTH, tile_segments=32)
+    n_b = ckv.count(d, atmo, p).cpu().numpy()
+    nb_o = oracle.segment_details(cfg, wl.segs)["n_b"].astype(np.int64)
+    np.testing.assert_array_equal(n_b, nb_o)
+    r = ckv.Runner(d, atmo, tels, p, 1 << 20)
+    out = r.run()
+    torch.cuda.synchronize()
+    res = out.result()
+    assert res["error"] == 0 and res["overflow"] == 0 and res["n_bunches"] == int(nb_o.sum())
+    n = res["n_records"]
+    off = out.tel_offsets.cpu().numpy()
+    rec = out.records[:n].cpu().numpy()
+    ids = out.ids[:n].cpu().numpy()
+    idx = np.arange(0, wl.segs.n, 97)
+    keep = np.isin(ids[:, 0], idx)
+    counts = np.diff(off)
+    group = np.repeat(np.arange(len(counts)), counts)[keep]
+    off_k = np.zeros(len(counts) + 1, dtype=np.int64)
+    off_k[1:] = np.cumsum(np.bincount(group, minlength=len(counts)))
+    sub = wl.segs.take(idx)
+    ores = oracle.run(cfg, sub, nthreads=16, seg_id=idx)
+    rep = compare_records(wl, cfg, ores, dict(offsets=off_k, rec=rec[keep], ids=ids[keep]),
+                          ckv.CKV_MIXED, segs=sub, seg_map=idx)
+    say(f"[gpu] curved 70 deg full size: {res['n_bunches']} bunches, {n} records; sampled {rep}")
