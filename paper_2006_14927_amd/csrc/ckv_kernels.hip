@@ -106,13 +106,6 @@ __device__ __forceinline__ int64_t wave_incl_scan(int64_t x)
     return x;
 }
 
-__device__ __forceinline__ int wave_min(int x)
-{
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d));
-    return x;
-}
-
 // Smallest x over the lanes where it is below `none` (at least one lane is):
 // take the first such lane's value and repeat while a lane holds a smaller one.
 // Passes = distinct values below the result + 1, usually one or two; ballots
@@ -126,13 +119,6 @@ __device__ __forceinline__ int wave_min_sparse(int x, int none)
         below = __ballot(x < m);
     }
     return m;
-}
-
-__device__ __forceinline__ int64_t wave_sum(int64_t x)
-{
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d);
-    return x;
 }
 
 __device__ __forceinline__ void wave_lds_sync()
