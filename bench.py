@@ -28,24 +28,27 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# --- algorithmic VALU operations per generated bunch: each arithmetic, logic,
-# compare, select or conversion the algorithm needs at the path's precision
-# counts once (an FMA is one operation; a 32x32->64 multiply, a reciprocal or
-# a square root is one operation).  Loop control, addressing and register moves
-# are not counted.  The derivation, step by step, is in the design notes.
+# --- algorithmic VALU work per generated bunch, in issue slots: each arithmetic,
+# logic, compare, select or conversion the algorithm needs at the path's precision,
+# weighted by its issue cost on this chip as measured by single-instruction rate
+# probes: 1 slot for FP32/FP64 add, mul and FMA, integer and logic operations,
+# conversions and the 32x32->64 multiply; 2 for an FP32 transcendental (rcp, sqrt,
+# sin, cos); 4 for an FP64 one (rcp, and the estimate inside a square root).  Loop
+# control, addressing and register moves are not counted.  The derivation, step by
+# step, is in the design notes.
 OPS_MIXED = {
     "philox4x32-10: 10 rounds x (2 mul32x32->64 + 4 xor)": 60,
     "uniforms u0, u2 (convert + scale)": 4,
     "emission point and time (FP64)": 7,
-    "azimuth sin/cos: quadrant fold + Taylor polynomials (FP32)": 26,
+    "azimuth: quadrant, angle in turns (4), hardware sin + cos (2 x 2), quadrant selects (6)": 14,
     "direction on the cone (FP32 perpendicular, FP64 sum)": 12,
-    "wavelength (inverse CDF, rcp)": 2,
+    "wavelength (inverse CDF: fma + rcp)": 3,
     "drop tests": 4,
     "table index (FP64 -> cell, fraction)": 7,
     "moments about psi_e, D1..D5: node moments shifted (15 FMA) + in-cell closed form (11)": 26,
-    "index at emission, n_e / n_obs": 9,
-    "1/w (FP64 rcp + 1 Newton step)": 3,
-    "series variable q": 5,
+    "index at emission (sqrt, 2 rcp), n_e / n_obs": 12,
+    "1/w (FP64 rcp + 1 Newton step)": 6,
+    "series variable q (rcp)": 6,
     "advance series S": 9,
     "time series T (n_e^2 times the advance series + a_k q^k D_{k+1})": 10,
     "ground point, arrival time": 5,
@@ -59,12 +62,12 @@ OPS_FP64 = {
     "emission point and time": 7,
     "azimuth sin/cos: quadrant fold + Taylor polynomials to a^17 (FP64)": 32,
     "direction on the cone": 9,
-    "wavelength (rcp + 2 Newton)": 7,
+    "wavelength (rcp + 2 Newton)": 10,
     "drop tests": 4,
     "table index": 6,
     "moments about psi_e, D1..D5: node shift + in-cell closed form": 26,
-    "index at emission (sqrt, 1/n_e by rcp + 2 Newton, n_e / n_obs)": 8,
-    "1/w (rcp + 2 Newton)": 5,
+    "index at emission (sqrt, 1/n_e by rcp + 2 Newton, n_e / n_obs)": 14,
+    "1/w (rcp + 2 Newton)": 8,
     "series variable q": 3,
     "advance series S": 9,
     "time series T (sharing the advance series)": 10,

@@ -269,30 +269,17 @@ __device__ __forceinline__ void step_setup(const Args& a, int64_t i, Setup& st)
 }
 
 // --------------------------------------------------------------------------
-// sin and cos of 2 pi (r + 1/2) / 2^32 in FP32, from the integer: the top two
-// bits give the quadrant, the rest the angle inside it, folded to [0, pi/4]
-// and evaluated with Taylor polynomials (errors below 2e-9 there).
+// sin and cos of 2 pi (r + 1/2) / 2^32 from the integer draw r, in turns.
+// Mixed path: the hardware sine and cosine, which take their argument in turns:
+// the quadrant from the top two bits, the angle inside it as an FP32 number of
+// turns in [0, 1/4) (rounding below 1e-7 rad); errors near 1e-7, i.e. ~2e-9 in
+// the photon direction once scaled by sin(theta_c) < 0.03.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ void sincos_turns(uint32_t r, float& s, float& c)
+__device__ __forceinline__ void sincos_turns_hw(uint32_t r, float& s, float& c)
 {
     const uint32_t q = r >> 30;
-    const uint32_t low = r & 0x3FFFFFFFu;
-    const bool upper = low >= 0x20000000u;
-    const uint32_t m = upper ? (0x3FFFFFFFu - low) : low;
-    const float kq = 1.46291807926715968e-9f;          // (pi/2) / 2^30
-    const float a = fmaf((float)m, kq, 0.5f * kq);
-    const float a2 = a * a;
-    float sa = fmaf(a2, 1.0f / 362880.0f, -1.0f / 5040.0f);
-    sa = fmaf(a2, sa, 1.0f / 120.0f);
-    sa = fmaf(a2, sa, -1.0f / 6.0f);
-    sa = a * fmaf(a2, sa, 1.0f);
-    float ca = fmaf(a2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
-    ca = fmaf(a2, ca, -1.0f / 720.0f);
-    ca = fmaf(a2, ca, 1.0f / 24.0f);
-    ca = fmaf(a2, ca, -0.5f);
-    ca = fmaf(a2, ca, 1.0f);
-    const float cq = upper ? sa : ca;
-    const float sq = upper ? ca : sa;
+    const float t = fmaf((float)(r & 0x3FFFFFFFu), 2.3283064365386963e-10f, 1.16415321826934814e-10f);
+    const float sq = __builtin_amdgcn_sinf(t), cq = __builtin_amdgcn_cosf(t);
     c = (q == 0) ? cq : (q == 1) ? -sq : (q == 2) ? -cq : sq;
     s = (q == 0) ? sq : (q == 1) ? cq : (q == 2) ? -sq : -cq;
 }
@@ -865,7 +852,7 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                                                       1.1641532182693481e-10) * a.dl);
                 } else {
                     float sp, cp;
-                    sincos_turns(r1, sp, cp);
+                    sincos_turns_hw(r1, sp, cp);
                     const float px = fmaf(cp, (float)e.sb1x, sp * (float)e.sb2x);
                     const float py = fmaf(cp, (float)e.sb1y, sp * (float)e.sb2y);
                     const float pz = fmaf(cp, (float)e.sb1z, sp * (float)e.sb2z);
