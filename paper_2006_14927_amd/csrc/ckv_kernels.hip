@@ -1449,7 +1449,9 @@ static_assert(sizeof(SoftStep) % 16 == 0, "soft step entry alignment");
 constexpr int kSoftTS = 32;
 // forward: 8 waves (<= 256 VGPRs, two waves per SIMD); adjoint: 4 waves, whose
 // reverse sweep needs more registers than two waves per SIMD leave
-__host__ __device__ constexpr int soft_max_waves(int mode) { return mode == 0 ? 8 : 4; }
+// 8 waves for both: the adjoint at 4 waves keeps 288 registers (one wave per SIMD);
+// built for 8 it gets 256 (two per SIMD) at the cost of a few spills, which is faster
+__host__ __device__ constexpr int soft_max_waves(int mode) { return mode == 0 ? 8 : 8; }
 // adjoint bins (dL/dpsi_i, dL/dP_j(h_i)) of the lowest kSoftBinNodes nodes live in
 // LDS (h_obs + 51 km on a 50 m grid); the rare contributions above go to HBM
 constexpr int kSoftBinNodes = 1024;
