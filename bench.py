@@ -100,6 +100,24 @@ def _hip():
     raise RuntimeError("libamdhip64.so not found")
 
 
+# hipDeviceAttribute_t values of this ROCm's hip_runtime_api.h
+_HIP_ATTR = {"clock_khz": 5, "mem_bus_bits": 59, "mem_clock_khz": 60, "cus": 63,
+             "lds_per_cu_bytes": 10002}
+
+
+def device_info(hip) -> dict:
+    """The chip's figures as the runtime reports them on the machine that runs this."""
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    hip.hipDeviceGetAttribute.argtypes = [C.POINTER(C.c_int), C.c_int, C.c_int]
+    out = {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
+           "hbm_gib": round(props.total_memory / 2 ** 30, 1)}
+    for k, attr in _HIP_ATTR.items():
+        v = C.c_int()
+        out[k] = int(v.value) if hip.hipDeviceGetAttribute(C.byref(v), attr, 0) == 0 else None
+    return out
+
+
 def _event(hip):
     e = C.c_void_p()
     if hip.hipEventCreate(C.byref(e)) != 0:
@@ -385,9 +403,18 @@ def cpu_baseline(wl, target_cpu_seconds: float = 20.0):
     t0 = time.perf_counter()
     r = oracle.run(cfg, wl.segs.take(idx), nthreads=threads, seg_id=idx)
     dt = time.perf_counter() - t0
-    return {"value": r.n_bunches / dt, "unit": "bunches/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th step of the shower ({len(idx)} steps, {r.n_bunches} "
-                      f"bunches, {len(r.seg)} records), FP64, {dt:.2f} s wall"}
+    out = {"value": r.n_bunches / dt, "unit": "bunches/s", "cores": threads, "kind": "oracle",
+           "sample": f"every {stride}th step of the shower ({len(idx)} steps, {r.n_bunches} "
+                     f"bunches, {len(r.seg)} records), FP64, {dt:.2f} s wall"}
+    # the same oracle on one thread, on a sample 1/threads the size
+    idx1 = idx[::threads]
+    t0 = time.perf_counter()
+    r1 = oracle.run(cfg, wl.segs.take(idx1), nthreads=1, seg_id=idx1)
+    dt1 = time.perf_counter() - t0
+    single = {"value": r1.n_bunches / dt1, "unit": "bunches/s", "cores": 1, "kind": "oracle",
+              "sample": f"every {stride * threads}th step ({len(idx1)} steps, {r1.n_bunches} bunches), "
+                        f"{dt1:.2f} s"}
+    return out, single
 
 
 def main(argv=None):
@@ -561,7 +588,7 @@ def main(argv=None):
         line["differentiation"] = d
     if not args.no_batched:
         torch.cuda.empty_cache()
-        b = batched_timing(hip, 3, use_cache=not args.no_tune_cache)
+        b = batched_timing(hip, 5, use_cache=not args.no_tune_cache)
         print(f"# batched: {b}", file=sys.stderr, flush=True)
         line["batched"] = b
         torch.cuda.empty_cache()
@@ -570,7 +597,8 @@ def main(argv=None):
     if args.order_study:
         line["step_order_study"] = order_study(hip, wl, atmo, tels, stream, args.steps, args.warmup)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl)
+        line["cpu_baseline"], line["cpu_baseline_one_thread"] = cpu_baseline(wl)
+    line["device"] = device_info(hip)
     print(json.dumps(line), flush=True)
     return 0
 
