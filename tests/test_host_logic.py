@@ -92,3 +92,16 @@ def test_stream_range_planning():
             if b - a > 1 and b % 4096 == 0:
                 assert (cum[b] - cum[a]) * ratio <= 0.8 * st.capacity + 1e-9
             a = b
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with a message
+    before any device is touched."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
