@@ -442,7 +442,7 @@ def main(argv=None):
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(showers and step ranges shard independently; see the design notes).",
               file=sys.stderr)
         return 2
