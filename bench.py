@@ -265,10 +265,24 @@ def diff_timing(hip, reps: int, n_showers: int = 64, n_seg: int = 500_000):
     nb = int(model.n_b.sum())
     if not bool(torch.isfinite(g).all()):
         raise RuntimeError("differentiation: non-finite gradient")
+    n_listed, cap = model.list_state()
+    # one pass with the adjoint recomputing every bunch, for comparison
+    model.use_list = False
+    ev = [_event(hip) for _ in range(4)]
+    g_full = step(ev)
+    torch.cuda.synchronize()
+    fwd_nolist = _elapsed_ms(hip, ev[0], ev[1])
+    bwd_full = _elapsed_ms(hip, ev[2], ev[3])
+    for e in ev:
+        hip.hipEventDestroy(e)
+    model.use_list = True
     wall = sorted(walls)[len(walls) // 2]
     return {"workload": dw.name, "showers": n_showers, "steps": dw.segs.n, "bunches": nb,
             "ms_per_shower": wall / n_showers, "fwd_kernel_ms": sum(fwd) / len(fwd),
             "bwd_kernel_ms": sum(bwd) / len(bwd), "wall_ms": wall,
+            "listed_bunches": n_listed, "list_complete": bool(0 <= n_listed <= cap),
+            "fwd_kernel_ms_without_list": fwd_nolist, "bwd_kernel_ms_every_bunch": bwd_full,
+            "grad_rel_diff_every_bunch": float((g_full - g).norm() / g.norm()),
             "grad_norm": float(g.norm())}
 
 

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define CKV_VERSION 111
+#define CKV_VERSION 112
 
 enum {
     CKV_OK = 0,
@@ -323,22 +323,43 @@ int ckv_atmo_params_backward(const ckv_atmo_param_spec* spec, const double* thet
    for edge width sigma_m > 0 (see ckv_array_create for the other arguments). */
 int ckv_array_create_soft(const double* x_m, const double* y_m, const double* r_m, int32_t n_tel,
                           double sigma_m, ckv_array** out);
+/* The bunches that enter the soft response: one id per bunch with z >= -40 at
+   some sphere, (global step index << 24) | bunch index k, in no particular
+   order.  Written by ckv_soft_forward, read by ckv_soft_backward, which then
+   recomputes only these bunches (the others contribute exactly zero).  The
+   caller owns both device buffers.  The forward claims slots in blocks of 512
+   and fills the slots of its last blocks that no bunch takes with 2^64 - 1,
+   which names no bunch; *count is the number of slots claimed.  The list is
+   complete iff 0 <= *count <= capacity (a bunch index of 2^24 or more, or a
+   step index of 2^40 or more, makes it incomplete). */
+typedef struct {
+    uint64_t* ids;        /* device, capacity entries */
+    int64_t capacity;     /* >= 0 */
+    int64_t* count;       /* device, one int64, written by the forward */
+} ckv_soft_list;
+
 /* S and A (device, n_showers x n_tel FP64, overwritten).  Same inputs as
    ckv_run plus n_b_frozen (device int64, one per step); the workspace is the
    one ckv_workspace_size(n, n_showers, n_tel, 0, params) gives.  arr must come
-   from ckv_array_create_soft.  params->precision is ignored (FP64).
+   from ckv_array_create_soft.  params->precision is ignored (FP64).  list
+   (may be NULL) receives the bunches with a nonzero weight.
    Asynchronous on `stream`. */
 int ckv_soft_forward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
                      const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
-                     double* S, double* A, void* workspace, size_t ws_bytes, void* stream);
+                     double* S, double* A, const ckv_soft_list* list, void* workspace,
+                     size_t ws_bytes, void* stream);
 /* Reverse pass: given dL/dS and dL/dA (device, n_showers x n_tel), recomputes
-   every bunch from its random numbers and writes dL/dpsi_i (device, n_nodes)
+   bunches from their random numbers and writes dL/dpsi_i (device, n_nodes)
    and dL/dP_j(h_i) (device, 5 x n_nodes), both overwritten; psi_0 also
-   carries the observation-level index.  Asynchronous on `stream`. */
+   carries the observation-level index.  list NULL: every bunch is recomputed.
+   list from the ckv_soft_forward of the same inputs: only the listed bunches
+   are, when the list is complete (checked on the device; else every bunch);
+   a list from other inputs gives a wrong gradient, and ids that name no bunch
+   of these inputs are skipped.  Asynchronous on `stream`. */
 int ckv_soft_backward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
                       const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
                       const double* dL_dS, const double* dL_dA, double* g_psi, double* g_P,
-                      void* workspace, size_t ws_bytes, void* stream);
+                      const ckv_soft_list* list, void* workspace, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -66,6 +66,10 @@ class _ParamSpec(C.Structure):
                 ("obs_level_m", C.c_double), ("step_m", C.c_double), ("top_m", C.c_double)]
 
 
+class _SoftList(C.Structure):
+    _fields_ = [("ids", C.c_void_p), ("capacity", C.c_int64), ("count", C.c_void_p)]
+
+
 class _Output(C.Structure):
     _fields_ = [("records", C.c_void_p), ("ids", C.c_void_p), ("capacity", C.c_int64),
                 ("tel_offsets", C.c_void_p), ("result", C.c_void_p),
@@ -106,9 +110,9 @@ def lib():
         L.ckv_atmo_params_backward.argtypes = [C.POINTER(_ParamSpec), P, P, P, P, P]
         L.ckv_array_create_soft.argtypes = [P, P, P, I32, D, C.POINTER(P)]
         L.ckv_soft_forward.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params),
-                                       P, P, P, P, P, P, C.c_size_t, P]
+                                       P, P, P, P, P, C.POINTER(_SoftList), P, C.c_size_t, P]
         L.ckv_soft_backward.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params),
-                                        P, P, P, P, P, P, P, P, C.c_size_t, P]
+                                        P, P, P, P, P, P, P, C.POINTER(_SoftList), P, C.c_size_t, P]
         _lib = L
     return _lib
 
@@ -638,10 +642,16 @@ class ParamSpec:
 
 
 class SoftModel:
-    """theta -> (S, A) per (shower, telescope), with bunch counts frozen at theta0."""
+    """theta -> (S, A) per (shower, telescope), with bunch counts frozen at theta0.
+
+    With use_list (default) the forward records the bunches that have a nonzero
+    weight and the backward at the same theta recomputes only those; the list
+    grows after a backward that found it too small (that backward, and any at
+    another theta, recompute every bunch)."""
 
     def __init__(self, segs, tels, spec: ParamSpec, theta0, sigma: float, *, bunch_size=5.0,
-                 lambda_min=300.0, lambda_max=600.0, seed=0x14927, device="cuda"):
+                 lambda_min=300.0, lambda_max=600.0, seed=0x14927, device="cuda",
+                 use_list=True, list_capacity=None):
         import torch
         self.spec = spec
         self.dsegs = segs if isinstance(segs, DeviceSegments) else DeviceSegments(segs, device=device)
@@ -659,6 +669,24 @@ class SoftModel:
         self._segs = self.dsegs.c_segments()
         self._showers = self.dsegs.c_showers()
         self._cache = None
+        self.use_list = bool(use_list)
+        self.list_count = torch.zeros(1, dtype=torch.int64, device=device)
+        self._list_theta = None
+        if self.use_list:
+            # an eighth of the bunches, plus the unfilled ends of the forward's
+            # 512-slot blocks (at most one per wave of the launch)
+            cap = list_capacity if list_capacity is not None else int(self.n_b.sum()) // 8 + (1 << 21)
+            self._alloc_list(int(cap))
+
+    def _alloc_list(self, capacity: int):
+        import torch
+        self.list_ids = torch.empty(max(capacity, 1), dtype=torch.int64, device=self.g_psi.device)
+        self._list = _SoftList(self.list_ids.data_ptr(), int(capacity), self.list_count.data_ptr())
+        self._list_theta = None
+
+    def list_state(self):
+        """(ids found by the last forward, capacity); synchronises."""
+        return int(self.list_count.item()), int(self._list.capacity) if self.use_list else 0
 
     def _atmo(self, theta):
         th = np.asarray(theta, dtype=np.float64)
@@ -671,11 +699,14 @@ class SoftModel:
         atmo = self._atmo(theta)
         S = torch.empty(self.shape, dtype=torch.float64, device=self.g_psi.device)
         A = torch.empty_like(S)
+        lst = C.byref(self._list) if self.use_list else None
         _check(lib().ckv_soft_forward(C.byref(self._segs), C.byref(self._showers), C.byref(self.params),
                                       atmo.handle, self.tels.handle, C.c_void_p(self.n_b.data_ptr()),
-                                      C.c_void_p(S.data_ptr()), C.c_void_p(A.data_ptr()),
+                                      C.c_void_p(S.data_ptr()), C.c_void_p(A.data_ptr()), lst,
                                       C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                       _stream_ptr(stream)))
+        if self.use_list:
+            self._list_theta = np.array(theta, dtype=np.float64, copy=True)
         return S, A
 
     def backward_tables(self, theta, gS, gA, stream=None):
@@ -683,18 +714,37 @@ class SoftModel:
         atmo = self._atmo(theta)
         gS = gS.to(self.g_psi.device, dtype=self.g_psi.dtype).contiguous()
         gA = gA.to(self.g_psi.device, dtype=self.g_psi.dtype).contiguous()
+        # the list is valid for the theta of the forward that wrote it
+        listed = self.use_list and self._list_theta is not None and \
+            np.array_equal(self._list_theta, np.asarray(theta, dtype=np.float64))
+        lst = C.byref(self._list) if listed else None
         _check(lib().ckv_soft_backward(C.byref(self._segs), C.byref(self._showers), C.byref(self.params),
                                        atmo.handle, self.tels.handle, C.c_void_p(self.n_b.data_ptr()),
                                        C.c_void_p(gS.data_ptr()), C.c_void_p(gA.data_ptr()),
                                        C.c_void_p(self.g_psi.data_ptr()), C.c_void_p(self.g_P.data_ptr()),
-                                       C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                       lst, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                        _stream_ptr(stream)))
         return self.g_psi, self.g_P
+
+    def grow_list(self) -> bool:
+        """After a forward: enlarge the list if it was too small (synchronises);
+        True when it was, so the next forward records a complete list."""
+        if not self.use_list:
+            return False
+        n, cap = self.list_state()
+        if 0 <= n <= cap:
+            return False
+        if n >= (1 << 62):
+            self.use_list = False       # ids beyond the packed range: recompute everything
+            return True
+        self._alloc_list(int(n * 1.25) + 1024)
+        return True
 
     def backward(self, theta, gS, gA, stream=None) -> np.ndarray:
         import torch
         g_psi, g_P = self.backward_tables(theta, gS, gA, stream)
         torch.cuda.synchronize()
+        self.grow_list()
         return self.spec.backward(theta, self._atmo(theta), g_psi.cpu().numpy(), g_P.cpu().numpy())
 
 

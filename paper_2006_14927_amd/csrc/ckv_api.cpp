@@ -497,16 +497,32 @@ static int soft_common(const ckv_segments* segs, const ckv_showers* showers,
     return CKV_OK;
 }
 
+static int check_list(const ckv_soft_list* list)
+{
+    if (list && (list->capacity < 0 || !list->count || (list->capacity > 0 && !list->ids))) {
+        set_error("soft list: need capacity >= 0, count and (capacity > 0) ids");
+        return CKV_ERR_ARG;
+    }
+    return CKV_OK;
+}
+
 int ckv_soft_forward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
                      const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
-                     double* S, double* A, void* workspace, size_t ws_bytes, void* stream)
+                     double* S, double* A, const ckv_soft_list* list, void* workspace,
+                     size_t ws_bytes, void* stream)
 {
     RunPlan plan{};
     if (int rc = soft_common(segs, showers, params, atmo, arr, n_b_frozen, workspace, ws_bytes,
                              stream, &plan))
         return rc;
     if (!S || !A) { set_error("NULL output"); return CKV_ERR_ARG; }
+    if (int rc = check_list(list)) return rc;
     SoftPlan sp{};
+    if (list) {
+        sp.ids = list->ids;
+        sp.ids_cap = list->capacity;
+        sp.ids_count = list->count;
+    }
     sp.n_b_frozen = n_b_frozen;
     sp.sigma = arr->soft_sigma;
     sp.S = S;
@@ -517,14 +533,20 @@ int ckv_soft_forward(const ckv_segments* segs, const ckv_showers* showers, const
 int ckv_soft_backward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
                       const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
                       const double* dL_dS, const double* dL_dA, double* g_psi, double* g_P,
-                      void* workspace, size_t ws_bytes, void* stream)
+                      const ckv_soft_list* list, void* workspace, size_t ws_bytes, void* stream)
 {
     RunPlan plan{};
     if (int rc = soft_common(segs, showers, params, atmo, arr, n_b_frozen, workspace, ws_bytes,
                              stream, &plan))
         return rc;
     if (!dL_dS || !dL_dA || !g_psi || !g_P) { set_error("NULL argument"); return CKV_ERR_ARG; }
+    if (int rc = check_list(list)) return rc;
     SoftPlan sp{};
+    if (list) {
+        sp.ids = list->ids;
+        sp.ids_cap = list->capacity;
+        sp.ids_count = list->count;
+    }
     sp.n_b_frozen = n_b_frozen;
     sp.sigma = arr->soft_sigma;
     sp.gS = dL_dS;

@@ -175,6 +175,9 @@ struct SoftPlan {
     double* A;
     double* g_psi;          // backward outputs (n_nodes)
     double* g_P;            // backward outputs (5 x n_nodes)
+    uint64_t* ids;          // bunch list (NULL: none)
+    int64_t ids_cap;
+    int64_t* ids_count;
 };
 int launch_soft(RunPlan& plan, const SoftPlan& sp, int mode);
 

@@ -1434,7 +1434,23 @@ struct SoftArgs {
     const int32_t* cell_off;
     const uint16_t* cell_list;
     const uint2* cell_ent;      // per cell: {offset, count | first sphere << 16}
+    // list of the bunches with a nonzero weight: written by the forward, read by the
+    // adjoint (ids (step << kSoftIdBits) | k; count > capacity: incomplete)
+    uint64_t* ids;
+    int64_t ids_cap;
+    int64_t* ids_count;
+    int32_t skip_if_listed;     // adjoint tile kernel: exit when the list is complete
 };
+
+constexpr int kSoftIdBits = 24;                          // bunch index bits of a list id
+constexpr int kSoftListChunk = 512;                      // list slots claimed per atomic
+constexpr unsigned long long kSoftListInvalid = 1ull << 62;   // or-ed into the count
+
+__device__ __forceinline__ bool soft_list_complete(const SoftArgs& sa)
+{
+    const int64_t n = *sa.ids_count;
+    return n >= 0 && n <= sa.ids_cap;
+}
 
 struct alignas(16) SoftStep {
     double x0, y0, h0, t0, u, v, w;
@@ -1526,10 +1542,227 @@ __device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, Sof
     return true;
 }
 
+// One bunch k of a soft-response step e (its random numbers from the counter
+// (k, seg_id, shower_id, 0)): emission, propagation and the soft weights over
+// the candidate spheres.  MODE 0 adds photons * Phi and photons * Phi * t into
+// acc (LDS, S then A per telescope); MODE 1 runs the adjoint of the bunch into
+// the table bins and g_psi0 and returns the step-level adjoints (dL/dcos_t,
+// dL/dsin_t, dL/dphotons) in o_cos, o_sin, o_phot.  Returns true when some
+// sphere has z >= -kSoftZCut, i.e. the bunch enters S, A and the gradient.
+template <int MODE, typename AddBin>
+__device__ __forceinline__ bool soft_bunch(const Args& a, const SoftArgs& sa, const SoftStep& e,
+                                           int32_t k, uint32_t seg_id, uint32_t shower_id, int s,
+                                           double t_ref, const double* tsh, double* acc,
+                                           AddBin& add_bin, double inv_nobs, double half_inv_nobs3,
+                                           double& g_psi0, double& o_cos, double& o_sin,
+                                           double& o_phot)
+{
+    const int N = a.n_nodes;
+    constexpr double a1 = -0.5, a2 = 0.375, a3 = -0.3125, a4 = 0.2734375;
+    const double ak[5] = {1.0, a1, a2, a3, a4};
+    const double inv_c = 1.0 / kSpeedOfLight;
+    constexpr double inv_sqrt2 = 0.70710678118654752440;
+    constexpr double inv_sqrt2pi = 0.39894228040143267794;
+    uint32_t r[4];
+    philox4x32_10((uint32_t)k, seg_id, shower_id, 0u, a.key0, a.key1, r);
+    const double u0 = ((double)r[0] + 0.5) * 2.3283064365386963e-10;
+    const double s_along = ((double)k + u0) * e.ds;
+    const double xe = e.x0 + s_along * e.u;
+    const double ye = e.y0 + s_along * e.v;
+    const double he = e.h0 - s_along * e.w;
+    const double te = e.t0 + s_along * e.inv_bc;
+    double sp, cp;
+    sincos_turns64(r[1], sp, cp);
+    const double Ex = cp * e.b1x + sp * e.b2x;
+    const double Ey = cp * e.b1y + sp * e.b2y;
+    const double Ez = cp * e.b1z + sp * e.b2z;
+    const double pu = e.cos_t * e.u + e.sin_t * Ex;
+    const double pv = e.cos_t * e.v + e.sin_t * Ey;
+    const double pw = e.cos_t * e.w - e.sin_t * Ez;
+    if (he < a.h_obs || he >= a.h_top || pw <= a.w_min) return false;
+    // atmosphere at emission
+    const double x = (he - a.h_obs) * a.inv_step;
+    int ie = (int)x;
+    ie = min(ie, N - 2);
+    const double fe = x - (double)ie;
+    const double* nd = a.node64 + (size_t)kNode64 * ie;
+    const double pa = nd[0], pb = nd[kNode64];
+    const double psi_e = pa + fe * (pb - pa);
+    const double dz = fe * a.step;
+    const double dh = he - a.h_obs;
+    // D_k = int (psi - psi_e)^k dh: node moments shifted to psi_e (Pascal
+    // triangle, P_0(h_i) = h_i - h_obs) plus the in-cell part of the linear
+    // profile, dz (psi_i - psi_e)^k / (k+1)
+    const double c = -psi_e, del = pa - psi_e;
+    double X1 = nd[1], X2 = nd[2], X3 = nd[3], X4 = nd[4], X5 = nd[5];
+    const double X0 = (double)ie * a.step;
+    X5 += c * X4; X4 += c * X3; X3 += c * X2; X2 += c * X1; X1 += c * X0;
+    X5 += c * X4; X4 += c * X3; X3 += c * X2; X2 += c * X1;
+    X5 += c * X4; X4 += c * X3; X3 += c * X2;
+    X5 += c * X4; X4 += c * X3;
+    X5 += c * X4;
+    const double dl2 = del * del, dl3 = dl2 * del, dl4 = dl3 * del;
+    double D[6];
+    D[0] = dh;
+    D[1] = X1 + dz * 0.5 * del;
+    D[2] = X2 + dz * (1.0 / 3.0) * dl2;
+    D[3] = X3 + dz * 0.25 * dl3;
+    D[4] = X4 + dz * 0.2 * dl4;
+    D[5] = X5 + dz * (1.0 / 6.0) * (dl4 * del);
+    const double ne2 = 1.0 + psi_e;
+    const double ne = sqrt(ne2);
+    const double inv_ne = rcp64(ne), inv_pw = rcp64(pw);
+    const double q = (inv_pw * inv_pw) * (inv_ne * inv_ne);
+    const double Sser = D[0] + q * (a1 * D[1] + q * (a2 * D[2] + q * (a3 * D[3] + q * a4 * D[4])));
+    const double U = (ne2 * D[0] + D[1]) +
+                     q * (a1 * (ne2 * D[1] + D[2]) +
+                          q * (a2 * (ne2 * D[2] + D[3]) +
+                               q * (a3 * (ne2 * D[3] + D[4]) + q * a4 * (ne2 * D[4] + D[5]))));
+    const double T = U * inv_ne * inv_pw * inv_c;
+    const double adv = Sser * inv_pw;
+    const double xg = xe + pu * adv;
+    const double yg = ye + pv * adv;
+    const double tt = te + T - t_ref;
+    const double uo = pu * ne * inv_nobs;
+    const double vo = pv * ne * inv_nobs;
+    const double p = e.photons;
+
+    // soft weights over candidate spheres
+    double g_xg = 0, g_yg = 0, g_uo = 0, g_vo = 0, g_t = 0, g_p = 0;
+    bool seen = false;
+    int cur = 0, cend = 0;
+    int first = -1;          // the cell's first sphere, known without a list read
+    bool brute = false;
+    const double wo2 = 1.0 - uo * uo - vo * vo;
+    if (wo2 >= kLevelW2[0]) {
+        const double fx = (xg - sa.gx0) * sa.inv_cell, fy = (yg - sa.gy0) * sa.inv_cell;
+        if (fx >= 0.0 && fy >= 0.0 && fx < (double)sa.nx && fy < (double)sa.ny) {
+            const int cidx = grid_level(wo2) * sa.level_cells + (int)fx * sa.ny + (int)fy;
+            const uint2 ce = sa.cell_ent[cidx];
+            cur = (int)ce.x;
+            cend = cur + (int)(ce.y & 0xFFFFu);
+            first = (int)(ce.y >> 16);
+        }
+    } else {
+        brute = true;
+        cend = a.n_tel;
+    }
+    for (; cur < cend; ++cur) {
+        const int kt = brute ? cur : (first >= 0 ? first : (int)sa.cell_list[cur]);
+        first = -1;
+        const double* tp = tsh + 4 * kt;                  // LDS
+        const double dx = xg - tp[0], dy = yg - tp[1];
+        const double b = dx * uo + dy * vo;
+        const double rho2 = dx * dx + dy * dy - b * b;
+        const double z = (tp[2] - rho2) * tp[3];
+        if (z < -kSoftZCut) continue;
+        seen = true;
+        const double W = 0.5 * erfc(-z * inv_sqrt2);
+        if (MODE == 0) {
+            atomicAdd(&acc[kt], p * W);
+            atomicAdd(&acc[a.n_tel + kt], p * W * tt);
+        } else {
+            const double gSk = sa.gS[(int64_t)s * a.n_tel + kt];
+            const double gAk = sa.gA[(int64_t)s * a.n_tel + kt];
+            g_p += gSk * W + gAk * W * tt;
+            g_t += gAk * p * W;
+            const double g_z = (gSk * p + gAk * p * tt) * inv_sqrt2pi * exp(-0.5 * z * z);
+            const double g_r2 = -g_z * tp[3];
+            g_xg += g_r2 * (2.0 * dx - 2.0 * b * uo);
+            g_yg += g_r2 * (2.0 * dy - 2.0 * b * vo);
+            g_uo += g_r2 * (-2.0 * b * dx);
+            g_vo += g_r2 * (-2.0 * b * dy);
+        }
+    }
+    if (MODE == 1 && (g_xg != 0.0 || g_yg != 0.0 || g_uo != 0.0 || g_vo != 0.0 || g_t != 0.0 ||
+                      g_p != 0.0)) {
+        // ---- reverse through propagation
+        double g_pu = g_uo * ne * inv_nobs + g_xg * adv;
+        double g_pv = g_vo * ne * inv_nobs + g_yg * adv;
+        double g_ne = (g_uo * pu + g_vo * pv) * inv_nobs;
+        // n_obs = sqrt(1 + psi_0): d(1/n_obs)/d psi_0 = -1 / (2 n_obs^3)
+        g_psi0 -= (g_uo * pu + g_vo * pv) * ne * half_inv_nobs3;
+        const double g_U = g_t * inv_c * inv_ne * inv_pw;
+        g_ne -= g_t * T * inv_ne;
+        double g_pw = -g_t * T * inv_pw;
+        const double XS = g_xg * pu + g_yg * pv;
+        const double g_S = XS * inv_pw;
+        g_pw -= XS * adv * inv_pw;
+        const double qk[5] = {1.0, q, q * q, q * q * q, q * q * q * q};
+        double gD[6] = {0, 0, 0, 0, 0, 0};
+        double g_q = 0.0;
+        for (int kk = 0; kk < 5; ++kk) {
+            const double akq = ak[kk] * qk[kk];
+            gD[kk] += g_S * akq + g_U * akq * ne2;
+            gD[kk + 1] += g_U * akq;
+            if (kk >= 1)
+                g_q += (g_S * D[kk] + g_U * (ne2 * D[kk] + D[kk + 1])) * (double)kk * ak[kk] * qk[kk - 1];
+        }
+        double g_ne2 = g_U * Sser;
+        g_ne2 -= g_q * q * inv_ne * inv_ne;
+        g_pw -= 2.0 * g_q * q * inv_pw;
+        g_ne2 += g_ne * 0.5 * inv_ne;
+        // D_k as a function of (P_j(h_i), psi_i, psi_e):
+        //   dD_k/dpsi_e = -k D_{k-1} + dz del^(k-1) / (k+1)
+        //   dD_k/dpsi_i = dz k del^(k-1) / (k+1)
+        const double dpow[5] = {1.0, del, dl2, dl3, dl4};
+        double g_psie = g_ne2, g_pa = 0.0;
+#pragma unroll
+        for (int kk = 1; kk <= 5; ++kk) {
+            const double inc = dz * dpow[kk - 1] * (1.0 / (double)(kk + 1));
+            g_psie += gD[kk] * (inc - (double)kk * D[kk - 1]);
+            g_pa += gD[kk] * ((double)kk * inc);
+        }
+        // dL/dP_j(h_i): the Pascal shift transposed
+        double G1 = gD[1], G2 = gD[2], G3 = gD[3], G4 = gD[4], G5 = gD[5];
+        G4 += c * G5;
+        G3 += c * G4; G4 += c * G5;
+        G2 += c * G3; G3 += c * G4; G4 += c * G5;
+        G1 += c * G2; G2 += c * G3; G3 += c * G4; G4 += c * G5;
+        G1 += c * G2; G2 += c * G3; G3 += c * G4; G4 += c * G5;
+        add_bin(1, ie, G1);
+        add_bin(2, ie, G2);
+        add_bin(3, ie, G3);
+        add_bin(4, ie, G4);
+        add_bin(5, ie, G5);
+        add_bin(0, ie, g_pa + (1.0 - fe) * g_psie);
+        add_bin(0, ie + 1, fe * g_psie);
+        // ---- reverse through the direction on the cone and the yield
+        const double g_cos = g_pu * e.u + g_pv * e.v + g_pw * e.w;
+        const double g_sin = g_pu * Ex + g_pv * Ey - g_pw * Ez;
+        o_cos = g_cos;
+        o_sin = g_sin;
+        o_phot = g_p;
+    }
+    return seen;
+}
+
+// Step-level part of the soft adjoint: dL/dcos_t, dL/dsin_t and dL/dphotons of
+// bunches of step es to dL/dpsi at the two table nodes around the step's
+// midpoint (cos_t = g1^(-1/2), sin^2 = 1 - 1/g1, g1 = (1 - r^2) n^2; linear in
+// the three inputs, so per-bunch and per-step application agree).
+template <typename AddBin>
+__device__ __forceinline__ void soft_step_reverse(const SoftStep& es, double g_cos, double g_sin,
+                                                  double g_phot, AddBin& add_bin)
+{
+    const double sin2 = es.sin_t * es.sin_t;
+    double g_sin2 = g_phot * es.kl_nb;
+    if (sin2 > 0.0) g_sin2 += g_sin / (2.0 * es.sin_t);
+    const double g_g1 = -0.5 * g_cos * es.cos_t * es.cos_t * es.cos_t + g_sin2 / (es.g1 * es.g1);
+    const double g_psim = g_g1 * (1.0 - es.r2);
+    if (g_psim != 0.0) {
+        add_bin(0, es.i_m, (1.0 - es.f_m) * g_psim);
+        add_bin(0, es.i_m + 1, es.f_m * g_psim);
+    }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args a, SoftArgs sa)
 {
     extern __shared__ __align__(16) unsigned char lds[];
+    // adjoint with a list from the forward: soft_list_kernel does the work unless
+    // the list is incomplete (the same decision in every thread of the grid)
+    if (MODE == 1 && sa.skip_if_listed && soft_list_complete(sa)) return;
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     const int N = a.n_nodes;
@@ -1559,17 +1792,14 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
         else atomicAdd(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
     };
 
-    const double a1 = -0.5, a2 = 0.375, a3 = -0.3125, a4 = 0.2734375;
-    const double ak[5] = {1.0, a1, a2, a3, a4};
-    const double inv_c = 1.0 / kSpeedOfLight;
-    const double inv_sqrt2 = 0.70710678118654752440;
-    const double inv_sqrt2pi = 0.39894228040143267794;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t le_mask = lt_mask | (1ull << lane);
     const double inv_nobs = 1.0 / a.n_obs;
     const double half_inv_nobs3 = 0.5 * inv_nobs * inv_nobs * inv_nobs;
     double g_psi0 = 0.0;
     const int64_t n_tiles = a.ctrl[kNumTiles];
+    int64_t lst_base = -1;       // the wave's current list chunk (-1: none) and its fill
+    int lst_fill = 0;
 
     for (;;) {
         int64_t t = 0;
@@ -1622,177 +1852,57 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
             const uint64_t starts = __ballot(flags[lane] != 0);
             flags[lane] = 0;
             const int si = cnt0 - 1 + __popcll(starts & le_mask);
-            if (!active) continue;
-            SoftStep& e = stash[si];
-            const int32_t k = j - e.boff;
-            uint32_t r[4];
-            philox4x32_10((uint32_t)k, (uint32_t)(seg_id0 + e.sidx), shower_id, 0u, a.key0, a.key1, r);
-            const double u0 = ((double)r[0] + 0.5) * 2.3283064365386963e-10;
-            const double s_along = ((double)k + u0) * e.ds;
-            const double xe = e.x0 + s_along * e.u;
-            const double ye = e.y0 + s_along * e.v;
-            const double he = e.h0 - s_along * e.w;
-            const double te = e.t0 + s_along * e.inv_bc;
-            double sp, cp;
-            sincos_turns64(r[1], sp, cp);
-            const double Ex = cp * e.b1x + sp * e.b2x;
-            const double Ey = cp * e.b1y + sp * e.b2y;
-            const double Ez = cp * e.b1z + sp * e.b2z;
-            const double pu = e.cos_t * e.u + e.sin_t * Ex;
-            const double pv = e.cos_t * e.v + e.sin_t * Ey;
-            const double pw = e.cos_t * e.w - e.sin_t * Ez;
-            if (he < a.h_obs || he >= a.h_top || pw <= a.w_min) continue;
-            // atmosphere at emission
-            const double x = (he - a.h_obs) * a.inv_step;
-            int ie = (int)x;
-            ie = min(ie, N - 2);
-            const double fe = x - (double)ie;
-            const double* nd = a.node64 + (size_t)kNode64 * ie;
-            const double pa = nd[0], pb = nd[kNode64];
-            const double psi_e = pa + fe * (pb - pa);
-            const double dz = fe * a.step;
-            const double dh = he - a.h_obs;
-            // D_k = int (psi - psi_e)^k dh: node moments shifted to psi_e (Pascal
-            // triangle, P_0(h_i) = h_i - h_obs) plus the in-cell part of the linear
-            // profile, dz (psi_i - psi_e)^k / (k+1)
-            const double c = -psi_e, del = pa - psi_e;
-            double X1 = nd[1], X2 = nd[2], X3 = nd[3], X4 = nd[4], X5 = nd[5];
-            const double X0 = (double)ie * a.step;
-            X5 += c * X4; X4 += c * X3; X3 += c * X2; X2 += c * X1; X1 += c * X0;
-            X5 += c * X4; X4 += c * X3; X3 += c * X2; X2 += c * X1;
-            X5 += c * X4; X4 += c * X3; X3 += c * X2;
-            X5 += c * X4; X4 += c * X3;
-            X5 += c * X4;
-            const double dl2 = del * del, dl3 = dl2 * del, dl4 = dl3 * del;
-            double D[6];
-            D[0] = dh;
-            D[1] = X1 + dz * 0.5 * del;
-            D[2] = X2 + dz * (1.0 / 3.0) * dl2;
-            D[3] = X3 + dz * 0.25 * dl3;
-            D[4] = X4 + dz * 0.2 * dl4;
-            D[5] = X5 + dz * (1.0 / 6.0) * (dl4 * del);
-            const double ne2 = 1.0 + psi_e;
-            const double ne = sqrt(ne2);
-            const double inv_ne = rcp64(ne), inv_pw = rcp64(pw);
-            const double q = (inv_pw * inv_pw) * (inv_ne * inv_ne);
-            const double Sser = D[0] + q * (a1 * D[1] + q * (a2 * D[2] + q * (a3 * D[3] + q * a4 * D[4])));
-            const double U = (ne2 * D[0] + D[1]) +
-                             q * (a1 * (ne2 * D[1] + D[2]) +
-                                  q * (a2 * (ne2 * D[2] + D[3]) +
-                                       q * (a3 * (ne2 * D[3] + D[4]) + q * a4 * (ne2 * D[4] + D[5]))));
-            const double T = U * inv_ne * inv_pw * inv_c;
-            const double adv = Sser * inv_pw;
-            const double xg = xe + pu * adv;
-            const double yg = ye + pv * adv;
-            const double tt = te + T - t_ref;
-            const double uo = pu * ne * inv_nobs;
-            const double vo = pv * ne * inv_nobs;
-            const double p = e.photons;
-
-            // soft weights over candidate spheres
-            double g_xg = 0, g_yg = 0, g_uo = 0, g_vo = 0, g_t = 0, g_p = 0;
-            int cur = 0, cend = 0;
-            int first = -1;          // the cell's first sphere, known without a list read
-            bool brute = false;
-            const double wo2 = 1.0 - uo * uo - vo * vo;
-            if (wo2 >= kLevelW2[0]) {
-                const double fx = (xg - sa.gx0) * sa.inv_cell, fy = (yg - sa.gy0) * sa.inv_cell;
-                if (fx >= 0.0 && fy >= 0.0 && fx < (double)sa.nx && fy < (double)sa.ny) {
-                    const int cidx = grid_level(wo2) * sa.level_cells + (int)fx * sa.ny + (int)fy;
-                    const uint2 ce = sa.cell_ent[cidx];
-                    cur = (int)ce.x;
-                    cend = cur + (int)(ce.y & 0xFFFFu);
-                    first = (int)(ce.y >> 16);
-                }
-            } else {
-                brute = true;
-                cend = a.n_tel;
-            }
-            for (; cur < cend; ++cur) {
-                const int kt = brute ? cur : (first >= 0 ? first : (int)sa.cell_list[cur]);
-                first = -1;
-                const double* tp = tsh + 4 * kt;                  // LDS
-                const double dx = xg - tp[0], dy = yg - tp[1];
-                const double b = dx * uo + dy * vo;
-                const double rho2 = dx * dx + dy * dy - b * b;
-                const double z = (tp[2] - rho2) * tp[3];
-                if (z < -kSoftZCut) continue;
-                const double W = 0.5 * erfc(-z * inv_sqrt2);
-                if (MODE == 0) {
-                    atomicAdd(&acc[kt], p * W);
-                    atomicAdd(&acc[a.n_tel + kt], p * W * tt);
-                } else {
-                    const double gSk = sa.gS[(int64_t)s * a.n_tel + kt];
-                    const double gAk = sa.gA[(int64_t)s * a.n_tel + kt];
-                    g_p += gSk * W + gAk * W * tt;
-                    g_t += gAk * p * W;
-                    const double g_z = (gSk * p + gAk * p * tt) * inv_sqrt2pi * exp(-0.5 * z * z);
-                    const double g_r2 = -g_z * tp[3];
-                    g_xg += g_r2 * (2.0 * dx - 2.0 * b * uo);
-                    g_yg += g_r2 * (2.0 * dy - 2.0 * b * vo);
-                    g_uo += g_r2 * (-2.0 * b * dx);
-                    g_vo += g_r2 * (-2.0 * b * dy);
+            bool seen = false;
+            if (active) {
+                SoftStep& e = stash[si];
+                const int32_t k = j - e.boff;
+                double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
+                seen = soft_bunch<MODE>(a, sa, e, k, (uint32_t)(seg_id0 + e.sidx), shower_id, s, t_ref,
+                                        tsh, acc, add_bin, inv_nobs, half_inv_nobs3, g_psi0, o_cos,
+                                        o_sin, o_phot);
+                if (MODE == 1 && (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)) {
+                    atomicAdd(&e.g_cos, o_cos);
+                    atomicAdd(&e.g_sin, o_sin);
+                    atomicAdd(&e.g_phot, o_phot);
                 }
             }
-            if (MODE == 1 && (g_xg != 0.0 || g_yg != 0.0 || g_uo != 0.0 || g_vo != 0.0 || g_t != 0.0 ||
-                              g_p != 0.0)) {
-                // ---- reverse through propagation
-                double g_pu = g_uo * ne * inv_nobs + g_xg * adv;
-                double g_pv = g_vo * ne * inv_nobs + g_yg * adv;
-                double g_ne = (g_uo * pu + g_vo * pv) * inv_nobs;
-                // n_obs = sqrt(1 + psi_0): d(1/n_obs)/d psi_0 = -1 / (2 n_obs^3)
-                g_psi0 -= (g_uo * pu + g_vo * pv) * ne * half_inv_nobs3;
-                const double g_U = g_t * inv_c * inv_ne * inv_pw;
-                g_ne -= g_t * T * inv_ne;
-                double g_pw = -g_t * T * inv_pw;
-                const double XS = g_xg * pu + g_yg * pv;
-                const double g_S = XS * inv_pw;
-                g_pw -= XS * adv * inv_pw;
-                const double qk[5] = {1.0, q, q * q, q * q * q, q * q * q * q};
-                double gD[6] = {0, 0, 0, 0, 0, 0};
-                double g_q = 0.0;
-                for (int kk = 0; kk < 5; ++kk) {
-                    const double akq = ak[kk] * qk[kk];
-                    gD[kk] += g_S * akq + g_U * akq * ne2;
-                    gD[kk + 1] += g_U * akq;
-                    if (kk >= 1)
-                        g_q += (g_S * D[kk] + g_U * (ne2 * D[kk] + D[kk + 1])) * (double)kk * ak[kk] * qk[kk - 1];
+            if (MODE == 0 && sa.ids_count) {
+                // the list the adjoint reads back: each wave fills chunks of
+                // kSoftListChunk slots, claimed with one atomic each (every lane
+                // keeps the same chunk state)
+                const uint64_t m = __ballot(seen);
+                if (m) {
+                    const int cnt = __popcll(m);
+                    const int room = lst_base >= 0 ? kSoftListChunk - lst_fill : 0;
+                    int64_t fresh = -1;
+                    if (cnt > room) {
+                        unsigned long long v = 0;
+                        if (lane == 0)
+                            v = atomicAdd((unsigned long long*)sa.ids_count, (unsigned long long)kSoftListChunk);
+                        fresh = (int64_t)__shfl(v, 0);
+                    }
+                    if (seen) {
+                        // bunch and step read back from the stash, not kept live
+                        const SoftStep& e = stash[si];
+                        const int32_t k = j - e.boff;
+                        const int64_t step_i = g0 + e.sidx;
+                        const int rank = __popcll(m & lt_mask);
+                        if ((uint32_t)k >= (1u << kSoftIdBits) ||
+                            (uint64_t)step_i >= (1ull << (64 - kSoftIdBits))) {
+                            atomicOr((unsigned long long*)sa.ids_count, kSoftListInvalid);
+                        } else {
+                            const int64_t slot = rank < room ? lst_base + lst_fill + rank : fresh + (rank - room);
+                            if (slot < sa.ids_cap)
+                                sa.ids[slot] = ((uint64_t)step_i << kSoftIdBits) | (uint64_t)(uint32_t)k;
+                        }
+                    }
+                    if (cnt > room) {
+                        lst_base = fresh;
+                        lst_fill = cnt - room;
+                    } else {
+                        lst_fill += cnt;
+                    }
                 }
-                double g_ne2 = g_U * Sser;
-                g_ne2 -= g_q * q * inv_ne * inv_ne;
-                g_pw -= 2.0 * g_q * q * inv_pw;
-                g_ne2 += g_ne * 0.5 * inv_ne;
-                // D_k as a function of (P_j(h_i), psi_i, psi_e):
-                //   dD_k/dpsi_e = -k D_{k-1} + dz del^(k-1) / (k+1)
-                //   dD_k/dpsi_i = dz k del^(k-1) / (k+1)
-                const double dpow[5] = {1.0, del, dl2, dl3, dl4};
-                double g_psie = g_ne2, g_pa = 0.0;
-#pragma unroll
-                for (int kk = 1; kk <= 5; ++kk) {
-                    const double inc = dz * dpow[kk - 1] * (1.0 / (double)(kk + 1));
-                    g_psie += gD[kk] * (inc - (double)kk * D[kk - 1]);
-                    g_pa += gD[kk] * ((double)kk * inc);
-                }
-                // dL/dP_j(h_i): the Pascal shift transposed
-                double G1 = gD[1], G2 = gD[2], G3 = gD[3], G4 = gD[4], G5 = gD[5];
-                G4 += c * G5;
-                G3 += c * G4; G4 += c * G5;
-                G2 += c * G3; G3 += c * G4; G4 += c * G5;
-                G1 += c * G2; G2 += c * G3; G3 += c * G4; G4 += c * G5;
-                G1 += c * G2; G2 += c * G3; G3 += c * G4; G4 += c * G5;
-                add_bin(1, ie, G1);
-                add_bin(2, ie, G2);
-                add_bin(3, ie, G3);
-                add_bin(4, ie, G4);
-                add_bin(5, ie, G5);
-                add_bin(0, ie, g_pa + (1.0 - fe) * g_psie);
-                add_bin(0, ie + 1, fe * g_psie);
-                // ---- reverse through the direction on the cone and the yield
-                const double g_cos = g_pu * e.u + g_pv * e.v + g_pw * e.w;
-                const double g_sin = g_pu * Ex + g_pv * Ey - g_pw * Ez;
-                atomicAdd(&e.g_cos, g_cos);
-                atomicAdd(&e.g_sin, g_sin);
-                atomicAdd(&e.g_phot, g_p);
             }
         }
         wave_lds_sync();
@@ -1807,18 +1917,16 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
         } else if (emits) {
             // ---- reverse through the step setup (index at the step midpoint)
             const SoftStep& es = stash[__popcll(emit_mask & lt_mask)];
-            const double sin2 = es.sin_t * es.sin_t;
-            double g_sin2 = es.g_phot * es.kl_nb;
-            if (sin2 > 0.0) g_sin2 += es.g_sin / (2.0 * es.sin_t);
-            // cos_t = g1^(-1/2), sin2 = 1 - 1/g1
-            const double g_g1 = -0.5 * es.g_cos * es.cos_t * es.cos_t * es.cos_t + g_sin2 / (es.g1 * es.g1);
-            const double g_psim = g_g1 * (1.0 - es.r2);
-            if (g_psim != 0.0) {
-                add_bin(0, es.i_m, (1.0 - es.f_m) * g_psim);
-                add_bin(0, es.i_m + 1, es.f_m * g_psim);
-            }
+            soft_step_reverse(es, es.g_cos, es.g_sin, es.g_phot, add_bin);
         }
         wave_lds_sync();
+    }
+    if (MODE == 0 && sa.ids_count && lst_base >= 0) {
+        // the rest of the wave's last chunk: an id that names no bunch
+        for (int q = lst_fill + lane; q < kSoftListChunk; q += kWave) {
+            const int64_t slot = lst_base + q;
+            if (slot < sa.ids_cap) sa.ids[slot] = ~0ull;
+        }
     }
     if (MODE == 1) {
         if (g_psi0 != 0.0) add_bin(0, 0, g_psi0);
@@ -1828,6 +1936,68 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
             const int j = qq / NB, i = qq - j * NB;
             if (v != 0.0) atomicAdd(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
         }
+    }
+}
+
+constexpr int kSoftListThreads = 512;
+
+// Adjoint over the forward's list: one listed bunch per thread, its step set up
+// again (bunch count frozen), the bunch recomputed from its random numbers and
+// reversed into the table bins, the step-level part applied per bunch.  Runs only
+// when the list is complete; ids that do not name a bunch of the inputs are skipped.
+__global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, SoftArgs sa)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    if (!soft_list_complete(sa)) return;
+    const int64_t n_ids = *sa.ids_count;
+    const int N = a.n_nodes;
+    const int NB = soft_bin_nodes(N);
+    double* bins = reinterpret_cast<double*>(lds);               // 6 x NB
+    double* tsh = bins + 6 * NB;                                 // n_tel x {X, Y, R^2, 1 / (2 R sigma)}
+    for (int q = threadIdx.x; q < 6 * NB; q += blockDim.x) bins[q] = 0.0;
+    for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x) {
+        tsh[4 * q] = a.tel[4 * q];
+        tsh[4 * q + 1] = a.tel[4 * q + 1];
+        tsh[4 * q + 2] = a.tel[4 * q + 3];
+        tsh[4 * q + 3] = 1.0 / (2.0 * a.tel[4 * q + 2] * sa.sigma);
+    }
+    __syncthreads();
+    auto add_bin = [&](int j, int i, double v) {
+        if (i < NB) atomicAdd(&bins[j * NB + i], v);
+        else atomicAdd(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
+    };
+    const double inv_nobs = 1.0 / a.n_obs;
+    const double half_inv_nobs3 = 0.5 * inv_nobs * inv_nobs * inv_nobs;
+    double g_psi0 = 0.0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_ids;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t id = sa.ids[q];
+        const int64_t i = (int64_t)(id >> kSoftIdBits);
+        const int32_t k = (int32_t)(id & ((1u << kSoftIdBits) - 1));
+        if (i >= a.n) continue;
+        const int64_t nbf = sa.nb_frozen[i];
+        if (k >= nbf) continue;
+        int lo = 0, hi = a.n_showers;          // the shower holding step i
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.seg_offsets[mid] <= i) lo = mid; else hi = mid;
+        }
+        SoftStep e;
+        if (!soft_step_setup(a, i, nbf, e)) continue;
+        const int64_t seg_id = (a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]);
+        const uint32_t shower_id = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
+        double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
+        soft_bunch<1>(a, sa, e, k, (uint32_t)seg_id, shower_id, lo, a.t_ref[lo], tsh, nullptr,
+                      add_bin, inv_nobs, half_inv_nobs3, g_psi0, o_cos, o_sin, o_phot);
+        if (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)
+            soft_step_reverse(e, o_cos, o_sin, o_phot, add_bin);
+    }
+    if (g_psi0 != 0.0) add_bin(0, 0, g_psi0);
+    __syncthreads();
+    for (int qq = threadIdx.x; qq < 6 * NB; qq += blockDim.x) {
+        const double v = bins[qq];
+        const int j = qq / NB, i = qq - j * NB;
+        if (v != 0.0) atomicAdd(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
     }
 }
 
@@ -2069,6 +2239,10 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     s.cell_off = ar->soft.d_cell_off;
     s.cell_list = ar->soft.d_cell_list;
     s.cell_ent = reinterpret_cast<const uint2*>(ar->soft.d_cell_ent);
+    s.ids = sp.ids;
+    s.ids_cap = sp.ids_cap;
+    s.ids_count = sp.ids_count;
+    s.skip_if_listed = mode == 1 && sp.ids_count ? 1 : 0;
     // as many waves as the kernel's launch bounds allow and the LDS holds
     const int wmax = soft_max_waves(mode);
     int waves = p.emit_waves > 0 && p.emit_waves < wmax ? p.emit_waves : wmax;
@@ -2084,6 +2258,8 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     if (mode == 0) {
         zero_kernel<<<64, 256, 0, st>>>(s.S, nst);
         zero_kernel<<<64, 256, 0, st>>>(s.A, nst);
+        // the list count starts at zero (all-zero bits: 0.0 is integer 0)
+        if (s.ids_count) zero_kernel<<<1, 64, 0, st>>>(reinterpret_cast<double*>(s.ids_count), 1);
     } else {
         zero_kernel<<<64, 256, 0, st>>>(s.g_psi, a.n_nodes);
         zero_kernel<<<64, 256, 0, st>>>(s.g_P, (int64_t)5 * a.n_nodes);
@@ -2104,6 +2280,17 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
             attr = true;
         }
         soft_kernel<1><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
+        if (s.ids_count) {
+            if (int rc = check_launch("soft")) return rc;
+            static bool attr_l = false;
+            if (!attr_l) {
+                (void)hipFuncSetAttribute((const void*)soft_list_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                attr_l = true;
+            }
+            const size_t lds_l = (size_t)6 * soft_bin_nodes(a.n_nodes) * sizeof(double) +
+                                 (size_t)a.n_tel * 4 * sizeof(double);
+            soft_list_kernel<<<2 * p.emit_grid, kSoftListThreads, lds_l, st>>>(a, s);
+        }
     }
     if (int rc = check_launch("soft")) return rc;
     if (p.params.event_end) (void)hipEventRecord((hipEvent_t)p.params.event_end, st);

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_version(L):
-    assert L.ckv_version() == 111
+    assert L.ckv_version() == 112
 
 
 def test_struct_sizes_match_header_layout():
@@ -44,6 +44,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(ckv._Params) == 4 * 8 + 8 + 4 * 4 + 2 * 8 + 8 + 2 * 4 + 8
     assert C.sizeof(ckv._Result) == 5 * 8 + 8 * 8 + 2 * 4
     assert C.sizeof(ckv._Output) == 7 * 8
+    assert C.sizeof(ckv._SoftList) == 3 * 8
 
 
 def _atmo_create(L, alt, eta, obs=2200.0, step=0.0):

@@ -133,3 +133,110 @@ def test_directional_derivative_larger_instance():
         fd = (4.0 * central(h) - central(2 * h)) / 3.0
         say(f"[gpu] directional: g.v={g @ v:.10e} fd={fd:.10e}")
         assert g @ v == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(g * v).sum())
+
+
+def _tables_backward(model, theta, gS, gA):
+    import torch
+    g_psi, g_P = model.backward_tables(theta, gS, gA)
+    torch.cuda.synchronize()
+    return g_psi.cpu().numpy().copy(), g_P.cpu().numpy().copy()
+
+
+def _random_cotangents(model, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    gS = torch.tensor(rng.normal(size=model.shape), dtype=torch.float64, device="cuda")
+    gA = torch.tensor(rng.normal(size=model.shape) * 1e-3, dtype=torch.float64, device="cuda")
+    return gS, gA
+
+
+def _assert_same_gradient(a, b):
+    for x, y in zip(a, b):
+        scale = np.abs(y).max()
+        assert scale > 0
+        np.testing.assert_allclose(x, y, rtol=1e-11, atol=1e-13 * scale)
+
+
+def test_listed_adjoint_equals_full_recompute(small):
+    """The adjoint over the forward's list of weighted bunches gives the gradient
+    of the adjoint that recomputes every bunch (FP64 sums in another order)."""
+    dw, orc, model = small
+    full = gpu_model_nolist(dw)
+    model.forward(dw.theta0)
+    full.forward(dw.theta0)
+    n, cap = model.list_state()
+    nb = int(model.n_b.sum())
+    say(f"[gpu] soft list: {n} slots for {nb} bunches ({n / nb:.3%}), capacity {cap}")
+    assert 0 < n <= cap
+    gS, gA = _random_cotangents(model, 11)
+    _assert_same_gradient(_tables_backward(model, dw.theta0, gS, gA),
+                          _tables_backward(full, dw.theta0, gS, gA))
+
+
+def gpu_model_nolist(dw, **kw):
+    spec = ckv.ParamSpec(dw.eta0, dw.layer_bounds, dw.n_knots, dw.knot_top, dw.obs_level, dw.step,
+                         dw.top)
+    return ckv.SoftModel(dw.segs, dw.tels, spec, dw.theta0, dw.sigma, seed=dw.seed, use_list=False,
+                         **kw)
+
+
+def test_list_is_the_set_of_weighted_bunches(small):
+    """Every listed id names a bunch of the oracle with z >= -40 at some sphere,
+    and every such bunch is listed once (z within 1e-6 of the cut excepted)."""
+    import torch
+    dw, orc, model = small
+    model.forward(dw.theta0)
+    n, cap = model.list_state()
+    assert n % 512 == 0 and n <= cap
+    ids = model.list_ids[:n].cpu().numpy().view(np.uint64)
+    ids = ids[ids != np.uint64(2 ** 64 - 1)]          # unfilled block ends
+    n = len(ids)
+    seg = (ids >> np.uint64(24)).astype(np.int64)
+    k = (ids & np.uint64((1 << 24) - 1)).astype(np.int64)
+    key = seg * (1 << 24) + k
+    assert len(np.unique(key)) == n
+    cfg = orc.cfg(dw.theta0)
+    nb = orc.nb
+    all_seg = np.repeat(np.arange(len(nb)), nb)
+    all_k = np.arange(len(all_seg)) - np.repeat(np.cumsum(nb) - nb, nb)
+    zmax = np.full(len(all_seg), -np.inf)
+    tx, ty, tr = dw.tels.x, dw.tels.y, dw.tels.r
+    for lo in range(0, len(all_seg), 50000):
+        sl = slice(lo, lo + 50000)
+        bd = oracle.bunch_details(cfg, dw.segs, all_seg[sl], all_k[sl])
+        ok = bd["status"] < 0
+        dx = bd["x_g"][:, None] - tx[None, :]
+        dy = bd["y_g"][:, None] - ty[None, :]
+        b = dx * bd["u_o"][:, None] + dy * bd["v_o"][:, None]
+        z = (tr[None, :] ** 2 - (dx * dx + dy * dy - b * b)) / (2.0 * tr[None, :] * dw.sigma)
+        zmax[sl] = np.where(ok, z.max(axis=1), -np.inf)
+    want = zmax >= -40.0
+    okey = all_seg * (1 << 24) + all_k
+    listed = np.isin(okey, key)
+    differ = listed != want
+    assert not np.isin(key, okey, invert=True).any()
+    assert np.all(np.abs(zmax[differ] + 40.0) <= 1e-6), (differ.sum(), zmax[differ][:5])
+    say(f"[gpu] soft list: {n} ids = oracle's weighted bunches ({want.sum()}), {differ.sum()} at the cut")
+
+
+def test_list_overflow_recomputes_everything_then_grows(small):
+    """A list too small for the forward is incomplete: the adjoint recomputes every
+    bunch (same gradient); grow_list enlarges it and the next pass uses it."""
+    dw, orc, model = small
+    spec = ckv.ParamSpec(dw.eta0, dw.layer_bounds, dw.n_knots, dw.knot_top, dw.obs_level, dw.step,
+                         dw.top)
+    m = ckv.SoftModel(dw.segs, dw.tels, spec, dw.theta0, dw.sigma, seed=dw.seed, list_capacity=16)
+    full = gpu_model_nolist(dw)
+    gS, gA = _random_cotangents(m, 12)
+    m.forward(dw.theta0)
+    full.forward(dw.theta0)
+    n, cap = m.list_state()
+    assert cap == 16 and n > cap
+    ref = _tables_backward(full, dw.theta0, gS, gA)
+    _assert_same_gradient(_tables_backward(m, dw.theta0, gS, gA), ref)
+    assert m.grow_list()
+    m.forward(dw.theta0)
+    n2, cap2 = m.list_state()
+    assert cap2 > n and n2 <= cap2
+    _assert_same_gradient(_tables_backward(m, dw.theta0, gS, gA), ref)
+    assert not m.grow_list()
