@@ -327,11 +327,10 @@ int ckv_array_create_soft(const double* x_m, const double* y_m, const double* r_
    some sphere, (global step index << 24) | bunch index k, in no particular
    order.  Written by ckv_soft_forward, read by ckv_soft_backward, which then
    recomputes only these bunches (the others contribute exactly zero).  The
-   caller owns both device buffers.  The forward claims slots in blocks of 512
-   and fills the slots of its last blocks that no bunch takes with 2^64 - 1,
-   which names no bunch; *count is the number of slots claimed.  The list is
-   complete iff 0 <= *count <= capacity (a bunch index of 2^24 or more, or a
-   step index of 2^40 or more, makes it incomplete). */
+   caller owns both device buffers.  *count is the number of such bunches (ids
+   beyond capacity are not written); the list is complete iff
+   0 <= *count <= capacity (a bunch index of 2^24 or more, or a step index of
+   2^40 or more, makes it incomplete). */
 typedef struct {
     uint64_t* ids;        /* device, capacity entries */
     int64_t capacity;     /* >= 0 */

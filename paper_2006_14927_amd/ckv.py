@@ -673,9 +673,7 @@ class SoftModel:
         self.list_count = torch.zeros(1, dtype=torch.int64, device=device)
         self._list_theta = None
         if self.use_list:
-            # an eighth of the bunches, plus the unfilled ends of the forward's
-            # 512-slot blocks (at most one per wave of the launch)
-            cap = list_capacity if list_capacity is not None else int(self.n_b.sum()) // 8 + (1 << 21)
+            cap = list_capacity if list_capacity is not None else int(self.n_b.sum()) // 8 + 1024
             self._alloc_list(int(cap))
 
     def _alloc_list(self, capacity: int):

@@ -1443,7 +1443,6 @@ struct SoftArgs {
 };
 
 constexpr int kSoftIdBits = 24;                          // bunch index bits of a list id
-constexpr int kSoftListChunk = 512;                      // list slots claimed per atomic
 constexpr unsigned long long kSoftListInvalid = 1ull << 62;   // or-ed into the count
 
 __device__ __forceinline__ bool soft_list_complete(const SoftArgs& sa)
@@ -1477,11 +1476,16 @@ __host__ __device__ inline int soft_bin_nodes(int n_nodes)
     return n_nodes < kSoftBinNodes ? n_nodes : kSoftBinNodes;
 }
 
-// per wave: step stash, flag row and (forward only) S, A per telescope
+constexpr int kSoftBitWords = 64;    // list: ballot words kept per wave before a flush
+
+// per wave: step stash, flag row and (forward only) S, A per telescope, the list
+// state {tile's first step, ids, capacity, count} and the ballots of listed
+// bunches of the last kSoftBitWords groups of 64 bunches
 __host__ __device__ inline size_t soft_wave_bytes(int mode, int n_tel)
 {
     return kSoftTS * sizeof(SoftStep) + kWave * sizeof(int32_t) +
-           (mode == 0 ? (size_t)2 * n_tel * sizeof(double) : 0);
+           (mode == 0 ? (size_t)2 * n_tel * sizeof(double) + (4 + kSoftBitWords) * sizeof(int64_t)
+                      : 0);
 }
 
 // per workgroup: adjoint bins, then {X, Y, R^2, 1 / (2 R sigma)} per telescope, then the waves
@@ -1756,7 +1760,62 @@ __device__ __forceinline__ void soft_step_reverse(const SoftStep& es, double g_c
     }
 }
 
-template <int MODE>
+// Soft forward: the listed bunches of ballot words bits[0..nw-1] (bit b of word q:
+// bunch j0 + 64 q + b of the tile) go to the list.  One atomic claims exactly
+// their slots; lane q writes the ids of word q, the step of its first bunch found
+// by binary search over the tile's stash (first-bunch offsets ascend) and the
+// later ones by moving forward from there (the lanes' searches overlap; this
+// measured faster than word-by-word writes with consecutive slots).  lst holds
+// {tile's first step, ids, capacity, count}.  Called by the whole wave.
+__device__ __forceinline__ void soft_list_flush(const int64_t* lst, const uint64_t* bits,
+                                                const SoftStep* stash, int n_emit, int64_t j0,
+                                                int nw, int lane)
+{
+    volatile const int64_t* vl = lst;
+    uint64_t word = lane < nw ? bits[lane] : 0ull;
+    const int c = __popcll(word);
+    const int64_t incl = wave_incl_scan((int64_t)c);
+    const int64_t tot = __shfl(incl, kWave - 1);
+    if (tot == 0) return;
+    unsigned long long* count = (unsigned long long*)vl[3];
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)tot);
+    base = __shfl(base, 0);
+    const int64_t g0 = vl[0], cap = vl[2];
+    uint64_t* ids = (uint64_t*)vl[1];
+    int64_t slot = (int64_t)base + (incl - c);
+    if (!word) return;
+    const int32_t jw = (int32_t)(j0 + kWave * lane);     // bunch of bit 0
+    int32_t jj = jw + __builtin_ctzll(word);
+    int lo = 0, hi = n_emit;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (stash[mid].boff <= jj) lo = mid; else hi = mid;
+    }
+    int32_t boff = stash[lo].boff;
+    int32_t next = lo + 1 < n_emit ? stash[lo + 1].boff : INT_MAX;
+    uint64_t step = (uint64_t)(g0 + stash[lo].sidx);
+    for (;;) {
+        while (jj >= next) {
+            ++lo;
+            boff = next;
+            next = lo + 1 < n_emit ? stash[lo + 1].boff : INT_MAX;
+            step = (uint64_t)(g0 + stash[lo].sidx);
+        }
+        const int32_t k = jj - boff;
+        if ((uint32_t)k >= (1u << kSoftIdBits) || step >= (1ull << (64 - kSoftIdBits)))
+            atomicOr(count, kSoftListInvalid);
+        else if (slot < cap)
+            ids[slot] = (step << kSoftIdBits) | (uint64_t)(uint32_t)k;
+        ++slot;
+        word &= word - 1;
+        if (!word) break;
+        jj = jw + __builtin_ctzll(word);
+    }
+}
+
+// LIST (forward only): also write the list of bunches with a nonzero weight
+template <int MODE, bool LIST>
 __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args a, SoftArgs sa)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -1774,6 +1833,8 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
     SoftStep* stash = reinterpret_cast<SoftStep*>(wbase);
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + kSoftTS * sizeof(SoftStep));
     double* acc = reinterpret_cast<double*>(flags + kWave);     // MODE 0: S then A per telescope
+    int64_t* lst = reinterpret_cast<int64_t*>(acc + 2 * a.n_tel);  // MODE 0: list state
+    uint64_t* bits = reinterpret_cast<uint64_t*>(lst + 4);          // MODE 0: ballot words
     if (MODE == 1)
         for (int q = threadIdx.x; q < 6 * NB; q += blockDim.x) bins[q] = 0.0;
     for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x) {
@@ -1782,8 +1843,17 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
         tsh[4 * q + 2] = a.tel[4 * q + 3];
         tsh[4 * q + 3] = 1.0 / (2.0 * a.tel[4 * q + 2] * sa.sigma);
     }
-    if (MODE == 0)
+    if (MODE == 0) {
         for (int q = lane; q < 2 * a.n_tel; q += kWave) acc[q] = 0.0;
+        if (lane == 0) {
+            // the list arguments are read from here where needed rather than
+            // held in scalar registers across the bunch loop
+            lst[0] = 0;
+            lst[1] = (int64_t)sa.ids;
+            lst[2] = sa.ids_cap;
+            lst[3] = (int64_t)sa.ids_count;
+        }
+    }
     flags[lane] = 0;
     __syncthreads();
     // j = 0: dL/dpsi_i, j = 1..5: dL/dP_j(h_i)
@@ -1798,8 +1868,6 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
     const double half_inv_nobs3 = 0.5 * inv_nobs * inv_nobs * inv_nobs;
     double g_psi0 = 0.0;
     const int64_t n_tiles = a.ctrl[kNumTiles];
-    int64_t lst_base = -1;       // the wave's current list chunk (-1: none) and its fill
-    int lst_fill = 0;
 
     for (;;) {
         int64_t t = 0;
@@ -1819,6 +1887,7 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
         const uint32_t shower_id = a.shower_ids ? a.shower_ids[s] : (uint32_t)s;
         const int64_t seg_id0 = (a.seg_id_base ? a.seg_id_base[s] : 0) + (g0 - sfirst);
         const double t_ref = a.t_ref[s];
+        if (LIST && lane == 0) lst[0] = g0;
 
         SoftStep st;
         int64_t nb = 0;
@@ -1866,42 +1935,17 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
                     atomicAdd(&e.g_phot, o_phot);
                 }
             }
-            if (MODE == 0 && sa.ids_count) {
-                // the list the adjoint reads back: each wave fills chunks of
-                // kSoftListChunk slots, claimed with one atomic each (every lane
-                // keeps the same chunk state)
+            if (LIST) {
+                // the list the adjoint reads back: one ballot word per 64 bunches
+                // in the wave's LDS, written out every kSoftBitWords words and at
+                // the end of the tile
                 const uint64_t m = __ballot(seen);
-                if (m) {
-                    const int cnt = __popcll(m);
-                    const int room = lst_base >= 0 ? kSoftListChunk - lst_fill : 0;
-                    int64_t fresh = -1;
-                    if (cnt > room) {
-                        unsigned long long v = 0;
-                        if (lane == 0)
-                            v = atomicAdd((unsigned long long*)sa.ids_count, (unsigned long long)kSoftListChunk);
-                        fresh = (int64_t)__shfl(v, 0);
-                    }
-                    if (seen) {
-                        // bunch and step read back from the stash, not kept live
-                        const SoftStep& e = stash[si];
-                        const int32_t k = j - e.boff;
-                        const int64_t step_i = g0 + e.sidx;
-                        const int rank = __popcll(m & lt_mask);
-                        if ((uint32_t)k >= (1u << kSoftIdBits) ||
-                            (uint64_t)step_i >= (1ull << (64 - kSoftIdBits))) {
-                            atomicOr((unsigned long long*)sa.ids_count, kSoftListInvalid);
-                        } else {
-                            const int64_t slot = rank < room ? lst_base + lst_fill + rank : fresh + (rank - room);
-                            if (slot < sa.ids_cap)
-                                sa.ids[slot] = ((uint64_t)step_i << kSoftIdBits) | (uint64_t)(uint32_t)k;
-                        }
-                    }
-                    if (cnt > room) {
-                        lst_base = fresh;
-                        lst_fill = cnt - room;
-                    } else {
-                        lst_fill += cnt;
-                    }
+                const int w = (int)((c0 >> 6) & (kSoftBitWords - 1));
+                if (lane == 0) bits[w] = m;
+                if (w == kSoftBitWords - 1 || c0 + kWave >= total) {
+                    wave_lds_sync();
+                    soft_list_flush(lst, bits, stash, __popcll(emit_mask), c0 - (int64_t)w * kWave,
+                                    w + 1, lane);
                 }
             }
         }
@@ -1920,13 +1964,6 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
             soft_step_reverse(es, es.g_cos, es.g_sin, es.g_phot, add_bin);
         }
         wave_lds_sync();
-    }
-    if (MODE == 0 && sa.ids_count && lst_base >= 0) {
-        // the rest of the wave's last chunk: an id that names no bunch
-        for (int q = lst_fill + lane; q < kSoftListChunk; q += kWave) {
-            const int64_t slot = lst_base + q;
-            if (slot < sa.ids_cap) sa.ids[slot] = ~0ull;
-        }
     }
     if (MODE == 1) {
         if (g_psi0 != 0.0) add_bin(0, 0, g_psi0);
@@ -2269,17 +2306,21 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     if (mode == 0) {
         static bool attr = false;
         if (!attr) {
-            (void)hipFuncSetAttribute((const void*)soft_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            (void)hipFuncSetAttribute((const void*)soft_kernel<0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            (void)hipFuncSetAttribute((const void*)soft_kernel<0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
-        soft_kernel<0><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
+        if (s.ids_count)
+            soft_kernel<0, true><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
+        else
+            soft_kernel<0, false><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
     } else {
         static bool attr = false;
         if (!attr) {
-            (void)hipFuncSetAttribute((const void*)soft_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            (void)hipFuncSetAttribute((const void*)soft_kernel<1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             attr = true;
         }
-        soft_kernel<1><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
+        soft_kernel<1, false><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
         if (s.ids_count) {
             if (int rc = check_launch("soft")) return rc;
             static bool attr_l = false;

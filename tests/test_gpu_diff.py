@@ -166,7 +166,7 @@ def test_listed_adjoint_equals_full_recompute(small):
     full.forward(dw.theta0)
     n, cap = model.list_state()
     nb = int(model.n_b.sum())
-    say(f"[gpu] soft list: {n} slots for {nb} bunches ({n / nb:.3%}), capacity {cap}")
+    say(f"[gpu] soft list: {n} of {nb} bunches ({n / nb:.3%}), capacity {cap}")
     assert 0 < n <= cap
     gS, gA = _random_cotangents(model, 11)
     _assert_same_gradient(_tables_backward(model, dw.theta0, gS, gA),
@@ -187,10 +187,8 @@ def test_list_is_the_set_of_weighted_bunches(small):
     dw, orc, model = small
     model.forward(dw.theta0)
     n, cap = model.list_state()
-    assert n % 512 == 0 and n <= cap
+    assert n <= cap
     ids = model.list_ids[:n].cpu().numpy().view(np.uint64)
-    ids = ids[ids != np.uint64(2 ** 64 - 1)]          # unfilled block ends
-    n = len(ids)
     seg = (ids >> np.uint64(24)).astype(np.int64)
     k = (ids & np.uint64((1 << 24) - 1)).astype(np.int64)
     key = seg * (1 << 24) + k
@@ -237,6 +235,6 @@ def test_list_overflow_recomputes_everything_then_grows(small):
     assert m.grow_list()
     m.forward(dw.theta0)
     n2, cap2 = m.list_state()
-    assert cap2 > n and n2 <= cap2
+    assert n2 == n and cap2 > n
     _assert_same_gradient(_tables_backward(m, dw.theta0, gS, gA), ref)
     assert not m.grow_list()
