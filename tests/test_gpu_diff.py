@@ -238,3 +238,26 @@ def test_list_overflow_recomputes_everything_then_grows(small):
     assert n2 == n and cap2 > n
     _assert_same_gradient(_tables_backward(m, dw.theta0, gS, gA), ref)
     assert not m.grow_list()
+
+
+def test_soft_list_argument_validation(small):
+    """A list with negative capacity, no count or no ids (capacity > 0) is refused
+    on the host by both entry points, before any work is queued."""
+    import ctypes as C
+    dw, orc, model = small
+    L = ckv.lib()
+    atmo = model._atmo(dw.theta0)
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    ws = (ptr(model.workspace), model.workspace.numel())
+    S = model.g_psi.new_empty(model.shape)
+    for bad in (ckv._SoftList(model.list_ids.data_ptr(), -1, model.list_count.data_ptr()),
+                ckv._SoftList(model.list_ids.data_ptr(), 10, None),
+                ckv._SoftList(None, 10, model.list_count.data_ptr())):
+        rc = L.ckv_soft_forward(C.byref(model._segs), C.byref(model._showers), C.byref(model.params),
+                                atmo.handle, model.tels.handle, ptr(model.n_b), ptr(S), ptr(S),
+                                C.byref(bad), *ws, None)
+        assert rc == -1 and b"soft list" in L.ckv_last_error()
+        rc = L.ckv_soft_backward(C.byref(model._segs), C.byref(model._showers), C.byref(model.params),
+                                 atmo.handle, model.tels.handle, ptr(model.n_b), ptr(S), ptr(S),
+                                 ptr(model.g_psi), ptr(model.g_P), C.byref(bad), *ws, None)
+        assert rc == -1 and b"soft list" in L.ckv_last_error()
