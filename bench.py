@@ -36,8 +36,7 @@ sys.path.insert(0, ROOT)
 # sin, cos); 4 for an FP64 one (rcp, and the estimate inside a square root).  An
 # operation the chip has as one instruction counts once (an FMA, a three-input XOR
 # such as Philox's hi ^ counter ^ key).  Loop
-# control, addressing and register moves are not counted.  The derivation, step by
-# step, is in the design notes.
+# control, addressing and register moves are not counted.
 OPS_MIXED = {
     "philox4x32-10: 10 rounds x (2 mul32x32->64 + 2 three-input xor)": 40,
     "uniforms u0, u2 (convert + scale)": 4,
@@ -459,7 +458,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
-              "(showers and step ranges shard independently; see the design notes).",
+              "(showers and step ranges would shard independently, one range per GPU).",
               file=sys.stderr)
         return 2
     import numpy as np

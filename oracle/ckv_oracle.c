@@ -11,8 +11,7 @@
  * read against the paper.  Build with -ffp-contract=off (no FMA contraction):
  * bunch counts must come out of the same IEEE operations as on the GPU.
  *
- * Where the paper is silent the following readings are used (each is listed
- * in the design notes of the repository):
+ * Where the paper is silent the following readings are used:
  *  - yield: Frank-Tamm with an index independent of wavelength, expectation
  *    value (no Poisson draw), band [lambda_min, lambda_max];
  *  - one index per step, taken at the step midpoint (yield, threshold, angle);
