@@ -25,7 +25,7 @@
  * values) do not fail the call: they are reported in ckv_result.
  *
  * Ownership: the caller owns every large device buffer (segments, records,
- * offsets, result, workspace).  Handles (ckv_atmo, ckv_array) are immutable
+ * offsets, result, workspace, soft bunch list).  Handles (ckv_atmo, ckv_array) are immutable
  * after creation, own only their small host and device tables, and may be
  * shared by concurrent runs on different streams.  ckv_run is re-entrant
  * given distinct workspaces and outputs.
