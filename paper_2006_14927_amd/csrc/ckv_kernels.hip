@@ -1489,10 +1489,20 @@ __host__ __device__ inline size_t soft_wave_bytes(int mode, int n_tel)
 }
 
 // per workgroup: adjoint bins, then {X, Y, R^2, 1 / (2 R sigma)} per telescope, then the waves
+// node records {psi, P1..P5} of the lowest kSoftNodeLds nodes staged in LDS for the
+// bunch lookups of the forward and of the listed adjoint
+constexpr int kSoftNodeLds = 1024;
+
+__host__ __device__ inline int soft_node_lds(int n_nodes)
+{
+    return n_nodes < kSoftNodeLds ? n_nodes : kSoftNodeLds;
+}
+
 __host__ __device__ inline size_t soft_lds_bytes(int mode, int n_nodes, int n_tel, int waves)
 {
     const size_t bins = mode == 1 ? (size_t)6 * soft_bin_nodes(n_nodes) * sizeof(double) : 0;
-    return bins + (size_t)n_tel * 4 * sizeof(double) + (size_t)waves * soft_wave_bytes(mode, n_tel);
+    const size_t nodes = mode == 0 ? (size_t)kNode64 * soft_node_lds(n_nodes) * sizeof(double) : 0;
+    return bins + (size_t)n_tel * 4 * sizeof(double) + nodes + (size_t)waves * soft_wave_bytes(mode, n_tel);
 }
 
 // step setup with a frozen bunch count; false when the step emits nothing
@@ -1553,11 +1563,13 @@ __device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, Sof
 // the table bins and g_psi0 and returns the step-level adjoints (dL/dcos_t,
 // dL/dsin_t, dL/dphotons) in o_cos, o_sin, o_phot.  Returns true when some
 // sphere has z >= -kSoftZCut, i.e. the bunch enters S, A and the gradient.
-template <int MODE, typename AddBin>
+// NODE_LDS: node records of the lowest n_lds nodes come from node_lds (LDS).
+template <int MODE, bool NODE_LDS, typename AddBin>
 __device__ __forceinline__ bool soft_bunch(const Args& a, const SoftArgs& sa, const SoftStep& e,
                                            int32_t k, uint32_t seg_id, uint32_t shower_id, int s,
                                            double t_ref, const double* tsh, double* acc,
                                            AddBin& add_bin, double inv_nobs, double half_inv_nobs3,
+                                           const double* node_lds, int n_lds,
                                            double& g_psi0, double& o_cos, double& o_sin,
                                            double& o_phot)
 {
@@ -1589,8 +1601,29 @@ __device__ __forceinline__ bool soft_bunch(const Args& a, const SoftArgs& sa, co
     int ie = (int)x;
     ie = min(ie, N - 2);
     const double fe = x - (double)ie;
-    const double* nd = a.node64 + (size_t)kNode64 * ie;
-    const double pa = nd[0], pb = nd[kNode64];
+    double pa, pb, X1, X2, X3, X4, X5;
+    if (NODE_LDS) {
+        // the LDS copy is read always (index clamped into it); a cell above it is
+        // read again from HBM with a distinct load kind, which keeps the compiler
+        // from fusing the two reads into one generic (flat) load
+        const double* nl = node_lds + (size_t)kNode64 * min(ie, n_lds - 2);
+        pa = nl[0]; X1 = nl[1]; X2 = nl[2]; X3 = nl[3]; X4 = nl[4]; X5 = nl[5];
+        pb = nl[kNode64];
+        if (ie + 1 >= n_lds) {
+            const double* nd = a.node64 + (size_t)kNode64 * ie;
+            pa = __builtin_nontemporal_load(nd);
+            X1 = __builtin_nontemporal_load(nd + 1);
+            X2 = __builtin_nontemporal_load(nd + 2);
+            X3 = __builtin_nontemporal_load(nd + 3);
+            X4 = __builtin_nontemporal_load(nd + 4);
+            X5 = __builtin_nontemporal_load(nd + 5);
+            pb = __builtin_nontemporal_load(nd + kNode64);
+        }
+    } else {
+        const double* nd = a.node64 + (size_t)kNode64 * ie;
+        pa = nd[0]; X1 = nd[1]; X2 = nd[2]; X3 = nd[3]; X4 = nd[4]; X5 = nd[5];
+        pb = nd[kNode64];
+    }
     const double psi_e = pa + fe * (pb - pa);
     const double dz = fe * a.step;
     const double dh = he - a.h_obs;
@@ -1598,7 +1631,6 @@ __device__ __forceinline__ bool soft_bunch(const Args& a, const SoftArgs& sa, co
     // triangle, P_0(h_i) = h_i - h_obs) plus the in-cell part of the linear
     // profile, dz (psi_i - psi_e)^k / (k+1)
     const double c = -psi_e, del = pa - psi_e;
-    double X1 = nd[1], X2 = nd[2], X3 = nd[3], X4 = nd[4], X5 = nd[5];
     const double X0 = (double)ie * a.step;
     X5 += c * X4; X4 += c * X3; X3 += c * X2; X2 += c * X1; X1 += c * X0;
     X5 += c * X4; X4 += c * X3; X3 += c * X2; X2 += c * X1;
@@ -1828,7 +1860,9 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
     const int NB = soft_bin_nodes(N);
     double* bins = reinterpret_cast<double*>(lds);                 // MODE 1: 6 x NB
     double* tsh = bins + (MODE == 1 ? 6 * NB : 0);     // n_tel x {X, Y, R^2, 1 / (2 R sigma)}
-    unsigned char* wbase = reinterpret_cast<unsigned char*>(tsh + 4 * a.n_tel) +
+    double* nlds = tsh + 4 * a.n_tel;                 // MODE 0: lowest node records
+    const int NL = soft_node_lds(N);
+    unsigned char* wbase = reinterpret_cast<unsigned char*>(nlds + (MODE == 0 ? kNode64 * NL : 0)) +
                            (size_t)wave * soft_wave_bytes(MODE, a.n_tel);
     SoftStep* stash = reinterpret_cast<SoftStep*>(wbase);
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + kSoftTS * sizeof(SoftStep));
@@ -1843,6 +1877,8 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
         tsh[4 * q + 2] = a.tel[4 * q + 3];
         tsh[4 * q + 3] = 1.0 / (2.0 * a.tel[4 * q + 2] * sa.sigma);
     }
+    if (MODE == 0)
+        for (int q = threadIdx.x; q < kNode64 * NL; q += blockDim.x) nlds[q] = a.node64[q];
     if (MODE == 0) {
         for (int q = lane; q < 2 * a.n_tel; q += kWave) acc[q] = 0.0;
         if (lane == 0) {
@@ -1926,9 +1962,10 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
                 SoftStep& e = stash[si];
                 const int32_t k = j - e.boff;
                 double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
-                seen = soft_bunch<MODE>(a, sa, e, k, (uint32_t)(seg_id0 + e.sidx), shower_id, s, t_ref,
-                                        tsh, acc, add_bin, inv_nobs, half_inv_nobs3, g_psi0, o_cos,
-                                        o_sin, o_phot);
+                seen = soft_bunch<MODE, MODE == 0>(a, sa, e, k, (uint32_t)(seg_id0 + e.sidx), shower_id,
+                                                   s, t_ref, tsh, acc, add_bin, inv_nobs,
+                                                   half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin,
+                                                   o_phot);
                 if (MODE == 1 && (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)) {
                     atomicAdd(&e.g_cos, o_cos);
                     atomicAdd(&e.g_sin, o_sin);
@@ -1991,7 +2028,10 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
     const int NB = soft_bin_nodes(N);
     double* bins = reinterpret_cast<double*>(lds);               // 6 x NB
     double* tsh = bins + 6 * NB;                                 // n_tel x {X, Y, R^2, 1 / (2 R sigma)}
+    double* nlds = tsh + 4 * a.n_tel;                            // lowest node records
+    const int NL = soft_node_lds(N);
     for (int q = threadIdx.x; q < 6 * NB; q += blockDim.x) bins[q] = 0.0;
+    for (int q = threadIdx.x; q < kNode64 * NL; q += blockDim.x) nlds[q] = a.node64[q];
     for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x) {
         tsh[4 * q] = a.tel[4 * q];
         tsh[4 * q + 1] = a.tel[4 * q + 1];
@@ -2024,8 +2064,8 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
         const int64_t seg_id = (a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]);
         const uint32_t shower_id = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
         double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
-        soft_bunch<1>(a, sa, e, k, (uint32_t)seg_id, shower_id, lo, a.t_ref[lo], tsh, nullptr,
-                      add_bin, inv_nobs, half_inv_nobs3, g_psi0, o_cos, o_sin, o_phot);
+        soft_bunch<1, true>(a, sa, e, k, (uint32_t)seg_id, shower_id, lo, a.t_ref[lo], tsh, nullptr,
+                            add_bin, inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin, o_phot);
         if (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)
             soft_step_reverse(e, o_cos, o_sin, o_phot, add_bin);
     }
@@ -2279,7 +2319,13 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     s.ids = sp.ids;
     s.ids_cap = sp.ids_cap;
     s.ids_count = sp.ids_count;
-    s.skip_if_listed = mode == 1 && sp.ids_count ? 1 : 0;
+    // listed adjoint: bins, spheres and the lowest node records in LDS (at most
+    // 128 KB for CKV_MAX_TEL spheres); beyond the LDS the adjoint recomputes everything
+    const size_t lds_l = (size_t)6 * soft_bin_nodes(a.n_nodes) * sizeof(double) +
+                         (size_t)a.n_tel * 4 * sizeof(double) +
+                         (size_t)kNode64 * soft_node_lds(a.n_nodes) * sizeof(double);
+    if (mode == 1 && lds_l > 160 * 1024) s.ids_count = nullptr;
+    s.skip_if_listed = mode == 1 && s.ids_count ? 1 : 0;
     // as many waves as the kernel's launch bounds allow and the LDS holds
     const int wmax = soft_max_waves(mode);
     int waves = p.emit_waves > 0 && p.emit_waves < wmax ? p.emit_waves : wmax;
@@ -2328,8 +2374,6 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
                 (void)hipFuncSetAttribute((const void*)soft_list_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
                 attr_l = true;
             }
-            const size_t lds_l = (size_t)6 * soft_bin_nodes(a.n_nodes) * sizeof(double) +
-                                 (size_t)a.n_tel * 4 * sizeof(double);
             soft_list_kernel<<<2 * p.emit_grid, kSoftListThreads, lds_l, st>>>(a, s);
         }
     }
