@@ -1479,12 +1479,12 @@ __host__ __device__ inline int soft_bin_nodes(int n_nodes)
 constexpr int kSoftBitWords = 64;    // list: ballot words kept per wave before a flush
 
 // per wave: step stash, flag row and (forward only) S, A per telescope, the list
-// state {tile's first step, ids, capacity, count} and the ballots of listed
-// bunches of the last kSoftBitWords groups of 64 bunches
+// state {tile's first step, ids, capacity, count, tile's emitting steps, unused}
+// and the ballots of listed bunches of the last kSoftBitWords groups of 64 bunches
 __host__ __device__ inline size_t soft_wave_bytes(int mode, int n_tel)
 {
     return kSoftTS * sizeof(SoftStep) + kWave * sizeof(int32_t) +
-           (mode == 0 ? (size_t)2 * n_tel * sizeof(double) + (4 + kSoftBitWords) * sizeof(int64_t)
+           (mode == 0 ? (size_t)2 * n_tel * sizeof(double) + (6 + kSoftBitWords) * sizeof(int64_t)
                       : 0);
 }
 
@@ -1798,10 +1798,10 @@ __device__ __forceinline__ void soft_step_reverse(const SoftStep& es, double g_c
 // by binary search over the tile's stash (first-bunch offsets ascend) and the
 // later ones by moving forward from there (the lanes' searches overlap; this
 // measured faster than word-by-word writes with consecutive slots).  lst holds
-// {tile's first step, ids, capacity, count}.  Called by the whole wave.
-__device__ __forceinline__ void soft_list_flush(const int64_t* lst, const uint64_t* bits,
-                                                const SoftStep* stash, int n_emit, int64_t j0,
-                                                int nw, int lane)
+// {tile's first step, ids, capacity, count, tile's emitting steps}.  Called by
+// the whole wave.
+__device__ __noinline__ void soft_list_flush(const int64_t* lst, const uint64_t* bits,
+                                                const SoftStep* stash, int64_t j0, int nw, int lane)
 {
     volatile const int64_t* vl = lst;
     uint64_t word = lane < nw ? bits[lane] : 0ull;
@@ -1817,6 +1817,7 @@ __device__ __forceinline__ void soft_list_flush(const int64_t* lst, const uint64
     uint64_t* ids = (uint64_t*)vl[1];
     int64_t slot = (int64_t)base + (incl - c);
     if (!word) return;
+    const int n_emit = (int)vl[4];
     const int32_t jw = (int32_t)(j0 + kWave * lane);     // bunch of bit 0
     int32_t jj = jw + __builtin_ctzll(word);
     int lo = 0, hi = n_emit;
@@ -1868,7 +1869,7 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + kSoftTS * sizeof(SoftStep));
     double* acc = reinterpret_cast<double*>(flags + kWave);     // MODE 0: S then A per telescope
     int64_t* lst = reinterpret_cast<int64_t*>(acc + 2 * a.n_tel);  // MODE 0: list state
-    uint64_t* bits = reinterpret_cast<uint64_t*>(lst + 4);          // MODE 0: ballot words
+    uint64_t* bits = reinterpret_cast<uint64_t*>(lst + 6);          // MODE 0: ballot words
     if (MODE == 1)
         for (int q = threadIdx.x; q < 6 * NB; q += blockDim.x) bins[q] = 0.0;
     for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x) {
@@ -1946,6 +1947,7 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
             st.sidx = lane;
             stash[__popcll(emit_mask & lt_mask)] = st;
         }
+        if (LIST && lane == 0) lst[4] = __popcll(emit_mask);
         wave_lds_sync();
 
         for (int64_t c0 = 0; c0 < total; c0 += kWave) {
@@ -1981,8 +1983,7 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
                 if (lane == 0) bits[w] = m;
                 if (w == kSoftBitWords - 1 || c0 + kWave >= total) {
                     wave_lds_sync();
-                    soft_list_flush(lst, bits, stash, __popcll(emit_mask), c0 - (int64_t)w * kWave,
-                                    w + 1, lane);
+                    soft_list_flush(lst, bits, stash, c0 - (int64_t)w * kWave, w + 1, lane);
                 }
             }
         }
