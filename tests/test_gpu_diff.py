@@ -261,3 +261,23 @@ def test_soft_list_argument_validation(small):
                                  atmo.handle, model.tels.handle, ptr(model.n_b), ptr(S), ptr(S),
                                  ptr(model.g_psi), ptr(model.g_P), C.byref(bad), *ws, None)
         assert rc == -1 and b"soft list" in L.ckv_last_error()
+
+
+def test_listed_adjoint_skips_ids_that_name_no_bunch(small):
+    """Ids past the last step, or past a step's bunch count, are skipped by the
+    listed adjoint: appended to a real list they leave the gradient unchanged."""
+    import torch
+    dw, orc, model = small
+    model.forward(dw.theta0)
+    gS, gA = _random_cotangents(model, 13)
+    ref = _tables_backward(model, dw.theta0, gS, gA)
+    n, cap = model.list_state()
+    assert n + 3 <= cap
+    nb = model.n_b.cpu().numpy()
+    step = int(np.flatnonzero(nb > 0)[0])
+    bogus = np.array([(dw.segs.n + 5) << 24, (step << 24) | int(nb[step] + 3), 2 ** 63 - 1],
+                     dtype=np.int64)
+    model.list_ids[n:n + 3] = torch.from_numpy(bogus).to(model.list_ids.device)
+    model.list_count.fill_(n + 3)
+    torch.cuda.synchronize()
+    _assert_same_gradient(_tables_backward(model, dw.theta0, gS, gA), ref)
