@@ -22,7 +22,10 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
+#include <set>
 #include <type_traits>
+#include <utility>
 
 #include "ckv_internal.h"
 
@@ -2091,6 +2094,19 @@ __global__ void zero_kernel(double* p, int64_t n)
 // --------------------------------------------------------------------------
 namespace {
 
+// Raises a kernel's dynamic-LDS limit the first time it is launched on a device
+// (once per kernel and device; safe when several host threads launch).
+void allow_lds(const void* kernel, int bytes)
+{
+    static std::mutex mu;
+    static std::set<std::pair<const void*, int>> done;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.insert({kernel, dev}).second)
+        (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 Args make_args(const RunPlan& p)
 {
     Args a{};
@@ -2198,12 +2214,7 @@ namespace {
 template <int PREC, int TS, int FEAT>
 int launch_emit(const Args& a, int grid, int waves, size_t lds, hipStream_t st)
 {
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void*)emit_kernel<PREC, TS, FEAT>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr = true;
-    }
+    allow_lds((const void*)emit_kernel<PREC, TS, FEAT>, 160 * 1024);
     emit_kernel<PREC, TS, FEAT><<<grid, waves * kWave, lds, st>>>(a);
     return check_launch("emit");
 }
@@ -2351,30 +2362,18 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     if (int rc = check_launch("zero")) return rc;
     if (p.params.event_begin) (void)hipEventRecord((hipEvent_t)p.params.event_begin, st);
     if (mode == 0) {
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void*)soft_kernel<0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            (void)hipFuncSetAttribute((const void*)soft_kernel<0, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
-        }
+        allow_lds((const void*)soft_kernel<0, false>, 160 * 1024);
+        allow_lds((const void*)soft_kernel<0, true>, 160 * 1024);
         if (s.ids_count)
             soft_kernel<0, true><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
         else
             soft_kernel<0, false><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
     } else {
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void*)soft_kernel<1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
-        }
+        allow_lds((const void*)soft_kernel<1, false>, 160 * 1024);
         soft_kernel<1, false><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
         if (s.ids_count) {
             if (int rc = check_launch("soft")) return rc;
-            static bool attr_l = false;
-            if (!attr_l) {
-                (void)hipFuncSetAttribute((const void*)soft_list_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-                attr_l = true;
-            }
+            allow_lds((const void*)soft_list_kernel, 160 * 1024);
             soft_list_kernel<<<2 * p.emit_grid, kSoftListThreads, lds_l, st>>>(a, s);
         }
     }
