@@ -48,7 +48,7 @@ def _load() -> Dict:
 
 def _store(cache: Dict) -> None:
     os.makedirs(os.path.dirname(CACHE_PATH), exist_ok=True)
-    tmp = CACHE_PATH + ".tmp"
+    tmp = f"{CACHE_PATH}.{os.getpid()}.tmp"      # one writer per file; replace is atomic
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     os.replace(tmp, CACHE_PATH)
