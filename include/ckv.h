@@ -291,7 +291,8 @@ int ckv_count(const ckv_segments* segs, const ckv_params* params, const ckv_atmo
  * zero in FP64).  Bunch counts are frozen: n_b_frozen[i] (from ckv_count at a
  * reference atmosphere) fixes the sub-steps, while yield, angle and photons
  * per bunch follow the current atmosphere; a step below threshold at the
- * current atmosphere emits nothing.  FP64 throughout.
+ * current atmosphere emits nothing.  S, A and the gradient are computed in FP64
+ * (with a bunch list, a mixed-precision pass only selects the bunches).
  * ------------------------------------------------------------------------- */
 
 /* log eta(h) = log eta0 - sum_l overlap([0, h], layer l) / H_l + Lambda(h):
@@ -323,14 +324,19 @@ int ckv_atmo_params_backward(const ckv_atmo_param_spec* spec, const double* thet
    for edge width sigma_m > 0 (see ckv_array_create for the other arguments). */
 int ckv_array_create_soft(const double* x_m, const double* y_m, const double* r_m, int32_t n_tel,
                           double sigma_m, ckv_array** out);
-/* The bunches that enter the soft response: one id per bunch with z >= -40 at
-   some sphere, (global step index << 24) | bunch index k, in no particular
-   order.  Written by ckv_soft_forward, read by ckv_soft_backward, which then
-   recomputes only these bunches (the others contribute exactly zero).  The
-   caller owns both device buffers.  *count is the number of such bunches (ids
-   beyond capacity are not written); the list is complete iff
-   0 <= *count <= capacity (a bunch index of 2^24 or more, or a step index of
-   2^40 or more, makes it incomplete). */
+/* Bunch list of the soft response.  With a list, ckv_soft_forward first screens
+   every bunch with the mixed-precision path against spheres of the cut radius
+   sqrt(R^2 + 2 R sigma 40) plus 1 cm (far above that path's errors), lists the
+   candidates and recomputes only those in FP64 for S and A; the list thus holds
+   every bunch with z >= -40 at some sphere (the ones that enter S, A and the
+   gradient) and a few just outside.  Ids are (global step index << 24) | bunch
+   index k, in no particular order.  ckv_soft_backward then recomputes only the
+   listed bunches (the others contribute exactly zero).  The caller owns both
+   device buffers.  *count is the number of candidates (ids beyond capacity are
+   not written); the list is complete iff 0 <= *count <= capacity (a bunch index
+   of 2^24 or more, or a step index of 2^40 or more, makes it incomplete).  With
+   an incomplete list the forward computes S and A from every bunch in FP64 and
+   the backward recomputes every bunch. */
 typedef struct {
     uint64_t* ids;        /* device, capacity entries */
     int64_t capacity;     /* >= 0 */

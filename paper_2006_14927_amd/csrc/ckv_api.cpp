@@ -348,11 +348,20 @@ static int array_create(const double* x_m, const double* y_m, const double* r_m,
     arr->r.assign(r_m, r_m + n_tel);
     arr->soft_sigma = sigma;
     int rc = build_array_grid(arr, arr->r, &arr->hit);
+    std::vector<double> tel_screen;
     if (!rc && sigma > 0.0) {
-        // beyond sqrt(R^2 + 2 R sigma z_cut) the soft weight is exactly zero
+        // beyond sqrt(R^2 + 2 R sigma z_cut) the soft weight is exactly zero; the grid
+        // and the screening spheres add a margin for the mixed-precision screening pass
         std::vector<double> reff(n_tel);
-        for (int32_t k = 0; k < n_tel; ++k)
-            reff[k] = std::sqrt(r_m[k] * r_m[k] + 2.0 * r_m[k] * sigma * kSoftZCut) * (1.0 + 1e-9);
+        tel_screen.resize(4 * (size_t)n_tel);
+        for (int32_t k = 0; k < n_tel; ++k) {
+            reff[k] = std::sqrt(r_m[k] * r_m[k] + 2.0 * r_m[k] * sigma * kSoftZCut) * (1.0 + 1e-9) +
+                      kScreenMargin;
+            tel_screen[4 * k] = x_m[k];
+            tel_screen[4 * k + 1] = y_m[k];
+            tel_screen[4 * k + 2] = reff[k];
+            tel_screen[4 * k + 3] = reff[k] * reff[k];
+        }
         rc = build_array_grid(arr, reff, &arr->soft);
     }
     if (!rc) {
@@ -368,7 +377,8 @@ static int array_create(const double* x_m, const double* y_m, const double* r_m,
         tel[4 * k + 3] = r_m[k] * r_m[k];
     }
     if ((rc = upload(tel.data(), tel.size(), &arr->d_tel)) || (rc = upload_grid(&arr->hit)) ||
-        (sigma > 0.0 && (rc = upload_grid(&arr->soft)))) {
+        (sigma > 0.0 && (rc = upload_grid(&arr->soft))) ||
+        (sigma > 0.0 && (rc = upload(tel_screen.data(), tel_screen.size(), &arr->d_tel_screen)))) {
         ckv_array_destroy(arr);
         return rc;
     }
@@ -393,6 +403,7 @@ int ckv_array_destroy(ckv_array* arr)
 {
     if (!arr) return CKV_OK;
     if (arr->d_tel) (void)hipFree(arr->d_tel);
+    if (arr->d_tel_screen) (void)hipFree(arr->d_tel_screen);
     free_grid(&arr->hit);
     free_grid(&arr->soft);
     delete arr;

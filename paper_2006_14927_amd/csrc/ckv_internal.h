@@ -105,8 +105,10 @@ struct ckv_array {
     std::vector<double> x, y, r;
     double* d_tel = nullptr;         // device, n_tel x 4: X, Y, R, R^2
     ckv_grid hit;                    // radii R (sphere crossings)
-    ckv_grid soft;                   // radii sqrt(R^2 + 2 R sigma z_cut) (soft response)
+    ckv_grid soft;                   // radii sqrt(R^2 + 2 R sigma z_cut) + margin (soft response)
     double soft_sigma = 0;           // 0: no soft grid
+    double* d_tel_screen = nullptr;  // device, n_tel x 4: X, Y, R_s, R_s^2 with R_s the soft
+                                     // cut radius plus kScreenMargin (screening pass)
 };
 
 namespace ckv {
@@ -122,6 +124,9 @@ int build_node_tables(const double* alt, const double* eta, int64_t n, double h_
 void build_depth_table(const double* alt, const double* depth, int64_t n, ckv_atmo* a);
 int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ckv_grid* g);
 constexpr double kSoftZCut = 40.0;   // Phi(-40) underflows to exactly 0 in FP64
+// margin of the soft response's screening spheres over the cut radius: far above the
+// mixed path's ground-point and direction errors (tolerances 1 mm and 1e-6)
+constexpr double kScreenMargin = 0.01;
 int param_spec_check(const ckv_atmo_param_spec* sp, const double* theta);
 void param_profile(const ckv_atmo_param_spec* sp, const double* theta, std::vector<double>* alt,
                    std::vector<double>* eta);

@@ -91,6 +91,12 @@ struct Args {
     int64_t capacity;
     int64_t* tel_offsets;
     ckv_result* result;
+    // screening pass of the soft response (kFeatScreen): frozen bunch counts and the
+    // list of candidate bunches {ids, capacity, count}
+    const int64_t* nb_frozen;
+    uint64_t* list_ids;
+    int64_t list_cap;
+    int64_t* list_count;
 };
 
 // --------------------------------------------------------------------------
@@ -572,6 +578,65 @@ __host__ __device__ inline size_t wave_bytes(int prec, int tile_segs, int n_tel,
     return (b + 15) & ~(size_t)15;
 }
 
+constexpr int kSoftIdBits = 24;                          // bunch index bits of a list id
+constexpr unsigned long long kSoftListInvalid = 1ull << 62;   // or-ed into the count
+
+// Screening pass: the candidate bunches of ballot words bits[0..nw-1] (bit b of
+// word q: bunch j0 + 64 q + b of the tile) go to the list.  One atomic claims exactly
+// their slots; lane q writes the ids of word q, the step of its first bunch found
+// by binary search over the tile's stash (first-bunch offsets ascend) and the
+// later ones by moving forward from there (the lanes' searches overlap; this
+// measured faster than word-by-word writes with consecutive slots).  lst holds
+// {tile's first step, ids, capacity, count, tile's emitting steps}.  Called by
+// the whole wave.
+template <typename E>
+__device__ __noinline__ void soft_list_flush(const int64_t* lst, const uint64_t* bits,
+                                                const E* stash, int64_t j0, int nw, int lane)
+{
+    volatile const int64_t* vl = lst;
+    uint64_t word = lane < nw ? bits[lane] : 0ull;
+    const int c = __popcll(word);
+    const int64_t incl = wave_incl_scan((int64_t)c);
+    const int64_t tot = __shfl(incl, kWave - 1);
+    if (tot == 0) return;
+    unsigned long long* count = (unsigned long long*)vl[3];
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)tot);
+    base = __shfl(base, 0);
+    const int64_t g0 = vl[0], cap = vl[2];
+    uint64_t* ids = (uint64_t*)vl[1];
+    int64_t slot = (int64_t)base + (incl - c);
+    if (!word) return;
+    const int n_emit = (int)vl[4];
+    const int32_t jw = (int32_t)(j0 + kWave * lane);     // bunch of bit 0
+    int32_t jj = jw + __builtin_ctzll(word);
+    int lo = 0, hi = n_emit;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (stash[mid].boff <= jj) lo = mid; else hi = mid;
+    }
+    int32_t boff = stash[lo].boff;
+    int32_t next = lo + 1 < n_emit ? stash[lo + 1].boff : INT_MAX;
+    uint64_t step = (uint64_t)(g0 + stash[lo].sidx);
+    for (;;) {
+        while (jj >= next) {
+            ++lo;
+            boff = next;
+            next = lo + 1 < n_emit ? stash[lo + 1].boff : INT_MAX;
+            step = (uint64_t)(g0 + stash[lo].sidx);
+        }
+        const int32_t k = jj - boff;
+        if ((uint32_t)k >= (1u << kSoftIdBits) || step >= (1ull << (64 - kSoftIdBits)))
+            atomicOr(count, kSoftListInvalid);
+        else if (slot < cap)
+            ids[slot] = (step << kSoftIdBits) | (uint64_t)(uint32_t)k;
+        ++slot;
+        word &= word - 1;
+        if (!word) break;
+        jj = jw + __builtin_ctzll(word);
+    }
+}
+
 // --------------------------------------------------------------------------
 // the bunch kernel
 // --------------------------------------------------------------------------
@@ -583,6 +648,14 @@ constexpr int kFeatExact = 2;
 constexpr int kFeatSearch = 4;   // node tables: binary search per bunch (alone, 32-step tiles)
 constexpr int kFeatCurved = 8;   // spherical shells, every bunch traced exactly (alone, 32-step tiles)
 constexpr int kFeatWide = 16;    // mixed kernel built for <= 8 waves per workgroup (twice the registers)
+// soft-response screening (mixed, alone, 32-step tiles): bunch counts frozen, each
+// bunch tested against spheres of the soft cut radius plus a margin, the candidates'
+// ids listed; no records
+constexpr int kFeatScreen = 32;
+// per wave, after the regular area: list state {tile's first step, ids, capacity,
+// count, emitting steps, unused} and the ballot words of the candidate bunches
+constexpr int kScreenWords = 64;
+constexpr size_t kScreenWaveBytes = (6 + kScreenWords) * sizeof(int64_t);
 
 __host__ __device__ inline size_t search_bytes(int n_nodes)
 {
@@ -613,6 +686,8 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
     constexpr bool EXACT = (FEAT & kFeatExact) != 0;
     constexpr bool SEARCH = (FEAT & kFeatSearch) != 0;
     constexpr bool CURVED = (FEAT & kFeatCurved) != 0;
+    constexpr bool SCREEN = (FEAT & kFeatScreen) != 0;
+    constexpr bool PARTIAL = PROF || SCREEN;      // table staged in part, the rest from HBM
     constexpr bool SLOWPATH = EXACT || CURVED;    // lanes that leave the moment series
     using T = typename std::conditional<PREC == 0, double, float>::type;
     using Entry = StepEntry<PREC>;
@@ -622,7 +697,7 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
     const int wave = threadIdx.x / kWave;
 
     // ---- stage the atmosphere table once per workgroup
-    const size_t tab_bytes = table_bytes(PREC, a.n_nodes, PROF);
+    const size_t tab_bytes = table_bytes(PREC, a.n_nodes, PARTIAL);
     {
         const uint4* src = reinterpret_cast<const uint4*>(PREC == 0 ? (const void*)a.node64
                                                                     : (const void*)a.cell32);
@@ -642,8 +717,17 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
         tel_sh[3 * q + 1] = a.tel[4 * q + 1];
         tel_sh[3 * q + 2] = a.tel[4 * q + 3];
     }
+    const size_t wv_bytes = wave_bytes(PREC, TS, a.n_tel, PROF ? a.prof_bins : 0);
     unsigned char* wbase = lds + ((tab_bytes + 15) & ~(size_t)15) + srch_bytes + tel_bytes(a.n_tel) +
-                           (size_t)wave * wave_bytes(PREC, TS, a.n_tel, PROF ? a.prof_bins : 0);
+                           (size_t)wave * (wv_bytes + (SCREEN ? kScreenWaveBytes : 0));
+    // screening: list state and ballot words after the wave's regular area
+    int64_t* lst = reinterpret_cast<int64_t*>(wbase + wv_bytes);
+    uint64_t* bits = reinterpret_cast<uint64_t*>(lst + 6);
+    if (SCREEN && lane == 0) {
+        lst[1] = (int64_t)a.list_ids;
+        lst[2] = a.list_cap;
+        lst[3] = (int64_t)a.list_count;
+    }
     Entry* stash = reinterpret_cast<Entry*>(wbase);
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + TS * sizeof(Entry));
     int64_t* wcnt = reinterpret_cast<int64_t*>(flags + kWave);
@@ -704,6 +788,18 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
             step_setup(a, g0 + lane, st);
             status = st.status;
             if (st.status < 0) nb = st.nb;
+            if (SCREEN && st.status < 0) {
+                // the soft response's sub-steps: the frozen count, light or not at
+                // the current atmosphere decided above
+                const int64_t f = a.nb_frozen[g0 + lane];
+                if (f > 0) {
+                    nb = f;
+                    st.ds = a.len[g0 + lane] / (double)f;
+                } else {
+                    nb = 0;
+                    status = -4;
+                }
+            }
         }
         int64_t incl = wave_incl_scan(nb);
         int64_t total = __shfl(incl, kWave - 1);
@@ -717,6 +813,10 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
         }
         const bool emits = status == -1;
         const uint64_t emit_mask = __ballot(emits);
+        if (SCREEN && lane == 0) {
+            lst[0] = g0;
+            lst[4] = __popcll(emit_mask);
+        }
         const int excl = (int)(incl - nb);      // first bunch of this lane's step
         if (emits) {
             Entry& e = stash[__popcll(emit_mask & lt_mask)];
@@ -924,12 +1024,12 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     if (PREC == 0) {
                         double n0[6], n1;
                         {
-                            const int cl = PROF ? min(ci, a.lds_entries - 2) : ci;
+                            const int cl = PARTIAL ? min(ci, a.lds_entries - 2) : ci;
                             const double* nd = tab64 + (size_t)kNode64 * cl;
                             for (int q = 0; q < 6; ++q) n0[q] = nd[q];
                             n1 = nd[kNode64];
                         }
-                        if (PROF && ci + 1 >= a.lds_entries) {
+                        if (PARTIAL && ci + 1 >= a.lds_entries) {
                             // a distinct load kind keeps the compiler from fusing the two
                             // reads into one generic (flat) load of a selected address
                             const double* nd = a.node64 + (size_t)kNode64 * ci;
@@ -943,12 +1043,12 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     } else {
                         float4 c_a, c_b;
                         {
-                            const int cl = PROF ? min(ci, a.lds_entries - 1) : ci;
+                            const int cl = PARTIAL ? min(ci, a.lds_entries - 1) : ci;
                             const float4* cc = reinterpret_cast<const float4*>(tab32 + (size_t)kCell32 * cl);
                             c_a = cc[0];
                             c_b = cc[1];
                         }
-                        if (PROF && ci >= a.lds_entries) {
+                        if (PARTIAL && ci >= a.lds_entries) {
                             // a distinct load kind keeps the compiler from fusing the two
                             // reads into one generic (flat) load of a selected address
                             const float* cg = a.cell32 + (size_t)kCell32 * ci;
@@ -1095,61 +1195,73 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                 }
             };
             advance();
-            // ---- record crossings; telescopes in ascending order, lanes (bunches) in order
-            while (__ballot(my_next != INT_MAX)) {
-                const int kmin = wave_min_sparse(my_next, INT_MAX);
-                const bool mine = my_next == kmin;
-                const uint64_t mask = __ballot(mine);
-                const int nmine = __popcll(mask);
-                const int below = __popcll(mask & lt_mask);
-                const int rank0 = tcount[kmin];
-                if (lane == 0) wcnt[kWcHits] += nmine;
-                // staging slots: the first `room` crossings fill the current
-                // block, the rest start a newly claimed one
-                const int room = blk >= 0 ? kStageBlock - blk_fill : 0;
-                int64_t nbk = -2;
-                if (nmine > room && blk != -2) {
-                    if (blk >= 0 && lane == 0) a.stage_fill[blk] = kStageBlock;
-                    if (lane == 0) nbk = (int64_t)atomicAdd((unsigned long long*)&a.ctrl[kBlockCounter], 1ull);
-                    nbk = uniform(nbk);
-                    if (nbk >= a.stage_blocks) {
-                        nbk = -2;
-                        if (lane == 0) atomicExch((unsigned long long*)&a.ctrl[kStageOverflow], 1ull);
-                    }
+            if constexpr (SCREEN) {
+                // candidates of the soft response: one ballot word per 64 bunches,
+                // flushed to the list when the buffer is full and at the tile's end
+                const uint64_t m = __ballot(my_next != INT_MAX);
+                const int w = (int)((c0 >> 6) & (kScreenWords - 1));
+                if (lane == 0) bits[w] = m;
+                if (w == kScreenWords - 1 || c0 + kWave >= total) {
+                    wave_lds_sync();
+                    soft_list_flush(lst, bits, stash, c0 - (int64_t)w * kWave, w + 1, lane);
                 }
-                if (mine) {
-                    int64_t slot = -1;
-                    if (below < room) slot = blk * kStageBlock + blk_fill + below;
-                    else if (nbk >= 0) slot = nbk * kStageBlock + (below - room);
-                    if (slot >= 0) {
-                        StageEntry* se = a.stage + slot;
-                        const double* tp = a.tel + 4 * kmin;
-                        float4* ef = reinterpret_cast<float4*>(se);
-                        ef[0] = make_float4((float)(xg - tp[0]), (float)(yg - tp[1]), uo, vo);
-                        ef[1] = make_float4(t_f, he_f, photons, lam);
-                        uint4* eu = reinterpret_cast<uint4*>(se);
-                        eu[2] = make_uint4((uint32_t)t, (uint32_t)kmin, (uint32_t)(rank0 + below), (uint32_t)s);
-                        int64_t* el = reinterpret_cast<int64_t*>(se);
-                        el[6] = g0 + sidx;
-                        el[7] = k;
+            } else {
+                // ---- record crossings; telescopes in ascending order, lanes (bunches) in order
+                while (__ballot(my_next != INT_MAX)) {
+                    const int kmin = wave_min_sparse(my_next, INT_MAX);
+                    const bool mine = my_next == kmin;
+                    const uint64_t mask = __ballot(mine);
+                    const int nmine = __popcll(mask);
+                    const int below = __popcll(mask & lt_mask);
+                    const int rank0 = tcount[kmin];
+                    if (lane == 0) wcnt[kWcHits] += nmine;
+                    // staging slots: the first `room` crossings fill the current
+                    // block, the rest start a newly claimed one
+                    const int room = blk >= 0 ? kStageBlock - blk_fill : 0;
+                    int64_t nbk = -2;
+                    if (nmine > room && blk != -2) {
+                        if (blk >= 0 && lane == 0) a.stage_fill[blk] = kStageBlock;
+                        if (lane == 0) nbk = (int64_t)atomicAdd((unsigned long long*)&a.ctrl[kBlockCounter], 1ull);
+                        nbk = uniform(nbk);
+                        if (nbk >= a.stage_blocks) {
+                            nbk = -2;
+                            if (lane == 0) atomicExch((unsigned long long*)&a.ctrl[kStageOverflow], 1ull);
+                        }
                     }
-                }
-                if (nmine > room) {
-                    if (blk != -2) {
-                        blk = nbk;               // -2 when the staging area is full
-                        blk_fill = nmine - room;
+                    if (mine) {
+                        int64_t slot = -1;
+                        if (below < room) slot = blk * kStageBlock + blk_fill + below;
+                        else if (nbk >= 0) slot = nbk * kStageBlock + (below - room);
+                        if (slot >= 0) {
+                            StageEntry* se = a.stage + slot;
+                            const double* tp = a.tel + 4 * kmin;
+                            float4* ef = reinterpret_cast<float4*>(se);
+                            ef[0] = make_float4((float)(xg - tp[0]), (float)(yg - tp[1]), uo, vo);
+                            ef[1] = make_float4(t_f, he_f, photons, lam);
+                            uint4* eu = reinterpret_cast<uint4*>(se);
+                            eu[2] = make_uint4((uint32_t)t, (uint32_t)kmin, (uint32_t)(rank0 + below), (uint32_t)s);
+                            int64_t* el = reinterpret_cast<int64_t*>(se);
+                            el[6] = g0 + sidx;
+                            el[7] = k;
+                        }
                     }
-                } else {
-                    blk_fill += nmine;
+                    if (nmine > room) {
+                        if (blk != -2) {
+                            blk = nbk;               // -2 when the staging area is full
+                            blk_fill = nmine - room;
+                        }
+                    } else {
+                        blk_fill += nmine;
+                    }
+                    if (lane == 0) tcount[kmin] = rank0 + nmine;
+                    wave_lds_sync();
+                    if (mine) advance();
                 }
-                if (lane == 0) tcount[kmin] = rank0 + nmine;
-                wave_lds_sync();
-                if (mine) advance();
             }
         }
         // ---- per-telescope crossings of this tile
         wave_lds_sync();
-        if (t < a.max_tiles) {
+        if (!SCREEN && t < a.max_tiles) {
             int32_t* row = a.counts + t * (int64_t)a.n_tel;
             for (int kk = lane; kk < a.n_tel; kk += kWave) {
                 row[kk] = tcount[kk];
@@ -1442,11 +1554,10 @@ struct SoftArgs {
     uint64_t* ids;
     int64_t ids_cap;
     int64_t* ids_count;
-    int32_t skip_if_listed;     // adjoint tile kernel: exit when the list is complete
+    int32_t skip_if_listed;     // tile kernels: exit when the list is complete
+    int32_t cand_lds_acc;       // candidate kernel: S, A of all (shower, sphere) pairs in LDS
 };
 
-constexpr int kSoftIdBits = 24;                          // bunch index bits of a list id
-constexpr unsigned long long kSoftListInvalid = 1ull << 62;   // or-ed into the count
 
 __device__ __forceinline__ bool soft_list_complete(const SoftArgs& sa)
 {
@@ -1479,16 +1590,11 @@ __host__ __device__ inline int soft_bin_nodes(int n_nodes)
     return n_nodes < kSoftBinNodes ? n_nodes : kSoftBinNodes;
 }
 
-constexpr int kSoftBitWords = 64;    // list: ballot words kept per wave before a flush
-
-// per wave: step stash, flag row and (forward only) S, A per telescope, the list
-// state {tile's first step, ids, capacity, count, tile's emitting steps, unused}
-// and the ballots of listed bunches of the last kSoftBitWords groups of 64 bunches
+// per wave: step stash, flag row and (forward only) S, A per telescope
 __host__ __device__ inline size_t soft_wave_bytes(int mode, int n_tel)
 {
     return kSoftTS * sizeof(SoftStep) + kWave * sizeof(int32_t) +
-           (mode == 0 ? (size_t)2 * n_tel * sizeof(double) + (6 + kSoftBitWords) * sizeof(int64_t)
-                      : 0);
+           (mode == 0 ? (size_t)2 * n_tel * sizeof(double) : 0);
 }
 
 // per workgroup: adjoint bins, then {X, Y, R^2, 1 / (2 R sigma)} per telescope, then the waves
@@ -1511,6 +1617,9 @@ __host__ __device__ inline size_t soft_lds_bytes(int mode, int n_nodes, int n_te
 // step setup with a frozen bunch count; false when the step emits nothing
 __device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, SoftStep& e)
 {
+    // no contraction: the threshold decision is the one of the FP64 definition and
+    // of the screening pass's step setup
+#pragma clang fp contract(off)
     const double x0 = a.x0[i], y0 = a.y0[i], h0 = a.h0[i];
     const double u = a.u[i], v = a.v[i], w = a.w[i];
     const double L = a.len[i], t0 = a.t0[i], E = a.energy[i];
@@ -1571,7 +1680,8 @@ template <int MODE, bool NODE_LDS, typename AddBin>
 __device__ __forceinline__ bool soft_bunch(const Args& a, const SoftArgs& sa, const SoftStep& e,
                                            int32_t k, uint32_t seg_id, uint32_t shower_id, int s,
                                            double t_ref, const double* tsh, double* acc,
-                                           AddBin& add_bin, double inv_nobs, double half_inv_nobs3,
+                                           double* accA, AddBin& add_bin, double inv_nobs,
+                                           double half_inv_nobs3,
                                            const double* node_lds, int n_lds,
                                            double& g_psi0, double& o_cos, double& o_sin,
                                            double& o_phot)
@@ -1699,7 +1809,7 @@ __device__ __forceinline__ bool soft_bunch(const Args& a, const SoftArgs& sa, co
         const double W = 0.5 * erfc(-z * inv_sqrt2);
         if (MODE == 0) {
             atomicAdd(&acc[kt], p * W);
-            atomicAdd(&acc[a.n_tel + kt], p * W * tt);
+            atomicAdd(&accA[kt], p * W * tt);
         } else {
             const double gSk = sa.gS[(int64_t)s * a.n_tel + kt];
             const double gAk = sa.gA[(int64_t)s * a.n_tel + kt];
@@ -1795,69 +1905,13 @@ __device__ __forceinline__ void soft_step_reverse(const SoftStep& es, double g_c
     }
 }
 
-// Soft forward: the listed bunches of ballot words bits[0..nw-1] (bit b of word q:
-// bunch j0 + 64 q + b of the tile) go to the list.  One atomic claims exactly
-// their slots; lane q writes the ids of word q, the step of its first bunch found
-// by binary search over the tile's stash (first-bunch offsets ascend) and the
-// later ones by moving forward from there (the lanes' searches overlap; this
-// measured faster than word-by-word writes with consecutive slots).  lst holds
-// {tile's first step, ids, capacity, count, tile's emitting steps}.  Called by
-// the whole wave.
-__device__ __noinline__ void soft_list_flush(const int64_t* lst, const uint64_t* bits,
-                                                const SoftStep* stash, int64_t j0, int nw, int lane)
-{
-    volatile const int64_t* vl = lst;
-    uint64_t word = lane < nw ? bits[lane] : 0ull;
-    const int c = __popcll(word);
-    const int64_t incl = wave_incl_scan((int64_t)c);
-    const int64_t tot = __shfl(incl, kWave - 1);
-    if (tot == 0) return;
-    unsigned long long* count = (unsigned long long*)vl[3];
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(count, (unsigned long long)tot);
-    base = __shfl(base, 0);
-    const int64_t g0 = vl[0], cap = vl[2];
-    uint64_t* ids = (uint64_t*)vl[1];
-    int64_t slot = (int64_t)base + (incl - c);
-    if (!word) return;
-    const int n_emit = (int)vl[4];
-    const int32_t jw = (int32_t)(j0 + kWave * lane);     // bunch of bit 0
-    int32_t jj = jw + __builtin_ctzll(word);
-    int lo = 0, hi = n_emit;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (stash[mid].boff <= jj) lo = mid; else hi = mid;
-    }
-    int32_t boff = stash[lo].boff;
-    int32_t next = lo + 1 < n_emit ? stash[lo + 1].boff : INT_MAX;
-    uint64_t step = (uint64_t)(g0 + stash[lo].sidx);
-    for (;;) {
-        while (jj >= next) {
-            ++lo;
-            boff = next;
-            next = lo + 1 < n_emit ? stash[lo + 1].boff : INT_MAX;
-            step = (uint64_t)(g0 + stash[lo].sidx);
-        }
-        const int32_t k = jj - boff;
-        if ((uint32_t)k >= (1u << kSoftIdBits) || step >= (1ull << (64 - kSoftIdBits)))
-            atomicOr(count, kSoftListInvalid);
-        else if (slot < cap)
-            ids[slot] = (step << kSoftIdBits) | (uint64_t)(uint32_t)k;
-        ++slot;
-        word &= word - 1;
-        if (!word) break;
-        jj = jw + __builtin_ctzll(word);
-    }
-}
-
-// LIST (forward only): also write the list of bunches with a nonzero weight
-template <int MODE, bool LIST>
+template <int MODE>
 __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args a, SoftArgs sa)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    // adjoint with a list from the forward: soft_list_kernel does the work unless
-    // the list is incomplete (the same decision in every thread of the grid)
-    if (MODE == 1 && sa.skip_if_listed && soft_list_complete(sa)) return;
+    // with a complete list soft_list_kernel (adjoint) or soft_cand_kernel (forward
+    // after the screening pass) does the work (the same decision in every thread)
+    if (sa.skip_if_listed && soft_list_complete(sa)) return;
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     const int N = a.n_nodes;
@@ -1871,8 +1925,6 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
     SoftStep* stash = reinterpret_cast<SoftStep*>(wbase);
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + kSoftTS * sizeof(SoftStep));
     double* acc = reinterpret_cast<double*>(flags + kWave);     // MODE 0: S then A per telescope
-    int64_t* lst = reinterpret_cast<int64_t*>(acc + 2 * a.n_tel);  // MODE 0: list state
-    uint64_t* bits = reinterpret_cast<uint64_t*>(lst + 6);          // MODE 0: ballot words
     if (MODE == 1)
         for (int q = threadIdx.x; q < 6 * NB; q += blockDim.x) bins[q] = 0.0;
     for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x) {
@@ -1883,17 +1935,8 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
     }
     if (MODE == 0)
         for (int q = threadIdx.x; q < kNode64 * NL; q += blockDim.x) nlds[q] = a.node64[q];
-    if (MODE == 0) {
+    if (MODE == 0)
         for (int q = lane; q < 2 * a.n_tel; q += kWave) acc[q] = 0.0;
-        if (lane == 0) {
-            // the list arguments are read from here where needed rather than
-            // held in scalar registers across the bunch loop
-            lst[0] = 0;
-            lst[1] = (int64_t)sa.ids;
-            lst[2] = sa.ids_cap;
-            lst[3] = (int64_t)sa.ids_count;
-        }
-    }
     flags[lane] = 0;
     __syncthreads();
     // j = 0: dL/dpsi_i, j = 1..5: dL/dP_j(h_i)
@@ -1927,7 +1970,6 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
         const uint32_t shower_id = a.shower_ids ? a.shower_ids[s] : (uint32_t)s;
         const int64_t seg_id0 = (a.seg_id_base ? a.seg_id_base[s] : 0) + (g0 - sfirst);
         const double t_ref = a.t_ref[s];
-        if (LIST && lane == 0) lst[0] = g0;
 
         SoftStep st;
         int64_t nb = 0;
@@ -1950,7 +1992,6 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
             st.sidx = lane;
             stash[__popcll(emit_mask & lt_mask)] = st;
         }
-        if (LIST && lane == 0) lst[4] = __popcll(emit_mask);
         wave_lds_sync();
 
         for (int64_t c0 = 0; c0 < total; c0 += kWave) {
@@ -1962,31 +2003,18 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
             const uint64_t starts = __ballot(flags[lane] != 0);
             flags[lane] = 0;
             const int si = cnt0 - 1 + __popcll(starts & le_mask);
-            bool seen = false;
             if (active) {
                 SoftStep& e = stash[si];
                 const int32_t k = j - e.boff;
                 double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
-                seen = soft_bunch<MODE, MODE == 0>(a, sa, e, k, (uint32_t)(seg_id0 + e.sidx), shower_id,
-                                                   s, t_ref, tsh, acc, add_bin, inv_nobs,
+                soft_bunch<MODE, MODE == 0>(a, sa, e, k, (uint32_t)(seg_id0 + e.sidx), shower_id,
+                                                   s, t_ref, tsh, acc, acc + a.n_tel, add_bin, inv_nobs,
                                                    half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin,
                                                    o_phot);
                 if (MODE == 1 && (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)) {
                     atomicAdd(&e.g_cos, o_cos);
                     atomicAdd(&e.g_sin, o_sin);
                     atomicAdd(&e.g_phot, o_phot);
-                }
-            }
-            if (LIST) {
-                // the list the adjoint reads back: one ballot word per 64 bunches
-                // in the wave's LDS, written out every kSoftBitWords words and at
-                // the end of the tile
-                const uint64_t m = __ballot(seen);
-                const int w = (int)((c0 >> 6) & (kSoftBitWords - 1));
-                if (lane == 0) bits[w] = m;
-                if (w == kSoftBitWords - 1 || c0 + kWave >= total) {
-                    wave_lds_sync();
-                    soft_list_flush(lst, bits, stash, c0 - (int64_t)w * kWave, w + 1, lane);
                 }
             }
         }
@@ -2069,7 +2097,7 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
         const uint32_t shower_id = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
         double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
         soft_bunch<1, true>(a, sa, e, k, (uint32_t)seg_id, shower_id, lo, a.t_ref[lo], tsh, nullptr,
-                            add_bin, inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin, o_phot);
+                            nullptr, add_bin, inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin, o_phot);
         if (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)
             soft_step_reverse(e, o_cos, o_sin, o_phot, add_bin);
     }
@@ -2079,6 +2107,71 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
         const double v = bins[qq];
         const int j = qq / NB, i = qq - j * NB;
         if (v != 0.0) atomicAdd(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
+    }
+}
+
+// Soft forward over the screening pass's candidate list: one candidate bunch per
+// thread, its step set up again with the frozen count and the bunch recomputed in
+// FP64 exactly as in the tile kernel; S and A are added straight into HBM.  Runs
+// only when the list is complete; ids that name no bunch are skipped.
+__global__ void __launch_bounds__(kSoftListThreads) soft_cand_kernel(Args a, SoftArgs sa)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    if (!soft_list_complete(sa)) return;
+    const int64_t n_ids = *sa.ids_count;
+    const int N = a.n_nodes;
+    double* tsh = reinterpret_cast<double*>(lds);                // n_tel x {X, Y, R^2, 1 / (2 R sigma)}
+    double* nlds = tsh + 4 * a.n_tel;                            // lowest node records
+    const int NL = soft_node_lds(N);
+    for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x) {
+        tsh[4 * q] = a.tel[4 * q];
+        tsh[4 * q + 1] = a.tel[4 * q + 1];
+        tsh[4 * q + 2] = a.tel[4 * q + 3];
+        tsh[4 * q + 3] = 1.0 / (2.0 * a.tel[4 * q + 2] * sa.sigma);
+    }
+    for (int q = threadIdx.x; q < kNode64 * NL; q += blockDim.x) nlds[q] = a.node64[q];
+    // S and A summed per workgroup in LDS when they fit (added to HBM once at the
+    // end): bunches near one sphere would otherwise all update the same two words
+    const int64_t nsk = (int64_t)a.n_showers * a.n_tel;
+    double* accS = nlds + kNode64 * NL;
+    double* accA = accS + nsk;
+    if (sa.cand_lds_acc)
+        for (int64_t q = threadIdx.x; q < 2 * nsk; q += blockDim.x) accS[q] = 0.0;
+    __syncthreads();
+    auto no_bins = [](int, int, double) {};
+    const double inv_nobs = 1.0 / a.n_obs;
+    const double half_inv_nobs3 = 0.5 * inv_nobs * inv_nobs * inv_nobs;
+    double g_psi0 = 0.0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_ids;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t id = sa.ids[q];
+        const int64_t i = (int64_t)(id >> kSoftIdBits);
+        const int32_t k = (int32_t)(id & ((1u << kSoftIdBits) - 1));
+        if (i >= a.n) continue;
+        const int64_t nbf = sa.nb_frozen[i];
+        if (k >= nbf) continue;
+        int lo = 0, hi = a.n_showers;          // the shower holding step i
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.seg_offsets[mid] <= i) lo = mid; else hi = mid;
+        }
+        SoftStep e;
+        if (!soft_step_setup(a, i, nbf, e)) continue;
+        const int64_t seg_id = (a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]);
+        const uint32_t shower_id = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
+        double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
+        double* rowS = (sa.cand_lds_acc ? accS : sa.S) + (int64_t)lo * a.n_tel;
+        double* rowA = (sa.cand_lds_acc ? accA : sa.A) + (int64_t)lo * a.n_tel;
+        soft_bunch<0, true>(a, sa, e, k, (uint32_t)seg_id, shower_id, lo, a.t_ref[lo], tsh, rowS,
+                            rowA, no_bins, inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin,
+                            o_phot);
+    }
+    if (sa.cand_lds_acc) {
+        __syncthreads();
+        for (int64_t q = threadIdx.x; q < nsk; q += blockDim.x) {
+            if (accS[q] != 0.0) atomicAdd(&sa.S[q], accS[q]);
+            if (accA[q] != 0.0) atomicAdd(&sa.A[q], accA[q]);
+        }
     }
 }
 
@@ -2308,6 +2401,7 @@ int launch_run(RunPlan& p)
 int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
 {
     Args a = make_args(p);
+    a.tile_segs = kSoftTS;          // the soft kernels walk 32-step tiles
     hipStream_t st = p.stream;
     const ckv_array* ar = p.arr;
     SoftArgs s{};
@@ -2337,7 +2431,42 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
                          (size_t)a.n_tel * 4 * sizeof(double) +
                          (size_t)kNode64 * soft_node_lds(a.n_nodes) * sizeof(double);
     if (mode == 1 && lds_l > 160 * 1024) s.ids_count = nullptr;
-    s.skip_if_listed = mode == 1 && s.ids_count ? 1 : 0;
+    s.skip_if_listed = s.ids_count ? 1 : 0;
+    // forward with a list: the screening pass (mixed bunch kernel against spheres of
+    // the cut radius plus a margin, frozen counts) lists the candidates, FP64
+    // recomputes them (soft_cand_kernel); the FP64 tile forward runs only if the
+    // list overflowed
+    Args e = a;
+    int e_waves = 0;
+    size_t e_lds = 0;
+    if (mode == 0 && s.ids_count) {
+        e.tel = ar->d_tel_screen;
+        e.gx0 = ar->soft.gx0;
+        e.gy0 = ar->soft.gy0;
+        e.inv_cell = ar->soft.inv_cell;
+        e.nx = ar->soft.nx;
+        e.ny = ar->soft.ny;
+        e.level_cells = ar->soft.level_cells;
+        e.cell_off = ar->soft.d_cell_off;
+        e.cell_list = ar->soft.d_cell_list;
+        e.cell_ent = reinterpret_cast<const uint2*>(ar->soft.d_cell_ent);
+        e.lds_entries = lds_entries(1, e.n_nodes, true);
+        e.nb_frozen = sp.n_b_frozen;
+        e.list_ids = sp.ids;
+        e.list_cap = sp.ids_cap;
+        e.list_count = sp.ids_count;
+        const size_t tab = (table_bytes(1, e.n_nodes, true) + 15) & ~(size_t)15;
+        const size_t per = wave_bytes(1, kSoftTS, e.n_tel, 0) + kScreenWaveBytes;
+        for (int wv = kMaxEmitWaves; wv >= 1 && !e_waves; wv /= 2)
+            if (tab + tel_bytes(e.n_tel) + (size_t)wv * per <= 160 * 1024) {
+                e_waves = wv;
+                e_lds = tab + tel_bytes(e.n_tel) + (size_t)wv * per;
+            }
+        if (!e_waves || e.n_nodes - 1 < 2) {
+            set_error("soft response: tables too large for the screening pass");
+            return CKV_ERR_TABLE;
+        }
+    }
     // as many waves as the kernel's launch bounds allow and the LDS holds
     const int wmax = soft_max_waves(mode);
     int waves = p.emit_waves > 0 && p.emit_waves < wmax ? p.emit_waves : wmax;
@@ -2362,15 +2491,24 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     if (int rc = check_launch("zero")) return rc;
     if (p.params.event_begin) (void)hipEventRecord((hipEvent_t)p.params.event_begin, st);
     if (mode == 0) {
-        allow_lds((const void*)soft_kernel<0, false>, 160 * 1024);
-        allow_lds((const void*)soft_kernel<0, true>, 160 * 1024);
-        if (s.ids_count)
-            soft_kernel<0, true><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
-        else
-            soft_kernel<0, false><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
+        allow_lds((const void*)soft_kernel<0>, 160 * 1024);
+        if (s.ids_count) {
+            allow_lds((const void*)emit_kernel<1, kSoftTS, kFeatScreen>, 160 * 1024);
+            emit_kernel<1, kSoftTS, kFeatScreen><<<p.emit_grid, e_waves * kWave, e_lds, st>>>(e);
+            if (int rc = check_launch("screen")) return rc;
+            size_t lds_c = (size_t)a.n_tel * 4 * sizeof(double) +
+                           (size_t)kNode64 * soft_node_lds(a.n_nodes) * sizeof(double);
+            const size_t acc_b = (size_t)2 * a.n_showers * a.n_tel * sizeof(double);
+            s.cand_lds_acc = lds_c + acc_b <= 160 * 1024 ? 1 : 0;
+            if (s.cand_lds_acc) lds_c += acc_b;
+            allow_lds((const void*)soft_cand_kernel, 160 * 1024);
+            soft_cand_kernel<<<2 * p.emit_grid, kSoftListThreads, lds_c, st>>>(a, s);
+            if (int rc = check_launch("soft candidates")) return rc;
+        }
+        soft_kernel<0><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
     } else {
-        allow_lds((const void*)soft_kernel<1, false>, 160 * 1024);
-        soft_kernel<1, false><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
+        allow_lds((const void*)soft_kernel<1>, 160 * 1024);
+        soft_kernel<1><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
         if (s.ids_count) {
             if (int rc = check_launch("soft")) return rc;
             allow_lds((const void*)soft_list_kernel, 160 * 1024);

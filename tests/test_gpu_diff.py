@@ -180,9 +180,10 @@ def gpu_model_nolist(dw, **kw):
                          **kw)
 
 
-def test_list_is_the_set_of_weighted_bunches(small):
-    """Every listed id names a bunch of the oracle with z >= -40 at some sphere,
-    and every such bunch is listed once (z within 1e-6 of the cut excepted)."""
+def test_list_holds_every_weighted_bunch(small):
+    """The forward's list (the mixed screening pass against spheres of the cut
+    radius plus 1 cm) names every bunch of the oracle with z >= -40 at some sphere,
+    each once; the others it names lie just outside the cut."""
     import torch
     dw, orc, model = small
     model.forward(dw.theta0)
@@ -211,10 +212,12 @@ def test_list_is_the_set_of_weighted_bunches(small):
     want = zmax >= -40.0
     okey = all_seg * (1 << 24) + all_k
     listed = np.isin(okey, key)
-    differ = listed != want
     assert not np.isin(key, okey, invert=True).any()
-    assert np.all(np.abs(zmax[differ] + 40.0) <= 1e-6), (differ.sum(), zmax[differ][:5])
-    say(f"[gpu] soft list: {n} ids = oracle's weighted bunches ({want.sum()}), {differ.sum()} at the cut")
+    assert np.all(listed[want]), (~listed[want]).sum()
+    extra = listed & ~want
+    assert np.all(zmax[extra] > -40.5), np.sort(zmax[extra])[:5]
+    say(f"[gpu] soft list: {n} ids, {want.sum()} weighted bunches of the oracle, {extra.sum()} "
+        f"candidates just outside the cut")
 
 
 def test_list_overflow_recomputes_everything_then_grows(small):
@@ -235,7 +238,7 @@ def test_list_overflow_recomputes_everything_then_grows(small):
     assert m.grow_list()
     m.forward(dw.theta0)
     n2, cap2 = m.list_state()
-    assert n2 == n and cap2 > n
+    assert n2 == n and cap2 > n       # the screening list does not depend on the capacity
     _assert_same_gradient(_tables_backward(m, dw.theta0, gS, gA), ref)
     assert not m.grow_list()
 
