@@ -973,7 +973,9 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                 // slow: traced exactly, cell by cell (grazing bunches; every bunch when curved,
                 // whose upward and turning drops the tracer decides)
                 bool slow = CURVED && drop_why < 0;
-                if (!CURVED && drop_why < 0 && pw <= a.w_min) {
+                // (screening keeps bunches down to w_min - 1e-6, ten times the mixed
+                // direction's error: the FP64 candidate pass applies the exact rule)
+                if (!CURVED && drop_why < 0 && pw <= (SCREEN ? a.w_min - 1e-6 : a.w_min)) {
                     if (EXACT) slow = true;
                     else drop_why = CKV_DROP_GRAZING;
                 }
