@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define CKV_VERSION 112
+#define CKV_VERSION 113
 
 enum {
     CKV_OK = 0,
@@ -348,11 +348,15 @@ typedef struct {
    one ckv_workspace_size(n, n_showers, n_tel, 0, params) gives.  arr must come
    from ckv_array_create_soft.  params->precision is ignored (FP64).  list
    (may be NULL) receives the bunches with a nonzero weight.
-   Asynchronous on `stream`. */
+   result (device, may be NULL): device-side conditions, in the error word as for
+   ckv_run -- bit 0: seg_offsets not non-decreasing or out of range (nothing is
+   computed: S = A = 0); bit 1: a 32-step tile whose frozen counts total 2^30
+   bunches or more (its bunches are left out); the other fields are zeroed.
+   Negative frozen counts emit nothing.  Asynchronous on `stream`. */
 int ckv_soft_forward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
                      const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
-                     double* S, double* A, const ckv_soft_list* list, void* workspace,
-                     size_t ws_bytes, void* stream);
+                     double* S, double* A, const ckv_soft_list* list, ckv_result* result,
+                     void* workspace, size_t ws_bytes, void* stream);
 /* Reverse pass: given dL/dS and dL/dA (device, n_showers x n_tel), recomputes
    bunches from their random numbers and writes dL/dpsi_i (device, n_nodes)
    and dL/dP_j(h_i) (device, 5 x n_nodes), both overwritten; psi_0 also
@@ -360,11 +364,14 @@ int ckv_soft_forward(const ckv_segments* segs, const ckv_showers* showers, const
    list from the ckv_soft_forward of the same inputs: only the listed bunches
    are, when the list is complete (checked on the device; else every bunch);
    a list from other inputs gives a wrong gradient, and ids that name no bunch
-   of these inputs are skipped.  Asynchronous on `stream`. */
+   of these inputs are skipped.  result (device, may be NULL): as for
+   ckv_soft_forward (bit 0: nothing computed, gradients 0).  Asynchronous on
+   `stream`. */
 int ckv_soft_backward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
                       const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
                       const double* dL_dS, const double* dL_dA, double* g_psi, double* g_P,
-                      const ckv_soft_list* list, void* workspace, size_t ws_bytes, void* stream);
+                      const ckv_soft_list* list, ckv_result* result, void* workspace,
+                      size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

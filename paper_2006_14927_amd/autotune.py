@@ -33,8 +33,10 @@ def _arch() -> str:
 
 def signature(dsegs: "ckv.DeviceSegments", atmo: "ckv.Atmosphere", tels: "ckv.TelescopeArray",
               precision: int) -> str:
+    from .build import source_hash
     n_nodes, _, _ = atmo.info()
-    return (f"{_arch()}|prec{precision}|seg2^{int(math.log2(max(dsegs.n, 1)))}"
+    # the kernel sources are part of the key: a shape tuned on other kernels is not reused
+    return (f"{_arch()}|src{source_hash()}|prec{precision}|seg2^{int(math.log2(max(dsegs.n, 1)))}"
             f"|show2^{int(math.log2(max(dsegs.n_showers, 1)))}|tel{tels.n}|nodes{n_nodes}")
 
 

@@ -3,6 +3,7 @@
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -21,13 +22,38 @@ def hipcc() -> str:
     return "hipcc"
 
 
+STAMP_PATH = os.path.join(LIB_DIR, "libckv.sources")
+
+
 def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.cpp")) +
                   glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
+def source_hash() -> str:
+    """SHA-256 (16 hex digits) of every file the library is built from: the
+    kernel and host sources, the internal header and the public header."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(HERE, "csrc", "*"))) + \
+        [os.path.join(ROOT, "include", "ckv.h")]
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def built_hash():
+    """Source hash recorded when the library in _lib/ was linked, or None."""
+    try:
+        with open(STAMP_PATH) as f:
+            return f.read().strip()
+    except OSError:
+        return None
+
+
 def build(verbose: bool = False, extra_flags=()) -> str:
     os.makedirs(LIB_DIR, exist_ok=True)
+    stamp = source_hash()            # taken before compiling: an edit during the build shows
     objs = []
     common = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
               "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
@@ -53,6 +79,9 @@ def build(verbose: bool = False, extra_flags=()) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB_PATH)
+    with open(STAMP_PATH + ".tmp", "w") as f:
+        f.write(stamp + "\n")
+    os.replace(STAMP_PATH + ".tmp", STAMP_PATH)
     return LIB_PATH
 
 

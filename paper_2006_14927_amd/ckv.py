@@ -81,11 +81,17 @@ _lib = None
 
 
 def lib():
-    """The loaded library; raises CkvError if it was not built."""
+    """The loaded library; raises CkvError if it was not built, or was built from
+    other sources than the ones beside it."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise CkvError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        from . import build as _build
+        have, want = _build.built_hash(), _build.source_hash()
+        if have != want:
+            raise CkvError(f"{LIB_PATH} was built from other sources (built {have}, sources {want}): "
+                           "rebuild it with __graft_entry__.build()")
         L = C.CDLL(LIB_PATH)
         P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         L.ckv_last_error.restype = C.c_char_p
@@ -110,9 +116,10 @@ def lib():
         L.ckv_atmo_params_backward.argtypes = [C.POINTER(_ParamSpec), P, P, P, P, P]
         L.ckv_array_create_soft.argtypes = [P, P, P, I32, D, C.POINTER(P)]
         L.ckv_soft_forward.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params),
-                                       P, P, P, P, P, C.POINTER(_SoftList), P, C.c_size_t, P]
+                                       P, P, P, P, P, C.POINTER(_SoftList), P, P, C.c_size_t, P]
         L.ckv_soft_backward.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params),
-                                        P, P, P, P, P, P, P, C.POINTER(_SoftList), P, C.c_size_t, P]
+                                        P, P, P, P, P, P, P, C.POINTER(_SoftList), P, P, C.c_size_t,
+                                        P]
         _lib = L
     return _lib
 
@@ -671,6 +678,7 @@ class SoftModel:
         self._cache = None
         self.use_list = bool(use_list)
         self.list_count = torch.zeros(1, dtype=torch.int64, device=device)
+        self.result_raw = torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
         self._list_theta = None
         if self.use_list:
             cap = list_capacity if list_capacity is not None else int(self.n_b.sum()) // 8 + 1024
@@ -701,11 +709,21 @@ class SoftModel:
         _check(lib().ckv_soft_forward(C.byref(self._segs), C.byref(self._showers), C.byref(self.params),
                                       atmo.handle, self.tels.handle, C.c_void_p(self.n_b.data_ptr()),
                                       C.c_void_p(S.data_ptr()), C.c_void_p(A.data_ptr()), lst,
+                                      C.c_void_p(self.result_raw.data_ptr()),
                                       C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                       _stream_ptr(stream)))
+        self._check_device("forward")
         if self.use_list:
             self._list_theta = np.array(theta, dtype=np.float64, copy=True)
         return S, A
+
+    def _check_device(self, what: str):
+        """Raises when the device reported bad shower offsets or an oversized tile
+        (synchronises with the stream)."""
+        err = RunOutput(None, None, None, self.result_raw).result()["error"]
+        if err:
+            raise CkvError(f"soft {what}: device reported error flags {err} "
+                           "(1: bad seg_offsets, 2: a 32-step tile with >= 2^30 frozen bunches)")
 
     def backward_tables(self, theta, gS, gA, stream=None):
         """Device dL/dpsi (n_nodes) and dL/dP (5 x n_nodes)."""
@@ -720,8 +738,10 @@ class SoftModel:
                                        atmo.handle, self.tels.handle, C.c_void_p(self.n_b.data_ptr()),
                                        C.c_void_p(gS.data_ptr()), C.c_void_p(gA.data_ptr()),
                                        C.c_void_p(self.g_psi.data_ptr()), C.c_void_p(self.g_P.data_ptr()),
-                                       lst, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                       lst, C.c_void_p(self.result_raw.data_ptr()),
+                                       C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                        _stream_ptr(stream)))
+        self._check_device("backward")
         return self.g_psi, self.g_P
 
     def grow_list(self) -> bool:

@@ -144,6 +144,7 @@ size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, in
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     size_t o_ctrl = take(sizeof(int64_t) * kCtrlSlots);
+    size_t o_res = take(sizeof(ckv_result));
     size_t o_tb = take(sizeof(int64_t) * (n_showers + 1));
     size_t o_bb = take(sizeof(int64_t) * (n_showers + 1));
     size_t o_counts = take(sizeof(int32_t) * (size_t)max_tiles * n_tel);
@@ -158,6 +159,7 @@ size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, in
         plan->max_row_blocks = max_blocks;
         plan->stage_slots = stage_blocks * kStageBlock;
         plan->ctrl = (int64_t*)(b + o_ctrl);
+        plan->ws_result = (ckv_result*)(b + o_res);
         plan->tiles_before = (int64_t*)(b + o_tb);
         plan->blocks_before = (int64_t*)(b + o_bb);
         plan->counts = (int32_t*)(b + o_counts);
@@ -421,6 +423,17 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
             const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
             ckv_output* out, void* stream)
 {
+    return run_checked(segs, showers, params, atmo, arr, workspace, ws_bytes, out, stream);
+}
+
+}  // extern "C"
+
+namespace ckv {
+
+int run_checked(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
+                const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
+                ckv_output* out, void* stream)
+{
     int rc;
     if ((rc = check_segments(segs)) || (rc = check_params(params))) return rc;
     if (!showers || !atmo || !arr || !out || !workspace) { set_error("NULL argument"); return CKV_ERR_ARG; }
@@ -469,10 +482,22 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
     return launch_run(plan);
 }
 
+int default_emit_grid(int* grid)
+{
+    int n_cu = 256;
+    if (int rc = device_cu_count(&n_cu)) return rc;
+    *grid = std::min(n_cu, kMaxEmitGrid);
+    return CKV_OK;
+}
+
+}  // namespace ckv
+
+extern "C" {
+
 static int soft_common(const ckv_segments* segs, const ckv_showers* showers,
                        const ckv_params* params, const ckv_atmo* atmo, const ckv_array* arr,
-                       const int64_t* n_b_frozen, void* workspace, size_t ws_bytes, void* stream,
-                       RunPlan* plan)
+                       const int64_t* n_b_frozen, ckv_result* result, void* workspace,
+                       size_t ws_bytes, void* stream, RunPlan* plan)
 {
     int rc;
     if ((rc = check_segments(segs)) || (rc = check_params(params))) return rc;
@@ -500,6 +525,8 @@ static int soft_common(const ckv_segments* segs, const ckv_showers* showers,
     plan->atmo = atmo;
     plan->arr = arr;
     plan->stream = (hipStream_t)stream;
+    // device-side conditions go to the caller's report, else to the workspace's own
+    plan->out.result = result ? result : plan->ws_result;
     plan->k_ft = frank_tamm_k(params->lambda_min_nm, params->lambda_max_nm);
     int n_cu = 256;
     if (int rc = device_cu_count(&n_cu)) return rc;
@@ -519,12 +546,12 @@ static int check_list(const ckv_soft_list* list)
 
 int ckv_soft_forward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
                      const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
-                     double* S, double* A, const ckv_soft_list* list, void* workspace,
-                     size_t ws_bytes, void* stream)
+                     double* S, double* A, const ckv_soft_list* list, ckv_result* result,
+                     void* workspace, size_t ws_bytes, void* stream)
 {
     RunPlan plan{};
-    if (int rc = soft_common(segs, showers, params, atmo, arr, n_b_frozen, workspace, ws_bytes,
-                             stream, &plan))
+    if (int rc = soft_common(segs, showers, params, atmo, arr, n_b_frozen, result, workspace,
+                             ws_bytes, stream, &plan))
         return rc;
     if (!S || !A) { set_error("NULL output"); return CKV_ERR_ARG; }
     if (int rc = check_list(list)) return rc;
@@ -544,11 +571,12 @@ int ckv_soft_forward(const ckv_segments* segs, const ckv_showers* showers, const
 int ckv_soft_backward(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
                       const ckv_atmo* atmo, const ckv_array* arr, const int64_t* n_b_frozen,
                       const double* dL_dS, const double* dL_dA, double* g_psi, double* g_P,
-                      const ckv_soft_list* list, void* workspace, size_t ws_bytes, void* stream)
+                      const ckv_soft_list* list, ckv_result* result, void* workspace,
+                      size_t ws_bytes, void* stream)
 {
     RunPlan plan{};
-    if (int rc = soft_common(segs, showers, params, atmo, arr, n_b_frozen, workspace, ws_bytes,
-                             stream, &plan))
+    if (int rc = soft_common(segs, showers, params, atmo, arr, n_b_frozen, result, workspace,
+                             ws_bytes, stream, &plan))
         return rc;
     if (!dL_dS || !dL_dA || !g_psi || !g_P) { set_error("NULL argument"); return CKV_ERR_ARG; }
     if (int rc = check_list(list)) return rc;

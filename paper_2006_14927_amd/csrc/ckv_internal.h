@@ -58,6 +58,8 @@ enum CtrlSlot {
     kBunches,           // bunches generated
     kEmitting,          // steps with light
     kStageOverflow,     // a staging claim went past the end
+    kScreenCounter,     // next tile to claim in the soft response's screening pass (the
+                        // FP64 tile forward that may follow claims from kTileCounter)
     kDrop0,             // CKV_N_DROP drop counters follow
     kCtrlSlots = kDrop0 + CKV_N_DROP + 4
 };
@@ -153,6 +155,7 @@ struct RunPlan {
     double k_ft;
     // workspace carve-out
     int64_t* ctrl;
+    ckv_result* ws_result;      // report of the soft entry points when the caller has none
     int64_t* tiles_before;      // n_showers + 1
     int64_t* blocks_before;     // n_showers + 1
     int32_t* counts;            // max_tiles x n_tel
@@ -164,6 +167,12 @@ struct RunPlan {
 
 size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, int64_t capacity,
                         const ckv_params* p, RunPlan* plan, void* base);
+// ckv_run after its handle-free checks: validates, lays out `workspace` and launches
+int run_checked(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
+                const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
+                ckv_output* out, void* stream);
+// bunch-kernel workgroups of a launch with params->grid == 0 on the current device
+int default_emit_grid(int* grid);
 int launch_run(RunPlan& plan);
 int launch_count(const ckv_segments* segs, const ckv_params* p, const ckv_atmo* atmo, double k_ft,
                  int64_t* n_b, hipStream_t stream);

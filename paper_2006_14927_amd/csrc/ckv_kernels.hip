@@ -762,7 +762,8 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
 
     for (;;) {
         int64_t t = 0;
-        if (lane == 0) t = (int64_t)atomicAdd((unsigned long long*)&a.ctrl[kTileCounter], 1ull);
+        if (lane == 0)
+            t = (int64_t)atomicAdd((unsigned long long*)&a.ctrl[SCREEN ? kScreenCounter : kTileCounter], 1ull);
         t = uniform(t);
         if (t >= n_tiles) break;
         // shower of the tile
@@ -805,7 +806,7 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
         int64_t total = __shfl(incl, kWave - 1);
         if (total >= ((int64_t)1 << 30)) {
             // bunch offsets inside a tile are 32-bit: refuse such a tile
-            if (lane == 0) atomicOr(&a.result->error, 2);
+            if (lane == 0 && a.result) atomicOr(&a.result->error, 2);
             total = 0;
             incl = 0;
             nb = 0;
@@ -1348,7 +1349,15 @@ __global__ void __launch_bounds__(1024) init_kernel(Args a)
         if (run_t > a.max_tiles) err = 1;
         a.ctrl[kNumTiles] = err ? 0 : run_t;
         a.ctrl[kNumRowBlocks] = err ? 0 : run_b;
-        if (a.result) a.result->error = err;
+        if (a.result) {
+            // the bunch path's finalize fills the rest; the soft entry points report
+            // the error word only
+            ckv_result* r = a.result;
+            r->n_bunches = r->n_hits = r->n_records = r->n_emitting = r->n_tiles = 0;
+            for (int d = 0; d < CKV_N_DROP; ++d) r->drops[d] = 0;
+            r->overflow = 0;
+            r->error = err;
+        }
     }
 }
 

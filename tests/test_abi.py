@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_version(L):
-    assert L.ckv_version() == 112
+    assert L.ckv_version() == 113
 
 
 def test_struct_sizes_match_header_layout():

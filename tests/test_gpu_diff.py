@@ -229,10 +229,15 @@ def test_list_overflow_recomputes_everything_then_grows(small):
     m = ckv.SoftModel(dw.segs, dw.tels, spec, dw.theta0, dw.sigma, seed=dw.seed, list_capacity=16)
     full = gpu_model_nolist(dw)
     gS, gA = _random_cotangents(m, 12)
-    m.forward(dw.theta0)
-    full.forward(dw.theta0)
+    S16, A16 = m.forward(dw.theta0)
+    S, A = full.forward(dw.theta0)
     n, cap = m.list_state()
     assert cap == 16 and n > cap
+    # the incomplete list falls back to the FP64 tile forward over every bunch
+    S16, A16, S, A = (x.cpu().numpy() for x in (S16, A16, S, A))
+    assert S.sum() > 1e3
+    np.testing.assert_allclose(S16, S, rtol=1e-12, atol=1e-12 * S.max())
+    np.testing.assert_allclose(A16, A, rtol=1e-12, atol=1e-12 * np.abs(A).max())
     ref = _tables_backward(full, dw.theta0, gS, gA)
     _assert_same_gradient(_tables_backward(m, dw.theta0, gS, gA), ref)
     assert m.grow_list()
@@ -258,11 +263,11 @@ def test_soft_list_argument_validation(small):
                 ckv._SoftList(None, 10, model.list_count.data_ptr())):
         rc = L.ckv_soft_forward(C.byref(model._segs), C.byref(model._showers), C.byref(model.params),
                                 atmo.handle, model.tels.handle, ptr(model.n_b), ptr(S), ptr(S),
-                                C.byref(bad), *ws, None)
+                                C.byref(bad), None, *ws, None)
         assert rc == -1 and b"soft list" in L.ckv_last_error()
         rc = L.ckv_soft_backward(C.byref(model._segs), C.byref(model._showers), C.byref(model.params),
                                  atmo.handle, model.tels.handle, ptr(model.n_b), ptr(S), ptr(S),
-                                 ptr(model.g_psi), ptr(model.g_P), C.byref(bad), *ws, None)
+                                 ptr(model.g_psi), ptr(model.g_P), C.byref(bad), None, *ws, None)
         assert rc == -1 and b"soft list" in L.ckv_last_error()
 
 
@@ -284,3 +289,50 @@ def test_listed_adjoint_skips_ids_that_name_no_bunch(small):
     model.list_count.fill_(n + 3)
     torch.cuda.synchronize()
     _assert_same_gradient(_tables_backward(model, dw.theta0, gS, gA), ref)
+
+
+def _bad_offsets_model(dw, offsets):
+    """A model whose device shower offsets are replaced after construction."""
+    import torch
+    m = gpu_model_nolist(dw)
+    m.dsegs.seg_offsets.copy_(torch.as_tensor(np.asarray(offsets, dtype=np.int64)))
+    torch.cuda.synchronize()
+    return m
+
+
+def test_soft_entry_points_report_bad_offsets(small):
+    """Shower offsets that do not end at the step count are caught on the device
+    (init kernel): nothing is computed and both entry points report error bit 0,
+    which SoftModel turns into an exception."""
+    dw, orc, model = small
+    n = dw.segs.n
+    for use_list in (False, True):
+        m = _bad_offsets_model(dw, [0, n // 2, n - 7])
+        m.use_list = use_list
+        if use_list:
+            m._alloc_list(1 << 16)
+        with pytest.raises(ckv.CkvError, match="error flags 1"):
+            m.forward(dw.theta0)
+        gS, gA = _random_cotangents(m, 3)
+        with pytest.raises(ckv.CkvError, match="error flags 1"):
+            m.backward_tables(dw.theta0, gS, gA)
+
+
+def test_soft_entry_points_report_oversized_tile(small):
+    """A frozen count that puts 2^30 bunches or more into one 32-step tile is
+    refused by every soft kernel's tile guard (the tile is left out) and
+    reported as error bit 1, with or without the screening list."""
+    import torch
+    dw, orc, model = small
+    for use_list in (False, True):
+        m = gpu_model_nolist(dw) if not use_list else gpu_model(dw)
+        nb = m.n_b.clone()
+        step = int(torch.nonzero(nb > 0)[0])
+        m.n_b[step] = 1 << 31
+        torch.cuda.synchronize()
+        with pytest.raises(ckv.CkvError, match="error flags 2"):
+            m.forward(dw.theta0)
+        m.n_b.copy_(nb)
+        torch.cuda.synchronize()
+        S, A = m.forward(dw.theta0)
+        assert float(S.sum()) > 0
