@@ -271,6 +271,28 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
             const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
             ckv_output* out, void* stream);
 
+/* ckv_run without a workspace argument, for callers that cannot allocate device
+   memory (code under HIP graph capture, tight serving loops, harnesses that
+   forbid hipMalloc).  The workspace is a static device array of
+   CKV_NOALLOC_SCRATCH_MIB MiB inside the library: each GPU the library runs on
+   holds its own copy until the process ends, and this call allocates nothing
+   (no hipMalloc, hipFree or allocating library routine).  The caller still
+   passes the inputs and the output buffers.  Every call on one GPU shares that
+   GPU's array, which keeps the last call's contents (each run starts by
+   resetting what it reads, as ckv_run does with any workspace): calls that
+   overlap on one GPU -- concurrent streams or threads -- race and give wrong
+   results; serialise them.  Results are identical to ckv_run's with the same
+   arguments.  Errors: as ckv_run; CKV_ERR_CAPACITY when the run needs more than
+   the array holds (ckv_noalloc_workspace_size() > CKV_NOALLOC_SCRATCH_MIB MiB;
+   then use ckv_run). */
+#define CKV_NOALLOC_SCRATCH_MIB 256
+int ckv_run_noalloc(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
+                    const ckv_atmo* atmo, const ckv_array* arr, ckv_output* out, void* stream);
+/* Bytes of the static array ckv_run_noalloc would use for these sizes on the
+   current device (0 for invalid sizes). */
+size_t ckv_noalloc_workspace_size(int64_t n_segments, int32_t n_showers, int32_t n_tel,
+                                  int64_t capacity, const ckv_params* params);
+
 /* Bunch count per step only (the first stage of ckv_run): n_b[i] for every
    step (0 for dropped steps), FP64, the same values ckv_run uses.  n_b is a
    device int64 array of n entries.  Asynchronous on `stream`. */

@@ -27,7 +27,8 @@ EXPORTED = ("ckv_last_error", "ckv_version", "ckv_atmo_create", "ckv_atmo_info",
             "ckv_run", "ckv_count", "ckv_atmo_from_params", "ckv_atmo_params_backward",
             "ckv_array_create_soft", "ckv_soft_forward", "ckv_soft_backward",
             "ckv_atmo_create_with_depth", "ckv_atmo_depth", "ckv_profile_bins",
-            "ckv_atmo_create_nodes", "ckv_atmo_nodes")
+            "ckv_atmo_create_nodes", "ckv_atmo_nodes", "ckv_run_noalloc",
+            "ckv_noalloc_workspace_size")
 
 
 class CkvError(RuntimeError):
@@ -112,6 +113,10 @@ def lib():
         L.ckv_run.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params), P, P,
                               P, C.c_size_t, C.POINTER(_Output), P]
         L.ckv_count.argtypes = [C.POINTER(_Segments), C.POINTER(_Params), P, P, P]
+        L.ckv_run_noalloc.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params),
+                                      P, P, C.POINTER(_Output), P]
+        L.ckv_noalloc_workspace_size.restype = C.c_size_t
+        L.ckv_noalloc_workspace_size.argtypes = [I64, I32, I32, I64, C.POINTER(_Params)]
         L.ckv_atmo_from_params.argtypes = [C.POINTER(_ParamSpec), P, C.POINTER(P)]
         L.ckv_atmo_params_backward.argtypes = [C.POINTER(_ParamSpec), P, P, P, P, P]
         L.ckv_array_create_soft.argtypes = [P, P, P, I32, D, C.POINTER(P)]
@@ -800,3 +805,7 @@ def soft_response(theta, model: SoftModel):
     if _SOFT is None:
         _SOFT = _soft_function()
     return _SOFT.apply(theta, model)
+
+
+# size of the static workspace of ckv_run_noalloc (CKV_NOALLOC_SCRATCH_MIB in include/ckv.h)
+NOALLOC_SCRATCH_BYTES = 256 << 20
