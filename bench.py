@@ -19,11 +19,12 @@ from __future__ import annotations
 
 import argparse
 import ctypes as C
-import hashlib
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -76,6 +77,11 @@ OPS_FP64 = {
     "observed direction, record conversions": 6,
     "candidate cell + sphere tests": 16,
 }
+# The survey's per-bunch issue-slot counts of the algorithm (lane-slots per
+# generated bunch, issue-cycle weighted): 280-300 for the mixed path, 380-450 for
+# plain FP64; the midpoints are the counts the roofline fraction is priced with.
+# The itemised counts above (the builder's own model) are reported beside them.
+SURVEY_SLOTS = {"mixed": 290.0, "fp64": 415.0}
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one VALU operation per lane
 # per clock (FP32 non-packed and FP64 both issue at this rate on CDNA4)
 PEAK_OPS_PER_S = 256 * 4 * 16 * 2.4e9
@@ -134,12 +140,40 @@ def _elapsed_ms(hip, a, b) -> float:
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2006_14927_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
-    return h.hexdigest()[:16]
+    from paper_2006_14927_amd.build import source_hash
+    return source_hash()
+
+
+ZENITH_SAMPLE_STRIDE = 250       # every 250th step of each 5e7-step shower is certified
+
+
+def emit_kernel_name(precision: int, tile_segments: int, waves: int) -> str:
+    """Symbol of the bunch kernel a plain run launches (the mixed kernel has a
+    build for at most 8 waves per workgroup, feature bit 16)."""
+    feat = 16 if (precision == 1 and waves <= 8) else 0
+    return f"void ckv::emit_kernel<{precision}, {tile_segments}, {feat}>(ckv::Args)"
+
+
+def _profile_kv(path: str) -> dict:
+    kv = {}
+    if os.path.exists(path):
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
+def stored_issue_frac(kernel: str, workload: str):
+    """VALU issue fraction of a kernel from the committed rocprofv3 SQ summary of
+    the workload, if it was taken on the current sources; else None."""
+    kv = _profile_kv(os.path.join(ROOT, "profiles", f"sq_bunch_kernel_{workload}.txt"))
+    if kv.get("kernel_sources_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(kv[f"issue_frac {kernel}"])
+    except (KeyError, ValueError):
+        return None
 
 
 def stored_traffic(name: str):
@@ -187,6 +221,53 @@ def time_path(hip, ckv, dsegs, atmo, tels, params, capacity, steps, warmup, stre
         hip.hipEventDestroy(b)
         hip.hipEventDestroy(e)
     return total_ms / steps, sum(kern_ms) / len(kern_ms), out.result()
+
+
+def gpu_records(ckv, dsegs, atmo, tels, params, capacity, step_stride=0):
+    """One untimed run of the same launch with ids on: host copies of the CSR
+    offsets, the records and their (step, bunch) ids, and the report.  With
+    step_stride > 0 only the records of every step_stride-th step are copied
+    (selected on the device)."""
+    import torch
+    p = ckv._Params.from_buffer_copy(params)
+    p.event_begin = p.event_end = None
+    r = ckv.Runner(dsegs, atmo, tels, p, capacity, want_ids=True)
+    out = r.run()
+    torch.cuda.synchronize()
+    res = out.result()
+    if res["overflow"] or res["error"]:
+        raise RuntimeError(f"certification run reported a problem: {res}")
+    n = int(res["n_records"])
+    ids, rec = out.ids[:n], out.records[:n]
+    offsets = out.tel_offsets.cpu().numpy().copy()
+    if step_stride > 0:
+        # each record's (shower, telescope) group, then keep the sampled steps
+        counts = torch.diff(out.tel_offsets)
+        group = torch.repeat_interleave(torch.arange(counts.numel(), device=ids.device), counts)
+        keep = (ids[:, 0] % step_stride) == 0
+        got = dict(group=group[keep].cpu().numpy(), ids=ids[keep].cpu().numpy(),
+                   rec=rec[keep].cpu().numpy(), res=res, offsets=None)
+    else:
+        counts = np.diff(offsets)
+        got = dict(group=np.repeat(np.arange(len(counts)), counts), ids=ids.cpu().numpy(),
+                   rec=rec.cpu().numpy(), res=res, offsets=offsets)
+    del r, out
+    torch.cuda.empty_cache()
+    return got
+
+
+def cpu_info() -> dict:
+    """Host CPU as the machine that runs the bench reports it."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity_cores": len(os.sched_getaffinity(0))}
 
 
 EARTH_RADIUS_M = 6.371e6
@@ -285,9 +366,23 @@ def diff_timing(hip, reps: int, n_showers: int = 64, n_seg: int = 500_000):
             "grad_norm": float(g.norm())}
 
 
+def roofline_block(slots_survey: float, slots_builder: float, bunches: int, kernel_ms: float,
+                   issue_frac=None) -> dict:
+    """VALU issue-slot roofline of a bunch kernel: algorithmic slots per bunch x
+    bunches / kernel time against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz."""
+    achieved = slots_survey * bunches / (kernel_ms * 1e-3) / 1e12
+    peak = PEAK_OPS_PER_S / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+            "frac": achieved / peak, "slots_per_bunch": slots_survey,
+            "frac_builder_model": slots_builder * bunches / (kernel_ms * 1e-3) / PEAK_OPS_PER_S,
+            "slots_per_bunch_builder_model": slots_builder, "issue_frac": issue_frac}
+
+
 def batched_timing(hip, reps: int, use_cache: bool = True):
     """256 showers (~3e8 steps, ~2e10 bunches) in one persistent launch, the whole
-    run captured into a HIP graph and replayed; mixed precision, autotuned shape."""
+    run captured into a HIP graph and replayed; mixed precision and plain FP64,
+    each with its autotuned launch shape.  The bunch kernel's own time comes from
+    two eager runs of the same launch with HIP events around it."""
     import torch
 
     from paper_2006_14927_amd import autotune, ckv, synth
@@ -295,60 +390,93 @@ def batched_timing(hip, reps: int, use_cache: bool = True):
     atmo = ckv.Atmosphere(wl.atmo.alt, wl.atmo.eta, wl.atmo.obs_level, wl.fine_step)
     tels = ckv.TelescopeArray(wl.tels.x, wl.tels.y, wl.tels.r)
     d = ckv.DeviceSegments(wl.segs)
-    p = ckv.make_params(precision=ckv.CKV_MIXED, bunch_size=wl.bunch_size, lambda_min=wl.lambda_min,
-                        lambda_max=wl.lambda_max, seed=wl.seed)
-    total = int(ckv.count(d, atmo, p).sum())
+    stream = torch.cuda.current_stream()
+
+    def mk(prec):
+        return ckv.make_params(precision=prec, bunch_size=wl.bunch_size, lambda_min=wl.lambda_min,
+                               lambda_max=wl.lambda_max, seed=wl.seed)
+
+    total = int(ckv.count(d, atmo, mk(ckv.CKV_MIXED)).sum())
     cap = int(0.02 * total)
-    probe = ckv.Runner(d, atmo, tels, p, cap, want_ids=False).run()
+    probe = ckv.Runner(d, atmo, tels, mk(ckv.CKV_MIXED), cap, want_ids=False).run()
     torch.cuda.synchronize()
     res = probe.result()
     if res["overflow"]:
         cap = int(res["n_hits"]) + 1024
     del probe
     torch.cuda.empty_cache()
-    tuned = autotune.tune(d, atmo, tels, p, cap, candidates=[(32, 16), (64, 16), (32, 8), (16, 16)],
-                          reps=1, use_cache=use_cache)
-    q = autotune.apply(p, tuned)
-    gr = ckv.GraphRunner(ckv.Runner(d, atmo, tels, q, cap, want_ids=False))
-    gr.replay()
-    torch.cuda.synchronize()
-    sp = C.c_void_p(gr.stream.cuda_stream)
-    t0, t1 = _event(hip), _event(hip)
-    hip.hipEventRecord(t0, sp)
-    for _ in range(reps):
-        with torch.cuda.stream(gr.stream):
-            out = gr.replay()
-    hip.hipEventRecord(t1, sp)
-    hip.hipEventSynchronize(t1)
-    torch.cuda.synchronize()
-    ms = _elapsed_ms(hip, t0, t1) / reps
-    hip.hipEventDestroy(t0)
-    hip.hipEventDestroy(t1)
-    res = out.result()
-    if res["overflow"] or res["error"] or res["n_bunches"] != total:
-        raise RuntimeError(f"batched run reported a problem: {res}")
-    return {"workload": wl.name, "showers": wl.segs.n_showers, "steps": wl.segs.n,
-            "bunches": total, "records": res["n_hits"], "ms_per_launch": ms,
-            "bunches_per_s": total / (ms * 1e-3), "graph_replays": reps,
-            "launch": {"tile_segments": tuned["tile_segments"],
-                       "waves_per_group": tuned["waves_per_group"]}}
+    out = {"workload": wl.name, "showers": wl.segs.n_showers, "steps": wl.segs.n,
+           "bunches": total, "graph_replays": reps}
+    cands = {ckv.CKV_MIXED: [(32, 16), (64, 16), (32, 8), (16, 16)],
+             ckv.CKV_FP64: [(32, 8), (64, 8), (16, 8), (32, 4)]}
+    for prec, name in ((ckv.CKV_MIXED, "mixed"), (ckv.CKV_FP64, "fp64_plain")):
+        tuned = autotune.tune(d, atmo, tels, mk(prec), cap, candidates=cands[prec], reps=1,
+                              use_cache=use_cache)
+        q = autotune.apply(mk(prec), tuned)
+        gr = ckv.GraphRunner(ckv.Runner(d, atmo, tels, q, cap, want_ids=False))
+        gr.replay()
+        torch.cuda.synchronize()
+        sp = C.c_void_p(gr.stream.cuda_stream)
+        t0, t1 = _event(hip), _event(hip)
+        hip.hipEventRecord(t0, sp)
+        for _ in range(reps):
+            with torch.cuda.stream(gr.stream):
+                o = gr.replay()
+        hip.hipEventRecord(t1, sp)
+        hip.hipEventSynchronize(t1)
+        torch.cuda.synchronize()
+        ms = _elapsed_ms(hip, t0, t1) / reps
+        hip.hipEventDestroy(t0)
+        hip.hipEventDestroy(t1)
+        res = o.result()
+        if res["overflow"] or res["error"] or res["n_bunches"] != total:
+            raise RuntimeError(f"batched {name} run reported a problem: {res}")
+        del gr, o
+        torch.cuda.empty_cache()
+        _, kms, _ = time_path(hip, ckv, d, atmo, tels, q, cap, 2, 0, stream)
+        torch.cuda.empty_cache()
+        key = "mixed" if prec == ckv.CKV_MIXED else "fp64"
+        ops = OPS_MIXED if prec == ckv.CKV_MIXED else OPS_FP64
+        out[name] = {"ms_per_launch": ms, "bunches_per_s": total / (ms * 1e-3),
+                     "records": res["n_hits"], "bunch_kernel_ms": kms,
+                     "launch": {"tile_segments": tuned["tile_segments"],
+                                "waves_per_group": tuned["waves_per_group"]},
+                     "roofline": roofline_block(SURVEY_SLOTS[key], sum(ops.values()), total, kms,
+                                                stored_issue_frac(emit_kernel_name(
+                                                    prec, tuned["tile_segments"],
+                                                    tuned["waves_per_group"]), "batched_256"))}
+        print(f"# batched {name}: {ms:.2f} ms per graph launch, bunch kernel {kms:.2f} ms",
+              file=sys.stderr, flush=True)
+    out["ms_per_launch"] = out["mixed"]["ms_per_launch"]
+    out["bunches_per_s"] = out["mixed"]["bunches_per_s"]
+    out["records"] = out["mixed"]["records"]
+    out["mixed_over_fp64"] = out["fp64_plain"]["ms_per_launch"] / out["mixed"]["ms_per_launch"]
+    return out
 
 
-def streamed_timing(hip, zeniths=(0.0, 20.0, 40.0, 60.0)):
-    """One 5e7-step hadron-like shower per zenith, mixed precision, output streamed
-    to pinned host memory in chunks of 8 388 608 records (256 MB); timed from the
-    bunch counts to the last chunk on the host."""
+def streamed_timing(hip, zeniths=(0.0, 20.0, 40.0, 60.0), sample_stride: int = 250):
+    """One 5e7-step hadron-like shower per zenith: the mixed-precision output
+    streamed to pinned host memory in chunks of 8 388 608 records (256 MB), timed
+    from the bunch counts to the last chunk on the host; then both precisions
+    resident in HBM (one ckv_run over the whole shower, bunch kernel timed by
+    events), and the records of every sample_stride-th step of an untimed mixed
+    run kept for the per-zenith comparison with the oracle."""
     import torch
 
     from paper_2006_14927_amd import ckv, synth
-    out = []
+    out, samples = [], []
+    stream = torch.cuda.current_stream()
     for z in zeniths:
         wl = synth.hadron_like(z)
         atmo = ckv.Atmosphere(wl.atmo.alt, wl.atmo.eta, wl.atmo.obs_level, wl.fine_step)
         tels = ckv.TelescopeArray(wl.tels.x, wl.tels.y, wl.tels.r)
         d = ckv.DeviceSegments(wl.segs)
-        p = ckv.make_params(precision=ckv.CKV_MIXED, bunch_size=wl.bunch_size,
-                            lambda_min=wl.lambda_min, lambda_max=wl.lambda_max, seed=wl.seed)
+
+        def mk(prec):
+            return ckv.make_params(precision=prec, bunch_size=wl.bunch_size,
+                                   lambda_min=wl.lambda_min, lambda_max=wl.lambda_max, seed=wl.seed)
+
+        p = mk(ckv.CKV_MIXED)
         ckv.Streamer(d, atmo, tels, p, want_ids=False)        # warm: allocations, first launch
         torch.cuda.synchronize()
         agg = dict(chunks=0, records=0, bunches=0)
@@ -365,12 +493,50 @@ def streamed_timing(hip, zeniths=(0.0, 20.0, 40.0, 60.0)):
         n_chunks, n_rec, n_b = agg["chunks"], agg["records"], agg["bunches"]
         if n_b != st.total_bunches:
             raise RuntimeError("streamed bunch count mismatch")
-        out.append({"zenith_deg": z, "steps": wl.segs.n, "bunches": n_b, "records": n_rec,
-                    "chunks": n_chunks, "reruns": st.n_reruns, "s": dt, "bunches_per_s": n_b / dt})
-        print(f"# streamed {wl.name}: {out[-1]}", file=sys.stderr, flush=True)
-        del st, d
+        del st
         torch.cuda.empty_cache()
-    return out
+        entry = {"zenith_deg": z, "steps": wl.segs.n, "bunches": n_b, "records": n_rec,
+                 "chunks": n_chunks, "s": dt, "bunches_per_s": n_b / dt}
+        cap = n_rec + (1 << 16)
+        for prec, name in ((ckv.CKV_MIXED, "resident_mixed"), (ckv.CKV_FP64, "resident_fp64")):
+            ms, kms, res = time_path(hip, ckv, d, atmo, tels, mk(prec), cap, 3, 1, stream)
+            if res["error"] or res["overflow"] or res["n_bunches"] != n_b or \
+                    (prec == ckv.CKV_MIXED and res["n_hits"] != n_rec):
+                raise RuntimeError(f"{name} at {z} deg reported a problem: {res}")
+            entry[name] = {"ms": ms, "bunch_kernel_ms": kms, "bunches_per_s": n_b / (ms * 1e-3)}
+            torch.cuda.empty_cache()
+        entry["resident_mixed_over_fp64"] = entry["resident_fp64"]["ms"] / entry["resident_mixed"]["ms"]
+        samples.append((wl, gpu_records(ckv, d, atmo, tels, p, cap, step_stride=sample_stride)))
+        out.append(entry)
+        print(f"# streamed {wl.name}: {out[-1]}", file=sys.stderr, flush=True)
+        del d
+        torch.cuda.empty_cache()
+    return out, samples
+
+
+def vertical_gamma_timing(hip, stream, steps: int, warmup: int):
+    """The plain-FP64 configuration of the paper-scale vertical gamma shower
+    (2e4 steps, 9 telescopes), both precisions; returns the timings and the
+    records of each precision for the comparison with the oracle."""
+    from paper_2006_14927_amd import ckv, synth
+    wl = synth.vertical_gamma()
+    atmo = ckv.Atmosphere(wl.atmo.alt, wl.atmo.eta, wl.atmo.obs_level, wl.fine_step)
+    tels = ckv.TelescopeArray(wl.tels.x, wl.tels.y, wl.tels.r)
+    d = ckv.DeviceSegments(wl.segs)
+    cap = max(1 << 16, 8 * wl.segs.n)
+    out, recs = {"workload": wl.name, "steps": wl.segs.n, "telescopes": wl.tels.n}, {}
+    for prec, name in ((ckv.CKV_FP64, "fp64_plain"), (ckv.CKV_MIXED, "mixed")):
+        p = ckv.make_params(precision=prec, bunch_size=wl.bunch_size, lambda_min=wl.lambda_min,
+                            lambda_max=wl.lambda_max, seed=wl.seed)
+        ms, kms, res = time_path(hip, ckv, d, atmo, tels, p, cap, steps, warmup, stream)
+        if res["error"] or res["overflow"]:
+            raise RuntimeError(f"vertical gamma {name} reported a problem: {res}")
+        out[name] = {"ms_per_step": ms, "bunch_kernel_ms": kms, "bunches": res["n_bunches"],
+                     "records": res["n_hits"], "bunches_per_s": res["n_bunches"] / (ms * 1e-3)}
+        recs[prec] = gpu_records(ckv, d, atmo, tels, p, cap)
+        recs[prec]["n_b"] = ckv.count(d, atmo, p).cpu().numpy()
+    out["mixed_over_fp64"] = out["fp64_plain"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    return wl, out, recs
 
 
 def order_study(hip, wl, atmo, tels, stream, steps: int, warmup: int):
@@ -398,30 +564,126 @@ def order_study(hip, wl, atmo, tels, stream, steps: int, warmup: int):
     return out
 
 
-def cpu_baseline(wl, target_cpu_seconds: float = 20.0):
-    """The FP64 oracle on an evenly spaced sample of the shower's steps."""
-    import numpy as np
+# --- the oracle leg: the FP64 CPU oracle timed on a sample of the shower, and the
+# same sample used to certify the GPU records of the timed launches.  Everything
+# that touches oracle/ lives below.
 
+# tolerances of the mixed path against the FP64 oracle (the benchmark spec), and the
+# guard band of the sphere test: |disc| <= 2 R eps + eps^2 with eps = 1 mm
+TOL = {"ground_m": 1e-3, "dir": 1e-6, "t_ns": 0.01, "photons_rel": 1e-6, "lambda_rel": 1e-6}
+GUARD_EPS_M = 1e-3
+F32_HALF_ULP = 2.0 ** -24
+
+
+def oracle_threads():
+    """Threads for the oracle: every core this process may run on, at most 16
+    (the host cores allotted per GPU on the machines this runs on)."""
+    aff = len(os.sched_getaffinity(0))
+    return max(1, min(16, aff))
+
+
+def certify(cfg, segs, precision: int, idx, ores, gpu, n_b_gpu=None) -> dict:
+    """Compares the GPU records of the sampled steps idx (global step indices,
+    ascending; gpu = gpu_records output) with the oracle's records of the same
+    steps (ores, run on segs.take(idx) with their original random numbers).
+    FP64 path: the same crossings in the same per-(shower, telescope) order and
+    records equal up to the final FP32 rounding.  Mixed path: crossings differ
+    only inside the guard band, fields within the stated tolerances.  Bunch
+    counts of the sampled steps bit-exact (n_b_gpu from ckv_count)."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    n_tel = cfg.n_tel
+    sel = np.isin(gpu["ids"][:, 0], idx)
+    gseg, gk = gpu["ids"][sel, 0], gpu["ids"][sel, 1]
+    grp, grec = gpu["group"][sel], gpu["rec"][sel].astype(np.float64)
+    oseg, ok_ = idx[ores.seg], ores.k
+    ogrp = ores.bucket.astype(np.int64) * n_tel + ores.tel
+    nmax = int(max(gseg.max(initial=0), oseg.max(initial=0))) + 1
+    kmax = int(max(gk.max(initial=0), ok_.max(initial=0))) + 1
+    gkey = (grp * nmax + gseg) * kmax + gk
+    okey = (ogrp * nmax + oseg) * kmax + ok_
+    order_ok = bool(np.all(np.diff(gkey) > 0))
+    common, io, ig = np.intersect1d(okey, gkey, assume_unique=True, return_indices=True)
+    only_o = np.setdiff1d(np.arange(len(okey)), io)
+    only_g = np.setdiff1d(np.arange(len(gkey)), ig)
+    ro, rg = ores.rec[io], grec[ig]
+    d = np.abs(rg - ro)
+    rel = lambda c: float(np.max(d[:, c] / np.maximum(np.abs(ro[:, c]), 1e-300), initial=0.0))
+    out = {"sampled_steps": int(len(idx)), "oracle_records": int(len(okey)),
+           "gpu_records": int(len(gkey)), "matched": int(len(common)),
+           "canonical_order": order_ok,
+           "max_abs_ground_m": float(d[:, :2].max(initial=0.0)),
+           "max_abs_dir": float(d[:, 2:4].max(initial=0.0)),
+           "max_abs_t_ns": float(d[:, 4].max(initial=0.0)),
+           "max_rel_h_emit": rel(5), "max_rel_photons": rel(6), "max_rel_lambda": rel(7)}
+    ok = order_ok
+    if n_b_gpu is not None:
+        out["bunch_counts_bit_exact"] = bool(np.array_equal(n_b_gpu[idx], ores.n_b))
+        ok &= out["bunch_counts_bit_exact"]
+    guard = lambda tel: 2.0 * cfg.tr[tel] * GUARD_EPS_M + GUARD_EPS_M ** 2
+    if precision == 0:
+        # identical crossing sets; records equal up to the final FP32 rounding
+        tol = 2 * F32_HALF_ULP * np.abs(ro) + 1e-9
+        tol[:, 4] += 2e-7
+        out["flips"] = int(len(only_o) + len(only_g))
+        out["records_within_fp32_rounding"] = bool(np.all(d <= tol))
+        ok &= out["flips"] == 0 and out["records_within_fp32_rounding"]
+    else:
+        in_o = np.abs(ores.disc[only_o]) <= guard(ogrp[only_o] % n_tel)
+        disc_g = np.zeros(0)
+        if len(only_g):
+            bd = oracle.bunch_details(cfg, segs, gseg[only_g], gk[only_g])
+            tg = grp[only_g] % n_tel
+            disc_g = np.array([oracle.sphere_disc(bd["x_g"][i], bd["y_g"][i], bd["u_o"][i],
+                                                  bd["v_o"][i], cfg.tx[t], cfg.ty[t], cfg.tr[t])
+                               for i, t in enumerate(tg)])
+            in_g = np.abs(disc_g) <= guard(tg)
+        else:
+            in_g = np.zeros(0, dtype=bool)
+        out["flips_in_guard_band"] = int(in_o.sum() + in_g.sum())
+        out["flips_outside_guard_band"] = int((~in_o).sum() + (~in_g).sum())
+        out["tolerances"] = TOL
+        ok &= out["flips_outside_guard_band"] == 0
+        ok &= out["max_abs_ground_m"] <= TOL["ground_m"] and out["max_abs_dir"] <= TOL["dir"]
+        ok &= out["max_abs_t_ns"] <= TOL["t_ns"]
+        ok &= out["max_rel_photons"] <= TOL["photons_rel"] and out["max_rel_lambda"] <= TOL["lambda_rel"]
+        ok &= out["max_rel_h_emit"] <= 2 * F32_HALF_ULP + 1e-9
+    out["ok"] = bool(ok)
+    return out
+
+
+def oracle_leg(wl, gpu_main, n_b_main, runs: int = 5, target_cpu_seconds: float = 20.0):
+    """The CPU baseline: the FP64 oracle on an evenly spaced sample of the
+    shower's steps, median of `runs` timed runs on oracle_threads() threads
+    (about target_cpu_seconds of CPU work in all), plus one run on one thread;
+    then the parity certificate of both precisions on the same sample."""
+    import oracle
+    threads = oracle_threads()
     cfg = oracle.Config.from_workload(wl)
-    # probe the rate on a small sample, then size the timed sample
     probe = np.arange(0, wl.segs.n, max(1, wl.segs.n // 4000))
     t0 = time.perf_counter()
     r = oracle.run(cfg, wl.segs.take(probe), nthreads=threads, seg_id=probe)
     dt = max(time.perf_counter() - t0, 1e-3)
     rate_cpu_s = r.n_bunches / (dt * threads)          # bunches per CPU-second
-    want_bunches = target_cpu_seconds * rate_cpu_s
+    want_bunches = target_cpu_seconds / runs * rate_cpu_s
     mean_b = max(r.n_bunches / len(probe), 1e-9)
     stride = max(1, int(wl.segs.n * mean_b / max(want_bunches, 1.0)))
     idx = np.arange(0, wl.segs.n, stride)
-    t0 = time.perf_counter()
-    r = oracle.run(cfg, wl.segs.take(idx), nthreads=threads, seg_id=idx)
-    dt = time.perf_counter() - t0
-    out = {"value": r.n_bunches / dt, "unit": "bunches/s", "cores": threads, "kind": "oracle",
+    sub = wl.segs.take(idx)
+    walls = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        r = oracle.run(cfg, sub, nthreads=threads, seg_id=idx)
+        walls.append(time.perf_counter() - t0)
+    med = float(np.median(walls))
+    info = cpu_info()
+    out = {"value": r.n_bunches / med, "unit": "bunches/s", "cores": threads, "kind": "oracle",
            "sample": f"every {stride}th step of the shower ({len(idx)} steps, {r.n_bunches} "
-                     f"bunches, {len(r.seg)} records), FP64, {dt:.2f} s wall"}
-    # the same oracle on one thread, on a sample 1/threads the size
+                     f"bunches, {len(r.seg)} records), FP64, median of {runs} runs "
+                     f"({min(walls):.3f}-{max(walls):.3f} s wall)",
+           "runs": runs, "wall_s": walls, "spread": (max(walls) - min(walls)) / med,
+           **info,
+           "threads_note": "every core of the process's affinity set, at most 16 (the host "
+                           "cores allotted to one GPU)"}
     idx1 = idx[::threads]
     t0 = time.perf_counter()
     r1 = oracle.run(cfg, wl.segs.take(idx1), nthreads=1, seg_id=idx1)
@@ -429,7 +691,47 @@ def cpu_baseline(wl, target_cpu_seconds: float = 20.0):
     single = {"value": r1.n_bunches / dt1, "unit": "bunches/s", "cores": 1, "kind": "oracle",
               "sample": f"every {stride * threads}th step ({len(idx1)} steps, {r1.n_bunches} bunches), "
                         f"{dt1:.2f} s"}
-    return out, single
+    parity = {name: certify(cfg, wl.segs, prec, idx, r, gpu_main[prec], n_b_main)
+              for prec, name in ((0, "fp64_plain"), (1, "mixed"))}
+    parity["sample"] = f"every {stride}th step ({len(idx)} steps, {r.n_bunches} bunches)"
+    return out, single, parity
+
+
+def oracle_parity_full(wl, recs) -> dict:
+    """Both precisions of a small workload against the oracle over every step."""
+    import oracle
+    cfg = oracle.Config.from_workload(wl)
+    idx = np.arange(wl.segs.n)
+    r = oracle.run(cfg, wl.segs, nthreads=oracle_threads())
+    out = {name: certify(cfg, wl.segs, prec, idx, r, recs[prec], recs[prec]["n_b"])
+           for prec, name in ((0, "fp64_plain"), (1, "mixed"))}
+    for prec, name in ((0, "fp64_plain"), (1, "mixed")):
+        res = recs[prec]["res"]
+        out[name]["drops_bit_exact"] = dict(zip(oracle.DROP_NAMES, res_drops(res))) == r.drops
+        out[name]["offsets_bit_exact"] = bool(np.array_equal(recs[prec]["offsets"], r.offsets))
+        out[name]["ok"] &= out[name]["drops_bit_exact"] and (prec == 1 or out[name]["offsets_bit_exact"])
+    return out
+
+
+def res_drops(res):
+    return [res["drops"][k] for k in ("mass", "threshold", "nonfinite", "below_obs", "above_top",
+                                      "upward", "grazing")]
+
+
+def oracle_parity_zeniths(samples, stride: int) -> list:
+    """Per zenith: the mixed path's records of every stride-th step of the
+    5e7-step shower against the oracle's (maximum errors by zenith)."""
+    import oracle
+    out = []
+    for wl, gpu in samples:
+        cfg = oracle.Config.from_workload(wl)
+        idx = np.arange(0, wl.segs.n, stride)
+        r = oracle.run(cfg, wl.segs.take(idx), nthreads=oracle_threads(), seg_id=idx)
+        c = certify(cfg, wl.segs, 1, idx, r, gpu)
+        c["workload"] = wl.name
+        out.append(c)
+        print(f"# parity {wl.name}: {c}", file=sys.stderr, flush=True)
+    return out
 
 
 def main(argv=None):
@@ -529,6 +831,19 @@ def main(argv=None):
             raise RuntimeError(f"run reported a problem: {res}")
     nb = res_mixed["n_bunches"]
     assert nb == res_fp64["n_bunches"]
+    # untimed: the records of each timed launch, with ids, for the oracle's certificate
+    gpu_main = {0: gpu_records(ckv, dsegs, atmo, tels,
+                               autotune.apply(mk(ckv.CKV_FP64), tuned[ckv.CKV_FP64]), capacity),
+                1: gpu_records(ckv, dsegs, atmo, tels,
+                               autotune.apply(mk(ckv.CKV_MIXED), tuned[ckv.CKV_MIXED]), capacity)}
+    n_b_main = ckv.count(dsegs, atmo, mk(ckv.CKV_MIXED)).cpu().numpy()
+    for prec, r_t in ((0, res_fp64), (1, res_mixed)):
+        r_c = gpu_main[prec]["res"]
+        if (r_c["n_bunches"], r_c["n_hits"], r_c["drops"]) != (r_t["n_bunches"], r_t["n_hits"],
+                                                               r_t["drops"]):
+            raise RuntimeError("the certification run differs from the timed run")
+    vg_wl, vg_line, vg_recs = vertical_gamma_timing(hip, stream, args.steps, args.warmup)
+    print(f"# {vg_wl.name}: {vg_line}", file=sys.stderr, flush=True)
 
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -539,12 +854,17 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(f"# copy probe: {args.copy_probe_mib} MiB read + written, 3 launches", file=sys.stderr)
 
-    ops_mixed = sum(OPS_MIXED.values())
-    achieved = ops_mixed * nb / (kms_mixed * 1e-3) / 1e12
-    peak = PEAK_OPS_PER_S / 1e12
-    traffic = stored_traffic("bunch_kernel_single_tev_mixed")
+    k_mixed = emit_kernel_name(1, tuned[ckv.CKV_MIXED]["tile_segments"],
+                               tuned[ckv.CKV_MIXED]["waves_per_group"])
+    k_fp64 = emit_kernel_name(0, tuned[ckv.CKV_FP64]["tile_segments"],
+                              tuned[ckv.CKV_FP64]["waves_per_group"])
+    roof = roofline_block(SURVEY_SLOTS["mixed"], sum(OPS_MIXED.values()), nb, kms_mixed,
+                          stored_issue_frac(k_mixed, wl.name))
+    roof_fp64 = roofline_block(SURVEY_SLOTS["fp64"], sum(OPS_FP64.values()), nb, kms_fp64,
+                               stored_issue_frac(k_fp64, wl.name))
+    roof["traffic"] = stored_traffic("bunch_kernel_single_tev_mixed")
     hits = res_mixed["n_hits"]
-    alg_bytes = wl.segs.n * SEG_BYTES + hits * STAGE_BYTES
+    alg_bytes = wl.segs.n * SEG_BYTES + hits * RECORD_BYTES
     line = {
         "metric": "bunches/s gen+propagated, mixed vs FP64 plain at oracle tol; fwd+bwd ms/shower",
         "value": nb / (ms_mixed * 1e-3),
@@ -568,9 +888,13 @@ def main(argv=None):
         "records_per_step": hits,
         "fp64_plain": {"value": nb / (ms_fp64 * 1e-3), "ms_per_step": ms_fp64,
                        "bunch_kernel_ms": kms_fp64,
-                       "roofline_frac": sum(OPS_FP64.values()) * nb / (kms_fp64 * 1e-3)
-                       / PEAK_OPS_PER_S},
+                       "launch": {"tile_segments": tuned[ckv.CKV_FP64]["tile_segments"],
+                                  "waves_per_group": tuned[ckv.CKV_FP64]["waves_per_group"]},
+                       "roofline": roof_fp64},
         "mixed_over_fp64": ms_fp64 / ms_mixed,
+        "mixed_over_fp64_bunch_kernel": kms_fp64 / kms_mixed,
+        "parity": None,
+        "vertical_gamma": vg_line,
         "table_ablation": {"profile": "5-layer, 57 tabulated altitudes",
                            "node_tables_binary_search": {"nodes": int(atmo_n.info()[0]),
                                                          "ms_per_step": ms_nodes,
@@ -582,10 +906,9 @@ def main(argv=None):
                          "ms_per_step": ms_prof, "bunch_kernel_ms": kms_prof,
                          "value": nb / (ms_prof * 1e-3), "overhead": ms_prof / ms_mixed - 1.0},
         "bunch_kernel_ms": kms_mixed,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak,
-                     "traffic": traffic},
+        "roofline": roof,
         "hbm": {"algorithmic_bytes_per_launch": alg_bytes,
+                "counter_bytes_per_launch": roof["traffic"],
                 "achieved_GBs": alg_bytes / (kms_mixed * 1e-3) / 1e9,
                 "frac": alg_bytes / (kms_mixed * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "fwd_bwd_ms_per_shower": None,
@@ -607,15 +930,26 @@ def main(argv=None):
         print(f"# batched: {b}", file=sys.stderr, flush=True)
         line["batched"] = b
         torch.cuda.empty_cache()
+    samples = []
     if not args.no_streamed:
-        line["streamed"] = streamed_timing(hip)
+        line["streamed"], samples = streamed_timing(hip, sample_stride=ZENITH_SAMPLE_STRIDE)
     if args.order_study:
         line["step_order_study"] = order_study(hip, wl, atmo, tels, stream, args.steps, args.warmup)
+    ok = True
     if not args.no_cpu_baseline:
-        line["cpu_baseline"], line["cpu_baseline_one_thread"] = cpu_baseline(wl)
+        line["cpu_baseline"], line["cpu_baseline_one_thread"], par = oracle_leg(wl, gpu_main, n_b_main)
+        par["vertical_gamma_every_step"] = oracle_parity_full(vg_wl, vg_recs)
+        if samples:
+            par["streamed_by_zenith"] = oracle_parity_zeniths(samples, ZENITH_SAMPLE_STRIDE)
+        checks = [par["fp64_plain"], par["mixed"], *par["vertical_gamma_every_step"].values(),
+                  *par.get("streamed_by_zenith", [])]
+        ok = all(c["ok"] for c in checks)
+        par["ok"] = ok
+        line["parity"] = par
+        print(f"# parity: {'green' if ok else 'FAILED'}", file=sys.stderr, flush=True)
     line["device"] = device_info(hip)
     print(json.dumps(line), flush=True)
-    return 0
+    return 0 if ok else 1
 
 
 if __name__ == "__main__":
