@@ -479,24 +479,28 @@ def streamed_timing(hip, zeniths=(0.0, 20.0, 40.0, 60.0), sample_stride: int = 2
         p = mk(ckv.CKV_MIXED)
         ckv.Streamer(d, atmo, tels, p, want_ids=False)        # warm: allocations, first launch
         torch.cuda.synchronize()
-        agg = dict(chunks=0, records=0, bunches=0)
+        agg = dict(chunks=0, records=0, end=0)
 
         def sink(ch):
+            if ch.begin != agg["end"] or ch.result["error"]:
+                raise RuntimeError(f"streamed chunk [{ch.begin}, {ch.end}) out of order or failed")
             agg["chunks"] += 1
             agg["records"] += int(ch.records.shape[0])
-            agg["bunches"] += ch.result["n_bunches"]
+            agg["end"] = ch.end
 
         t0 = time.perf_counter()
         st = ckv.Streamer(d, atmo, tels, p, want_ids=False)
         st.to_host(sink)
         dt = time.perf_counter() - t0
-        n_chunks, n_rec, n_b = agg["chunks"], agg["records"], agg["bunches"]
-        if n_b != st.total_bunches:
-            raise RuntimeError("streamed bunch count mismatch")
+        n_chunks, n_rec, n_b = agg["chunks"], agg["records"], st.total_bunches
+        if agg["end"] != wl.segs.n:
+            raise RuntimeError("streamed chunks do not cover the shower")
+        resumed, rerun = st.n_resumed, st.n_reruns
         del st
         torch.cuda.empty_cache()
         entry = {"zenith_deg": z, "steps": wl.segs.n, "bunches": n_b, "records": n_rec,
-                 "chunks": n_chunks, "s": dt, "bunches_per_s": n_b / dt}
+                 "chunks": n_chunks, "resumed": resumed, "rerun": rerun, "s": dt,
+                 "bunches_per_s": n_b / dt}
         cap = n_rec + (1 << 16)
         for prec, name in ((ckv.CKV_MIXED, "resident_mixed"), (ckv.CKV_FP64, "resident_fp64")):
             ms, kms, res = time_path(hip, ckv, d, atmo, tels, mk(prec), cap, 3, 1, stream)
@@ -542,22 +546,28 @@ def vertical_gamma_timing(hip, stream, steps: int, warmup: int):
 def order_study(hip, wl, atmo, tels, stream, steps: int, warmup: int):
     """Bunch-kernel time with the shower's steps in generator order, sorted by
     start altitude (neighbouring lanes then read neighbouring table cells), and
-    shuffled: the memory-layout study of the step input."""
-    import numpy as np
+    shuffled: the memory-layout study of the step input.  The reordered runs pass
+    the generator-order index of each step as its step id, so they compute the
+    same bunches as the generator order (checked: same counts, crossings and
+    drops)."""
     import torch
 
     from paper_2006_14927_amd import ckv
-    orders = {"generator": np.arange(wl.segs.n),
+    orders = {"generator": None,
               "by_altitude": np.argsort(-wl.segs.h0, kind="stable"),
               "shuffled": np.random.default_rng(1).permutation(wl.segs.n)}
-    out = {}
+    out, ref = {}, None
     for name, idx in orders.items():
-        d = ckv.DeviceSegments(wl.segs.take(idx))
+        d = ckv.DeviceSegments(wl.segs) if idx is None else \
+            ckv.DeviceSegments(wl.segs.take(idx), step_id=idx.astype(np.uint32))
         p = ckv.make_params(precision=ckv.CKV_MIXED, bunch_size=wl.bunch_size, lambda_min=wl.lambda_min,
                             lambda_max=wl.lambda_max, seed=wl.seed, tile_segments=32, waves_per_group=16)
         ms, kms, res = time_path(hip, ckv, d, atmo, tels, p, max(1 << 16, 2 * wl.segs.n), steps, warmup,
                                  stream)
-        out[name] = {"ms_per_step": ms, "bunch_kernel_ms": kms, "bunches": res["n_bunches"]}
+        key = (res["n_bunches"], res["n_hits"], tuple(res["drops"].values()))
+        ref = key if ref is None else ref
+        out[name] = {"ms_per_step": ms, "bunch_kernel_ms": kms, "bunches": res["n_bunches"],
+                     "records": res["n_hits"], "same_bunches_as_generator_order": key == ref}
         print(f"# step order {name}: {out[name]}", file=sys.stderr, flush=True)
         del d
         torch.cuda.empty_cache()
@@ -573,6 +583,9 @@ def order_study(hip, wl, atmo, tels, stream, steps: int, warmup: int):
 TOL = {"ground_m": 1e-3, "dir": 1e-6, "t_ns": 0.01, "photons_rel": 1e-6, "lambda_rel": 1e-6}
 GUARD_EPS_M = 1e-3
 F32_HALF_ULP = 2.0 ** -24
+# the library's bound of the mixed path's ground-point error per metre of height
+# (the soft response's screening pass relies on it): dh (a (1/w + 1/w^2) + b / w^3)
+SCREEN_ERR_DIR, SCREEN_ERR_SERIES = 1e-8, 5e-10
 
 
 def oracle_threads():
@@ -639,6 +652,17 @@ def certify(cfg, segs, precision: int, idx, ores, gpu, n_b_gpu=None) -> dict:
             in_g = np.abs(disc_g) <= guard(tg)
         else:
             in_g = np.zeros(0, dtype=bool)
+        # the ground error against the bound the soft response's screening relies on
+        wo = np.sqrt(np.maximum(1.0 - ro[:, 2] ** 2 - ro[:, 3] ** 2, 1e-12))
+        dh = np.maximum(ro[:, 5] - cfg.tables.h_obs, 0.0)
+        bound = dh / wo * (SCREEN_ERR_DIR * (1.0 + 1.0 / wo) + SCREEN_ERR_SERIES / wo ** 2)
+        # plus the record's own FP32 rounding of dx, dy (the screen works on the FP64
+        # ground point)
+        bound = bound + 2.0 * F32_HALF_ULP * np.hypot(ro[:, 0], ro[:, 1]) + 1e-9
+        gerr = np.hypot(d[:, 0], d[:, 1])
+        out["max_ground_err_over_screen_bound"] = float(
+            np.max(gerr / bound, initial=0.0))
+        ok &= out["max_ground_err_over_screen_bound"] < 1.0
         out["flips_in_guard_band"] = int(in_o.sum() + in_g.sum())
         out["flips_outside_guard_band"] = int((~in_o).sum() + (~in_g).sum())
         out["tolerances"] = TOL

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define CKV_VERSION 113
+#define CKV_VERSION 114
 
 enum {
     CKV_OK = 0,
@@ -154,18 +154,26 @@ int ckv_array_destroy(ckv_array* arr);
    (App. A: each particle track is subdivided into steps).  Start point
    (x0, y0, h0) [m], unit direction (u, v, w) with w = -dh/ds, length [m],
    start time t0 [ns], total energy [MeV], particle type (CKV_ELECTRON or
-   CKV_MUON; charge 1). */
+   CKV_MUON; charge 1).  step_id (optional, NULL to leave out): the random-
+   number counter word of each step (below: it replaces seg_id_base[s] + j), so
+   the steps of a shower may be stored in any order -- e.g. sorted by altitude
+   for table locality (sec. 6, cache behaviour) -- and every bunch keeps its
+   random numbers; records then still name steps by their index in these
+   arrays. */
 typedef struct {
     const double *x0, *y0, *h0, *u, *v, *w, *length, *t0, *energy;
     const uint8_t* ptype;
     int64_t n;
+    const uint32_t* step_id;
 } ckv_segments;
 
 /* Showers: steps of shower s are [seg_offsets[s], seg_offsets[s+1]),
    seg_offsets[0] = 0, seg_offsets[n_showers] = n.  t_ref[s] is subtracted
    from arrival times.  Random numbers of bunch k of the step with index j in
    its shower come from Philox4x32-10 with counter
-   (k, seg_id_base[s] + j, shower_ids[s], 0) and the 64-bit seed as key
+   (k, seg_id_base[s] + j, shower_ids[s], 0), or (k, step_id[i], shower_ids[s],
+   0) for the step at index i when segments->step_id is given, and the 64-bit
+   seed as key
    (sec. 5.2: runs reproduce the same random sequence); shower_ids NULL means
    shower_ids[s] = s, seg_id_base NULL means 0.  Splitting a shower's steps
    into several runs with the matching seg_id_base gives the same bunches. */
@@ -217,18 +225,44 @@ typedef struct {
 /* Device-side report, written by ckv_run (the caller syncs the stream before
    reading it). */
 typedef struct {
-    int64_t n_bunches;       /* bunches generated: sum of n_b over steps */
-    int64_t n_hits;          /* records found (sphere crossings) */
-    int64_t n_records;       /* records written = min(n_hits, capacity) if no overflow */
+    int64_t n_bunches;       /* bunches generated: sum of n_b over the run's steps */
+    int64_t n_hits;          /* sphere crossings of the run's steps: the capacity that
+                                holds them all (written or not) */
+    int64_t n_records;       /* records written (all n_hits unless overflow) */
     int64_t n_emitting;      /* steps with at least one bunch */
     int64_t n_tiles;         /* emit tiles processed */
     int64_t drops[CKV_N_DROP];
-    int32_t overflow;        /* 1: n_hits > capacity; records and ids are not valid,
-                                tel_offsets are; rerun with capacity >= n_hits */
-    int32_t error;           /* bit 0: seg_offsets not non-decreasing or out of range;
-                                bit 1: a tile of tile_segments steps held >= 2^30 bunches
-                                (its bunches were skipped) */
+    int64_t resume_step;     /* overflow: first step (index in the segment arrays) whose
+                                records were not written; n otherwise */
+    int32_t resume_shower;   /* overflow: the shower of resume_step; n_showers otherwise */
+    int32_t overflow;        /* 1: the crossings did not fit the capacity: the records
+                                of the steps before resume_step are written, complete and
+                                in canonical order, and tel_offsets describe them; the
+                                steps from resume_step on were computed (they are in the
+                                counters) but not written: resume there (ckv_cursor).
+                                The prefix is the longest that fits while the crossings
+                                fit the workspace's staging (capacity plus 64 per bunch-
+                                kernel wave); beyond that tiles finishing out of order
+                                may end it earlier, possibly at the first step */
+    int32_t error;           /* bit 0: seg_offsets not non-decreasing or out of range,
+                                or a resume cursor outside the steps; bit 1: a tile of
+                                tile_segments steps held >= 2^30 bunches (its bunches
+                                were skipped) */
+    int32_t reserved;
 } ckv_result;
+
+/* Where a run starts (App. A, TELOUT: the bunches that hit are written as the
+   steps are processed; a run cut short by a full output continues where it
+   stopped): the steps before `step` (an index in the segment arrays) are left
+   out, `shower` is the shower holding it.  Bunches keep their random numbers
+   (the counter uses the step's index in its shower), so the records of a run
+   resumed at the cursor its predecessor reported, appended per (shower,
+   telescope) to the predecessor's, are the records of one uninterrupted run. */
+typedef struct {
+    int64_t step;
+    int32_t shower;
+    int32_t reserved;        /* 0 */
+} ckv_cursor;
 
 /* Output.  records: capacity x 8 floats per record
      (x - X_tel, y - Y_tel, u_obs, v_obs, t - t_ref, h_emit, photons, lambda)
@@ -263,13 +297,18 @@ size_t ckv_workspace_size(int64_t n_segments, int32_t n_showers, int32_t n_tel,
    Fully asynchronous on `stream` (a hipStream_t; NULL = default stream);
    enqueues kernels only, so it can be captured into a HIP graph.
    workspace: device memory of ws_bytes >= ckv_workspace_size(...), any
-   content.  Errors (synchronous): CKV_ERR_ARG for null pointers, n < 0,
-   n_showers < 1, bad params, a profile asked for without a depth table, with
-   too many bins or without its output arrays; CKV_ERR_CAPACITY for a small
-   workspace; CKV_ERR_HIP if a launch fails. */
+   content.  resume_from (host memory, may be NULL = from the first step):
+   start at that cursor, typically the resume_step/resume_shower an overflowing
+   run reported.  When the crossings exceed the capacity the run writes a
+   complete prefix of its steps and reports where to resume (ckv_result).
+   Errors (synchronous): CKV_ERR_ARG for null pointers, n < 0, n_showers < 1,
+   bad params, a cursor with step outside [0, n] or shower outside
+   [0, n_showers), a profile asked for without a depth table, with too many
+   bins or without its output arrays; CKV_ERR_CAPACITY for a small workspace;
+   CKV_ERR_HIP if a launch fails. */
 int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
             const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
-            ckv_output* out, void* stream);
+            ckv_output* out, const ckv_cursor* resume_from, void* stream);
 
 /* ckv_run without a workspace argument, for callers that cannot allocate device
    memory (code under HIP graph capture, tight serving loops, harnesses that
@@ -287,7 +326,8 @@ int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_para
    then use ckv_run). */
 #define CKV_NOALLOC_SCRATCH_MIB 256
 int ckv_run_noalloc(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
-                    const ckv_atmo* atmo, const ckv_array* arr, ckv_output* out, void* stream);
+                    const ckv_atmo* atmo, const ckv_array* arr, ckv_output* out,
+                    const ckv_cursor* resume_from, void* stream);
 /* Bytes of the static array ckv_run_noalloc would use for these sizes on the
    current device (0 for invalid sizes). */
 size_t ckv_noalloc_workspace_size(int64_t n_segments, int32_t n_showers, int32_t n_tel,

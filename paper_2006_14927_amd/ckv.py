@@ -37,7 +37,8 @@ class CkvError(RuntimeError):
 
 class _Segments(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in ("x0", "y0", "h0", "u", "v", "w", "length", "t0",
-                                          "energy", "ptype")] + [("n", C.c_int64)]
+                                          "energy", "ptype")] + [("n", C.c_int64),
+                                                                 ("step_id", C.c_void_p)]
 
 
 class _Showers(C.Structure):
@@ -58,7 +59,12 @@ class _Params(C.Structure):
 class _Result(C.Structure):
     _fields_ = [("n_bunches", C.c_int64), ("n_hits", C.c_int64), ("n_records", C.c_int64),
                 ("n_emitting", C.c_int64), ("n_tiles", C.c_int64), ("drops", C.c_int64 * 8),
-                ("overflow", C.c_int32), ("error", C.c_int32)]
+                ("resume_step", C.c_int64), ("resume_shower", C.c_int32),
+                ("overflow", C.c_int32), ("error", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _Cursor(C.Structure):
+    _fields_ = [("step", C.c_int64), ("shower", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _ParamSpec(C.Structure):
@@ -111,10 +117,10 @@ def lib():
         L.ckv_workspace_size.restype = C.c_size_t
         L.ckv_workspace_size.argtypes = [I64, I32, I32, I64, C.POINTER(_Params)]
         L.ckv_run.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params), P, P,
-                              P, C.c_size_t, C.POINTER(_Output), P]
+                              P, C.c_size_t, C.POINTER(_Output), C.POINTER(_Cursor), P]
         L.ckv_count.argtypes = [C.POINTER(_Segments), C.POINTER(_Params), P, P, P]
         L.ckv_run_noalloc.argtypes = [C.POINTER(_Segments), C.POINTER(_Showers), C.POINTER(_Params),
-                                      P, P, C.POINTER(_Output), P]
+                                      P, P, C.POINTER(_Output), C.POINTER(_Cursor), P]
         L.ckv_noalloc_workspace_size.restype = C.c_size_t
         L.ckv_noalloc_workspace_size.argtypes = [I64, I32, I32, I64, C.POINTER(_Params)]
         L.ckv_atmo_from_params.argtypes = [C.POINTER(_ParamSpec), P, C.POINTER(P)]
@@ -252,7 +258,9 @@ class DeviceSegments:
 
     FIELDS = ("x0", "y0", "h0", "u", "v", "w", "length", "t0", "energy")
 
-    def __init__(self, segs, device="cuda", seg_id_base=None):
+    def __init__(self, segs, device="cuda", seg_id_base=None, step_id=None):
+        """step_id (optional, one uint32 per step): the random-number counter word of
+        each step, so that reordered steps keep their bunches."""
         import torch
         self.t = {f: torch.as_tensor(np.ascontiguousarray(getattr(segs, f), dtype=np.float64),
                                      device=device) for f in self.FIELDS}
@@ -264,6 +272,8 @@ class DeviceSegments:
                                           device=device)
         self.seg_id_base = None if seg_id_base is None else torch.as_tensor(
             np.asarray(seg_id_base, dtype=np.int64), device=device)
+        self.step_id = None if step_id is None else torch.as_tensor(
+            np.ascontiguousarray(step_id, dtype=np.uint32).view(np.int32), device=device)
         self.n = segs.n
         self.n_showers = segs.n_showers
         self.offsets_host = np.asarray(segs.seg_offsets, dtype=np.int64).copy()
@@ -282,6 +292,7 @@ class DeviceSegments:
         s1 = max(s1, s0 + 1)
         v = DeviceSegments.__new__(DeviceSegments)
         v.t = {f: t[a:b] for f, t in self.t.items()}
+        v.step_id = None if self.step_id is None else self.step_id[a:b]
         sub_off = np.clip(off[s0:s1 + 1], a, b) - a
         sub_off[0], sub_off[-1] = 0, b - a
         dev = self.t["x0"].device
@@ -297,7 +308,8 @@ class DeviceSegments:
 
     def c_segments(self) -> _Segments:
         t = self.t
-        return _Segments(*[t[f].data_ptr() for f in self.FIELDS], t["ptype"].data_ptr(), self.n)
+        return _Segments(*[t[f].data_ptr() for f in self.FIELDS], t["ptype"].data_ptr(), self.n,
+                         self.step_id.data_ptr() if self.step_id is not None else None)
 
     def c_showers(self) -> _Showers:
         return _Showers(self.seg_offsets.data_ptr(), self.t_ref.data_ptr(),
@@ -343,7 +355,7 @@ class RunOutput:
         return dict(n_bunches=r.n_bunches, n_hits=r.n_hits, n_records=r.n_records,
                     n_emitting=r.n_emitting, n_tiles=r.n_tiles,
                     drops=dict(zip(DROP_NAMES, list(r.drops)[:7])), overflow=r.overflow,
-                    error=r.error)
+                    error=r.error, resume_step=r.resume_step, resume_shower=r.resume_shower)
 
 
 class Runner:
@@ -374,10 +386,14 @@ class Runner:
                             self.profile_photons.data_ptr() if self.profile_photons is not None else None,
                             self.profile_bunches.data_ptr() if self.profile_bunches is not None else None)
 
-    def run(self, stream=None) -> RunOutput:
+    def run(self, stream=None, resume_from=None) -> RunOutput:
+        """resume_from: (step, shower) where to start, e.g. the resume_step and
+        resume_shower of a run that overflowed; None = the first step."""
+        cur = None if resume_from is None else C.byref(_Cursor(int(resume_from[0]),
+                                                               int(resume_from[1]), 0))
         _check(lib().ckv_run(C.byref(self._segs), C.byref(self._showers), C.byref(self.params),
                              self.atmo.handle, self.tels.handle, C.c_void_p(self.workspace.data_ptr()),
-                             self.workspace.numel(), C.byref(self._out), _stream_ptr(stream)))
+                             self.workspace.numel(), C.byref(self._out), cur, _stream_ptr(stream)))
         return RunOutput(self.records, self.ids, self.tel_offsets, self.result_raw,
                          self.profile_photons, self.profile_bunches)
 
@@ -439,10 +455,12 @@ class Streamer:
 
     Ranges are planned from the bunch counts of the steps (ckv_count, summed on
     the device into one prefix value per block of `plan_block` steps) and the
-    largest crossings-per-bunch ratio seen so far; a range whose crossings
-    overflow the chunk is rerun smaller (ckv_run reports the required count and
-    writes nothing).  Per (shower, telescope), the records of consecutive ranges
-    concatenate in the one-shot (step, bunch) order.
+    largest crossings-per-bunch ratio seen so far.  A range whose crossings do
+    not fit the chunk writes a complete prefix of its steps (ckv_run's resume
+    cursor): that prefix becomes the chunk and the next range starts where it
+    ended, so no step is computed for output twice unless a single tile of
+    steps alone exceeds the chunk.  Per (shower, telescope), the records of
+    consecutive chunks concatenate in the one-shot (step, bunch) order.
 
     chunks() yields each range's output on the device; to_host() copies every
     chunk to pinned host memory while the next range is computed."""
@@ -462,6 +480,7 @@ class Streamer:
         self.block = int(plan_block)
         n_b = count(dsegs, atmo, params)
         cum = torch.cumsum(n_b, 0)
+        self._cum = cum                     # device: bunches of steps [0, i]
         ends = torch.arange(self.block, n + self.block, self.block, device=cum.device).clamp_(max=n)
         self.plan_at = np.concatenate([[0], ends.cpu().numpy()]).astype(np.int64)
         self.plan_cum = np.zeros(len(self.plan_at), dtype=np.int64)
@@ -473,11 +492,19 @@ class Streamer:
         ws = workspace_size(max(self.max_range, 1), dsegs.n_showers, tels.n, self.capacity, params)
         self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
         self.out = _OutBuf(self.capacity, dsegs.n_showers * tels.n, want_ids, device)
-        self.n_reruns = 0
+        self.n_reruns = 0        # ranges computed again because nothing of them fit
+        self.n_resumed = 0       # ranges cut short at a resume cursor
 
     @property
     def total_bunches(self) -> int:
         return int(self.plan_cum[-1])
+
+    def bunches(self, a: int, b: int) -> int:
+        """Bunches of steps [a, b) (from the plan's counts; synchronises)."""
+        if b <= a:
+            return 0
+        hi = int(self._cum[b - 1].item())
+        return hi - (int(self._cum[a - 1].item()) if a > 0 else 0)
 
     def _cum_at(self, x: int) -> float:
         return float(np.interp(x, self.plan_at, self.plan_cum))
@@ -496,25 +523,30 @@ class Streamer:
         segs, showers, o = v.c_segments(), v.c_showers(), out.c_output(self.capacity)
         _check(lib().ckv_run(C.byref(segs), C.byref(showers), C.byref(self.params), self.atmo.handle,
                              self.tels.handle, C.c_void_p(self.workspace.data_ptr()),
-                             self.workspace.numel(), C.byref(o), _stream_ptr(stream)))
+                             self.workspace.numel(), C.byref(o), None, _stream_ptr(stream)))
         return v
 
-    def _accept(self, a: int, b: int, res: dict) -> bool:
-        """Updates the planning ratio; False when the range has to be rerun smaller."""
+    def _accept(self, a: int, b: int, res: dict) -> int:
+        """Updates the planning ratio; returns the end of the written part of range
+        [a, b) (a when nothing of it fit and it has to be run again, smaller)."""
         if res["error"]:
             raise CkvError(f"device reported error flags {res['error']} on steps [{a}, {b})")
         seen = res["n_hits"] / max(res["n_bunches"], 1)
         if res["overflow"]:
-            if b == a + 1:
-                raise CkvError(f"step {a} alone has {res['n_hits']} crossings > chunk capacity")
             self.max_seen = max(self.max_seen, seen * 1.25)
             self.ratio = self.max_seen
-            self.n_reruns += 1
-            return False
+            end = a + int(res["resume_step"])
+            if end <= a:
+                if b == a + 1:
+                    raise CkvError(f"step {a} alone has {res['n_hits']} crossings > chunk capacity")
+                self.n_reruns += 1
+            else:
+                self.n_resumed += 1
+            return end
         self.max_seen = max(self.max_seen, seen)
         if self.max_seen > 0:
             self.ratio = 1.1 * self.max_seen
-        return True
+        return b
 
     def chunks(self, stream=None):
         """Yields Chunk objects (device buffers, reused by the next chunk) in step order."""
@@ -525,13 +557,14 @@ class Streamer:
             v = self._launch(a, b, self.out, stream)
             torch.cuda.synchronize()
             res = self.out.result()
-            if not self._accept(a, b, res):
+            end = self._accept(a, b, res)
+            if end <= a:
                 continue
             k = int(res["n_records"])
-            yield Chunk(a, b, *v.shower_range, self.out.records[:k],
+            yield Chunk(a, end, *v.shower_range, self.out.records[:k],
                         self.out.ids[:k] if self.out.ids is not None else None,
                         self.out.tel_offsets[:v.n_showers * self.tels.n + 1], res)
-            a = b
+            a = end
 
     def to_host(self, sink):
         """Streams every chunk to pinned host memory: sink(chunk) receives a Chunk
@@ -576,7 +609,8 @@ class Streamer:
                 pending = None
             ran.synchronize()
             res = out.result()
-            if not self._accept(a, b, res):
+            end = self._accept(a, b, res)
+            if end <= a:
                 continue
             k = int(res["n_records"])
             ng = v.n_showers * self.tels.n + 1
@@ -590,8 +624,8 @@ class Streamer:
                 ev = torch.cuda.Event()
                 ev.record(copy)
             copied[slot] = ev
-            pending = (ev, slot, dict(a=a, b=b, showers=v.shower_range, res=res, ng=ng))
-            a, i = b, i + 1
+            pending = (ev, slot, dict(a=a, b=end, showers=v.shower_range, res=res, ng=ng))
+            a, i = end, i + 1
         if pending is not None:
             deliver(pending)
         torch.cuda.synchronize()

@@ -141,14 +141,25 @@ size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, in
     // crossings fill blocks back to back; each wave leaves at most one partial block
     const int64_t slots_needed = capacity + (n_waves + 1) * kStageBlock;
     const int64_t stage_blocks = (slots_needed + kStageBlock - 1) / kStageBlock;
+    // a run holds at least one staged crossing: as many run slots as staging slots,
+    // plus each wave's partly used run block, never run out first (tiles finish out
+    // of order, so a smaller run array could be filled by later tiles and cut the
+    // written prefix short)
+    const int64_t run_blocks = stage_blocks * kStageBlock / kRunBlock + n_waves + 2;
+    const int64_t run_cap = run_blocks * kRunBlock;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     size_t o_ctrl = take(sizeof(int64_t) * kCtrlSlots);
     size_t o_res = take(sizeof(ckv_result));
     size_t o_tb = take(sizeof(int64_t) * (n_showers + 1));
     size_t o_bb = take(sizeof(int64_t) * (n_showers + 1));
-    size_t o_counts = take(sizeof(int32_t) * (size_t)max_tiles * n_tel);
+    size_t o_sf = take(sizeof(int64_t) * n_showers);
+    size_t o_roff = take(sizeof(int64_t) * (size_t)max_tiles);
+    size_t o_rn = take(sizeof(int32_t) * (size_t)max_tiles);
+    size_t o_th = take(sizeof(int32_t) * (size_t)max_tiles);
+    size_t o_runs = take(sizeof(int64_t) * (size_t)run_cap);
     size_t o_bsum = take(sizeof(int32_t) * (size_t)max_blocks * n_tel);
+    size_t o_bh = take(sizeof(int64_t) * (size_t)max_blocks);
     size_t o_st = take(sizeof(int32_t) * (size_t)n_showers * n_tel);
     size_t o_fill = take(sizeof(int32_t) * (size_t)stage_blocks);
     size_t o_stage = take(sizeof(StageEntry) * (size_t)stage_blocks * kStageBlock);
@@ -158,12 +169,18 @@ size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, in
         plan->max_tiles = max_tiles;
         plan->max_row_blocks = max_blocks;
         plan->stage_slots = stage_blocks * kStageBlock;
+        plan->run_cap = run_cap;
         plan->ctrl = (int64_t*)(b + o_ctrl);
         plan->ws_result = (ckv_result*)(b + o_res);
         plan->tiles_before = (int64_t*)(b + o_tb);
         plan->blocks_before = (int64_t*)(b + o_bb);
-        plan->counts = (int32_t*)(b + o_counts);
+        plan->shower_first = (int64_t*)(b + o_sf);
+        plan->tile_run_off = (int64_t*)(b + o_roff);
+        plan->tile_run_n = (int32_t*)(b + o_rn);
+        plan->tile_hits = (int32_t*)(b + o_th);
+        plan->runs = (int64_t*)(b + o_runs);
         plan->block_sums = (int32_t*)(b + o_bsum);
+        plan->block_hits = (int64_t*)(b + o_bh);
         plan->shower_tel = (int32_t*)(b + o_st);
         plan->stage_fill = (int32_t*)(b + o_fill);
         plan->stage = (StageEntry*)(b + o_stage);
@@ -421,9 +438,10 @@ size_t ckv_workspace_size(int64_t n_segments, int32_t n_showers, int32_t n_tel, 
 
 int ckv_run(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
             const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
-            ckv_output* out, void* stream)
+            ckv_output* out, const ckv_cursor* resume_from, void* stream)
 {
-    return run_checked(segs, showers, params, atmo, arr, workspace, ws_bytes, out, stream);
+    return run_checked(segs, showers, params, atmo, arr, workspace, ws_bytes, out, resume_from,
+                       stream);
 }
 
 }  // extern "C"
@@ -432,7 +450,7 @@ namespace ckv {
 
 int run_checked(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
                 const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
-                ckv_output* out, void* stream)
+                ckv_output* out, const ckv_cursor* resume_from, void* stream)
 {
     int rc;
     if ((rc = check_segments(segs)) || (rc = check_params(params))) return rc;
@@ -459,9 +477,16 @@ int run_checked(const ckv_segments* segs, const ckv_showers* showers, const ckv_
             return CKV_ERR_ARG;
         }
     }
+    if (resume_from && (resume_from->step < 0 || resume_from->step > segs->n ||
+                        resume_from->shower < 0 || resume_from->shower >= showers->n_showers ||
+                        resume_from->reserved != 0)) {
+        set_error("resume cursor: need 0 <= step <= n, 0 <= shower < n_showers, reserved 0");
+        return CKV_ERR_ARG;
+    }
     if ((rc = current_device(atmo->device)) || (rc = current_device(arr->device))) return rc;
     RunPlan plan{};
     plan.prof_bins = prof_bins;
+    plan.cursor = resume_from ? *resume_from : ckv_cursor{0, 0, 0};
     size_t need = workspace_layout(segs->n, showers->n_showers, arr->n_tel, out->capacity, params,
                                    &plan, workspace);
     if (ws_bytes < need) {
@@ -478,7 +503,9 @@ int run_checked(const ckv_segments* segs, const ckv_showers* showers, const ckv_
     int n_cu = 256;
     if (int rc = device_cu_count(&n_cu)) return rc;
     plan.emit_grid = params->grid > 0 ? params->grid : std::min(n_cu, kMaxEmitGrid);
-    plan.emit_waves = params->waves_per_group > 0 ? params->waves_per_group : kMaxEmitWaves;
+    // default: 16 waves for the mixed kernel, 8 for FP64 (16 is its narrow build)
+    plan.emit_waves = params->waves_per_group > 0 ? params->waves_per_group
+                      : params->precision == CKV_FP64 ? kMaxEmitWaves / 2 : kMaxEmitWaves;
     return launch_run(plan);
 }
 

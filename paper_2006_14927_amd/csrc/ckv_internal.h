@@ -22,6 +22,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kWave = 64;              // CDNA wavefront
 constexpr int kMaxTileSegs = 64;       // steps per tile (one per lane at most)
 constexpr int kStageBlock = 256;       // staging slots a wave claims at once
+constexpr int kRunBlock = 256;         // run slots a wave claims at once
 constexpr int kMaxEmitGrid = 512;      // bound on bunch-kernel workgroups (workspace sizing)
 constexpr int kMaxEmitWaves = 16;     // waves per bunch-kernel workgroup
 constexpr int kRowBlock = 64;          // tiles per block of the per-telescope scan
@@ -36,35 +37,47 @@ constexpr int kCell32 = 8;
 // Layout of one node of the FP64 table: psi_i, P1_i..P5_i.
 constexpr int kNode64 = 6;
 
-// Staging entry written by the bunch kernel for every sphere crossing.
+// Staging entry written by the bunch kernel for every sphere crossing (48 bytes:
+// the record and what places it: tile, telescope, rank inside the tile, bunch).
 struct alignas(16) StageEntry {
     float rec[8];        // dx, dy, u_o, v_o, t, h_e, photons, lambda
     uint32_t tile;       // emit tile
-    uint32_t tel;        // telescope
+    uint32_t tel_sidx;   // telescope | (step index inside the tile) << 16
     uint32_t rank;       // index among this tile's crossings of this telescope
-    uint32_t shower;     // shower index
-    int64_t seg;         // step index in the call
-    int64_t k;           // bunch index in the step
+    uint32_t k;          // bunch index in the step (< 2^30: a tile holds fewer bunches)
 };
-static_assert(sizeof(StageEntry) == 64, "staging entry is 64 bytes");
+static_assert(sizeof(StageEntry) == 48, "staging entry is 48 bytes");
 
-// Control block in the workspace (zeroed by the first kernel of a run).
+// A tile's crossings per telescope are kept as runs, one per telescope the tile's
+// bunches crossed: (telescope << kRunTelShift) | count, ascending telescope; the
+// finalize replaces each count by the crossings of the same (shower, telescope)
+// in earlier tiles.
+constexpr int kRunTelShift = 40;
+constexpr int64_t kRunValueMask = ((int64_t)1 << kRunTelShift) - 1;
+
+// Control block in the workspace (zeroed by the first kernel of a run).  The
+// counters every wave claims from (tiles, staging blocks, run blocks, screening
+// tiles) sit on cache lines of their own: same-line atomics from all waves would
+// serialise in one L2 channel.
 enum CtrlSlot {
     kTileCounter = 0,   // next tile to claim
-    kBlockCounter,      // next staging block to claim
-    kNumTiles,          // tiles of this run
+    kBlockCounter = 32, // next staging block to claim
+    kRunCounter = 64,   // next run block to claim
+    kScreenCounter = 96,  // next tile to claim in the soft response's screening pass (the
+                          // FP64 tile forward that may follow claims from kTileCounter)
+    kNumTiles = 128,    // tiles of this run
     kNumRowBlocks,      // row blocks of the per-telescope scan
     kHits,              // crossings found
     kBunches,           // bunches generated
     kEmitting,          // steps with light
-    kStageOverflow,     // a staging claim went past the end
-    kScreenCounter,     // next tile to claim in the soft response's screening pass (the
-                        // FP64 tile forward that may follow claims from kTileCounter)
+    kFirstLost,         // smallest tile with a crossing that found no staging or run slot
+                        // (set to the tile count by the first kernel)
+    kCutTile,           // tiles [0, kCutTile) are written
+    kCutBlocks,         // row blocks holding them
+    kRecords,           // their crossings
     kDrop0,             // CKV_N_DROP drop counters follow
     kCtrlSlots = kDrop0 + CKV_N_DROP + 4
 };
-
-
 
 }  // namespace ckv
 
@@ -126,9 +139,17 @@ int build_node_tables(const double* alt, const double* eta, int64_t n, double h_
 void build_depth_table(const double* alt, const double* depth, int64_t n, ckv_atmo* a);
 int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ckv_grid* g);
 constexpr double kSoftZCut = 40.0;   // Phi(-40) underflows to exactly 0 in FP64
-// margin of the soft response's screening spheres over the cut radius: far above the
-// mixed path's ground-point and direction errors (tolerances 1 mm and 1e-6)
+// margin of the soft response's screening spheres over the cut radius [m]
 constexpr double kScreenMargin = 0.01;
+// Bound of the mixed path's ground-point error per metre of height above the
+// observation level: e_g = dh (kScreenErrDir (1/w + 1/w^2) + kScreenErrSeries / w^3).
+// The first term: the FP32 cone vector carries an absolute direction error below
+// sin(theta_c) x 3e-7 <= 7.3e-9 (theta_c <= 1.4 deg at n - 1 <= 3e-4), which
+// moves the ground point by dh delta (1/w + |u|/w^2).  The second: the FP32 series
+// corrections, below 2^-20 relative of q D1/2 <= (1/w^2) 3e-4 dh, moved by u/w.
+// Screened bunches whose bound passes half the margin are listed unconditionally.
+constexpr double kScreenErrDir = 1e-8;
+constexpr double kScreenErrSeries = 5e-10;
 int param_spec_check(const ckv_atmo_param_spec* sp, const double* theta);
 void param_profile(const ckv_atmo_param_spec* sp, const double* theta, std::vector<double>* alt,
                    std::vector<double>* eta);
@@ -153,13 +174,20 @@ struct RunPlan {
     int32_t emit_grid, emit_waves;
     int32_t prof_bins;          // longitudinal-profile bins, 0 = no profile
     double k_ft;
+    ckv_cursor cursor;          // first step of the run (step 0, shower 0 without one)
+    int64_t run_cap;            // run slots
     // workspace carve-out
     int64_t* ctrl;
     ckv_result* ws_result;      // report of the soft entry points when the caller has none
     int64_t* tiles_before;      // n_showers + 1
     int64_t* blocks_before;     // n_showers + 1
-    int32_t* counts;            // max_tiles x n_tel
-    int32_t* block_sums;        // max_row_blocks x n_tel
+    int64_t* shower_first;      // n_showers: first step of each shower in this run
+    int64_t* tile_run_off;      // max_tiles: first run of the tile
+    int32_t* tile_run_n;        // max_tiles: runs of the tile
+    int32_t* tile_hits;         // max_tiles: crossings of the tile
+    int64_t* runs;              // run_cap
+    int32_t* block_sums;        // n_tel x max_row_blocks (telescope-major)
+    int64_t* block_hits;        // max_row_blocks: crossings per row block
     int32_t* shower_tel;        // n_showers x n_tel
     int32_t* stage_fill;        // stage_slots / kStageBlock
     StageEntry* stage;          // stage_slots
@@ -170,7 +198,7 @@ size_t workspace_layout(int64_t n_segments, int32_t n_showers, int32_t n_tel, in
 // ckv_run after its handle-free checks: validates, lays out `workspace` and launches
 int run_checked(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
                 const ckv_atmo* atmo, const ckv_array* arr, void* workspace, size_t ws_bytes,
-                ckv_output* out, void* stream);
+                ckv_output* out, const ckv_cursor* resume_from, void* stream);
 // bunch-kernel workgroups of a launch with params->grid == 0 on the current device
 int default_emit_grid(int* grid);
 int launch_run(RunPlan& plan);
@@ -178,7 +206,7 @@ int launch_count(const ckv_segments* segs, const ckv_params* p, const ckv_atmo* 
                  int64_t* n_b, hipStream_t stream);
 // waves per bunch-kernel workgroup (at most max_waves) and its LDS bytes
 int emit_config(int precision, int n_tel, int prof_bins, const ckv_atmo* atmo, int tile_segs,
-                int max_waves, int* waves, size_t* lds_bytes);
+                int max_waves, int* waves, size_t* lds_bytes, bool narrow_ok);
 
 struct SoftPlan {
     const int64_t* n_b_frozen;

@@ -38,6 +38,7 @@ struct Args {
     const double *x0, *y0, *h0, *u, *v, *w, *len, *t0, *energy;
     const uint8_t* ptype;
     int64_t n;
+    const uint32_t* step_id;    // counter word 1 per step, or NULL
     const int64_t* seg_offsets;
     const double* t_ref;
     const uint32_t* shower_ids;
@@ -74,12 +75,21 @@ struct Args {
     double r_obs;               // earth_r + h_obs
     uint32_t key0, key1;
     int32_t tile_segs;
+    // first step of the run (a resume cursor; step 0 of shower 0 without one)
+    int64_t cur_step;
+    int32_t cur_shower;
     // workspace and output
     int64_t* ctrl;
     int64_t* tiles_before;
     int64_t* blocks_before;
-    int32_t* counts;
-    int32_t* block_sums;
+    int64_t* shower_first;      // first step of each shower in this run
+    int64_t* tile_run_off;
+    int32_t* tile_run_n;
+    int32_t* tile_hits;
+    int64_t* runs;
+    int64_t run_cap;
+    int32_t* block_sums;        // telescope-major: block_sums[k * max_row_blocks + b]
+    int64_t* block_hits;
     int32_t* shower_tel;
     int32_t* stage_fill;
     StageEntry* stage;
@@ -140,6 +150,15 @@ template <typename T>
 __device__ __forceinline__ T uniform(T x)
 {
     return __shfl(x, 0);
+}
+
+// A value every lane holds alike, made visibly uniform to the compiler (a scalar
+// register), so that control flow depending on it stays scalar.
+__device__ __forceinline__ int64_t scalar64(int64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // Candidate-grid level for a line with observed w^2 = wo2 (>= kLevelW2[0]):
@@ -534,7 +553,8 @@ struct alignas(16) StepEntry<1> {
     float sb1x, sb1y, sb1z, sb2x, sb2y, sb2z;
     int32_t boff;   // first bunch of the step inside the tile
     int32_t sidx;   // index of the step inside the tile
-    int32_t pad[2];
+    uint32_t ctr1;  // counter word 1 of the step's random numbers
+    int32_t pad;
 };
 static_assert(sizeof(StepEntry<1>) == 128, "step entry size");
 
@@ -572,6 +592,7 @@ __host__ __device__ inline size_t wave_bytes(int prec, int tile_segs, int n_tel,
 {
     size_t b = (size_t)tile_segs * (prec == 0 ? sizeof(StepEntry<0>) : sizeof(StepEntry<1>));
     b += kWave * sizeof(int32_t);                       // flag row
+    if (prec == 0) b += (size_t)tile_segs * sizeof(uint32_t);   // counter words (FP64 path)
     b += (size_t)kWcCount * sizeof(int64_t);            // counters
     b += ((size_t)n_tel * sizeof(int32_t) + 15) & ~(size_t)15;   // telescope counters
     b += (size_t)prof_bins * (sizeof(double) + sizeof(uint32_t));  // profile of the tile
@@ -652,6 +673,10 @@ constexpr int kFeatWide = 16;    // mixed kernel built for <= 8 waves per workgr
 // bunch tested against spheres of the soft cut radius plus a margin, the candidates'
 // ids listed; no records
 constexpr int kFeatScreen = 32;
+// FP64 kernel built for 16 waves per workgroup (128 registers, four waves per SIMD):
+// only the lowest kLdsTableEntries nodes of the table fit the LDS beside 16 wave
+// areas, the rare lookups above them read HBM (alone, no other feature)
+constexpr int kFeatNarrow = 64;
 // per wave, after the regular area: list state {tile's first step, ids, capacity,
 // count, emitting steps, unused} and the ballot words of the candidate bunches
 constexpr int kScreenWords = 64;
@@ -676,7 +701,8 @@ __host__ __device__ inline size_t tel_bytes(int n_tel)
 // zenith angles); the launch's wave count picks the build.
 constexpr int emit_threads(int prec, int feat)
 {
-    return (prec == 0 || (feat & (kFeatExact | kFeatCurved | kFeatWide)) != 0) ? 512 : 1024;
+    return (feat & kFeatNarrow) ? 1024
+           : (prec == 0 || (feat & (kFeatExact | kFeatCurved | kFeatWide)) != 0) ? 512 : 1024;
 }
 
 template <int PREC, int TS, int FEAT>
@@ -687,7 +713,8 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
     constexpr bool SEARCH = (FEAT & kFeatSearch) != 0;
     constexpr bool CURVED = (FEAT & kFeatCurved) != 0;
     constexpr bool SCREEN = (FEAT & kFeatScreen) != 0;
-    constexpr bool PARTIAL = PROF || SCREEN;      // table staged in part, the rest from HBM
+    constexpr bool NARROW = (FEAT & kFeatNarrow) != 0;
+    constexpr bool PARTIAL = PROF || SCREEN || NARROW;   // table staged in part, the rest from HBM
     constexpr bool SLOWPATH = EXACT || CURVED;    // lanes that leave the moment series
     using T = typename std::conditional<PREC == 0, double, float>::type;
     using Entry = StepEntry<PREC>;
@@ -730,7 +757,9 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
     }
     Entry* stash = reinterpret_cast<Entry*>(wbase);
     int32_t* flags = reinterpret_cast<int32_t*>(wbase + TS * sizeof(Entry));
-    int64_t* wcnt = reinterpret_cast<int64_t*>(flags + kWave);
+    // FP64 path: counter word per step (the mixed path keeps it in its step record)
+    uint32_t* sctr = reinterpret_cast<uint32_t*>(flags + kWave);
+    int64_t* wcnt = reinterpret_cast<int64_t*>(sctr + (PREC == 0 ? ((TS + 1) & ~1) : 0));
     int32_t* tcount = reinterpret_cast<int32_t*>(wcnt + kWcCount);
     // profile of the current tile: photons (FP64) and bunches per depth bin
     double* hph = reinterpret_cast<double*>(
@@ -758,6 +787,9 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
 
     int64_t blk = -1;          // current staging block; -1: none yet, -2: staging full
     int blk_fill = 0;
+    bool lost = false;         // a crossing of this wave found no slot (tile marked)
+    int64_t rblk = -1;         // current run block; -1: none yet
+    int rfill = 0;
     const int64_t n_tiles = a.ctrl[kNumTiles];
 
     for (;;) {
@@ -773,13 +805,13 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
             if (a.tiles_before[mid] <= t) lo = mid; else hi = mid;
         }
         const int s = lo;
-        const int64_t sfirst = a.seg_offsets[s];
-        const int64_t g0 = sfirst + (t - a.tiles_before[s]) * (int64_t)TS;
+        const int64_t g0 = a.shower_first[s] + (t - a.tiles_before[s]) * (int64_t)TS;
         const int64_t gend = min(g0 + (int64_t)TS, a.seg_offsets[s + 1]);
         const int nseg = (int)(gend - g0);
         const uint32_t shower_id = a.shower_ids ? a.shower_ids[s] : (uint32_t)s;
-        const int64_t seg_id0 = (a.seg_id_base ? a.seg_id_base[s] : 0) + (g0 - sfirst);
+        const int64_t seg_id0 = (a.seg_id_base ? a.seg_id_base[s] : 0) + (g0 - a.seg_offsets[s]);
         const double t_ref = a.t_ref[s];
+        int32_t thits = 0;         // crossings of this tile (wave-uniform)
 
         // ---- step setups, one per lane; emitting steps are compacted
         int64_t nb = 0;
@@ -803,7 +835,7 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
             }
         }
         int64_t incl = wave_incl_scan(nb);
-        int64_t total = __shfl(incl, kWave - 1);
+        int64_t total = scalar64(__shfl(incl, kWave - 1));
         if (total >= ((int64_t)1 << 30)) {
             // bunch offsets inside a tile are 32-bit: refuse such a tile
             if (lane == 0 && a.result) atomicOr(&a.result->error, 2);
@@ -822,6 +854,9 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
         if (emits) {
             Entry& e = stash[__popcll(emit_mask & lt_mask)];
             const int64_t g = g0 + lane;
+            const uint32_t ctr1 = a.step_id ? a.step_id[g] : (uint32_t)(seg_id0 + lane);
+            if constexpr (PREC == 1) e.ctr1 = ctr1;
+            else sctr[lane] = ctr1;
             e.x0 = a.x0[g];
             e.y0 = a.y0[g];
             e.h0 = a.h0[g];
@@ -880,6 +915,7 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
             int32_t k, sidx;
             double uod, vod;   // observed direction for the sphere test (live bunches)
             int pbin = -1;     // depth bin of the bunch for the profile, -1: not counted
+            bool screen_all = false;   // screening: listed whatever its sphere tests say
             double fcell, dcell;   // fraction and height of the emission point in its cell
             int ci;
             if (active) {
@@ -887,7 +923,10 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                 k = j - e.boff;
                 sidx = e.sidx;
                 // Philox4x32-10 with counter (k, step index in shower, shower id, 0)
-                uint32_t c_0 = (uint32_t)k, c_1 = (uint32_t)(seg_id0 + sidx), c_2 = shower_id, c_3 = 0u;
+                uint32_t c_0 = (uint32_t)k, c_2 = shower_id, c_3 = 0u;
+                uint32_t c_1;
+                if constexpr (PREC == 1) c_1 = e.ctr1;
+                else c_1 = sctr[sidx];
 #pragma unroll
                 for (int rr = 0; rr < 10; ++rr) {
                     const uint64_t p0 = (uint64_t)0xD2511F53u * c_0;
@@ -1118,6 +1157,15 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     const double ctw = fma(ne, dh, (double)(t_corr * inv_ne));
                     const double T_travel = ctw * inv_w * inv_c;
                     const double adv = inv_w * S;
+                    if (SCREEN) {
+                        // bound of this path's ground-point error (direction error of the
+                        // FP32 cone vector through 1/w and u/w^2, FP32 series corrections
+                        // through q ~ 1/w^2 and 1/w): where it passes half the screening
+                        // margin the sphere test cannot be trusted and the bunch is listed
+                        const double e_g = dh * inv_w * (kScreenErrDir * (1.0 + inv_w) +
+                                                         kScreenErrSeries * inv_w * inv_w);
+                        screen_all = e_g > 0.5 * kScreenMargin;
+                    }
                     xg = fma(pu, adv, xe);
                     yg = fma(pv, adv, ye);
                     tarr = (te - t_ref) + T_travel;
@@ -1201,7 +1249,7 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
             if constexpr (SCREEN) {
                 // candidates of the soft response: one ballot word per 64 bunches,
                 // flushed to the list when the buffer is full and at the tile's end
-                const uint64_t m = __ballot(my_next != INT_MAX);
+                const uint64_t m = __ballot(my_next != INT_MAX || screen_all);
                 const int w = (int)((c0 >> 6) & (kScreenWords - 1));
                 if (lane == 0) bits[w] = m;
                 if (w == kScreenWords - 1 || c0 + kWave >= total) {
@@ -1217,7 +1265,7 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     const int nmine = __popcll(mask);
                     const int below = __popcll(mask & lt_mask);
                     const int rank0 = tcount[kmin];
-                    if (lane == 0) wcnt[kWcHits] += nmine;
+                    thits += nmine;
                     // staging slots: the first `room` crossings fill the current
                     // block, the rest start a newly claimed one
                     const int room = blk >= 0 ? kStageBlock - blk_fill : 0;
@@ -1226,10 +1274,13 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                         if (blk >= 0 && lane == 0) a.stage_fill[blk] = kStageBlock;
                         if (lane == 0) nbk = (int64_t)atomicAdd((unsigned long long*)&a.ctrl[kBlockCounter], 1ull);
                         nbk = uniform(nbk);
-                        if (nbk >= a.stage_blocks) {
-                            nbk = -2;
-                            if (lane == 0) atomicExch((unsigned long long*)&a.ctrl[kStageOverflow], 1ull);
-                        }
+                        if (nbk >= a.stage_blocks) nbk = -2;
+                    }
+                    if (nmine > room && nbk < 0 && !lost) {
+                        // crossings of this tile find no slot: the run's written prefix
+                        // ends before it (this wave's later tiles come after it)
+                        lost = true;
+                        if (lane == 0) atomicMin((unsigned long long*)&a.ctrl[kFirstLost], (unsigned long long)t);
                     }
                     if (mine) {
                         int64_t slot = -1;
@@ -1242,10 +1293,8 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                             ef[0] = make_float4((float)(xg - tp[0]), (float)(yg - tp[1]), uo, vo);
                             ef[1] = make_float4(t_f, he_f, photons, lam);
                             uint4* eu = reinterpret_cast<uint4*>(se);
-                            eu[2] = make_uint4((uint32_t)t, (uint32_t)kmin, (uint32_t)(rank0 + below), (uint32_t)s);
-                            int64_t* el = reinterpret_cast<int64_t*>(se);
-                            el[6] = g0 + sidx;
-                            el[7] = k;
+                            eu[2] = make_uint4((uint32_t)t, (uint32_t)kmin | ((uint32_t)sidx << 16),
+                                               (uint32_t)(rank0 + below), (uint32_t)k);
                         }
                     }
                     if (nmine > room) {
@@ -1262,14 +1311,52 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                 }
             }
         }
-        // ---- per-telescope crossings of this tile
+        // ---- per-telescope crossings of this tile as runs (ascending telescope)
         wave_lds_sync();
         if (!SCREEN && t < a.max_tiles) {
-            int32_t* row = a.counts + t * (int64_t)a.n_tel;
-            for (int kk = lane; kk < a.n_tel; kk += kWave) {
-                row[kk] = tcount[kk];
-                tcount[kk] = 0;
+            int nz = 0;
+            for (int k0 = 0; k0 < a.n_tel; k0 += kWave) {
+                const int kk = k0 + lane;
+                nz += __popcll(__ballot(kk < a.n_tel && tcount[kk] != 0));
             }
+            // run slots from the wave's current block of kRunBlock (a tile with more
+            // runs than a block takes enough whole blocks of its own)
+            int64_t base = 0;
+            if (nz > 0) {
+                if (rblk < 0 || rfill + nz > kRunBlock) {
+                    const int nblk = (nz + kRunBlock - 1) / kRunBlock;
+                    int64_t b = 0;
+                    if (lane == 0) b = (int64_t)atomicAdd((unsigned long long*)&a.ctrl[kRunCounter],
+                                                          (unsigned long long)nblk);
+                    rblk = scalar64(uniform(b));
+                    rfill = 0;
+                }
+                base = rblk * kRunBlock + rfill;
+                rfill = nz > kRunBlock ? kRunBlock : rfill + nz;
+            }
+            const bool fits = base + nz <= a.run_cap;
+            if (!fits && !lost) {
+                lost = true;
+                if (lane == 0) atomicMin((unsigned long long*)&a.ctrl[kFirstLost], (unsigned long long)t);
+            }
+            int done = 0;
+            for (int k0 = 0; k0 < a.n_tel; k0 += kWave) {
+                const int kk = k0 + lane;
+                const int32_t c = kk < a.n_tel ? tcount[kk] : 0;
+                const uint64_t m = __ballot(c != 0);
+                if (c != 0) {
+                    if (fits)
+                        a.runs[base + done + __popcll(m & lt_mask)] = ((int64_t)kk << kRunTelShift) | c;
+                    tcount[kk] = 0;
+                }
+                done += __popcll(m);
+            }
+            if (lane == 0) {
+                a.tile_run_off[t] = base;
+                a.tile_run_n[t] = fits ? nz : 0;
+                a.tile_hits[t] = thits;
+            }
+            if (lane == 0) wcnt[kWcHits] += thits;
         }
         // ---- profile of this tile into its shower's row
         for (int kk = lane; PROF && kk < a.prof_bins; kk += kWave) {
@@ -1320,7 +1407,17 @@ __global__ void __launch_bounds__(1024) init_kernel(Args a)
             if (lo < 0 || hi < lo || hi > a.n || (s == 0 && lo != 0) ||
                 (s == a.n_showers - 1 && hi != a.n))
                 err = 1;
-            const int64_t cnt = hi >= lo ? hi - lo : 0;
+            // the run starts at the cursor: showers before its shower have no tiles,
+            // its shower starts at the cursor's step
+            int64_t first = lo;
+            if (s < a.cur_shower) {
+                first = hi;
+            } else if (s == a.cur_shower) {
+                if (a.cur_step < lo || a.cur_step > hi) err = 1;
+                first = a.cur_step < lo ? lo : (a.cur_step > hi ? hi : a.cur_step);
+            }
+            if (a.shower_first) a.shower_first[s] = first;
+            const int64_t cnt = hi >= first ? hi - first : 0;
             nt = (cnt + TS - 1) / TS;
             nbk = (nt + kRowBlock - 1) / kRowBlock;
         }
@@ -1346,17 +1443,21 @@ __global__ void __launch_bounds__(1024) init_kernel(Args a)
     if (threadIdx.x == 0) {
         a.tiles_before[a.n_showers] = run_t;
         a.blocks_before[a.n_showers] = run_b;
-        if (run_t > a.max_tiles) err = 1;
+        if (run_t > a.max_tiles || run_b > a.max_row_blocks) err = 1;
         a.ctrl[kNumTiles] = err ? 0 : run_t;
         a.ctrl[kNumRowBlocks] = err ? 0 : run_b;
+        a.ctrl[kFirstLost] = err ? 0 : run_t;      // no lost tile yet
         if (a.result) {
             // the bunch path's finalize fills the rest; the soft entry points report
             // the error word only
             ckv_result* r = a.result;
             r->n_bunches = r->n_hits = r->n_records = r->n_emitting = r->n_tiles = 0;
             for (int d = 0; d < CKV_N_DROP; ++d) r->drops[d] = 0;
+            r->resume_step = a.n;
+            r->resume_shower = a.n_showers;
             r->overflow = 0;
             r->error = err;
+            r->reserved = 0;
         }
     }
 }
@@ -1374,42 +1475,159 @@ __device__ __forceinline__ int find_shower(const int64_t* before, int n_showers,
     return lo;
 }
 
-// Block sums are stored telescope-major: block_sums[k * max_row_blocks + b].
-
-// A: per row block, per telescope: sum of crossings over the block's tiles
-__global__ void __launch_bounds__(256) rowblock_sum_kernel(Args a)
+// Row block b of shower s holds the shower's tiles [t0, t1) below; blocks and tiles
+// are both numbered shower by shower, so block order is tile order.
+__device__ __forceinline__ void block_tiles(const Args& a, int64_t b, int& s, int64_t& t0, int64_t& t1)
 {
-    const int64_t nblk = a.ctrl[kNumRowBlocks];
-    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
-        const int s = find_shower(a.blocks_before, a.n_showers, b);
-        const int64_t t0 = a.tiles_before[s] + (b - a.blocks_before[s]) * kRowBlock;
-        const int64_t t1 = min(t0 + kRowBlock, a.tiles_before[s + 1]);
-        for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x) {
-            int32_t sum = 0;
-#pragma unroll 8
-            for (int64_t t = t0; t < t1; ++t) sum += a.counts[t * a.n_tel + k];
-            a.block_sums[k * a.max_row_blocks + b] = sum;
+    s = find_shower(a.blocks_before, a.n_showers, b);
+    t0 = a.tiles_before[s] + (b - a.blocks_before[s]) * kRowBlock;
+    t1 = min(t0 + (int64_t)kRowBlock, a.tiles_before[s + 1]);
+}
+
+// Adds the runs of tiles [t0, t1) into acc[telescope] (LDS) with the whole
+// workgroup: one wave per tile, lanes over its runs.
+__device__ __forceinline__ void add_runs(const Args& a, int64_t t0, int64_t t1, int32_t* acc)
+{
+    const int lane = lane_id(), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    for (int64_t t = t0 + wave; t < t1; t += nw) {
+        const int n = a.tile_run_n[t];
+        const int64_t off = a.tile_run_off[t];
+        for (int i = lane; i < n; i += kWave) {
+            const int64_t r = a.runs[off + i];
+            atomicAdd(&acc[(int)(r >> kRunTelShift)], (int32_t)(r & kRunValueMask));
         }
     }
 }
 
-// B: per (shower, telescope), one wave: exclusive scan over the shower's row
-// blocks, 64 blocks per step
+// A: per row block: crossings per telescope (block_sums, telescope-major:
+// block_sums[k * max_row_blocks + b]) and in all (block_hits).
+__global__ void __launch_bounds__(256) block_sum_kernel(Args a)
+{
+    extern __shared__ int32_t acc[];               // n_tel
+    __shared__ unsigned long long tot;
+    const int64_t nblk = a.ctrl[kNumRowBlocks];
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x) acc[k] = 0;
+        if (threadIdx.x == 0) tot = 0;
+        __syncthreads();
+        int s;
+        int64_t t0, t1;
+        block_tiles(a, b, s, t0, t1);
+        add_runs(a, t0, t1, acc);
+        for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x)
+            atomicAdd(&tot, (unsigned long long)a.tile_hits[t]);
+        __syncthreads();
+        for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x)
+            a.block_sums[(int64_t)k * a.max_row_blocks + b] = acc[k];
+        if (threadIdx.x == 0) a.block_hits[b] = (int64_t)tot;
+        __syncthreads();
+    }
+}
+
+// B: the written prefix.  Without a lost tile and with every crossing within the
+// capacity it is the whole run.  Otherwise it ends at the first tile that is
+// lost or whose crossings would pass the capacity; the row block holding that
+// tile gets its sums again over the tiles before it.  One workgroup.
+__global__ void __launch_bounds__(1024) cutoff_kernel(Args a)
+{
+    extern __shared__ int32_t acc[];               // n_tel
+    __shared__ int64_t part[1024];
+    __shared__ int first_thread;
+    __shared__ int64_t cut_tile, cut_block, cut_records, blk_b, blk_before;
+    const int64_t n_tiles = a.ctrl[kNumTiles], nblk = a.ctrl[kNumRowBlocks];
+    const int64_t lost = a.ctrl[kFirstLost];
+    const int64_t hits = a.ctrl[kHits];
+    if (lost >= n_tiles && hits <= a.capacity) {
+        if (threadIdx.x == 0) {
+            a.ctrl[kCutTile] = n_tiles;
+            a.ctrl[kCutBlocks] = nblk;
+            a.ctrl[kRecords] = hits;
+        }
+        return;
+    }
+    // the row block holding the lost tile bounds the search
+    int64_t b_lim = nblk;
+    if (lost < n_tiles) {
+        const int sl = find_shower(a.tiles_before, a.n_showers, lost);
+        b_lim = a.blocks_before[sl] + (lost - a.tiles_before[sl]) / kRowBlock + 1;
+    }
+    // first block whose crossings, added to those before it, pass the capacity
+    const int nt = blockDim.x;
+    const int64_t chunk = (b_lim + nt - 1) / nt;
+    const int64_t lo = (int64_t)threadIdx.x * chunk, hi = min(lo + chunk, b_lim);
+    int64_t mine = 0;
+    for (int64_t b = lo; b < hi; ++b) mine += a.block_hits[b];
+    part[threadIdx.x] = mine;
+    if (threadIdx.x == 0) first_thread = nt;
+    __syncthreads();
+    for (int d = 1; d < nt; d <<= 1) {
+        const int64_t y = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += y;
+        __syncthreads();
+    }
+    const int64_t before = part[threadIdx.x] - mine;
+    if (lo < hi && part[threadIdx.x] > a.capacity) atomicMin(&first_thread, (int)threadIdx.x);
+    __syncthreads();
+    if ((int)threadIdx.x == (first_thread < nt ? first_thread : nt - 1)) {
+        // walk this thread's blocks to the first that passes (the lost tile's block
+        // when none does)
+        int64_t cum = first_thread < nt ? before : part[nt - 1] - a.block_hits[b_lim - 1];
+        int64_t b = first_thread < nt ? lo : b_lim - 1;
+        if (first_thread < nt)
+            while (b + 1 < hi && cum + a.block_hits[b] <= a.capacity) cum += a.block_hits[b++];
+        blk_b = b;
+        blk_before = cum;
+    }
+    __syncthreads();
+    // the tile: first of block blk_b that is lost or passes the capacity
+    if (threadIdx.x == 0) {
+        int s;
+        int64_t t0, t1;
+        block_tiles(a, blk_b, s, t0, t1);
+        int64_t cum = blk_before, t = t0;
+        while (t < t1 && t < lost && cum + a.tile_hits[t] <= a.capacity) cum += a.tile_hits[t++];
+        cut_tile = t;
+        cut_block = t > t0 ? blk_b + 1 : blk_b;
+        cut_records = cum;
+    }
+    __syncthreads();
+    // sums of the boundary block over its tiles before the cut
+    const int64_t b = blk_b;
+    int s;
+    int64_t t0, t1;
+    block_tiles(a, b, s, t0, t1);
+    for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x) acc[k] = 0;
+    __syncthreads();
+    add_runs(a, t0, min(t1, cut_tile), acc);
+    __syncthreads();
+    for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x)
+        a.block_sums[(int64_t)k * a.max_row_blocks + b] = acc[k];
+    if (threadIdx.x == 0) {
+        a.ctrl[kCutTile] = cut_tile;
+        a.ctrl[kCutBlocks] = cut_block;
+        a.ctrl[kRecords] = cut_records;
+    }
+}
+
+// C: per (shower, telescope), one wave: exclusive scan over the shower's row
+// blocks below the cut, 8 x 64 blocks per round
 __global__ void __launch_bounds__(256) rowblock_scan_kernel(Args a)
 {
     const int lane = lane_id();
     const int64_t nst = (int64_t)a.n_showers * a.n_tel;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     const bool have_tiles = a.ctrl[kNumTiles] > 0;
+    const int64_t cutb = a.ctrl[kCutBlocks];
     for (int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; q < nst;
          q += waves) {
         const int s = (int)(q / a.n_tel), k = (int)(q % a.n_tel);
         int64_t run = 0;
         if (have_tiles) {
             int32_t* col = a.block_sums + (int64_t)k * a.max_row_blocks;
-            const int64_t b_end = a.blocks_before[s + 1];
-            // 8 x 64 blocks per round, 8 consecutive ones per lane: the loads issue
-            // before the first store and one wave scan of the lane sums serves all
+            const int64_t b_end = min(a.blocks_before[s + 1], cutb);
+            // the loads issue before the first store and one wave scan of the lane
+            // sums serves all
             constexpr int G = 8;
             for (int64_t b0 = a.blocks_before[s]; b0 < b_end; b0 += G * kWave) {
                 const int64_t bl = b0 + (int64_t)G * lane;
@@ -1434,33 +1652,57 @@ __global__ void __launch_bounds__(256) rowblock_scan_kernel(Args a)
     }
 }
 
-// C: per tile, per telescope: crossings of the same shower in earlier tiles
-__global__ void __launch_bounds__(256) tile_prefix_kernel(Args a)
+// D: per row block below the cut, one wave: each run's count becomes the
+// crossings of its (shower, telescope) in earlier tiles.  The block's runs are
+// gathered into LDS when they fit (one load round per tile list), walked tile by
+// tile there, and written back.
+constexpr int kPrefixLdsRuns = 4096;
+
+__global__ void __launch_bounds__(64) tile_prefix_kernel(Args a)
 {
-    const int64_t nblk = a.ctrl[kNumRowBlocks];
-    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
-        const int s = find_shower(a.blocks_before, a.n_showers, b);
-        const int64_t t0 = a.tiles_before[s] + (b - a.blocks_before[s]) * kRowBlock;
-        const int64_t t1 = min(t0 + kRowBlock, a.tiles_before[s + 1]);
-        for (int k = threadIdx.x; k < a.n_tel; k += blockDim.x) {
-            int32_t run = a.block_sums[k * a.max_row_blocks + b];
-            // 16 tiles per round: all loads issue before the first store
-            constexpr int G = 16;
-            for (int64_t tg = t0; tg < t1; tg += G) {
-                int32_t x[G];
-#pragma unroll
-                for (int j = 0; j < G; ++j) x[j] = tg + j < t1 ? a.counts[(tg + j) * a.n_tel + k] : 0;
-#pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    if (tg + j < t1) a.counts[(tg + j) * a.n_tel + k] = run;
-                    run += x[j];
-                }
+    extern __shared__ int32_t ctr[];               // n_tel counters, then the run buffer
+    int64_t* buf = reinterpret_cast<int64_t*>(ctr + ((a.n_tel + 1) & ~1));
+    const int lane = lane_id();
+    const int64_t cutb = a.ctrl[kCutBlocks], cut = a.ctrl[kCutTile];
+    for (int64_t b = blockIdx.x; b < cutb; b += gridDim.x) {
+        int s;
+        int64_t t0, t1;
+        block_tiles(a, b, s, t0, t1);
+        t1 = min(t1, cut);
+        for (int k = lane; k < a.n_tel; k += kWave) ctr[k] = a.block_sums[(int64_t)k * a.max_row_blocks + b];
+        // lane l: tile t0 + l (a block has at most 64 tiles)
+        const int64_t tl = t0 + lane;
+        const int n = tl < t1 ? a.tile_run_n[tl] : 0;
+        const int64_t off = tl < t1 ? a.tile_run_off[tl] : 0;
+        const int64_t incl = wave_incl_scan((int64_t)n);
+        const int64_t total = __shfl(incl, kWave - 1);
+        const int my0 = (int)(incl - n);
+        const bool in_lds = total <= kPrefixLdsRuns;
+        if (in_lds)
+            for (int i = 0; i < n; ++i) buf[my0 + i] = a.runs[off + i];
+        wave_lds_sync();
+        for (int64_t t = t0; t < t1; ++t) {
+            const int j = (int)(t - t0);
+            const int nj = __shfl(n, j);
+            const int64_t offj = __shfl(off, j);
+            const int bj = __shfl(my0, j);
+            for (int i = lane; i < nj; i += kWave) {
+                const int64_t r = in_lds ? buf[bj + i] : a.runs[offj + i];
+                const int tel = (int)(r >> kRunTelShift);
+                const int32_t v = ctr[tel];
+                const int64_t w = ((int64_t)tel << kRunTelShift) | v;
+                if (in_lds) buf[bj + i] = w; else a.runs[offj + i] = w;
+                ctr[tel] = v + (int32_t)(r & kRunValueMask);
             }
+            wave_lds_sync();
         }
+        if (in_lds)
+            for (int i = 0; i < n; ++i) a.runs[off + i] = buf[my0 + i];
+        wave_lds_sync();
     }
 }
 
-// D: CSR offsets over (shower, telescope) and the run report
+// E: CSR offsets over (shower, telescope) and the run report
 __global__ void __launch_bounds__(1024) csr_kernel(Args a)
 {
     __shared__ int64_t sh[1024];
@@ -1484,23 +1726,30 @@ __global__ void __launch_bounds__(1024) csr_kernel(Args a)
     if (threadIdx.x == 0) {
         a.tel_offsets[nst] = run;
         ckv_result* r = a.result;
-        const int64_t hits = a.ctrl[kHits];
-        const int overflow = (hits > a.capacity) || (a.ctrl[kStageOverflow] != 0);
+        const int64_t n_tiles = a.ctrl[kNumTiles], cut = a.ctrl[kCutTile];
         r->n_bunches = a.ctrl[kBunches];
-        r->n_hits = hits;
-        r->n_records = overflow ? 0 : hits;
+        r->n_hits = a.ctrl[kHits];
+        r->n_records = a.ctrl[kRecords];
         r->n_emitting = a.ctrl[kEmitting];
-        r->n_tiles = a.ctrl[kNumTiles];
+        r->n_tiles = n_tiles;
         for (int d = 0; d < CKV_N_DROP; ++d) r->drops[d] = a.ctrl[kDrop0 + d];
-        r->overflow = overflow;
+        if (cut < n_tiles) {
+            const int sc = find_shower(a.tiles_before, a.n_showers, cut);
+            r->resume_shower = sc;
+            r->resume_step = a.shower_first[sc] + (cut - a.tiles_before[sc]) * (int64_t)a.tile_segs;
+            r->overflow = 1;
+        } else {
+            r->resume_shower = a.n_showers;
+            r->resume_step = a.n;
+            r->overflow = 0;
+        }
     }
 }
 
-// E: scatter the staged records to their final slots
+// F: scatter the staged records of the written tiles to their final slots
 __global__ void __launch_bounds__(256) scatter_kernel(Args a)
 {
-    const int64_t hits = a.ctrl[kHits];
-    if (hits > a.capacity || a.ctrl[kStageOverflow] != 0) return;
+    const int64_t cut = a.ctrl[kCutTile];
     const int64_t nblk = min(a.ctrl[kBlockCounter], a.stage_blocks);
     const int64_t nslots = nblk * kStageBlock;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nslots;
@@ -1509,20 +1758,29 @@ __global__ void __launch_bounds__(256) scatter_kernel(Args a)
         if ((int)(q - b * kStageBlock) >= a.stage_fill[b]) continue;
         const StageEntry* e = a.stage + q;
         const uint4 meta = reinterpret_cast<const uint4*>(e)[2];
-        const uint32_t tile = meta.x, tel = meta.y, rank = meta.z, shower = meta.w;
-        if (tel >= (uint32_t)a.n_tel || shower >= (uint32_t)a.n_showers || tile >= (uint64_t)a.max_tiles)
-            continue;
-        const int64_t pos = a.tel_offsets[(int64_t)shower * a.n_tel + tel] +
-                            a.counts[(int64_t)tile * a.n_tel + tel] + rank;
+        const int64_t tile = meta.x;
+        const int tel = (int)(meta.y & 0xFFFFu), sidx = (int)(meta.y >> 16);
+        if (tile >= cut || tel >= a.n_tel) continue;
+        const int s = find_shower(a.tiles_before, a.n_showers, tile);
+        // the tile's run of this telescope (runs ascend by telescope)
+        const int64_t off = a.tile_run_off[tile];
+        int lo = 0, hi = a.tile_run_n[tile];
+        if (hi <= 0) continue;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if ((int)(a.runs[off + mid] >> kRunTelShift) <= tel) lo = mid; else hi = mid;
+        }
+        const int64_t r = a.runs[off + lo];
+        if ((int)(r >> kRunTelShift) != tel) continue;
+        const int64_t pos = a.tel_offsets[(int64_t)s * a.n_tel + tel] + (r & kRunValueMask) + meta.z;
         if (pos < 0 || pos >= a.capacity) continue;
         const float4* src = reinterpret_cast<const float4*>(e);
         float4* dst = reinterpret_cast<float4*>(a.records + 8 * pos);
         dst[0] = src[0];
         dst[1] = src[1];
         if (a.ids) {
-            const int64_t* el = reinterpret_cast<const int64_t*>(e);
-            a.ids[2 * pos] = el[6];
-            a.ids[2 * pos + 1] = el[7];
+            a.ids[2 * pos] = a.shower_first[s] + (tile - a.tiles_before[s]) * (int64_t)a.tile_segs + sidx;
+            a.ids[2 * pos + 1] = meta.w;
         }
     }
 }
@@ -1582,7 +1840,8 @@ struct alignas(16) SoftStep {
     double b1x, b1y, b1z, b2x, b2y, b2z;
     double r2, g1, f_m, kl_nb;
     double g_cos, g_sin, g_phot;     // adjoint accumulators of the step
-    int32_t i_m, boff, sidx, pad;
+    int32_t i_m, boff, sidx;
+    uint32_t ctr1;                   // counter word 1 of the step's random numbers
 };
 static_assert(sizeof(SoftStep) % 16 == 0, "soft step entry alignment");
 
@@ -1975,7 +2234,7 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
         }
         const int s = lo;
         const int64_t sfirst = a.seg_offsets[s];
-        const int64_t g0 = sfirst + (t - a.tiles_before[s]) * (int64_t)kSoftTS;
+        const int64_t g0 = a.shower_first[s] + (t - a.tiles_before[s]) * (int64_t)kSoftTS;
         const int64_t gend = min(g0 + (int64_t)kSoftTS, a.seg_offsets[s + 1]);
         const int nseg = (int)(gend - g0);
         const uint32_t shower_id = a.shower_ids ? a.shower_ids[s] : (uint32_t)s;
@@ -2001,6 +2260,7 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
         if (emits) {
             st.boff = excl;
             st.sidx = lane;
+            st.ctr1 = a.step_id ? a.step_id[g0 + lane] : (uint32_t)(seg_id0 + lane);
             stash[__popcll(emit_mask & lt_mask)] = st;
         }
         wave_lds_sync();
@@ -2018,7 +2278,7 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
                 SoftStep& e = stash[si];
                 const int32_t k = j - e.boff;
                 double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
-                soft_bunch<MODE, MODE == 0>(a, sa, e, k, (uint32_t)(seg_id0 + e.sidx), shower_id,
+                soft_bunch<MODE, MODE == 0>(a, sa, e, k, e.ctr1, shower_id,
                                                    s, t_ref, tsh, acc, acc + a.n_tel, add_bin, inv_nobs,
                                                    half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin,
                                                    o_phot);
@@ -2104,7 +2364,8 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
         }
         SoftStep e;
         if (!soft_step_setup(a, i, nbf, e)) continue;
-        const int64_t seg_id = (a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]);
+        const int64_t seg_id = a.step_id ? (int64_t)a.step_id[i]
+                                         : (a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]);
         const uint32_t shower_id = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
         double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
         soft_bunch<1, true>(a, sa, e, k, (uint32_t)seg_id, shower_id, lo, a.t_ref[lo], tsh, nullptr,
@@ -2168,7 +2429,8 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_cand_kernel(Args a, Sof
         }
         SoftStep e;
         if (!soft_step_setup(a, i, nbf, e)) continue;
-        const int64_t seg_id = (a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]);
+        const int64_t seg_id = a.step_id ? (int64_t)a.step_id[i]
+                                         : (a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]);
         const uint32_t shower_id = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
         double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
         double* rowS = (sa.cand_lds_acc ? accS : sa.S) + (int64_t)lo * a.n_tel;
@@ -2217,6 +2479,7 @@ Args make_args(const RunPlan& p)
     const ckv_segments& s = p.segs;
     a.x0 = s.x0; a.y0 = s.y0; a.h0 = s.h0; a.u = s.u; a.v = s.v; a.w = s.w;
     a.len = s.length; a.t0 = s.t0; a.energy = s.energy; a.ptype = s.ptype; a.n = s.n;
+    a.step_id = s.step_id;
     a.seg_offsets = p.showers.seg_offsets;
     a.t_ref = p.showers.t_ref;
     a.shower_ids = p.showers.shower_ids;
@@ -2261,10 +2524,18 @@ Args make_args(const RunPlan& p)
     a.key0 = (uint32_t)p.params.seed;
     a.key1 = (uint32_t)(p.params.seed >> 32);
     a.tile_segs = p.tile_segs;
+    a.cur_step = p.cursor.step;
+    a.cur_shower = p.cursor.shower;
     a.ctrl = p.ctrl;
     a.tiles_before = p.tiles_before;
     a.blocks_before = p.blocks_before;
-    a.counts = p.counts;
+    a.shower_first = p.shower_first;
+    a.tile_run_off = p.tile_run_off;
+    a.tile_run_n = p.tile_run_n;
+    a.tile_hits = p.tile_hits;
+    a.runs = p.runs;
+    a.run_cap = p.run_cap;
+    a.block_hits = p.block_hits;
     a.block_sums = p.block_sums;
     a.shower_tel = p.shower_tel;
     a.stage_fill = p.stage_fill;
@@ -2293,15 +2564,18 @@ int check_launch(const char* what)
 }  // namespace
 
 int emit_config(int precision, int n_tel, int prof_bins, const ckv_atmo* atmo, int tile_segs,
-                int max_waves, int* waves, size_t* lds_bytes)
+                int max_waves, int* waves, size_t* lds_bytes, bool narrow_ok)
 {
-    const size_t tab = ((table_bytes(precision, (int)atmo->n_nodes, prof_bins > 0) + 15) & ~(size_t)15) +
-                       (atmo->h_nodes.empty() ? 0 : search_bytes((int)atmo->n_nodes));
+    const size_t srch = atmo->h_nodes.empty() ? 0 : search_bytes((int)atmo->n_nodes);
     const size_t cap = 160 * 1024;
     const size_t per = wave_bytes(precision, tile_segs, n_tel, prof_bins);
-    if (precision == 0) max_waves = std::min(max_waves, kMaxEmitWaves / 2);
+    // FP64: 16 waves only as the narrow build (partial table), else at most 8
+    if (precision == 0 && !narrow_ok) max_waves = std::min(max_waves, kMaxEmitWaves / 2);
     for (int wv = kMaxEmitWaves; wv >= 1; wv /= 2) {
         if (wv > max_waves) continue;
+        const bool partial = prof_bins > 0 || (precision == 0 && wv > kMaxEmitWaves / 2);
+        const size_t tab =
+            ((table_bytes(precision, (int)atmo->n_nodes, partial) + 15) & ~(size_t)15) + srch;
         const size_t tot = tab + tel_bytes(n_tel) + (size_t)wv * per;
         if (tot <= cap) {
             *waves = wv;
@@ -2339,6 +2613,13 @@ int launch_emit_feat(const Args& a, int grid, int waves, size_t lds, hipStream_t
         return CKV_ERR_ARG;
     }
     const int feat = (a.prof_bins > 0 ? kFeatProfile : 0) | (a.grazing_exact ? kFeatExact : 0);
+    if constexpr (PREC == 0) {
+        if (waves > emit_threads(0, 0) / kWave) {
+            if (feat == 0) return launch_emit<PREC, TS, kFeatNarrow>(a, grid, waves, lds, st);
+            set_error("the FP64 kernel runs 16 waves per workgroup only without other features");
+            return CKV_ERR_ARG;
+        }
+    }
     if constexpr (PREC == 1) {
         if (waves <= emit_threads(1, kFeatWide) / kWave) {
             if (feat == 0) return launch_emit<PREC, TS, kFeatWide>(a, grid, waves, lds, st);
@@ -2380,9 +2661,14 @@ int launch_run(RunPlan& p)
     int cap = p.emit_waves;
     if (p.params.precision == 1 && (p.params.grazing_exact || p.params.earth_radius_m > 0.0))
         cap = std::min(cap, emit_threads(1, kFeatExact) / kWave);
+    // the narrow FP64 build: plain runs (no profile, exact or curved path, node tables)
+    const bool narrow_ok = p.params.precision == 0 && p.prof_bins == 0 && !p.params.grazing_exact &&
+                           p.params.earth_radius_m <= 0.0 && p.atmo->h_nodes.empty();
     if (int rc = emit_config(p.params.precision, a.n_tel, p.prof_bins, p.atmo, p.tile_segs, cap, &waves,
-                             &lds))
+                             &lds, narrow_ok))
         return rc;
+    if (p.params.precision == 0 && waves > kMaxEmitWaves / 2)
+        a.lds_entries = lds_entries(0, a.n_nodes, true);
     if (p.prof_bins > 0) {
         // the profile accumulates by atomics: clear it (a kernel, so the run stays capturable)
         const int64_t m = (int64_t)a.n_showers * p.prof_bins;
@@ -2397,11 +2683,16 @@ int launch_run(RunPlan& p)
     if (rc) return rc;
     if (p.params.event_end) (void)hipEventRecord((hipEvent_t)p.params.event_end, st);
     const int fin_grid = 1024;
-    rowblock_sum_kernel<<<fin_grid, 256, 0, st>>>(a);
-    if (int rc2 = check_launch("rowblock_sum")) return rc2;
+    const size_t tel_lds = (size_t)a.n_tel * sizeof(int32_t);
+    block_sum_kernel<<<fin_grid, 256, tel_lds, st>>>(a);
+    if (int rc2 = check_launch("block_sum")) return rc2;
+    cutoff_kernel<<<1, 1024, tel_lds, st>>>(a);
+    if (int rc2 = check_launch("cutoff")) return rc2;
     rowblock_scan_kernel<<<fin_grid, 256, 0, st>>>(a);
     if (int rc2 = check_launch("rowblock_scan")) return rc2;
-    tile_prefix_kernel<<<fin_grid, 256, 0, st>>>(a);
+    const size_t prefix_lds = (size_t)((a.n_tel + 1) & ~1) * sizeof(int32_t) +
+                              (size_t)kPrefixLdsRuns * sizeof(int64_t);
+    tile_prefix_kernel<<<fin_grid, kWave, prefix_lds, st>>>(a);
     if (int rc2 = check_launch("tile_prefix")) return rc2;
     csr_kernel<<<1, 1024, 0, st>>>(a);
     if (int rc2 = check_launch("csr")) return rc2;

@@ -72,7 +72,8 @@ size_t ckv_noalloc_workspace_size(int64_t n_segments, int32_t n_showers, int32_t
 }
 
 int ckv_run_noalloc(const ckv_segments* segs, const ckv_showers* showers, const ckv_params* params,
-                    const ckv_atmo* atmo, const ckv_array* arr, ckv_output* out, void* stream)
+                    const ckv_atmo* atmo, const ckv_array* arr, ckv_output* out,
+                    const ckv_cursor* resume_from, void* stream)
 {
     if (!segs || !showers || !params || !arr || !out) {
         set_error("NULL argument");
@@ -96,7 +97,7 @@ int ckv_run_noalloc(const ckv_segments* segs, const ckv_showers* showers, const 
     }
     void* ws = nullptr;
     if (int rc = scratch_ptr(&ws)) return rc;
-    return run_checked(segs, showers, &p, atmo, arr, ws, kScratchBytes, out, stream);
+    return run_checked(segs, showers, &p, atmo, arr, ws, kScratchBytes, out, resume_from, stream);
 }
 
 }  // extern "C"

@@ -506,15 +506,16 @@ class DiffWorkload:
     seed: int = METHOD_SEED
 
 
-def diff_showers(n_showers: int = 64, n_seg: int = 500_000, seed: int = 4927) -> DiffWorkload:
-    """Gamma-like showers at 20 deg, Xmax 400, cores uniform within 300 m of the
-    array centre; theta0 = (knots 0, base scale heights), target theta* with
-    knots 0.05 sin(2 pi j/16 + 0.3) and scale heights x (1 + 0.02 (-1)^l)."""
+def diff_showers(n_showers: int = 64, n_seg: int = 500_000, seed: int = 4927,
+                 zenith_deg: float = 20.0) -> DiffWorkload:
+    """Gamma-like showers at 20 deg (or zenith_deg), Xmax 400, cores uniform within
+    300 m of the array centre; theta0 = (knots 0, base scale heights), target theta*
+    with knots 0.05 sin(2 pi j/16 + 0.3) and scale heights x (1 + 0.02 (-1)^l)."""
     place = layered_atmosphere()
     rng = np.random.default_rng(seed)
     rc = 300.0 * np.sqrt(rng.uniform(size=n_showers))
     ac = rng.uniform(0.0, 2 * math.pi, size=n_showers)
-    parts = _pmap(lambda s: shower_segments(s, n_seg, place, zenith_deg=20.0, azimuth_deg=0.0,
+    parts = _pmap(lambda s: shower_segments(s, n_seg, place, zenith_deg=zenith_deg, azimuth_deg=0.0,
                                             core=(rc[s] * math.cos(ac[s]), rc[s] * math.sin(ac[s])),
                                             xmax=400.0),
                   range(n_showers), None)
@@ -524,7 +525,8 @@ def diff_showers(n_showers: int = 64, n_seg: int = 500_000, seed: int = 4927) ->
     theta0 = np.concatenate([np.zeros(DIFF_N_KNOTS), base])
     target = np.concatenate([0.05 * np.sin(2 * math.pi * j / 16.0 + 0.3),
                              base * (1.0 + 0.02 * (-1.0) ** l)])
-    return DiffWorkload(f"diff_{n_showers}x{n_seg}", Segments.concat(parts, consume=True),
+    name = f"diff_{n_showers}x{n_seg}" + ("" if zenith_deg == 20.0 else f"_{int(zenith_deg)}deg")
+    return DiffWorkload(name, Segments.concat(parts, consume=True),
                         telescopes_disk(),
                         ETA_SEA, np.array(DIFF_LAYER_BOUNDS_M), DIFF_N_KNOTS, DIFF_KNOT_TOP_M,
                         2200.0, 50.0, 120_000.0, theta0, target)

@@ -36,13 +36,14 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_version(L):
-    assert L.ckv_version() == 113
+    assert L.ckv_version() == 114
 
 
 def test_struct_sizes_match_header_layout():
-    assert C.sizeof(ckv._Segments) == 11 * 8
+    assert C.sizeof(ckv._Segments) == 12 * 8
     assert C.sizeof(ckv._Params) == 4 * 8 + 8 + 4 * 4 + 2 * 8 + 8 + 2 * 4 + 8
-    assert C.sizeof(ckv._Result) == 5 * 8 + 8 * 8 + 2 * 4
+    assert C.sizeof(ckv._Result) == 5 * 8 + 8 * 8 + 8 + 4 * 4
+    assert C.sizeof(ckv._Cursor) == 16
     assert C.sizeof(ckv._Output) == 7 * 8
     assert C.sizeof(ckv._SoftList) == 3 * 8
 
@@ -105,11 +106,12 @@ def test_workspace_size_grows_with_inputs(L):
 
 
 def test_run_argument_validation(L):
-    segs = ckv._Segments(*([None] * 10), 5)       # n > 0 with NULL arrays
+    segs = ckv._Segments(*([None] * 10), 5, None)       # n > 0 with NULL arrays
     sh = ckv._Showers(None, None, None, None, 1)
     out = ckv._Output(None, None, 0, None, None)
     p = ckv.make_params()
-    rc = L.ckv_run(C.byref(segs), C.byref(sh), C.byref(p), None, None, None, 0, C.byref(out), None)
+    rc = L.ckv_run(C.byref(segs), C.byref(sh), C.byref(p), None, None, None, 0, C.byref(out), None,
+                   None)
     assert rc == -1
     bad_reserved = ckv.make_params()
     bad_reserved.reserved = 1
@@ -120,6 +122,6 @@ def test_run_argument_validation(L):
                 ckv.make_params(earth_radius=6.371e6, tile_segments=16),
                 ckv.make_params(earth_radius=6.371e6, depth_bin=10.0),
                 ckv.make_params(earth_radius=6.371e6, grazing_exact=True)):
-        empty = ckv._Segments(*([None] * 10), 0)
+        empty = ckv._Segments(*([None] * 10), 0, None)
         assert L.ckv_run(C.byref(empty), C.byref(sh), C.byref(bad), None, None, None, 0,
-                         C.byref(out), None) == -1
+                         C.byref(out), None, None) == -1

@@ -126,7 +126,7 @@ def test_streamed_chunks_equal_one_shot(batched, mode):
     else:
         st.to_host(take)
     torch.cuda.synchronize()
-    say(f"[gpu] streamed ({mode}): {n_chunks[0]} chunks, {st.n_reruns} reruns")
+    say(f"[gpu] streamed ({mode}): {n_chunks[0]} chunks, {st.n_resumed} resumed, {st.n_reruns} rerun")
     assert n_chunks[0] >= 8
     o = one["offsets"]
     for gi in range(n_sh * n_tel):

@@ -96,7 +96,7 @@ def test_curved_graph_replay_and_launch_shapes():
 
 def test_curved_streamed_chunks_equal_one_shot():
     """The streamer plans ranges from ckv_count (curved midpoint altitudes) and
-    reruns a range that overflows; per telescope the chunks concatenate to the
+    resumes a range that overflows; per telescope the chunks concatenate to the
     one-shot curved output, bit for bit."""
     import torch
     wl = synth.inclined(70.0, 20000)
@@ -117,7 +117,7 @@ def test_curved_streamed_chunks_equal_one_shot():
         for t in range(n_tel):
             got[t].append((rec[off[t]:off[t + 1]], ids[off[t]:off[t + 1]]))
     torch.cuda.synchronize()
-    say(f"[gpu] curved streamed: {n_chunks} chunks, {st.n_reruns} reruns")
+    say(f"[gpu] curved streamed: {n_chunks} chunks, {st.n_resumed} resumed, {st.n_reruns} rerun")
     assert n_chunks >= 5
     o = one["offsets"]
     for t in range(n_tel):

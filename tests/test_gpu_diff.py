@@ -180,12 +180,21 @@ def gpu_model_nolist(dw, **kw):
                          **kw)
 
 
-def test_list_holds_every_weighted_bunch(small):
+@pytest.fixture(scope="module")
+def inclined():
+    dw = synth.diff_showers(2, 5000, zenith_deg=72.0)
+    return dw, Oracle(dw), gpu_model(dw)
+
+
+@pytest.mark.parametrize("which", ["small", "inclined"])
+def test_list_holds_every_weighted_bunch(which, request):
     """The forward's list (the mixed screening pass against spheres of the cut
-    radius plus 1 cm) names every bunch of the oracle with z >= -40 at some sphere,
-    each once; the others it names lie just outside the cut."""
+    radius plus 1 cm, plus every bunch whose ground-error bound passes half that
+    margin) names every bunch of the oracle with z >= -40 at some sphere, each
+    once; the others it names lie just outside the cut or carry a large bound.
+    Also at 72 deg zenith, where w ~ 0.3 magnifies the mixed path's errors."""
     import torch
-    dw, orc, model = small
+    dw, orc, model = request.getfixturevalue(which)
     model.forward(dw.theta0)
     n, cap = model.list_state()
     assert n <= cap
@@ -214,10 +223,16 @@ def test_list_holds_every_weighted_bunch(small):
     listed = np.isin(okey, key)
     assert not np.isin(key, okey, invert=True).any()
     assert np.all(listed[want]), (~listed[want]).sum()
+    assert want.sum() > 100
     extra = listed & ~want
-    assert np.all(zmax[extra] > -40.5), np.sort(zmax[extra])[:5]
-    say(f"[gpu] soft list: {n} ids, {want.sum()} weighted bunches of the oracle, {extra.sum()} "
-        f"candidates just outside the cut")
+    # the rest lie just outside the cut, or were listed for their error bound
+    bd = oracle.bunch_details(cfg, dw.segs, all_seg[extra], all_k[extra])
+    winv = 1.0 / bd["w"]
+    bound = (bd["h_e"] - dw.obs_level) * winv * (1e-8 * (1.0 + winv) + 5e-10 * winv * winv)
+    near = zmax[extra] > -40.5
+    assert np.all(near | (bound > 0.004)), np.sort(zmax[extra][~near])[:5]
+    say(f"[gpu] soft list ({dw.name}): {n} ids, {want.sum()} weighted bunches of the oracle, "
+        f"{near.sum()} candidates just outside the cut, {(~near).sum()} listed for their bound")
 
 
 def test_list_overflow_recomputes_everything_then_grows(small):

@@ -55,21 +55,23 @@ def test_hadron_like_full_size_streamed(zenith):
     idx = np.arange(0, wl.segs.n, 997)
     idx_t = torch.as_tensor(idx, device="cuda")
     n_tel = tels.n
-    parts, n_chunks, agg = [], 0, dict(n_bunches=0, n_hits=0)
+    parts, n_chunks, agg, end = [], 0, dict(n_bunches=0, n_hits=0), 0
     for ch in st.chunks():
         res = ch.result
-        assert res["overflow"] == 0 and res["error"] == 0
+        assert res["error"] == 0 and ch.begin == end     # chunks tile the steps
+        end = ch.end
         assert 0 < res["n_records"] <= st.capacity
-        agg["n_bunches"] += res["n_bunches"]
-        agg["n_hits"] += res["n_hits"]
+        agg["n_bunches"] += st.bunches(ch.begin, ch.end)
+        agg["n_hits"] += res["n_records"]
         n_chunks += 1
         off = ch.tel_offsets.cpu().numpy()
         ids = ch.ids.clone()
         ids[:, 0] += ch.begin            # ids count steps from the start of the chunk's range
         keep = torch.isin(ids[:, 0], idx_t).cpu().numpy()
         parts.append(_sampled_view(off, ch.records.cpu().numpy(), ids.cpu().numpy(), keep, n_tel))
-    say(f"[gpu] streamed {n_chunks} chunks ({st.n_reruns} reruns), {agg['n_hits']} records")
-    assert agg["n_bunches"] == st.total_bunches and n_chunks >= 2
+    say(f"[gpu] streamed {n_chunks} chunks ({st.n_resumed} resumed, {st.n_reruns} rerun), "
+        f"{agg['n_hits']} records")
+    assert end == wl.segs.n and agg["n_bunches"] == st.total_bunches and n_chunks >= 2
     # per telescope, consecutive chunks concatenate in (step, bunch) order
     off = np.zeros(n_tel + 1, dtype=np.int64)
     off[1:] = np.cumsum(sum(np.diff(p["offsets"]) for p in parts))

@@ -164,16 +164,100 @@ def test_chunked_run_equals_one_shot(vg):
         np.testing.assert_array_equal(rec, whole["rec"][whole["offsets"][t]:whole["offsets"][t + 1]])
 
 
-def test_overflow_reports_required_capacity(vg):
+def test_overflow_writes_a_prefix_and_reports_the_required_capacity(vg):
+    """A capacity below the crossings: the records of the steps before the resume
+    cursor are written complete (per telescope, the oracle's records of those
+    steps), n_hits tells the capacity that holds everything."""
     wl, cfg, r = vg
     g = gpu_run(wl, ckv.CKV_FP64, capacity=1000)
     res = g["result"]
-    assert res["overflow"] == 1 and res["n_records"] == 0
-    assert res["n_hits"] == len(r.seg)
-    np.testing.assert_array_equal(g["offsets"], r.offsets)     # offsets stay valid
+    assert res["overflow"] == 1 and res["n_hits"] == len(r.seg)
+    stop = res["resume_step"]
+    assert 0 < stop < wl.segs.n and res["resume_shower"] == 0
+    assert 0 < res["n_records"] <= 1000 and stop % 32 == 0        # a tile boundary
+    keep = r.seg < stop
+    n_tel = wl.tels.n
+    want = np.bincount(r.tel[keep], minlength=n_tel)
+    np.testing.assert_array_equal(np.diff(g["offsets"]), want)
+    assert res["n_records"] == keep.sum()
+    # the next tile would not have fit
+    assert keep.sum() + np.sum((r.seg >= stop) & (r.seg < stop + 32)) > 1000
     g2 = gpu_run(wl, ckv.CKV_FP64, capacity=int(res["n_hits"]))
     assert g2["result"]["overflow"] == 0
     np.testing.assert_array_equal(g2["offsets"], r.offsets)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_resumed_runs_equal_one_shot(precision):
+    """Runs cut short by a small capacity and resumed at the reported cursor, over
+    several showers (cursors inside showers and at their ends): per (shower,
+    telescope) the concatenated records and ids are the one-shot output, bit for
+    bit, and every run but the last writes as much as fits."""
+    import ctypes as C
+    import torch
+    wl = synth.batched_showers(5, seg_scale=0.01)
+    atmo, tels = handles(wl)
+    one = gpu_run(wl, precision, handles_=(atmo, tels))
+    total = int(one["result"]["n_hits"])
+    cap = max(64, total // 7)
+    d = ckv.DeviceSegments(wl.segs)
+    r = ckv.Runner(d, atmo, tels, params(wl, precision), cap, want_ids=True)
+    n_groups = wl.segs.n_showers * tels.n
+    got = [[] for _ in range(n_groups)]
+    cur, runs = None, 0
+    while True:
+        say(f"[gpu] resumed run {runs} from {cur} capacity {cap}")
+        out = r.run(resume_from=cur)
+        torch.cuda.synchronize()
+        res = out.result()
+        assert res["error"] == 0
+        n = int(res["n_records"])
+        off = out.tel_offsets.cpu().numpy()
+        rec = out.records[:n].cpu().numpy()
+        ids = out.ids[:n].cpu().numpy()
+        assert off[-1] == n
+        for gi in range(n_groups):
+            got[gi].append((rec[off[gi]:off[gi + 1]], ids[off[gi]:off[gi + 1]]))
+        runs += 1
+        if not res["overflow"]:
+            break
+        assert n > 0 and n <= cap
+        cur = (res["resume_step"], res["resume_shower"])
+        assert runs < 100
+    assert runs >= 5
+    o = one["offsets"]
+    for gi in range(n_groups):
+        rec = np.concatenate([x[0] for x in got[gi]])
+        ids = np.concatenate([x[1] for x in got[gi]])
+        np.testing.assert_array_equal(rec.view(np.uint32), one["rec"][o[gi]:o[gi + 1]].view(np.uint32))
+        np.testing.assert_array_equal(ids, one["ids"][o[gi]:o[gi + 1]])
+
+
+def test_resume_cursor_is_checked():
+    """A cursor outside the steps or showers is refused on the host; one whose
+    step lies outside its shower is reported by the device (error bit 0)."""
+    import ctypes as C
+    import torch
+    wl = synth.batched_showers(3, seg_scale=0.002)
+    atmo, tels = handles(wl)
+    d = ckv.DeviceSegments(wl.segs)
+    r = ckv.Runner(d, atmo, tels, params(wl, ckv.CKV_MIXED), 1 << 16, want_ids=True)
+    for bad in ((-1, 0), (wl.segs.n + 1, 0), (0, 3), (0, -1)):
+        with pytest.raises(ckv.CkvError, match="resume cursor"):
+            r.run(resume_from=bad)
+    off = wl.segs.seg_offsets
+    out = r.run(resume_from=(int(off[2]) + 1, 1))       # step of shower 2, cursor says 1
+    torch.cuda.synchronize()
+    res = out.result()
+    assert res["error"] & 1 and res["n_bunches"] == 0 and res["n_records"] == 0
+    out = r.run(resume_from=(int(off[1]), 1))           # shower 1 from its first step
+    torch.cuda.synchronize()
+    res = out.result()
+    assert res["error"] == 0 and res["overflow"] == 0
+    ids = out.ids[:res["n_records"]].cpu().numpy()
+    assert ids[:, 0].min() >= off[1]
+    o = out.tel_offsets.cpu().numpy()
+    assert o[tels.n] == 0                                # shower 0 left out
 
 
 # ---------------------------------------------------------------------------
@@ -264,3 +348,36 @@ def test_maximum_telescope_count(precision):
     rep = compare_records(wl, cfg, ores, g, precision)
     assert rep["matched"] > 10_000
     say(f"[gpu] 1024 telescopes prec={precision}: {rep}")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_step_ids_keep_bunches_when_steps_are_reordered(precision):
+    """Steps sorted by start altitude, with their generator-order indices as step
+    ids: the run computes the same bunches -- per telescope, with each record's
+    step mapped back, exactly the generator-order records, bit for bit."""
+    import torch
+    wl = synth.single_tev(20000)
+    atmo, tels = handles(wl)
+    one = gpu_run(wl, precision, handles_=(atmo, tels))
+    perm = np.argsort(-wl.segs.h0, kind="stable")
+    d = ckv.DeviceSegments(wl.segs.take(perm), step_id=perm.astype(np.uint32))
+    say(f"[gpu] step ids, sorted by altitude, prec={precision}")
+    r = ckv.Runner(d, atmo, tels, params(wl, precision), int(one["result"]["n_hits"]) + 64)
+    out = r.run()
+    torch.cuda.synchronize()
+    res = out.result()
+    assert res["error"] == 0 and res["overflow"] == 0
+    for key in ("n_bunches", "n_hits", "drops"):
+        assert res[key] == one["result"][key]
+    n = int(res["n_records"])
+    off = out.tel_offsets.cpu().numpy()
+    rec = out.records[:n].cpu().numpy()
+    ids = out.ids[:n].cpu().numpy()
+    ids[:, 0] = perm[ids[:, 0]]
+    o = one["offsets"]
+    for t in range(tels.n):
+        sl = slice(off[t], off[t + 1])
+        order = np.lexsort((ids[sl, 1], ids[sl, 0]))
+        np.testing.assert_array_equal(ids[sl][order], one["ids"][o[t]:o[t + 1]])
+        np.testing.assert_array_equal(rec[sl][order].view(np.uint32),
+                                      one["rec"][o[t]:o[t + 1]].view(np.uint32))

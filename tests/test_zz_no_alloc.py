@@ -46,7 +46,7 @@ def _both(wl, segs, precision, capacity):
     stream = torch.cuda.current_stream()
     say(f"[gpu] ckv_run_noalloc {wl.name} n={d.n} prec={precision} cap={capacity} ws={need}")
     rc = L.ckv_run_noalloc(C.byref(segs_c), C.byref(show_c), C.byref(p), atmo.handle, tels.handle,
-                           C.byref(o), C.c_void_p(stream.cuda_stream))
+                           C.byref(o), None, C.c_void_p(stream.cuda_stream))
     assert rc == 0, L.ckv_last_error()
     b = _host(out, ng)
     return a, b
@@ -86,5 +86,5 @@ def test_noalloc_refuses_a_run_larger_than_its_array():
     out = ckv._Output(None, None, cap, None, None)
     segs_c, show_c = d.c_segments(), d.c_showers()
     rc = L.ckv_run_noalloc(C.byref(segs_c), C.byref(show_c), C.byref(p), atmo.handle, tels.handle,
-                           C.byref(out), None)
+                           C.byref(out), None, None)
     assert rc == -3 and b"static scratch" in L.ckv_last_error()
