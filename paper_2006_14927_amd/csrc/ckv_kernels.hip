@@ -705,6 +705,114 @@ constexpr int emit_threads(int prec, int feat)
            : (prec == 0 || (feat & (kFeatExact | kFeatCurved | kFeatWide)) != 0) ? 512 : 1024;
 }
 
+// Step setups of a tile, one per lane (emitting steps compacted into the stash),
+// the bunch-count scan and the step-level counters; returns the tile's bunch
+// count and this lane's step state.  Not inlined: the step arrays' pointers and
+// the setup's registers then take no room in the bunch loop.  Called by the
+// whole wave.
+struct TileSetup {
+    int64_t total;
+    int excl;
+    bool emits;
+};
+
+template <int PREC, int TS, int FEAT>
+__device__ __forceinline__ TileSetup tile_setup(const Args& a, int64_t g0, int nseg, int64_t seg_id0,
+                                                int lane, uint64_t lt_mask, StepEntry<PREC>* stash,
+                                                uint32_t* sctr, int64_t* wcnt, int64_t* lst)
+{
+    constexpr bool SCREEN = (FEAT & kFeatScreen) != 0;
+    using T = typename std::conditional<PREC == 0, double, float>::type;
+    using Entry = StepEntry<PREC>;
+    int64_t nb = 0;
+    int status = -2;   // -2: no step in this lane
+    Setup st;
+    if (lane < nseg) {
+        step_setup(a, g0 + lane, st);
+        status = st.status;
+        if (st.status < 0) nb = st.nb;
+        if (SCREEN && st.status < 0) {
+            // the soft response's sub-steps: the frozen count, light or not at
+            // the current atmosphere decided above
+            const int64_t f = a.nb_frozen[g0 + lane];
+            if (f > 0) {
+                nb = f;
+                st.ds = a.len[g0 + lane] / (double)f;
+            } else {
+                nb = 0;
+                status = -4;
+            }
+        }
+    }
+    int64_t incl = wave_incl_scan(nb);
+    int64_t total = scalar64(__shfl(incl, kWave - 1));
+    if (total >= ((int64_t)1 << 30)) {
+        // bunch offsets inside a tile are 32-bit: refuse such a tile
+        if (lane == 0 && a.result) atomicOr(&a.result->error, 2);
+        total = 0;
+        incl = 0;
+        nb = 0;
+        status = status == -1 ? -3 : status;
+    }
+    const bool emits = status == -1;
+    const uint64_t emit_mask = __ballot(emits);
+    if (SCREEN && lane == 0) {
+        lst[0] = g0;
+        lst[4] = __popcll(emit_mask);
+    }
+    const int excl = (int)(incl - nb);      // first bunch of this lane's step
+    if (emits) {
+        Entry& e = stash[__popcll(emit_mask & lt_mask)];
+        const int64_t g = g0 + lane;
+        const uint32_t ctr1 = a.step_id ? a.step_id[g] : (uint32_t)(seg_id0 + lane);
+        if constexpr (PREC == 1) e.ctr1 = ctr1;
+        else sctr[lane] = ctr1;
+        e.x0 = a.x0[g];
+        e.y0 = a.y0[g];
+        e.h0 = a.h0[g];
+        e.t0 = a.t0[g];
+        e.u = a.u[g];
+        e.v = a.v[g];
+        e.w = a.w[g];
+        e.cos_t = st.cos_t;
+        e.ds = st.ds;
+        e.inv_bc = st.inv_bc;
+        e.sb1x = (T)(st.sin_t * st.b1x);
+        e.sb1y = (T)(st.sin_t * st.b1y);
+        e.sb1z = (T)(st.sin_t * st.b1z);
+        e.sb2x = (T)(st.sin_t * st.b2x);
+        e.sb2y = (T)(st.sin_t * st.b2y);
+        e.sb2z = (T)(st.sin_t * st.b2z);
+        e.photons = st.photons;
+        e.boff = excl;
+        e.sidx = lane;
+    }
+    {
+        const int d_mass = __popcll(__ballot(status == CKV_DROP_MASS));
+        const int d_thr = __popcll(__ballot(status == CKV_DROP_THRESHOLD));
+        const int d_nf = __popcll(__ballot(status == CKV_DROP_NONFINITE));
+        if (lane == 0) {
+            wcnt[kWcBunches] += total;
+            wcnt[kWcEmitting] += __popcll(emit_mask);
+            wcnt[kWcDrop0 + CKV_DROP_MASS] += d_mass;
+            wcnt[kWcDrop0 + CKV_DROP_THRESHOLD] += d_thr;
+            wcnt[kWcDrop0 + CKV_DROP_NONFINITE] += d_nf;
+        }
+    }
+    return TileSetup{total, (int)(incl - nb), status == -1};
+}
+
+// The same as a called function (the mixed kernel's choice: its step setup's
+// registers and the step arrays' pointers then take no room in the bunch loop,
+// 100 -> 8 scalar spills; the FP64 kernel, with 256 registers, runs faster inline).
+template <int PREC, int TS, int FEAT>
+__device__ __noinline__ TileSetup tile_setup_call(const Args& a, int64_t g0, int nseg, int64_t seg_id0,
+                                                  int lane, uint64_t lt_mask, StepEntry<PREC>* stash,
+                                                  uint32_t* sctr, int64_t* wcnt, int64_t* lst)
+{
+    return tile_setup<PREC, TS, FEAT>(a, g0, nseg, seg_id0, lane, lt_mask, stash, sctr, wcnt, lst);
+}
+
 template <int PREC, int TS, int FEAT>
 __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
 {
@@ -813,82 +921,21 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
         const double t_ref = a.t_ref[s];
         int32_t thits = 0;         // crossings of this tile (wave-uniform)
 
-        // ---- step setups, one per lane; emitting steps are compacted
-        int64_t nb = 0;
-        int status = -2;   // -2: no step in this lane
-        Setup st;
-        if (lane < nseg) {
-            step_setup(a, g0 + lane, st);
-            status = st.status;
-            if (st.status < 0) nb = st.nb;
-            if (SCREEN && st.status < 0) {
-                // the soft response's sub-steps: the frozen count, light or not at
-                // the current atmosphere decided above
-                const int64_t f = a.nb_frozen[g0 + lane];
-                if (f > 0) {
-                    nb = f;
-                    st.ds = a.len[g0 + lane] / (double)f;
-                } else {
-                    nb = 0;
-                    status = -4;
-                }
-            }
+        // ---- step setups, one per lane; emitting steps are compacted.  The mixed
+        // kernel calls it out of line, handing the callee the arguments where the
+        // launch put them (the kernel argument segment) rather than a private copy.
+        TileSetup ts_;
+        if constexpr (PREC == 1) {
+            const Args& ka = *(const Args*)__builtin_amdgcn_kernarg_segment_ptr();
+            ts_ = tile_setup_call<PREC, TS, FEAT>(ka, g0, nseg, seg_id0, lane, lt_mask, stash, sctr, wcnt,
+                                                  lst);
+        } else {
+            ts_ = tile_setup<PREC, TS, FEAT>(a, g0, nseg, seg_id0, lane, lt_mask, stash, sctr, wcnt, lst);
         }
-        int64_t incl = wave_incl_scan(nb);
-        int64_t total = scalar64(__shfl(incl, kWave - 1));
-        if (total >= ((int64_t)1 << 30)) {
-            // bunch offsets inside a tile are 32-bit: refuse such a tile
-            if (lane == 0 && a.result) atomicOr(&a.result->error, 2);
-            total = 0;
-            incl = 0;
-            nb = 0;
-            status = status == -1 ? -3 : status;
-        }
-        const bool emits = status == -1;
+        const int64_t total = ts_.total;
+        const bool emits = ts_.emits;
+        const int excl = ts_.excl;
         const uint64_t emit_mask = __ballot(emits);
-        if (SCREEN && lane == 0) {
-            lst[0] = g0;
-            lst[4] = __popcll(emit_mask);
-        }
-        const int excl = (int)(incl - nb);      // first bunch of this lane's step
-        if (emits) {
-            Entry& e = stash[__popcll(emit_mask & lt_mask)];
-            const int64_t g = g0 + lane;
-            const uint32_t ctr1 = a.step_id ? a.step_id[g] : (uint32_t)(seg_id0 + lane);
-            if constexpr (PREC == 1) e.ctr1 = ctr1;
-            else sctr[lane] = ctr1;
-            e.x0 = a.x0[g];
-            e.y0 = a.y0[g];
-            e.h0 = a.h0[g];
-            e.t0 = a.t0[g];
-            e.u = a.u[g];
-            e.v = a.v[g];
-            e.w = a.w[g];
-            e.cos_t = st.cos_t;
-            e.ds = st.ds;
-            e.inv_bc = st.inv_bc;
-            e.sb1x = (T)(st.sin_t * st.b1x);
-            e.sb1y = (T)(st.sin_t * st.b1y);
-            e.sb1z = (T)(st.sin_t * st.b1z);
-            e.sb2x = (T)(st.sin_t * st.b2x);
-            e.sb2y = (T)(st.sin_t * st.b2y);
-            e.sb2z = (T)(st.sin_t * st.b2z);
-            e.photons = st.photons;
-            e.boff = excl;
-            e.sidx = lane;
-        }
-        {
-            const int d_mass = __popcll(__ballot(status == CKV_DROP_MASS));
-            const int d_thr = __popcll(__ballot(status == CKV_DROP_THRESHOLD));
-            const int d_nf = __popcll(__ballot(status == CKV_DROP_NONFINITE));
-            if (lane == 0) {
-                wcnt[kWcBunches] += total;
-                wcnt[kWcEmitting] += __popcll(emit_mask);
-                wcnt[kWcDrop0 + CKV_DROP_MASS] += d_mass;
-                wcnt[kWcDrop0 + CKV_DROP_THRESHOLD] += d_thr;
-                wcnt[kWcDrop0 + CKV_DROP_NONFINITE] += d_nf;
-            }
-        }
         wave_lds_sync();
 
         // ---- bunches of the tile, one per lane
