@@ -2365,6 +2365,57 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
 
 constexpr int kSoftListThreads = 512;
 
+// Listed bunches of a wave (ids q0 + lane, consecutive): the step setup and the
+// shower lookup are done once per run of lanes that name the same step (the
+// screening pass lists a step's bunches together) and passed to the run's other
+// lanes by lane shuffles.  REV: also the step-level values of the reverse sweep.
+// True for lanes whose id names a bunch of the inputs on a step that gives light.
+// Called by the whole wave.
+template <bool REV>
+__device__ __forceinline__ bool listed_setup(const Args& a, const SoftArgs& sa, int64_t q, bool have,
+                                             int lane, SoftStep& e, int& shower, uint32_t& ctr1,
+                                             int32_t& k)
+{
+    const uint64_t id = have ? sa.ids[q] : ~0ull;
+    const int64_t i = have ? (int64_t)(id >> kSoftIdBits) : -1;
+    k = (int32_t)(id & ((1u << kSoftIdBits) - 1));
+    const bool named = have && i < a.n;
+    const int64_t nbf = named ? sa.nb_frozen[i] : 0;
+    const int64_t i_prev = __shfl_up(i, 1);
+    const bool head = named && (lane == 0 || i_prev != i);
+    int lit = 0, lo = 0;
+    uint32_t c1 = 0;
+    if (head) {
+        int hi = a.n_showers;                   // the shower holding step i
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.seg_offsets[mid] <= i) lo = mid; else hi = mid;
+        }
+        lit = soft_step_setup(a, i, nbf, e) ? 1 : 0;
+        c1 = a.step_id ? a.step_id[i]
+                       : (uint32_t)((a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]));
+    }
+    // the run's head: the nearest head lane at or below this one
+    const uint64_t heads = __ballot(head);
+    const uint64_t le = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
+    const uint64_t mine = heads & le;
+    const int src = mine ? 63 - __builtin_clzll(mine) : lane;
+    lit = __shfl(lit, src);
+    shower = __shfl(lo, src);
+    ctr1 = __shfl(c1, src);
+    e.x0 = __shfl(e.x0, src); e.y0 = __shfl(e.y0, src); e.h0 = __shfl(e.h0, src);
+    e.t0 = __shfl(e.t0, src); e.u = __shfl(e.u, src); e.v = __shfl(e.v, src); e.w = __shfl(e.w, src);
+    e.cos_t = __shfl(e.cos_t, src); e.sin_t = __shfl(e.sin_t, src);
+    e.photons = __shfl(e.photons, src); e.ds = __shfl(e.ds, src); e.inv_bc = __shfl(e.inv_bc, src);
+    e.b1x = __shfl(e.b1x, src); e.b1y = __shfl(e.b1y, src); e.b1z = __shfl(e.b1z, src);
+    e.b2x = __shfl(e.b2x, src); e.b2y = __shfl(e.b2y, src); e.b2z = __shfl(e.b2z, src);
+    if (REV) {
+        e.r2 = __shfl(e.r2, src); e.g1 = __shfl(e.g1, src); e.f_m = __shfl(e.f_m, src);
+        e.kl_nb = __shfl(e.kl_nb, src); e.i_m = __shfl(e.i_m, src);
+    }
+    return named && lit && k < nbf;
+}
+
 // Adjoint over the forward's list: one listed bunch per thread, its step set up
 // again (bunch count frozen), the bunch recomputed from its random numbers and
 // reversed into the table bins, the step-level part applied per bunch.  Runs only
@@ -2396,26 +2447,18 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
     const double inv_nobs = 1.0 / a.n_obs;
     const double half_inv_nobs3 = 0.5 * inv_nobs * inv_nobs * inv_nobs;
     double g_psi0 = 0.0;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_ids;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t id = sa.ids[q];
-        const int64_t i = (int64_t)(id >> kSoftIdBits);
-        const int32_t k = (int32_t)(id & ((1u << kSoftIdBits) - 1));
-        if (i >= a.n) continue;
-        const int64_t nbf = sa.nb_frozen[i];
-        if (k >= nbf) continue;
-        int lo = 0, hi = a.n_showers;          // the shower holding step i
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (a.seg_offsets[mid] <= i) lo = mid; else hi = mid;
-        }
+    const int lane = lane_id();
+    for (int64_t q0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); q0 < n_ids;
+         q0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = q0 + lane;
         SoftStep e;
-        if (!soft_step_setup(a, i, nbf, e)) continue;
-        const int64_t seg_id = a.step_id ? (int64_t)a.step_id[i]
-                                         : (a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]);
+        int lo;
+        uint32_t seg_id;
+        int32_t k;
+        if (!listed_setup<true>(a, sa, q, q < n_ids, lane, e, lo, seg_id, k)) continue;
         const uint32_t shower_id = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
         double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
-        soft_bunch<1, true>(a, sa, e, k, (uint32_t)seg_id, shower_id, lo, a.t_ref[lo], tsh, nullptr,
+        soft_bunch<1, true>(a, sa, e, k, seg_id, shower_id, lo, a.t_ref[lo], tsh, nullptr,
                             nullptr, add_bin, inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin, o_phot);
         if (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)
             soft_step_reverse(e, o_cos, o_sin, o_phot, add_bin);
@@ -2461,28 +2504,20 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_cand_kernel(Args a, Sof
     const double inv_nobs = 1.0 / a.n_obs;
     const double half_inv_nobs3 = 0.5 * inv_nobs * inv_nobs * inv_nobs;
     double g_psi0 = 0.0;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n_ids;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t id = sa.ids[q];
-        const int64_t i = (int64_t)(id >> kSoftIdBits);
-        const int32_t k = (int32_t)(id & ((1u << kSoftIdBits) - 1));
-        if (i >= a.n) continue;
-        const int64_t nbf = sa.nb_frozen[i];
-        if (k >= nbf) continue;
-        int lo = 0, hi = a.n_showers;          // the shower holding step i
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (a.seg_offsets[mid] <= i) lo = mid; else hi = mid;
-        }
+    const int lane = lane_id();
+    for (int64_t q0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); q0 < n_ids;
+         q0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = q0 + lane;
         SoftStep e;
-        if (!soft_step_setup(a, i, nbf, e)) continue;
-        const int64_t seg_id = a.step_id ? (int64_t)a.step_id[i]
-                                         : (a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]);
+        int lo;
+        uint32_t seg_id;
+        int32_t k;
+        if (!listed_setup<false>(a, sa, q, q < n_ids, lane, e, lo, seg_id, k)) continue;
         const uint32_t shower_id = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
         double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
         double* rowS = (sa.cand_lds_acc ? accS : sa.S) + (int64_t)lo * a.n_tel;
         double* rowA = (sa.cand_lds_acc ? accA : sa.A) + (int64_t)lo * a.n_tel;
-        soft_bunch<0, true>(a, sa, e, k, (uint32_t)seg_id, shower_id, lo, a.t_ref[lo], tsh, rowS,
+        soft_bunch<0, true>(a, sa, e, k, seg_id, shower_id, lo, a.t_ref[lo], tsh, rowS,
                             rowA, no_bins, inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin,
                             o_phot);
     }
