@@ -900,6 +900,118 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
     int rfill = 0;
     const int64_t n_tiles = a.ctrl[kNumTiles];
 
+    // Atmosphere at an emission point in cell ci at fraction f (node tables: dcell_
+    // above the cell's lower node h_i): psi_e and D_k = int_{h_obs}^{h_e} (psi -
+    // psi_e)^k dh, k = 1..5.  Below h_i the node moments are shifted to psi_e,
+    // sum_j C(k,j) (-psi_e)^(k-j) P_j(h_i) with P_0(h_i) = h_i - h_obs (Pascal-triangle
+    // shift); inside the cell psi is linear from psi_i to psi_e, so the rest is
+    // dz (psi_i - psi_e)^k / (k+1).  The bunch loop takes D_1..D_4 for the advance;
+    // the arrival time, needed only for a crossing's record, takes D_5 as well.
+    struct CellMoments { T psi_e, D1, D2, D3, D4, D5; };
+    auto cell_moments = [&](int ci, T f, double dcell_) {
+        T psi_i, dpsi, P0, P1, P2, P3, P4, P5;
+        // LDS read always (index clamped into the staged part); the rare
+        // lookups above it are replaced by a read from HBM
+        if (PREC == 0) {
+            double n0[6], n1;
+            {
+                const int cl = PARTIAL ? min(ci, a.lds_entries - 2) : ci;
+                const double* nd = tab64 + (size_t)kNode64 * cl;
+                for (int q = 0; q < 6; ++q) n0[q] = nd[q];
+                n1 = nd[kNode64];
+            }
+            if (PARTIAL && ci + 1 >= a.lds_entries) {
+                // a distinct load kind keeps the compiler from fusing the two
+                // reads into one generic (flat) load of a selected address
+                const double* nd = a.node64 + (size_t)kNode64 * ci;
+                for (int q = 0; q < 6; ++q) n0[q] = __builtin_nontemporal_load(nd + q);
+                n1 = __builtin_nontemporal_load(nd + kNode64);
+            }
+            psi_i = n0[0];
+            dpsi = n1 - n0[0];
+            P0 = SEARCH ? hn_lds[ci] - a.h_obs : (double)ci * a.step;
+            P1 = n0[1]; P2 = n0[2]; P3 = n0[3]; P4 = n0[4]; P5 = n0[5];
+        } else {
+            float4 c_a, c_b;
+            {
+                const int cl = PARTIAL ? min(ci, a.lds_entries - 1) : ci;
+                const float4* cc = reinterpret_cast<const float4*>(tab32 + (size_t)kCell32 * cl);
+                c_a = cc[0];
+                c_b = cc[1];
+            }
+            if (PARTIAL && ci >= a.lds_entries) {
+                // a distinct load kind keeps the compiler from fusing the two
+                // reads into one generic (flat) load of a selected address
+                const float* cg = a.cell32 + (size_t)kCell32 * ci;
+                c_a = make_float4(__builtin_nontemporal_load(cg), __builtin_nontemporal_load(cg + 1),
+                                  __builtin_nontemporal_load(cg + 2), __builtin_nontemporal_load(cg + 3));
+                c_b = make_float4(__builtin_nontemporal_load(cg + 4), __builtin_nontemporal_load(cg + 5),
+                                  __builtin_nontemporal_load(cg + 6), __builtin_nontemporal_load(cg + 7));
+            }
+            psi_i = c_a.x; dpsi = c_a.y; P1 = c_a.z; P2 = c_a.w;
+            P3 = c_b.x; P4 = c_b.y; P5 = c_b.z;
+            P0 = c_b.w;
+        }
+        CellMoments m;
+        m.psi_e = psi_i + f * dpsi;
+        const T dz = SEARCH ? (T)dcell_ : f * (PREC == 0 ? (T)a.step : (T)step32);
+        const T c1 = -m.psi_e;
+        T X0 = P0, X1 = P1, X2 = P2, X3 = P3, X4 = P4, X5 = P5;
+        X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2; X2 += c1 * X1; X1 += c1 * X0;
+        X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2; X2 += c1 * X1;
+        X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2;
+        X5 += c1 * X4; X4 += c1 * X3;
+        X5 += c1 * X4;
+        const T del = -f * dpsi;               // psi_i - psi_e
+        const T e1 = dz * del, e2 = e1 * del, e3 = e2 * del, e4 = e3 * del, e5 = e4 * del;
+        m.D1 = X1 + e1 * (T)0.5;
+        m.D2 = X2 + e2 * (T)(1.0 / 3.0);
+        m.D3 = X3 + e3 * (T)0.25;
+        m.D4 = X4 + e4 * (T)0.2;
+        m.D5 = X5 + e5 * (T)(1.0 / 6.0);
+        return m;
+    };
+    // Index terms at emission (n_e = 1 + delta_e) for a photon of vertical cosine w:
+    // n_e, 1/w, n_e / n_obs (the observed direction's scale), q = 1/(n_e w)^2, 1/n_e
+    // and n_e^2.
+    struct IndexTerms { double ne, inv_w; T ratio, q, inv_ne, ne2; };
+    auto index_terms = [&](T psi_e, double pw) {
+        IndexTerms x;
+        x.ne2 = (T)1 + psi_e;
+        if (PREC == 0) {
+            x.ne = sqrt(1.0 + (double)psi_e);
+            x.ratio = (T)(x.ne * inv_nobs64);
+            x.inv_w = rcp64(pw);
+            x.inv_ne = (T)rcp64(x.ne);
+            x.q = (T)(x.inv_w * x.inv_w) * (x.inv_ne * x.inv_ne);
+        } else {
+            const float de = (float)psi_e * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_sqrtf(1.0f + (float)psi_e));
+            x.ne = 1.0 + (double)de;
+            x.ratio = 1.0f + (de - d_obs) * inv_1pdobs;
+            // reciprocal of w: the hardware estimate (relative error below 2^-24 on
+            // this chip) and one Newton step, 2e-15 relative
+            const double r_w = __builtin_amdgcn_rcp(pw);
+            x.inv_w = fma(r_w, fma(-pw, r_w, 1.0), r_w);
+            x.q = (T)__builtin_amdgcn_rcpf((float)x.ne2 * (float)(pw * pw));
+            x.inv_ne = (T)__builtin_amdgcn_rcpf(1.0f + de);
+        }
+        return x;
+    };
+    // series part of the horizontal advance, S - dh = sum_{k>=1} a_k q^k D_k
+    auto advance_series = [&](const CellMoments& m, T q) {
+        return q * (a1 * m.D1 + q * (a2 * m.D2 + q * (a3 * m.D3 + q * a4 * m.D4)));
+    };
+    // travel time from the emission height dh above the observation level:
+    // c * time * w = n_e dh + (1/n_e) [D1 + sum_{k>=1} a_k q^k (n_e^2 D_k + D_{k+1})]
+    //              = n_e dh + (1/n_e) [D1 + n_e^2 s_corr + sum_{k>=1} a_k q^k D_{k+1}]
+    auto travel_time = [&](const CellMoments& m, const IndexTerms& ix, T s_corr, double dh) {
+        const T q = ix.q;
+        const T t_corr = m.D1 + ix.ne2 * s_corr +
+                         q * (a1 * m.D2 + q * (a2 * m.D3 + q * (a3 * m.D4 + q * a4 * m.D5)));
+        const double ctw = fma(ix.ne, dh, (double)(t_corr * ix.inv_ne));
+        return ctw * ix.inv_w * inv_c;
+    };
+
     for (;;) {
         int64_t t = 0;
         if (lane == 0)
@@ -935,7 +1047,6 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
         const int64_t total = ts_.total;
         const bool emits = ts_.emits;
         const int excl = ts_.excl;
-        const uint64_t emit_mask = __ballot(emits);
         wave_lds_sync();
 
         // ---- bunches of the tile, one per lane
@@ -957,14 +1068,20 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
             bool alive = false;
             int drop_why = -1;
             // read only in lanes that emit a live bunch: left undefined elsewhere
-            double xg, yg, he, tarr;
-            float uo, vo, lam, photons, he_f, t_f;
+            double xg, yg, he;
             int32_t k, sidx;
             double uod, vod;   // observed direction for the sphere test (live bunches)
             int pbin = -1;     // depth bin of the bunch for the profile, -1: not counted
             bool screen_all = false;   // screening: listed whatever its sphere tests say
-            double fcell, dcell;   // fraction and height of the emission point in its cell
+            double fcell, dcell = 0.0;   // fraction and height of the emission point in its cell
             int ci;
+            // what a crossing's record needs beyond the above; the record itself is
+            // completed only in chunks that hold a crossing
+            double t_rec;        // mixed fast path: emission time - t_ref; else the arrival time
+            double w_rec;        // mixed fast path: w of the photon at emission
+            T f_rec;             // mixed fast path: fraction of the emission point in its cell
+            bool fast_rec = false;
+            uint32_t r2_rec;     // the wavelength's draw
             if (active) {
                 const Entry& e = stash[si];
                 k = j - e.boff;
@@ -1037,9 +1154,6 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     pu = ct * tu + (cp * (double)e.sb1x + sp * (double)e.sb2x);
                     pv = ct * tv + (cp * (double)e.sb1y + sp * (double)e.sb2y);
                     pw = ct * tw - (cp * (double)e.sb1z + sp * (double)e.sb2z);
-                    photons = (float)e.photons;
-                    lam = (float)rcp64(a.inv_l1 - fma((double)r2, 2.3283064365386963e-10,
-                                                      1.1641532182693481e-10) * a.dl);
                 } else {
                     float sp, cp;
                     sincos_turns_hw(r1, sp, cp);
@@ -1049,10 +1163,8 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     pu = fma(ct, tu, (double)px);
                     pv = fma(ct, tv, (double)py);
                     pw = fma(ct, tw, -(double)pz);
-                    photons = (float)e.photons;
-                    const float u2 = fmaf((float)r2, 2.3283064365386963e-10f, 1.16415321826934814e-10f);
-                    lam = __builtin_amdgcn_rcpf(fmaf(-u2, (float)a.dl, (float)a.inv_l1));
                 }
+                r2_rec = r2;
                 // drop rules
                 if (he < a.h_obs) drop_why = CKV_DROP_BELOW_OBS;
                 else if (he >= a.h_top) drop_why = CKV_DROP_ABOVE_TOP;
@@ -1097,134 +1209,45 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                         uod = pu * ne_x / a.n_obs;
                         vod = pv * ne_x / a.n_obs;
                     }
-                    tarr = (te - t_ref) + T_x;
-                    uo = (float)uod;
-                    vo = (float)vod;
-                    t_f = (float)tarr;
-                    he_f = (float)he;
+                    t_rec = (te - t_ref) + T_x;
                 }
                 if (drop_why < 0 && !slow) {
                     alive = true;
                     // ---- atmosphere at the emission altitude (uniform table, no search)
                     const T f = (T)fcell;
-                    T psi_i, dpsi, P0, P1, P2, P3, P4, P5;
-                    // LDS read always (index clamped into the staged part); the rare
-                    // lookups above it are replaced by a read from HBM
-                    if (PREC == 0) {
-                        double n0[6], n1;
-                        {
-                            const int cl = PARTIAL ? min(ci, a.lds_entries - 2) : ci;
-                            const double* nd = tab64 + (size_t)kNode64 * cl;
-                            for (int q = 0; q < 6; ++q) n0[q] = nd[q];
-                            n1 = nd[kNode64];
-                        }
-                        if (PARTIAL && ci + 1 >= a.lds_entries) {
-                            // a distinct load kind keeps the compiler from fusing the two
-                            // reads into one generic (flat) load of a selected address
-                            const double* nd = a.node64 + (size_t)kNode64 * ci;
-                            for (int q = 0; q < 6; ++q) n0[q] = __builtin_nontemporal_load(nd + q);
-                            n1 = __builtin_nontemporal_load(nd + kNode64);
-                        }
-                        psi_i = n0[0];
-                        dpsi = n1 - n0[0];
-                        P0 = SEARCH ? hn_lds[ci] - a.h_obs : (double)ci * a.step;
-                        P1 = n0[1]; P2 = n0[2]; P3 = n0[3]; P4 = n0[4]; P5 = n0[5];
-                    } else {
-                        float4 c_a, c_b;
-                        {
-                            const int cl = PARTIAL ? min(ci, a.lds_entries - 1) : ci;
-                            const float4* cc = reinterpret_cast<const float4*>(tab32 + (size_t)kCell32 * cl);
-                            c_a = cc[0];
-                            c_b = cc[1];
-                        }
-                        if (PARTIAL && ci >= a.lds_entries) {
-                            // a distinct load kind keeps the compiler from fusing the two
-                            // reads into one generic (flat) load of a selected address
-                            const float* cg = a.cell32 + (size_t)kCell32 * ci;
-                            c_a = make_float4(__builtin_nontemporal_load(cg), __builtin_nontemporal_load(cg + 1),
-                                              __builtin_nontemporal_load(cg + 2), __builtin_nontemporal_load(cg + 3));
-                            c_b = make_float4(__builtin_nontemporal_load(cg + 4), __builtin_nontemporal_load(cg + 5),
-                                              __builtin_nontemporal_load(cg + 6), __builtin_nontemporal_load(cg + 7));
-                        }
-                        psi_i = c_a.x; dpsi = c_a.y; P1 = c_a.z; P2 = c_a.w;
-                        P3 = c_b.x; P4 = c_b.y; P5 = c_b.z;
-                        P0 = c_b.w;
-                    }
-                    const T psi_e = psi_i + f * dpsi;
-                    const T dz = SEARCH ? (T)dcell : f * (PREC == 0 ? (T)a.step : (T)step32);
-                    // D_k = int_{h_obs}^{h_e} (psi - psi_e)^k dh, k = 1..5, split at the
-                    // cell's lower node h_i: below it, the node moments shifted to psi_e,
-                    // sum_j C(k,j) (-psi_e)^(k-j) P_j(h_i) with P_0(h_i) = h_i - h_obs
-                    // (Pascal-triangle shift);
-                    // inside the cell, psi is linear from psi_i to psi_e, so the rest
-                    // is dz (psi_i - psi_e)^k / (k+1).
-                    const double dh = he - a.h_obs;
-                    const T c1 = -psi_e;
-                    T X0 = P0, X1 = P1, X2 = P2, X3 = P3, X4 = P4, X5 = P5;
-                    X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2; X2 += c1 * X1; X1 += c1 * X0;
-                    X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2; X2 += c1 * X1;
-                    X5 += c1 * X4; X4 += c1 * X3; X3 += c1 * X2;
-                    X5 += c1 * X4; X4 += c1 * X3;
-                    X5 += c1 * X4;
-                    const T del = -f * dpsi;               // psi_i - psi_e
-                    const T e1 = dz * del, e2 = e1 * del, e3 = e2 * del, e4 = e3 * del, e5 = e4 * del;
-                    const T D1 = X1 + e1 * (T)0.5;
-                    const T D2 = X2 + e2 * (T)(1.0 / 3.0);
-                    const T D3 = X3 + e3 * (T)0.25;
-                    const T D4 = X4 + e4 * (T)0.2;
-                    const T D5 = X5 + e5 * (T)(1.0 / 6.0);
-                    // index at emission: n_e = 1 + delta_e
-                    const T ne2 = (T)1 + psi_e;
-                    double ne, inv_w;
-                    T ratio, q, inv_ne;
-                    if (PREC == 0) {
-                        ne = sqrt(1.0 + (double)psi_e);
-                        ratio = (T)(ne * inv_nobs64);
-                        inv_w = rcp64(pw);
-                        inv_ne = (T)rcp64(ne);
-                        q = (T)(inv_w * inv_w) * (inv_ne * inv_ne);
-                    } else {
-                        const float de = (float)psi_e * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_sqrtf(1.0f + (float)psi_e));
-                        ne = 1.0 + (double)de;
-                        ratio = 1.0f + (de - d_obs) * inv_1pdobs;
-                        // reciprocal of w: the hardware estimate (relative error below
-                        // 2^-24 on this chip) and one Newton step, 2e-15 relative
-                        const double r_w = __builtin_amdgcn_rcp(pw);
-                        inv_w = fma(r_w, fma(-pw, r_w, 1.0), r_w);
-                        q = (T)__builtin_amdgcn_rcpf((float)ne2 * (float)(pw * pw));
-                        inv_ne = (T)__builtin_amdgcn_rcpf(1.0f + de);
-                    }
+                    const CellMoments m = cell_moments(ci, f, dcell);
+                    const IndexTerms ix = index_terms(m.psi_e, pw);
                     // horizontal advance: S = dh + sum_{k>=1} a_k q^k D_k
-                    const T s_corr = q * (a1 * D1 + q * (a2 * D2 + q * (a3 * D3 + q * a4 * D4)));
+                    const double dh = he - a.h_obs;
+                    const T s_corr = advance_series(m, ix.q);
                     const double S = dh + (double)s_corr;
-                    // c * time * w = n_e dh + (1/n_e) [D1 + sum_{k>=1} a_k q^k (n_e^2 D_k + D_{k+1})]
-                    //              = n_e dh + (1/n_e) [D1 + n_e^2 s_corr + sum_{k>=1} a_k q^k D_{k+1}]
-                    const T t_corr = D1 + ne2 * s_corr +
-                                     q * (a1 * D2 + q * (a2 * D3 + q * (a3 * D4 + q * a4 * D5)));
-                    const double ctw = fma(ne, dh, (double)(t_corr * inv_ne));
-                    const double T_travel = ctw * inv_w * inv_c;
-                    const double adv = inv_w * S;
+                    const double adv = ix.inv_w * S;
                     if (SCREEN) {
                         // bound of this path's ground-point error (direction error of the
                         // FP32 cone vector through 1/w and u/w^2, FP32 series corrections
                         // through q ~ 1/w^2 and 1/w): where it passes half the screening
                         // margin the sphere test cannot be trusted and the bunch is listed
-                        const double e_g = dh * inv_w * (kScreenErrDir * (1.0 + inv_w) +
-                                                         kScreenErrSeries * inv_w * inv_w);
+                        const double e_g = dh * ix.inv_w * (kScreenErrDir * (1.0 + ix.inv_w) +
+                                                            kScreenErrSeries * ix.inv_w * ix.inv_w);
                         screen_all = e_g > 0.5 * kScreenMargin;
                     }
                     xg = fma(pu, adv, xe);
                     yg = fma(pv, adv, ye);
-                    tarr = (te - t_ref) + T_travel;
                     // the sphere test takes the observed direction at the path's
                     // precision (FP64 path: before the record's FP32 rounding)
-                    const T uT = (T)pu * ratio, vT = (T)pv * ratio;
-                    uo = (float)uT;
-                    vo = (float)vT;
+                    const T uT = (T)pu * ix.ratio, vT = (T)pv * ix.ratio;
                     uod = (double)uT;
                     vod = (double)vT;
-                    t_f = (float)tarr;
-                    he_f = (float)he;
+                    if constexpr (PREC == 0) {
+                        // FP64: the arrival time at once (keeping the inputs of its
+                        // recomputation live costs this build more than it saves)
+                        t_rec = (te - t_ref) + travel_time(m, ix, s_corr, dh);
+                    } else {
+                        t_rec = te - t_ref;
+                        w_rec = pw;
+                        f_rec = f;
+                        fast_rec = true;
+                    }
                 }
             }
             {
@@ -1304,6 +1327,41 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     soft_list_flush(lst, bits, stash, c0 - (int64_t)w * kWave, w + 1, lane);
                 }
             } else {
+                // ---- the records of the crossing bunches.  About one chunk in five holds
+                // a crossing, so the wavelength and the record's roundings are done here,
+                // for those lanes; the mixed path also takes the arrival time's series
+                // (the only user of D_5 and 1/n_e) here, recomputed from the table rather
+                // than kept live through the sphere tests.
+                float uo, vo, t_f, he_f, photons, lam;
+                int32_t k_rec, sidx_rec;
+                if (__ballot(my_next != INT_MAX)) {
+                    if (my_next != INT_MAX) {
+                        const Entry& er = stash[si];
+                        k_rec = j - er.boff;
+                        sidx_rec = er.sidx;
+                        photons = (float)er.photons;
+                        if (PREC == 0) {
+                            lam = (float)rcp64(a.inv_l1 - fma((double)r2_rec, 2.3283064365386963e-10,
+                                                              1.1641532182693481e-10) * a.dl);
+                        } else {
+                            const float u2 = fmaf((float)r2_rec, 2.3283064365386963e-10f,
+                                                  1.16415321826934814e-10f);
+                            lam = __builtin_amdgcn_rcpf(fmaf(-u2, (float)a.dl, (float)a.inv_l1));
+                        }
+                        double tarr = t_rec;
+                        if constexpr (PREC == 1) {
+                            if (fast_rec) {
+                                const CellMoments m = cell_moments(ci, f_rec, dcell);
+                                const IndexTerms ix = index_terms(m.psi_e, w_rec);
+                                tarr += travel_time(m, ix, advance_series(m, ix.q), he - a.h_obs);
+                            }
+                        }
+                        uo = (float)uod;
+                        vo = (float)vod;
+                        t_f = (float)tarr;
+                        he_f = (float)he;
+                    }
+                }
                 // ---- record crossings; telescopes in ascending order, lanes (bunches) in order
                 while (__ballot(my_next != INT_MAX)) {
                     const int kmin = wave_min_sparse(my_next, INT_MAX);
@@ -1340,8 +1398,8 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                             ef[0] = make_float4((float)(xg - tp[0]), (float)(yg - tp[1]), uo, vo);
                             ef[1] = make_float4(t_f, he_f, photons, lam);
                             uint4* eu = reinterpret_cast<uint4*>(se);
-                            eu[2] = make_uint4((uint32_t)t, (uint32_t)kmin | ((uint32_t)sidx << 16),
-                                               (uint32_t)(rank0 + below), (uint32_t)k);
+                            eu[2] = make_uint4((uint32_t)t, (uint32_t)kmin | ((uint32_t)sidx_rec << 16),
+                                               (uint32_t)(rank0 + below), (uint32_t)k_rec);
                         }
                     }
                     if (nmine > room) {
