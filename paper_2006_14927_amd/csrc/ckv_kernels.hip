@@ -1930,6 +1930,17 @@ struct SoftArgs {
     int64_t* ids_count;
     int32_t skip_if_listed;     // tile kernels: exit when the list is complete
     int32_t cand_lds_acc;       // candidate kernel: S, A of all (shower, sphere) pairs in LDS
+    int32_t shower_lds;         // listed kernels: the per-shower table in LDS
+};
+
+// Per shower, for the listed kernels: first step, counter-word base (the counter
+// word of step i is ctr_base + i without caller step ids), t_ref and the shower id.
+struct ShowerRec {
+    int64_t first;
+    int64_t ctr_base;
+    double t_ref;
+    uint32_t id;
+    uint32_t pad;
 };
 
 
@@ -1990,7 +2001,8 @@ __host__ __device__ inline size_t soft_lds_bytes(int mode, int n_nodes, int n_te
 }
 
 // step setup with a frozen bunch count; false when the step emits nothing
-__device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, SoftStep& e)
+__device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, SoftStep& e,
+                                       const double* node_lds = nullptr, int n_lds = 0)
 {
     // no contraction: the threshold decision is the one of the FP64 definition and
     // of the screening pass's step setup
@@ -2011,23 +2023,30 @@ __device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, Sof
     int64_t im = (int64_t)floor(x);
     if (im > a.n_nodes - 2) im = a.n_nodes - 2;
     const double fm = x - (double)im;
-    const double lo = a.node64[kNode64 * im], hi = a.node64[kNode64 * (im + 1)];
+    // psi at the two nodes: from the LDS copy of the lowest nodes when it holds them
+    const double* nd = im + 1 < n_lds ? node_lds : a.node64;
+    const double lo = nd[kNode64 * im], hi = nd[kNode64 * (im + 1)];
     const double psi = lo + fm * (hi - lo);
     const double n2 = 1.0 + psi;
     const double num = psi - n2 * r2;
     if (!(num > 0.0)) return false;
-    const double sin2 = num / (n2 * (1.0 - r2));
-    const double nbd = (double)nb;
-    e.x0 = x0; e.y0 = y0; e.h0 = h0; e.t0 = t0; e.u = u; e.v = v; e.w = w;
-    e.photons = (a.k_ft * L) * sin2 / nbd;
+    // past the threshold test the step's values take reciprocals from the hardware
+    // estimate and two Newton steps (within an ulp or two of the quotient): nothing
+    // decides on them, and S, A and the gradient move by a few ulps at most
     e.g1 = (1.0 - r2) * n2;
-    e.cos_t = 1.0 / sqrt(e.g1);
+    const double sin2 = num * rcp64(e.g1);
+    const double nbd = (double)nb;
+    const double inv_nb = rcp64(nbd);
+    e.x0 = x0; e.y0 = y0; e.h0 = h0; e.t0 = t0; e.u = u; e.v = v; e.w = w;
+    e.kl_nb = (a.k_ft * L) * inv_nb;
+    e.photons = e.kl_nb * sin2;
+    e.cos_t = rcp64(sqrt(e.g1));
     e.sin_t = sqrt(sin2);
-    e.ds = L / nbd;
-    e.inv_bc = 1.0 / (sqrt(1.0 - r2) * kSpeedOfLight);
+    e.ds = L * inv_nb;
+    e.inv_bc = rcp64(sqrt(1.0 - r2) * kSpeedOfLight);
     const double Dx = u, Dy = v, Dz = -w;
     const double sgn = copysign(1.0, Dz);
-    const double ia = -1.0 / (sgn + Dz);
+    const double ia = -rcp64(sgn + Dz);
     const double ib = Dx * Dy * ia;
     e.b1x = 1.0 + sgn * Dx * Dx * ia;
     e.b1y = sgn * ib;
@@ -2038,7 +2057,6 @@ __device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, Sof
     e.r2 = r2;
     e.f_m = fm;
     e.i_m = (int32_t)im;
-    e.kl_nb = a.k_ft * L / nbd;
     e.g_cos = e.g_sin = e.g_phot = 0.0;
     return true;
 }
@@ -2421,20 +2439,23 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
     }
 }
 
-constexpr int kSoftListThreads = 512;
+constexpr int kSoftListThreads = 512;   // listed adjoint: workgroup size
+constexpr int kSoftCandThreads = 512;   // listed forward: workgroup size
 
-// Listed bunches of a wave (ids q0 + lane, consecutive): the step setup and the
-// shower lookup are done once per run of lanes that name the same step (the
-// screening pass lists a step's bunches together) and passed to the run's other
-// lanes by lane shuffles.  REV: also the step-level values of the reverse sweep.
+// Listed bunches of a wave (consecutive list entries, one per lane; id is the
+// lane's entry, loaded by the caller): the step setup and the shower lookup are
+// done once per run of lanes that name the same step (the screening pass lists a
+// step's bunches together) and passed to the run's other lanes by lane shuffles.
+// shr: the per-shower table in LDS, or null (then from HBM); node_lds: the lowest
+// n_lds node records in LDS.  REV: also the step-level values of the reverse sweep.
 // True for lanes whose id names a bunch of the inputs on a step that gives light.
 // Called by the whole wave.
 template <bool REV>
-__device__ __forceinline__ bool listed_setup(const Args& a, const SoftArgs& sa, int64_t q, bool have,
-                                             int lane, SoftStep& e, int& shower, uint32_t& ctr1,
-                                             int32_t& k)
+__device__ __forceinline__ bool listed_setup(const Args& a, const SoftArgs& sa, uint64_t id, bool have,
+                                             int lane, const ShowerRec* shr, const double* node_lds,
+                                             int n_lds, SoftStep& e, int& shower, uint32_t& ctr1,
+                                             uint32_t& shower_id, double& t_ref, int32_t& k)
 {
-    const uint64_t id = have ? sa.ids[q] : ~0ull;
     const int64_t i = have ? (int64_t)(id >> kSoftIdBits) : -1;
     k = (int32_t)(id & ((1u << kSoftIdBits) - 1));
     const bool named = have && i < a.n;
@@ -2442,16 +2463,29 @@ __device__ __forceinline__ bool listed_setup(const Args& a, const SoftArgs& sa, 
     const int64_t i_prev = __shfl_up(i, 1);
     const bool head = named && (lane == 0 || i_prev != i);
     int lit = 0, lo = 0;
-    uint32_t c1 = 0;
+    uint32_t c1 = 0, sid = 0;
+    double tr = 0.0;
     if (head) {
         int hi = a.n_showers;                   // the shower holding step i
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (a.seg_offsets[mid] <= i) lo = mid; else hi = mid;
+        if (shr) {
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (shr[mid].first <= i) lo = mid; else hi = mid;
+            }
+            c1 = a.step_id ? a.step_id[i] : (uint32_t)(shr[lo].ctr_base + i);
+            sid = shr[lo].id;
+            tr = shr[lo].t_ref;
+        } else {
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (a.seg_offsets[mid] <= i) lo = mid; else hi = mid;
+            }
+            c1 = a.step_id ? a.step_id[i]
+                           : (uint32_t)((a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]));
+            sid = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
+            tr = a.t_ref[lo];
         }
-        lit = soft_step_setup(a, i, nbf, e) ? 1 : 0;
-        c1 = a.step_id ? a.step_id[i]
-                       : (uint32_t)((a.seg_id_base ? a.seg_id_base[lo] : 0) + (i - a.seg_offsets[lo]));
+        lit = soft_step_setup(a, i, nbf, e, node_lds, n_lds) ? 1 : 0;
     }
     // the run's head: the nearest head lane at or below this one
     const uint64_t heads = __ballot(head);
@@ -2461,6 +2495,8 @@ __device__ __forceinline__ bool listed_setup(const Args& a, const SoftArgs& sa, 
     lit = __shfl(lit, src);
     shower = __shfl(lo, src);
     ctr1 = __shfl(c1, src);
+    shower_id = __shfl(sid, src);
+    t_ref = __shfl(tr, src);
     e.x0 = __shfl(e.x0, src); e.y0 = __shfl(e.y0, src); e.h0 = __shfl(e.h0, src);
     e.t0 = __shfl(e.t0, src); e.u = __shfl(e.u, src); e.v = __shfl(e.v, src); e.w = __shfl(e.w, src);
     e.cos_t = __shfl(e.cos_t, src); e.sin_t = __shfl(e.sin_t, src);
@@ -2472,6 +2508,20 @@ __device__ __forceinline__ bool listed_setup(const Args& a, const SoftArgs& sa, 
         e.kl_nb = __shfl(e.kl_nb, src); e.i_m = __shfl(e.i_m, src);
     }
     return named && lit && k < nbf;
+}
+
+// Per-shower table of the listed kernels, staged into LDS by the workgroup.
+__device__ __forceinline__ void stage_showers(const Args& a, ShowerRec* shr)
+{
+    for (int q = threadIdx.x; q < a.n_showers; q += blockDim.x) {
+        ShowerRec r;
+        r.first = a.seg_offsets[q];
+        r.ctr_base = (a.seg_id_base ? a.seg_id_base[q] : 0) - a.seg_offsets[q];
+        r.t_ref = a.t_ref[q];
+        r.id = a.shower_ids ? a.shower_ids[q] : (uint32_t)q;
+        r.pad = 0;
+        shr[q] = r;
+    }
 }
 
 // Adjoint over the forward's list: one listed bunch per thread, its step set up
@@ -2497,6 +2547,8 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
         tsh[4 * q + 2] = a.tel[4 * q + 3];
         tsh[4 * q + 3] = 1.0 / (2.0 * a.tel[4 * q + 2] * sa.sigma);
     }
+    ShowerRec* shr = sa.shower_lds ? reinterpret_cast<ShowerRec*>(nlds + kNode64 * NL) : nullptr;
+    if (shr) stage_showers(a, shr);
     __syncthreads();
     auto add_bin = [&](int j, int i, double v) {
         if (i < NB) atomicAdd(&bins[j * NB + i], v);
@@ -2506,20 +2558,29 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
     const double half_inv_nobs3 = 0.5 * inv_nobs * inv_nobs * inv_nobs;
     double g_psi0 = 0.0;
     const int lane = lane_id();
-    for (int64_t q0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); q0 < n_ids;
-         q0 += (int64_t)gridDim.x * blockDim.x) {
+    // each lane's next list entry is loaded one round ahead, while the current
+    // bunch is computed
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t q0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1));
+    uint64_t id = q0 + lane < n_ids ? sa.ids[q0 + lane] : ~0ull;
+    for (; q0 < n_ids; q0 += stride) {
         const int64_t q = q0 + lane;
+        const uint64_t id_next = q + stride < n_ids ? sa.ids[q + stride] : ~0ull;
         SoftStep e;
         int lo;
-        uint32_t seg_id;
+        uint32_t seg_id, shower_id;
+        double t_ref;
         int32_t k;
-        if (!listed_setup<true>(a, sa, q, q < n_ids, lane, e, lo, seg_id, k)) continue;
-        const uint32_t shower_id = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
-        double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
-        soft_bunch<1, true>(a, sa, e, k, seg_id, shower_id, lo, a.t_ref[lo], tsh, nullptr,
-                            nullptr, add_bin, inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin, o_phot);
-        if (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)
-            soft_step_reverse(e, o_cos, o_sin, o_phot, add_bin);
+        if (listed_setup<true>(a, sa, id, q < n_ids, lane, shr, nlds, NL, e, lo, seg_id, shower_id,
+                               t_ref, k)) {
+            double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
+            soft_bunch<1, true>(a, sa, e, k, seg_id, shower_id, lo, t_ref, tsh, nullptr, nullptr,
+                                add_bin, inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin,
+                                o_phot);
+            if (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)
+                soft_step_reverse(e, o_cos, o_sin, o_phot, add_bin);
+        }
+        id = id_next;
     }
     if (g_psi0 != 0.0) add_bin(0, 0, g_psi0);
     __syncthreads();
@@ -2534,7 +2595,7 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
 // thread, its step set up again with the frozen count and the bunch recomputed in
 // FP64 exactly as in the tile kernel; S and A are added straight into HBM.  Runs
 // only when the list is complete; ids that name no bunch are skipped.
-__global__ void __launch_bounds__(kSoftListThreads) soft_cand_kernel(Args a, SoftArgs sa)
+__global__ void __launch_bounds__(kSoftCandThreads) soft_cand_kernel(Args a, SoftArgs sa)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     if (!soft_list_complete(sa)) return;
@@ -2557,27 +2618,38 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_cand_kernel(Args a, Sof
     double* accA = accS + nsk;
     if (sa.cand_lds_acc)
         for (int64_t q = threadIdx.x; q < 2 * nsk; q += blockDim.x) accS[q] = 0.0;
+    ShowerRec* shr = sa.shower_lds
+                         ? reinterpret_cast<ShowerRec*>(sa.cand_lds_acc ? accA + nsk : accS)
+                         : nullptr;
+    if (shr) stage_showers(a, shr);
     __syncthreads();
     auto no_bins = [](int, int, double) {};
     const double inv_nobs = 1.0 / a.n_obs;
     const double half_inv_nobs3 = 0.5 * inv_nobs * inv_nobs * inv_nobs;
     double g_psi0 = 0.0;
     const int lane = lane_id();
-    for (int64_t q0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); q0 < n_ids;
-         q0 += (int64_t)gridDim.x * blockDim.x) {
+    // each lane's next list entry is loaded one round ahead, while the current
+    // bunch is computed
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t q0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~(kWave - 1));
+    uint64_t id = q0 + lane < n_ids ? sa.ids[q0 + lane] : ~0ull;
+    for (; q0 < n_ids; q0 += stride) {
         const int64_t q = q0 + lane;
+        const uint64_t id_next = q + stride < n_ids ? sa.ids[q + stride] : ~0ull;
         SoftStep e;
         int lo;
-        uint32_t seg_id;
+        uint32_t seg_id, shower_id;
+        double t_ref;
         int32_t k;
-        if (!listed_setup<false>(a, sa, q, q < n_ids, lane, e, lo, seg_id, k)) continue;
-        const uint32_t shower_id = a.shower_ids ? a.shower_ids[lo] : (uint32_t)lo;
-        double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
-        double* rowS = (sa.cand_lds_acc ? accS : sa.S) + (int64_t)lo * a.n_tel;
-        double* rowA = (sa.cand_lds_acc ? accA : sa.A) + (int64_t)lo * a.n_tel;
-        soft_bunch<0, true>(a, sa, e, k, seg_id, shower_id, lo, a.t_ref[lo], tsh, rowS,
-                            rowA, no_bins, inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin,
-                            o_phot);
+        if (listed_setup<false>(a, sa, id, q < n_ids, lane, shr, nlds, NL, e, lo, seg_id, shower_id,
+                                t_ref, k)) {
+            double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
+            double* rowS = (sa.cand_lds_acc ? accS : sa.S) + (int64_t)lo * a.n_tel;
+            double* rowA = (sa.cand_lds_acc ? accA : sa.A) + (int64_t)lo * a.n_tel;
+            soft_bunch<0, true>(a, sa, e, k, seg_id, shower_id, lo, t_ref, tsh, rowS, rowA, no_bins,
+                                inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin, o_phot);
+        }
+        id = id_next;
     }
     if (sa.cand_lds_acc) {
         __syncthreads();
@@ -2869,10 +2941,12 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     s.ids_count = sp.ids_count;
     // listed adjoint: bins, spheres and the lowest node records in LDS (at most
     // 128 KB for CKV_MAX_TEL spheres); beyond the LDS the adjoint recomputes everything
-    const size_t lds_l = (size_t)6 * soft_bin_nodes(a.n_nodes) * sizeof(double) +
-                         (size_t)a.n_tel * 4 * sizeof(double) +
-                         (size_t)kNode64 * soft_node_lds(a.n_nodes) * sizeof(double);
+    size_t lds_l = (size_t)6 * soft_bin_nodes(a.n_nodes) * sizeof(double) +
+                   (size_t)a.n_tel * 4 * sizeof(double) +
+                   (size_t)kNode64 * soft_node_lds(a.n_nodes) * sizeof(double);
     if (mode == 1 && lds_l > 160 * 1024) s.ids_count = nullptr;
+    // the listed kernels keep the per-shower table in LDS when it fits beside the rest
+    const size_t shr_b = (size_t)a.n_showers * sizeof(ShowerRec);
     s.skip_if_listed = s.ids_count ? 1 : 0;
     // forward with a list: the screening pass (mixed bunch kernel against spheres of
     // the cut radius plus a margin, frozen counts) lists the candidates, FP64
@@ -2943,8 +3017,10 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
             const size_t acc_b = (size_t)2 * a.n_showers * a.n_tel * sizeof(double);
             s.cand_lds_acc = lds_c + acc_b <= 160 * 1024 ? 1 : 0;
             if (s.cand_lds_acc) lds_c += acc_b;
+            s.shower_lds = lds_c + shr_b <= 160 * 1024 ? 1 : 0;
+            if (s.shower_lds) lds_c += shr_b;
             allow_lds((const void*)soft_cand_kernel, 160 * 1024);
-            soft_cand_kernel<<<2 * p.emit_grid, kSoftListThreads, lds_c, st>>>(a, s);
+            soft_cand_kernel<<<2 * p.emit_grid, kSoftCandThreads, lds_c, st>>>(a, s);
             if (int rc = check_launch("soft candidates")) return rc;
         }
         soft_kernel<0><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
@@ -2953,6 +3029,8 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
         soft_kernel<1><<<p.emit_grid, waves * kWave, lds, st>>>(a, s);
         if (s.ids_count) {
             if (int rc = check_launch("soft")) return rc;
+            s.shower_lds = lds_l + shr_b <= 160 * 1024 ? 1 : 0;
+            if (s.shower_lds) lds_l += shr_b;
             allow_lds((const void*)soft_list_kernel, 160 * 1024);
             soft_list_kernel<<<2 * p.emit_grid, kSoftListThreads, lds_l, st>>>(a, s);
         }
