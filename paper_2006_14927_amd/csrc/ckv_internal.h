@@ -60,10 +60,11 @@ constexpr int64_t kRunValueMask = ((int64_t)1 << kRunTelShift) - 1;
 // tiles) sit on cache lines of their own: same-line atomics from all waves would
 // serialise in one L2 channel.
 enum CtrlSlot {
-    kTileCounter = 0,   // next tile to claim
+    kTileCounter = 0,   // next tile to claim (the mixed bunch kernel: tiles claimed past
+                        // each wave's first, the next being the grid's wave count plus this)
     kBlockCounter = 32, // next staging block to claim
     kRunCounter = 64,   // next run block to claim
-    kScreenCounter = 96,  // next tile to claim in the soft response's screening pass (the
+    kScreenCounter = 96,  // as kTileCounter, for the soft response's screening pass (the
                           // FP64 tile forward that may follow claims from kTileCounter)
     kNumTiles = 128,    // tiles of this run
     kNumRowBlocks,      // row blocks of the per-telescope scan

@@ -1012,11 +1012,23 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
         return ctw * ix.inv_w * inv_c;
     };
 
+    // tiles are claimed from the counter.  The mixed kernel takes each wave's first
+    // tile by its index in the grid and offsets later claims by the grid's wave count,
+    // so the launch does not start with every wave's atomic on the one counter (the
+    // FP64 kernel measured slower with it: the extra scalar state spills)
+    constexpr bool kStaticFirst = PREC == 1;
+    const int64_t n_waves_grid = kStaticFirst ? (int64_t)gridDim.x * (blockDim.x / kWave) : 0;
+    const int64_t t_first = kStaticFirst ? scalar64((int64_t)blockIdx.x * (blockDim.x / kWave) + wave) : 0;
+    bool first_tile = kStaticFirst;
     for (;;) {
-        int64_t t = 0;
-        if (lane == 0)
-            t = (int64_t)atomicAdd((unsigned long long*)&a.ctrl[SCREEN ? kScreenCounter : kTileCounter], 1ull);
-        t = uniform(t);
+        int64_t t = t_first;
+        if (!first_tile) {
+            if (lane == 0)
+                t = n_waves_grid +
+                    (int64_t)atomicAdd((unsigned long long*)&a.ctrl[SCREEN ? kScreenCounter : kTileCounter], 1ull);
+            t = kStaticFirst ? scalar64(t) : uniform(t);
+        }
+        first_tile = false;
         if (t >= n_tiles) break;
         // shower of the tile
         int lo = 0, hi = a.n_showers;   // tiles_before[lo] <= t < tiles_before[hi]
@@ -1477,18 +1489,23 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
         wave_lds_sync();
     }
 
-    // ---- close the staging block and publish counters
+    // ---- close the staging block and publish counters: the workgroup's waves are
+    // summed in LDS and the first wave adds the sums, one atomic per counter and
+    // workgroup (one per wave queued thousands of atomics on the counters' line at
+    // the end of every launch)
     if (blk >= 0 && lane == 0) a.stage_fill[blk] = blk_fill;
-    wave_lds_sync();
-    if (lane == 0) {
-        const int64_t v_b = wcnt[kWcBunches], v_e = wcnt[kWcEmitting], v_h = wcnt[kWcHits];
-        if (v_h) atomicAdd((unsigned long long*)&a.ctrl[kHits], (unsigned long long)v_h);
-        if (v_b) atomicAdd((unsigned long long*)&a.ctrl[kBunches], (unsigned long long)v_b);
-        if (v_e) atomicAdd((unsigned long long*)&a.ctrl[kEmitting], (unsigned long long)v_e);
-        for (int d = 0; d < CKV_N_DROP; ++d) {
-            const int64_t v = wcnt[kWcDrop0 + d];
-            if (v) atomicAdd((unsigned long long*)&a.ctrl[kDrop0 + d], (unsigned long long)v);
-        }
+    __syncthreads();
+    if (wave == 0 && lane < kWcCount) {
+        const size_t wstride = wv_bytes + (SCREEN ? kScreenWaveBytes : 0);
+        const unsigned char* w0 = reinterpret_cast<const unsigned char*>(wcnt);
+        int64_t v = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w)
+            v += reinterpret_cast<const int64_t*>(w0 + (size_t)w * wstride)[lane];
+        const int slot = lane == kWcBunches ? kBunches
+                       : lane == kWcEmitting ? kEmitting
+                       : lane == kWcHits ? kHits
+                       : kDrop0 + (lane - kWcDrop0);
+        if (v) atomicAdd((unsigned long long*)&a.ctrl[slot], (unsigned long long)v);
     }
 }
 
