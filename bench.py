@@ -594,7 +594,7 @@ def order_study(hip, wl, atmo, tels, stream, steps: int, warmup: int):
 # same sample used to certify the GPU records of the timed launches.  Everything
 # that touches oracle/ lives below.
 
-# tolerances of the mixed path against the FP64 oracle (the benchmark spec), and the
+# tolerances the mixed path is held to against the FP64 oracle, and the
 # guard band of the sphere test: |disc| <= 2 R eps + eps^2 with eps = 1 mm
 TOL = {"ground_m": 1e-3, "dir": 1e-6, "t_ns": 0.01, "photons_rel": 1e-6, "lambda_rel": 1e-6}
 GUARD_EPS_M = 1e-3
