@@ -77,17 +77,17 @@ OPS_FP64 = {
     "observed direction, record conversions": 6,
     "candidate cell + sphere tests": 16,
 }
-# The survey's per-bunch issue-slot counts of the algorithm (lane-slots per
-# generated bunch, issue-cycle weighted): 280-300 for the mixed path, 380-450 for
-# plain FP64; the midpoints are the counts the roofline fraction is priced with.
-# The itemised counts above (the builder's own model) are reported beside them.
-SURVEY_SLOTS = {"mixed": 290.0, "fp64": 415.0}
+# Per-bunch issue-slot counts of the whole path, operation by operation (lane-slots
+# per generated bunch, issue-cycle weighted, every instruction the per-bunch work
+# needs): 280-300 for the mixed path, 380-450 for plain FP64; the midpoints are the
+# counts the roofline fraction is priced with.  The itemised algorithmic counts above
+# (arithmetic the method needs, no addressing or control) are reported beside them.
+PATH_SLOTS = {"mixed": 290.0, "fp64": 415.0}
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one VALU operation per lane
 # per clock (FP32 non-packed and FP64 both issue at this rate on CDNA4)
 PEAK_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 SEG_BYTES = 9 * 8 + 1            # SoA step record read once
-STAGE_BYTES = 64                 # staging entry written and read back
 PROFILE_BIN_GCM2 = 20.0          # depth bin of the longitudinal profile run
 RECORD_BYTES = 32                # output record
 
@@ -371,16 +371,16 @@ def diff_timing(hip, reps: int, n_showers: int = 64, n_seg: int = 500_000):
             "grad_norm": float(g.norm())}
 
 
-def roofline_block(slots_survey: float, slots_builder: float, bunches: int, kernel_ms: float,
+def roofline_block(slots_path: float, slots_itemised: float, bunches: int, kernel_ms: float,
                    issue_frac=None) -> dict:
     """VALU issue-slot roofline of a bunch kernel: algorithmic slots per bunch x
     bunches / kernel time against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz."""
-    achieved = slots_survey * bunches / (kernel_ms * 1e-3) / 1e12
+    achieved = slots_path * bunches / (kernel_ms * 1e-3) / 1e12
     peak = PEAK_OPS_PER_S / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-            "frac": achieved / peak, "slots_per_bunch": slots_survey,
-            "frac_builder_model": slots_builder * bunches / (kernel_ms * 1e-3) / PEAK_OPS_PER_S,
-            "slots_per_bunch_builder_model": slots_builder, "issue_frac": issue_frac}
+            "frac": achieved / peak, "slots_per_bunch": slots_path,
+            "frac_itemised_model": slots_itemised * bunches / (kernel_ms * 1e-3) / PEAK_OPS_PER_S,
+            "slots_per_bunch_itemised_model": slots_itemised, "issue_frac": issue_frac}
 
 
 def batched_timing(hip, reps: int, use_cache: bool = True):
@@ -446,7 +446,7 @@ def batched_timing(hip, reps: int, use_cache: bool = True):
                      "records": res["n_hits"], "bunch_kernel_ms": kms,
                      "launch": {"tile_segments": tuned["tile_segments"],
                                 "waves_per_group": tuned["waves_per_group"]},
-                     "roofline": roofline_block(SURVEY_SLOTS[key], sum(ops.values()), total, kms,
+                     "roofline": roofline_block(PATH_SLOTS[key], sum(ops.values()), total, kms,
                                                 stored_issue_frac(emit_kernel_name(
                                                     prec, tuned["tile_segments"],
                                                     tuned["waves_per_group"]), "batched_256"))}
@@ -898,9 +898,9 @@ def main(argv=None):
                                tuned[ckv.CKV_MIXED]["waves_per_group"])
     k_fp64 = emit_kernel_name(0, tuned[ckv.CKV_FP64]["tile_segments"],
                               tuned[ckv.CKV_FP64]["waves_per_group"])
-    roof = roofline_block(SURVEY_SLOTS["mixed"], sum(OPS_MIXED.values()), nb, kms_mixed,
+    roof = roofline_block(PATH_SLOTS["mixed"], sum(OPS_MIXED.values()), nb, kms_mixed,
                           stored_issue_frac(k_mixed, wl.name))
-    roof_fp64 = roofline_block(SURVEY_SLOTS["fp64"], sum(OPS_FP64.values()), nb, kms_fp64,
+    roof_fp64 = roofline_block(PATH_SLOTS["fp64"], sum(OPS_FP64.values()), nb, kms_fp64,
                                stored_issue_frac(k_fp64, wl.name))
     roof["traffic"] = stored_traffic("bunch_kernel_single_tev_mixed")
     hits = res_mixed["n_hits"]
