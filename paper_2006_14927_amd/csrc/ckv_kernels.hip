@@ -1606,17 +1606,42 @@ __device__ __forceinline__ void block_tiles(const Args& a, int64_t b, int& s, in
     t1 = min(t0 + (int64_t)kRowBlock, a.tiles_before[s + 1]);
 }
 
+// Tile of the j-th run (0 <= q < the lanes' total) among lanes 0..m-1 holding
+// inclusive run counts `incl` (one tile per lane): the first lane whose count
+// passes q.  m is a power of two, the same in every lane.
+__device__ __forceinline__ int run_tile(int64_t incl, int64_t q, int m)
+{
+    int lo = 0;
+    for (int step = m >> 1; step > 0; step >>= 1)
+        if (__shfl(incl, lo + step - 1) <= q) lo += step;
+    return lo;
+}
+
 // Adds the runs of tiles [t0, t1) into acc[telescope] (LDS) with the whole
-// workgroup: one wave per tile, lanes over its runs.
+// workgroup.  Each wave takes groups of kRowBlock / waves tiles: its lanes load
+// the group's run counts and offsets in one round, then walk the group's runs in
+// flat order (a run per lane), so the loads of different tiles are not chained.
 __device__ __forceinline__ void add_runs(const Args& a, int64_t t0, int64_t t1, int32_t* acc)
 {
     const int lane = lane_id(), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    for (int64_t t = t0 + wave; t < t1; t += nw) {
-        const int n = a.tile_run_n[t];
-        const int64_t off = a.tile_run_off[t];
-        for (int i = lane; i < n; i += kWave) {
-            const int64_t r = a.runs[off + i];
-            atomicAdd(&acc[(int)(r >> kRunTelShift)], (int32_t)(r & kRunValueMask));
+    int g = kRowBlock / nw;                         // tiles per group: a power of two
+    if (g < 1) g = 1;
+    for (int64_t base = t0 + (int64_t)wave * g; base < t1; base += (int64_t)nw * g) {
+        const int64_t t = base + lane;
+        const bool mine = lane < g && t < t1;
+        const int n = mine ? a.tile_run_n[t] : 0;
+        const int64_t off = mine ? a.tile_run_off[t] : 0;
+        const int64_t incl = wave_incl_scan((int64_t)n);
+        const int64_t total = __shfl(incl, kWave - 1);
+        // the whole wave runs every round (the shuffles read every lane)
+        for (int64_t q0 = 0; q0 < total; q0 += kWave) {
+            const int64_t q = q0 + lane;
+            const int j = run_tile(incl, q, g);
+            const int64_t off_j = __shfl(off, j), first_j = __shfl(incl, j) - __shfl((int64_t)n, j);
+            if (q < total) {
+                const int64_t r = a.runs[off_j + (q - first_j)];
+                atomicAdd(&acc[(int)(r >> kRunTelShift)], (int32_t)(r & kRunValueMask));
+            }
         }
     }
 }
@@ -1800,8 +1825,15 @@ __global__ void __launch_bounds__(64) tile_prefix_kernel(Args a)
         const int64_t total = __shfl(incl, kWave - 1);
         const int my0 = (int)(incl - n);
         const bool in_lds = total <= kPrefixLdsRuns;
+        // the block's runs into LDS in flat order, a run per lane (the loads of
+        // different tiles are not chained)
         if (in_lds)
-            for (int i = 0; i < n; ++i) buf[my0 + i] = a.runs[off + i];
+            for (int64_t q0 = 0; q0 < total; q0 += kWave) {
+                const int64_t q = q0 + lane;
+                const int j = run_tile(incl, q, kWave);
+                const int64_t off_j = __shfl(off, j), first_j = __shfl(incl, j) - __shfl((int64_t)n, j);
+                if (q < total) buf[q] = a.runs[off_j + (q - first_j)];
+            }
         wave_lds_sync();
         for (int64_t t = t0; t < t1; ++t) {
             const int j = (int)(t - t0);
@@ -1819,7 +1851,12 @@ __global__ void __launch_bounds__(64) tile_prefix_kernel(Args a)
             wave_lds_sync();
         }
         if (in_lds)
-            for (int i = 0; i < n; ++i) a.runs[off + i] = buf[my0 + i];
+            for (int64_t q0 = 0; q0 < total; q0 += kWave) {
+                const int64_t q = q0 + lane;
+                const int j = run_tile(incl, q, kWave);
+                const int64_t off_j = __shfl(off, j), first_j = __shfl(incl, j) - __shfl((int64_t)n, j);
+                if (q < total) a.runs[off_j + (q - first_j)] = buf[q];
+            }
         wave_lds_sync();
     }
 }
