@@ -150,6 +150,40 @@ def test_reruns_and_tilings_give_identical_bytes(vg):
         np.testing.assert_array_equal(g["ids"], base["ids"])
 
 
+def test_fp64_builds_give_identical_bytes():
+    """The FP64 kernel's 8-wave build (whole table in LDS) and its 16-wave build
+    (lowest 1536 nodes in LDS, the rest read from HBM) give the same bytes at
+    every tile size (on this 50 m table every emission cell lies in the staged
+    part; the next test reads cells from HBM)."""
+    wl = synth.single_tev(20_000)
+    base = gpu_run(wl, ckv.CKV_FP64, tile_segments=32, waves_per_group=8)
+    assert base["result"]["n_hits"] > 0
+    for kw in (dict(tile_segments=16, waves_per_group=16), dict(tile_segments=32, waves_per_group=16),
+               dict(tile_segments=8, waves_per_group=16, grid=300)):
+        g = gpu_run(wl, ckv.CKV_FP64, **kw)
+        np.testing.assert_array_equal(g["offsets"], base["offsets"])
+        np.testing.assert_array_equal(g["rec"].view(np.uint32), base["rec"].view(np.uint32))
+        np.testing.assert_array_equal(g["ids"], base["ids"])
+
+
+def test_fp64_sixteen_waves_above_the_staged_table():
+    """A 5 m table (23 560 nodes): the 16-wave FP64 build keeps the lowest 1536
+    nodes (7.7 km) in LDS and reads every emission cell above them from HBM; its
+    records match the oracle (FP64 rules: offsets and identities bit-exact,
+    fields within the records' FP32 rounding)."""
+    import dataclasses
+    wl = dataclasses.replace(synth.single_tev(20_000), fine_step=5.0)
+    cfg = oracle.Config.from_workload(wl)
+    r = oracle.run(cfg, wl.segs, nthreads=8)
+    g = gpu_run(wl, ckv.CKV_FP64, tile_segments=16, waves_per_group=16)
+    res = g["result"]
+    assert res["error"] == 0 and res["overflow"] == 0
+    assert res["n_bunches"] == r.n_bunches and res["drops"] == r.drops
+    np.testing.assert_array_equal(g["offsets"], r.offsets)
+    rep = compare_records(wl, cfg, r, g, ckv.CKV_FP64)
+    say(f"[gpu] fp64 16 waves, 5 m table: {rep}")
+
+
 def test_chunked_run_equals_one_shot(vg):
     wl, cfg, r = vg
     whole = gpu_run(wl, ckv.CKV_FP64)
