@@ -301,15 +301,19 @@ __device__ __forceinline__ void step_setup(const Args& a, int64_t i, Setup& st)
 // Mixed path: the hardware sine and cosine, which take their argument in turns:
 // the quadrant from the top two bits, the angle inside it as an FP32 number of
 // turns in [0, 1/4) (rounding below 1e-7 rad); errors near 1e-7, i.e. ~2e-9 in
-// the photon direction once scaled by sin(theta_c) < 0.03.
+// the photon direction once scaled by sin(theta_c) < 0.03.  The quadrant's
+// rotation, (s, c) = (sq, cq), (cq, -sq), (-sq, -cq), (-cq, sq) for q = 0..3, is
+// a swap on bit 30 of r and sign flips on bit 31 (sine) and on bit 31 of
+// r + 2^30 (cosine).
 // --------------------------------------------------------------------------
 __device__ __forceinline__ void sincos_turns_hw(uint32_t r, float& s, float& c)
 {
-    const uint32_t q = r >> 30;
     const float t = fmaf((float)(r & 0x3FFFFFFFu), 2.3283064365386963e-10f, 1.16415321826934814e-10f);
     const float sq = __builtin_amdgcn_sinf(t), cq = __builtin_amdgcn_cosf(t);
-    c = (q == 0) ? cq : (q == 1) ? -sq : (q == 2) ? -cq : sq;
-    s = (q == 0) ? sq : (q == 1) ? cq : (q == 2) ? -sq : -cq;
+    const bool swap = (r & 0x40000000u) != 0;
+    const uint32_t s0 = __float_as_uint(swap ? cq : sq), c0 = __float_as_uint(swap ? sq : cq);
+    s = __uint_as_float(s0 ^ (r & 0x80000000u));
+    c = __uint_as_float(c0 ^ ((r + 0x40000000u) & 0x80000000u));
 }
 
 // The same in FP64 for the FP64 path: quadrant and half-quadrant fold from the
