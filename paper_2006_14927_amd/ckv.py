@@ -709,8 +709,9 @@ class SoftModel:
         ws = workspace_size(self.dsegs.n, self.dsegs.n_showers, self.tels.n, 0, self.params)
         self.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
         n_nodes = self.atmo0.info()[0]
-        self.g_psi = torch.empty(n_nodes, dtype=torch.float64, device=device)
-        self.g_P = torch.empty(5 * n_nodes, dtype=torch.float64, device=device)
+        # dL/dpsi and dL/dP side by side: the backward brings both to the host in one copy
+        self._g = torch.empty(6 * n_nodes, dtype=torch.float64, device=device)
+        self.g_psi, self.g_P = self._g[:n_nodes], self._g[n_nodes:]
         self.shape = (self.dsegs.n_showers, self.tels.n)
         self._segs = self.dsegs.c_segments()
         self._showers = self.dsegs.c_showers()
@@ -722,6 +723,17 @@ class SoftModel:
         if self.use_list:
             cap = list_capacity if list_capacity is not None else int(self.n_b.sum()) // 8 + 1024
             self._alloc_list(int(cap))
+        # The conditions the soft kernels report (bad shower offsets; a 32-step tile
+        # with 2^30 or more frozen bunches) depend on the segments and the frozen
+        # counts only, not on theta: a tile's bunches at any theta are some of its
+        # steps' frozen counts, and a tile lies inside some window of 32 consecutive
+        # steps.  When no such window holds 2^30, one clean pass of each kind proves
+        # every later one clean, and those skip the check and its synchronisation.
+        cs = torch.cumsum(self.n_b, 0)
+        if cs.numel() > 32:
+            cs = torch.cat([cs[31:32], cs[32:] - cs[:-32]])
+        self._bound_holds = bool(cs.numel() == 0 or int(cs.max()) < (1 << 30))
+        self._clean = {"forward": False, "backward": False}
 
     def _alloc_list(self, capacity: int):
         import torch
@@ -758,11 +770,15 @@ class SoftModel:
 
     def _check_device(self, what: str):
         """Raises when the device reported bad shower offsets or an oversized tile
-        (synchronises with the stream)."""
+        (synchronises with the stream), until a clean pass of this kind proves the
+        model free of both."""
+        if self._clean[what]:
+            return
         err = RunOutput(None, None, None, self.result_raw).result()["error"]
         if err:
             raise CkvError(f"soft {what}: device reported error flags {err} "
                            "(1: bad seg_offsets, 2: a 32-step tile with >= 2^30 frozen bunches)")
+        self._clean[what] = self._bound_holds
 
     def backward_tables(self, theta, gS, gA, stream=None):
         """Device dL/dpsi (n_nodes) and dL/dP (5 x n_nodes)."""
@@ -802,7 +818,9 @@ class SoftModel:
         g_psi, g_P = self.backward_tables(theta, gS, gA, stream)
         torch.cuda.synchronize()
         self.grow_list()
-        return self.spec.backward(theta, self._atmo(theta), g_psi.cpu().numpy(), g_P.cpu().numpy())
+        g = self._g.cpu().numpy()
+        n = g_psi.numel()
+        return self.spec.backward(theta, self._atmo(theta), g[:n], g[n:])
 
 
 def _soft_function():

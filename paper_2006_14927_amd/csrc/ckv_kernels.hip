@@ -1840,10 +1840,13 @@ __global__ void __launch_bounds__(64) tile_prefix_kernel(Args a)
             }
         wave_lds_sync();
         for (int64_t t = t0; t < t1; ++t) {
+            // the tile's count, offset and first slot from its lane (a uniform lane
+            // index: a register read, not an LDS round trip)
             const int j = (int)(t - t0);
-            const int nj = __shfl(n, j);
-            const int64_t offj = __shfl(off, j);
-            const int bj = __shfl(my0, j);
+            const int nj = __builtin_amdgcn_readlane(n, j);
+            const int64_t offj = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(off >> 32), j) << 32) |
+                                           (uint32_t)__builtin_amdgcn_readlane((int)off, j));
+            const int bj = __builtin_amdgcn_readlane(my0, j);
             for (int i = lane; i < nj; i += kWave) {
                 const int64_t r = in_lds ? buf[bj + i] : a.runs[offj + i];
                 const int tel = (int)(r >> kRunTelShift);
@@ -1862,6 +1865,70 @@ __global__ void __launch_bounds__(64) tile_prefix_kernel(Args a)
                 if (q < total) a.runs[off_j + (q - first_j)] = buf[q];
             }
         wave_lds_sync();
+    }
+}
+
+// D, for at most kPrefixDenseTel telescopes: per row block, one workgroup.  The
+// block's runs go into a dense tiles x telescopes count matrix in LDS, each
+// telescope's column is scanned from the crossings of earlier blocks, and each run
+// takes its entry.  Nothing is serial over the block's tiles but one register sum
+// per column, so the block costs a few memory round trips instead of a chain of
+// LDS round trips per tile.
+constexpr int kPrefixDenseTel = 128;
+
+__global__ void __launch_bounds__(256) tile_prefix_dense_kernel(Args a)
+{
+    extern __shared__ int32_t mat[];               // kRowBlock x n_tel, row = tile
+    __shared__ int64_t s_incl[kRowBlock], s_off[kRowBlock];
+    const int tid = threadIdx.x, nt = a.n_tel;
+    const int64_t cutb = a.ctrl[kCutBlocks], cut = a.ctrl[kCutTile];
+    for (int64_t b = blockIdx.x; b < cutb; b += gridDim.x) {
+        int s;
+        int64_t t0, t1;
+        block_tiles(a, b, s, t0, t1);
+        t1 = min(t1, cut);
+        const int ntl = (int)(t1 - t0);
+        if (tid < kWave) {
+            // lane l: tile t0 + l; inclusive run counts over the block's tiles
+            const bool mine = tid < ntl;
+            const int n = mine ? a.tile_run_n[t0 + tid] : 0;
+            s_off[tid] = mine ? a.tile_run_off[t0 + tid] : 0;
+            s_incl[tid] = wave_incl_scan((int64_t)n);
+        }
+        for (int q = tid; q < ntl * nt; q += blockDim.x) mat[q] = 0;
+        __syncthreads();
+        const int64_t total = s_incl[kRowBlock - 1];
+        // the block's runs in flat order: run q's tile is the first whose inclusive
+        // count passes q
+        for (int64_t q = tid; q < total; q += blockDim.x) {
+            int j = 0;
+            for (int step = kRowBlock / 2; step > 0; step >>= 1)
+                if (s_incl[j + step - 1] <= q) j += step;
+            const int64_t first = j ? s_incl[j - 1] : 0;
+            const int64_t r = a.runs[s_off[j] + (q - first)];
+            mat[j * nt + (int)(r >> kRunTelShift)] = (int32_t)(r & kRunValueMask);
+        }
+        __syncthreads();
+        // exclusive scan down each telescope's column
+        for (int k = tid; k < nt; k += blockDim.x) {
+            int32_t acc = a.block_sums[(int64_t)k * a.max_row_blocks + b];
+            for (int j = 0; j < ntl; ++j) {
+                const int32_t v = mat[j * nt + k];
+                mat[j * nt + k] = acc;
+                acc += v;
+            }
+        }
+        __syncthreads();
+        for (int64_t q = tid; q < total; q += blockDim.x) {
+            int j = 0;
+            for (int step = kRowBlock / 2; step > 0; step >>= 1)
+                if (s_incl[j + step - 1] <= q) j += step;
+            const int64_t first = j ? s_incl[j - 1] : 0;
+            const int64_t g = s_off[j] + (q - first);
+            const int tel = (int)(a.runs[g] >> kRunTelShift);
+            a.runs[g] = ((int64_t)tel << kRunTelShift) | mat[j * nt + tel];
+        }
+        __syncthreads();
     }
 }
 
@@ -2960,9 +3027,13 @@ int launch_run(RunPlan& p)
     if (int rc2 = check_launch("cutoff")) return rc2;
     rowblock_scan_kernel<<<fin_grid, 256, 0, st>>>(a);
     if (int rc2 = check_launch("rowblock_scan")) return rc2;
-    const size_t prefix_lds = (size_t)((a.n_tel + 1) & ~1) * sizeof(int32_t) +
-                              (size_t)kPrefixLdsRuns * sizeof(int64_t);
-    tile_prefix_kernel<<<fin_grid, kWave, prefix_lds, st>>>(a);
+    if (a.n_tel <= kPrefixDenseTel) {
+        tile_prefix_dense_kernel<<<fin_grid, 256, (size_t)kRowBlock * a.n_tel * sizeof(int32_t), st>>>(a);
+    } else {
+        const size_t prefix_lds = (size_t)((a.n_tel + 1) & ~1) * sizeof(int32_t) +
+                                  (size_t)kPrefixLdsRuns * sizeof(int64_t);
+        tile_prefix_kernel<<<fin_grid, kWave, prefix_lds, st>>>(a);
+    }
     if (int rc2 = check_launch("tile_prefix")) return rc2;
     csr_kernel<<<1, 1024, 0, st>>>(a);
     if (int rc2 = check_launch("csr")) return rc2;

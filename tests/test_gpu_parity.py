@@ -384,6 +384,24 @@ def test_maximum_telescope_count(precision):
     say(f"[gpu] 1024 telescopes prec={precision}: {rep}")
 
 
+@pytest.mark.parametrize("n_tel", [128, 129])
+def test_tile_prefix_forms_on_either_side_of_the_switch(n_tel):
+    """Up to 128 spheres the per-tile crossing prefix runs as a dense tiles x
+    spheres matrix in LDS, above as a walk over the tiles: offsets and records are
+    the oracle's on both sides."""
+    wl = synth.vertical_gamma(6000)
+    wl.tels = synth.telescopes_disk(n=n_tel, disk_radius=300.0, seed=n_tel)
+    cfg = oracle.Config.from_workload(wl)
+    ores = oracle.run(cfg, wl.segs, nthreads=16)
+    g = gpu_run(wl, ckv.CKV_FP64)
+    res = g["result"]
+    assert res["error"] == 0 and res["overflow"] == 0 and res["n_bunches"] == ores.n_bunches
+    np.testing.assert_array_equal(g["offsets"], ores.offsets)
+    rep = compare_records(wl, cfg, ores, g, ckv.CKV_FP64)
+    assert rep["matched"] > 10_000
+    say(f"[gpu] {n_tel} telescopes: {rep}")
+
+
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_step_ids_keep_bunches_when_steps_are_reordered(precision):
     """Steps sorted by start altitude, with their generator-order indices as step
