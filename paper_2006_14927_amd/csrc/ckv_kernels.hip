@@ -1976,42 +1976,119 @@ __global__ void __launch_bounds__(1024) csr_kernel(Args a)
     }
 }
 
-// F: scatter the staged records of the written tiles to their final slots
+// F: scatter the staged records of the written tiles to their final slots.  A
+// slot's place is its (shower, telescope) offset, plus its telescope's crossings
+// in earlier tiles of the shower (its run's value), plus its rank in the tile.
+// Each thread takes kScatterSlots slots a round and issues the loads that do not
+// depend on one another together: the block fills, then the entries (record and
+// placement at once), then the tile's run list, the shower's offset and the
+// shower (tile bounds staged in LDS for up to kScatterShowerLds showers), then the
+// searches over the runs side by side.
+constexpr int kScatterSlots = 2;
+constexpr int kScatterShowerLds = 2048;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // plain 16-byte vector
+
+struct ScatterSlot {
+    u32x4 rec0, rec1, meta;
+    int64_t off, base;
+    int n, tel, shower, lo, len;
+    bool live;
+};
+
+__device__ __forceinline__ void scatter_fill(const Args& a, ScatterSlot& x, int64_t q, int64_t nslots)
+{
+    const int64_t b = q < nslots ? q / kStageBlock : 0;
+    x.live = q < nslots && (int)(q - b * kStageBlock) < a.stage_fill[b];
+}
+
+// (a slot that is not live reads slot 0, which every such slot shares)
+__device__ __forceinline__ void scatter_entry(const Args& a, ScatterSlot& x, int64_t q)
+{
+    const u32x4* e = reinterpret_cast<const u32x4*>(a.stage + (x.live ? q : 0));
+    x.rec0 = e[0];
+    x.rec1 = e[1];
+    x.meta = e[2];
+}
+
+__device__ __forceinline__ void scatter_tile(const Args& a, ScatterSlot& x, const int64_t* before, int64_t cut)
+{
+    const int64_t tile = x.meta.x;
+    x.tel = (int)(x.meta.y & 0xFFFFu);
+    x.live = x.live && tile < cut && x.tel < a.n_tel;
+    x.n = 0;
+    x.lo = 0;
+    if (x.live) {
+        x.shower = find_shower(before, a.n_showers, tile);
+        x.off = a.tile_run_off[tile];
+        x.n = a.tile_run_n[tile];
+        x.base = a.tel_offsets[(int64_t)x.shower * a.n_tel + x.tel];
+    }
+    x.len = x.n;
+}
+
+// one halving step of the search for the tile's run of the slot's telescope (runs
+// ascend by telescope)
+__device__ __forceinline__ void scatter_halve(const Args& a, ScatterSlot& x)
+{
+    if (x.len > 1) {
+        const int half = x.len >> 1;
+        if ((int)(a.runs[x.off + x.lo + half] >> kRunTelShift) <= x.tel) x.lo += half;
+        x.len -= half;
+    }
+}
+
+__device__ __forceinline__ void scatter_store(const Args& a, const ScatterSlot& x, const int64_t* before)
+{
+    if (!x.live || x.n <= 0) return;
+    const int64_t r = a.runs[x.off + x.lo];
+    if ((int)(r >> kRunTelShift) != x.tel) return;
+    const int64_t pos = x.base + (r & kRunValueMask) + x.meta.z;
+    if (pos < 0 || pos >= a.capacity) return;
+    u32x4* dst = reinterpret_cast<u32x4*>(a.records + 8 * pos);
+    dst[0] = x.rec0;
+    dst[1] = x.rec1;
+    if (a.ids) {
+        const int s = x.shower;
+        a.ids[2 * pos] = a.shower_first[s] + ((int64_t)x.meta.x - before[s]) * (int64_t)a.tile_segs +
+                         (int)(x.meta.y >> 16);
+        a.ids[2 * pos + 1] = x.meta.w;
+    }
+}
+
+__device__ __forceinline__ void scatter_pair(const Args& a, const int64_t* before, int64_t q0,
+                                             int64_t stride, int64_t nslots, int64_t cut)
+{
+    ScatterSlot x, y;
+    const int64_t q1 = q0 + stride;
+    scatter_fill(a, x, q0, nslots);
+    scatter_fill(a, y, q1, nslots);
+    scatter_entry(a, x, q0);
+    scatter_entry(a, y, q1);
+    scatter_tile(a, x, before, cut);
+    scatter_tile(a, y, before, cut);
+    while (x.len > 1 || y.len > 1) {
+        scatter_halve(a, x);
+        scatter_halve(a, y);
+    }
+    scatter_store(a, x, before);
+    scatter_store(a, y, before);
+}
+
 __global__ void __launch_bounds__(256) scatter_kernel(Args a)
 {
+    __shared__ int64_t s_before[kScatterShowerLds + 1];
+    const bool lds_showers = a.n_showers <= kScatterShowerLds;
+    if (lds_showers)
+        for (int q = threadIdx.x; q <= a.n_showers; q += blockDim.x) s_before[q] = a.tiles_before[q];
+    __syncthreads();
     const int64_t cut = a.ctrl[kCutTile];
     const int64_t nblk = min(a.ctrl[kBlockCounter], a.stage_blocks);
     const int64_t nslots = nblk * kStageBlock;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nslots;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = q / kStageBlock;
-        if ((int)(q - b * kStageBlock) >= a.stage_fill[b]) continue;
-        const StageEntry* e = a.stage + q;
-        const uint4 meta = reinterpret_cast<const uint4*>(e)[2];
-        const int64_t tile = meta.x;
-        const int tel = (int)(meta.y & 0xFFFFu), sidx = (int)(meta.y >> 16);
-        if (tile >= cut || tel >= a.n_tel) continue;
-        const int s = find_shower(a.tiles_before, a.n_showers, tile);
-        // the tile's run of this telescope (runs ascend by telescope)
-        const int64_t off = a.tile_run_off[tile];
-        int lo = 0, hi = a.tile_run_n[tile];
-        if (hi <= 0) continue;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if ((int)(a.runs[off + mid] >> kRunTelShift) <= tel) lo = mid; else hi = mid;
-        }
-        const int64_t r = a.runs[off + lo];
-        if ((int)(r >> kRunTelShift) != tel) continue;
-        const int64_t pos = a.tel_offsets[(int64_t)s * a.n_tel + tel] + (r & kRunValueMask) + meta.z;
-        if (pos < 0 || pos >= a.capacity) continue;
-        const float4* src = reinterpret_cast<const float4*>(e);
-        float4* dst = reinterpret_cast<float4*>(a.records + 8 * pos);
-        dst[0] = src[0];
-        dst[1] = src[1];
-        if (a.ids) {
-            a.ids[2 * pos] = a.shower_first[s] + (tile - a.tiles_before[s]) * (int64_t)a.tile_segs + sidx;
-            a.ids[2 * pos + 1] = meta.w;
-        }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q0 < nslots; q0 += kScatterSlots * stride) {
+        if (lds_showers) scatter_pair(a, s_before, q0, stride, nslots, cut);
+        else scatter_pair(a, a.tiles_before, q0, stride, nslots, cut);
     }
 }
 
