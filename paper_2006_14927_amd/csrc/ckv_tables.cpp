@@ -275,21 +275,24 @@ void param_backward(const ckv_atmo_param_spec* sp, const double* theta, const ck
     const int64_t m = a->n_nodes;
     const double step = a->step;
     std::vector<double> gpsi(g_psi, g_psi + m);
-    for (int j = 1; j <= 5; ++j) {
-        const double* gp = g_P + (size_t)(j - 1) * m;
-        double suffix = 0.0;                       // sum of g_P over nodes i >= c + 1
-        for (int64_t c = m - 2; c >= 0; --c) {
-            suffix += gp[c + 1];
-            const double lo = a->psi[c], hi = a->psi[c + 1];
-            // d h_j / d lo and d h_j / d hi
+    double suffix[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // per j: sum of g_P_j over nodes >= c + 1
+    for (int64_t c = m - 2; c >= 0; --c) {
+        const double lo = a->psi[c], hi = a->psi[c + 1];
+        double pl[5], ph[5];                       // lo^k, hi^k for k < 5
+        pl[0] = ph[0] = 1.0;
+        for (int k = 1; k < 5; ++k) {
+            pl[k] = pl[k - 1] * lo;
+            ph[k] = ph[k - 1] * hi;
+        }
+        for (int j = 1; j <= 5; ++j) {
+            suffix[j] += g_P[(size_t)(j - 1) * m + c + 1];
+            // d h_j / d lo and d h_j / d hi, h_j(lo, hi) = sum_q lo^(j-q) hi^q
             double dlo = 0.0, dhi = 0.0;
-            for (int q = 0; q <= j; ++q) {
-                if (j - q >= 1) dlo += (double)(j - q) * std::pow(lo, j - q - 1) * std::pow(hi, q);
-                if (q >= 1) dhi += (double)q * std::pow(lo, j - q) * std::pow(hi, q - 1);
-            }
+            for (int q = 0; q < j; ++q) dlo += (double)(j - q) * pl[j - q - 1] * ph[q];
+            for (int q = 1; q <= j; ++q) dhi += (double)q * pl[j - q] * ph[q - 1];
             const double w = step / (double)(j + 1);
-            gpsi[c] += suffix * w * dlo;
-            gpsi[c + 1] += suffix * w * dhi;
+            gpsi[c] += suffix[j] * w * dlo;
+            gpsi[c + 1] += suffix[j] * w * dhi;
         }
     }
     const int32_t nk = sp->n_knots, nl = sp->n_layers;

@@ -35,6 +35,26 @@ def test_batched_showers_parity(batched, precision):
     say(f"[gpu] batched prec={precision}: tiles={res['n_tiles']} {rep}")
 
 
+@pytest.mark.parametrize("precision", [ckv.CKV_FP64, ckv.CKV_MIXED])
+def test_more_showers_than_the_scatter_stages(precision):
+    """2100 showers of 1..160 steps: more than the 2048 whose tile bounds the scatter
+    keeps in LDS, so it finds each record's shower in HBM; offsets, ids and records
+    are still the oracle's."""
+    wl = synth.batched_showers(2100, seg_scale=4e-5)
+    assert wl.segs.n_showers == 2100
+    cfg = oracle.Config.from_workload(wl)
+    r = oracle.run(cfg, wl.segs, nthreads=8)
+    g = gpu_run(wl, precision)
+    res = g["result"]
+    assert res["error"] == 0 and res["overflow"] == 0
+    assert res["n_bunches"] == r.n_bunches and res["drops"] == r.drops
+    if precision == ckv.CKV_FP64:
+        np.testing.assert_array_equal(g["offsets"], r.offsets)
+    rep = compare_records(wl, cfg, r, g, precision)
+    assert rep["matched"] > 40_000
+    say(f"[gpu] 2100 showers prec={precision}: {rep}")
+
+
 def test_graph_replays_match_eager(batched):
     import torch
     wl, cfg, r = batched
