@@ -810,11 +810,21 @@ __device__ __forceinline__ TileSetup tile_setup(const Args& a, int64_t g0, int n
 // registers and the step arrays' pointers then take no room in the bunch loop,
 // 100 -> 8 scalar spills; the FP64 kernel, with 256 registers, runs faster inline).
 template <int PREC, int TS, int FEAT>
-__device__ __noinline__ TileSetup tile_setup_call(const Args& a, int64_t g0, int nseg, int64_t seg_id0,
-                                                  int lane, uint64_t lt_mask, StepEntry<PREC>* stash,
-                                                  uint32_t* sctr, int64_t* wcnt, int64_t* lst)
+__device__ __noinline__ TileSetup tile_setup_call(uint64_t args_at, int64_t g0, int nseg, int64_t seg_id0,
+                                                  int lane, uint64_t lt_mask, uint32_t stash_at,
+                                                  uint32_t sctr_at, uint32_t wcnt_at, uint32_t lst_at)
 {
-    return tile_setup<PREC, TS, FEAT>(a, g0, nseg, seg_id0, lane, lt_mask, stash, sctr, wcnt, lst);
+    extern __shared__ __align__(16) unsigned char lds[];
+    // the launch's argument block, at the address the kernel passes: wave-uniform and
+    // read-only, so the setup reads it with scalar loads
+    const uint64_t at_u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(args_at >> 32)) << 32) |
+                          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)args_at);
+    const Args& a = *(const Args*)reinterpret_cast<const __attribute__((address_space(4))) Args*>(at_u);
+    return tile_setup<PREC, TS, FEAT>(a, g0, nseg, seg_id0, lane, lt_mask,
+                                      reinterpret_cast<StepEntry<PREC>*>(lds + stash_at),
+                                      reinterpret_cast<uint32_t*>(lds + sctr_at),
+                                      reinterpret_cast<int64_t*>(lds + wcnt_at),
+                                      reinterpret_cast<int64_t*>(lds + lst_at));
 }
 
 template <int PREC, int TS, int FEAT>
@@ -1054,9 +1064,10 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
         // launch put them (the kernel argument segment) rather than a private copy.
         TileSetup ts_;
         if constexpr (PREC == 1) {
-            const Args& ka = *(const Args*)__builtin_amdgcn_kernarg_segment_ptr();
-            ts_ = tile_setup_call<PREC, TS, FEAT>(ka, g0, nseg, seg_id0, lane, lt_mask, stash, sctr, wcnt,
-                                                  lst);
+            auto at = [&](const void* p) { return (uint32_t)((const unsigned char*)p - lds); };
+            const uint64_t args_at = (uint64_t)__builtin_amdgcn_kernarg_segment_ptr();
+            ts_ = tile_setup_call<PREC, TS, FEAT>(args_at, g0, nseg, seg_id0, lane, lt_mask, at(stash), at(sctr),
+                                                  at(wcnt), at(lst));
         } else {
             ts_ = tile_setup<PREC, TS, FEAT>(a, g0, nseg, seg_id0, lane, lt_mask, stash, sctr, wcnt, lst);
         }
