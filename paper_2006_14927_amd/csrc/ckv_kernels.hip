@@ -611,28 +611,37 @@ constexpr unsigned long long kSoftListInvalid = 1ull << 62;   // or-ed into the 
 // their slots; lane q writes the ids of word q, the step of its first bunch found
 // by binary search over the tile's stash (first-bunch offsets ascend) and the
 // later ones by moving forward from there (the lanes' searches overlap; this
-// measured faster than word-by-word writes with consecutive slots).  lst holds
+// measured faster than word-by-word writes with consecutive slots).  lst (its
+// offset in the dynamic LDS, as for bits and stash) holds
 // {tile's first step, ids, capacity, count, tile's emitting steps}.  Called by
 // the whole wave.
 template <typename E>
-__device__ __noinline__ void soft_list_flush(const int64_t* lst, const uint64_t* bits,
-                                                const E* stash, int64_t j0, int nw, int lane)
+__device__ __noinline__ void soft_list_flush(uint32_t lst_at, uint32_t bits_at, uint32_t stash_at, int64_t j0,
+                                             int nw, int lane)
 {
-    volatile const int64_t* vl = lst;
+    // the wave's areas, by their offsets in the dynamic LDS (LDS accesses, not
+    // generic ones)
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int64_t* lst = reinterpret_cast<const int64_t*>(lds + lst_at);
+    const uint64_t* bits = reinterpret_cast<const uint64_t*>(lds + bits_at);
+    const E* stash = reinterpret_cast<const E*>(lds + stash_at);
+    // (the caller's lane 0 wrote lst before the call; the wave's LDS accesses are in order)
+    const int64_t l_g0 = lst[0], l_ids = lst[1], l_cap = lst[2], l_count = lst[3], l_emit = lst[4];
     uint64_t word = lane < nw ? bits[lane] : 0ull;
     const int c = __popcll(word);
     const int64_t incl = wave_incl_scan((int64_t)c);
     const int64_t tot = __shfl(incl, kWave - 1);
     if (tot == 0) return;
-    unsigned long long* count = (unsigned long long*)vl[3];
+    using GU64 = __attribute__((address_space(1))) unsigned long long;
+    unsigned long long* count = (unsigned long long*)reinterpret_cast<GU64*>(l_count);
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(count, (unsigned long long)tot);
     base = __shfl(base, 0);
-    const int64_t g0 = vl[0], cap = vl[2];
-    uint64_t* ids = (uint64_t*)vl[1];
+    const int64_t g0 = l_g0, cap = l_cap;
+    uint64_t* ids = (uint64_t*)reinterpret_cast<GU64*>(l_ids);
     int64_t slot = (int64_t)base + (incl - c);
     if (!word) return;
-    const int n_emit = (int)vl[4];
+    const int n_emit = (int)l_emit;
     const int32_t jw = (int32_t)(j0 + kWave * lane);     // bunch of bit 0
     int32_t jj = jw + __builtin_ctzll(word);
     int lo = 0, hi = n_emit;
@@ -1351,7 +1360,9 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                 if (lane == 0) bits[w] = m;
                 if (w == kScreenWords - 1 || c0 + kWave >= total) {
                     wave_lds_sync();
-                    soft_list_flush(lst, bits, stash, c0 - (int64_t)w * kWave, w + 1, lane);
+                    soft_list_flush<Entry>((uint32_t)((unsigned char*)lst - lds), (uint32_t)((unsigned char*)bits - lds),
+                                           (uint32_t)((unsigned char*)stash - lds), c0 - (int64_t)w * kWave, w + 1,
+                                           lane);
                 }
             } else {
                 // ---- the records of the crossing bunches.  About one chunk in five holds
