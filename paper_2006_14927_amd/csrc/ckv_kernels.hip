@@ -109,6 +109,31 @@ struct Args {
     int64_t* list_count;
 };
 
+// Memory accesses whose address space is explicit.  Where one access may go to LDS
+// or to HBM, a generic pointer makes the compiler use one generic (flat)
+// instruction for both, which costs every access, also the LDS ones; reads and
+// atomics through these types keep the two kinds apart.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+using LdsF64 = __attribute__((address_space(3))) double;
+using HbmF64 = __attribute__((address_space(1))) double;
+using LdsF32x4 = __attribute__((address_space(3))) f32x4;
+using HbmF32x4 = __attribute__((address_space(1))) f32x4;
+
+__device__ __forceinline__ const LdsF64* as_lds(const double* p) { return (const LdsF64*)p; }
+__device__ __forceinline__ const HbmF64* as_hbm(const double* p) { return (const HbmF64*)p; }
+__device__ __forceinline__ const LdsF32x4* as_lds4(const float* p) { return (const LdsF32x4*)p; }
+__device__ __forceinline__ const HbmF32x4* as_hbm4(const float* p) { return (const HbmF32x4*)p; }
+
+__device__ __forceinline__ void lds_add(double* p, double v)
+{
+    __hip_atomic_fetch_add((LdsF64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void hbm_add(double* p, double v)
+{
+    __hip_atomic_fetch_add((HbmF64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // --------------------------------------------------------------------------
 // wave helpers
 // --------------------------------------------------------------------------
@@ -934,7 +959,11 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
     auto cell_moments = [&](int ci, T f, double dcell_) {
         T psi_i, dpsi, P0, P1, P2, P3, P4, P5;
         // LDS read always (index clamped into the staged part); the rare
-        // lookups above it are replaced by a read from HBM
+        // lookups above it are replaced by a read from HBM.  The FP32 table's two
+        // reads go through their own address spaces, so the compiler cannot fuse
+        // them into one generic (flat) load for every lookup.  The FP64 narrow build
+        // keeps the fused generic load: typed, it spills more and runs 0.5 %
+        // slower.
         if (PREC == 0) {
             double n0[6], n1;
             {
@@ -944,8 +973,6 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                 n1 = nd[kNode64];
             }
             if (PARTIAL && ci + 1 >= a.lds_entries) {
-                // a distinct load kind keeps the compiler from fusing the two
-                // reads into one generic (flat) load of a selected address
                 const double* nd = a.node64 + (size_t)kNode64 * ci;
                 for (int q = 0; q < 6; ++q) n0[q] = __builtin_nontemporal_load(nd + q);
                 n1 = __builtin_nontemporal_load(nd + kNode64);
@@ -955,21 +982,17 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
             P0 = SEARCH ? hn_lds[ci] - a.h_obs : (double)ci * a.step;
             P1 = n0[1]; P2 = n0[2]; P3 = n0[3]; P4 = n0[4]; P5 = n0[5];
         } else {
-            float4 c_a, c_b;
+            f32x4 c_a, c_b;
             {
                 const int cl = PARTIAL ? min(ci, a.lds_entries - 1) : ci;
-                const float4* cc = reinterpret_cast<const float4*>(tab32 + (size_t)kCell32 * cl);
+                const LdsF32x4* cc = as_lds4(tab32 + (size_t)kCell32 * cl);
                 c_a = cc[0];
                 c_b = cc[1];
             }
             if (PARTIAL && ci >= a.lds_entries) {
-                // a distinct load kind keeps the compiler from fusing the two
-                // reads into one generic (flat) load of a selected address
-                const float* cg = a.cell32 + (size_t)kCell32 * ci;
-                c_a = make_float4(__builtin_nontemporal_load(cg), __builtin_nontemporal_load(cg + 1),
-                                  __builtin_nontemporal_load(cg + 2), __builtin_nontemporal_load(cg + 3));
-                c_b = make_float4(__builtin_nontemporal_load(cg + 4), __builtin_nontemporal_load(cg + 5),
-                                  __builtin_nontemporal_load(cg + 6), __builtin_nontemporal_load(cg + 7));
+                const HbmF32x4* cg = as_hbm4(a.cell32 + (size_t)kCell32 * ci);
+                c_a = cg[0];
+                c_b = cg[1];
             }
             psi_i = c_a.x; dpsi = c_a.y; P1 = c_a.z; P2 = c_a.w;
             P3 = c_b.x; P4 = c_b.y; P5 = c_b.z;
@@ -2248,8 +2271,14 @@ __device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, Sof
     if (im > a.n_nodes - 2) im = a.n_nodes - 2;
     const double fm = x - (double)im;
     // psi at the two nodes: from the LDS copy of the lowest nodes when it holds them
-    const double* nd = im + 1 < n_lds ? node_lds : a.node64;
-    const double lo = nd[kNode64 * im], hi = nd[kNode64 * (im + 1)];
+    double lo, hi;
+    if (im + 1 < n_lds) {
+        lo = as_lds(node_lds)[kNode64 * im];
+        hi = as_lds(node_lds)[kNode64 * (im + 1)];
+    } else {
+        lo = as_hbm(a.node64)[kNode64 * im];
+        hi = as_hbm(a.node64)[kNode64 * (im + 1)];
+    }
     const double psi = lo + fm * (hi - lo);
     const double n2 = 1.0 + psi;
     const double num = psi - n2 * r2;
@@ -2293,7 +2322,7 @@ __device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, Sof
 // dL/dsin_t, dL/dphotons) in o_cos, o_sin, o_phot.  Returns true when some
 // sphere has z >= -kSoftZCut, i.e. the bunch enters S, A and the gradient.
 // NODE_LDS: node records of the lowest n_lds nodes come from node_lds (LDS).
-template <int MODE, bool NODE_LDS, typename AddBin>
+template <int MODE, bool NODE_LDS, bool ACC_LDS, typename AddBin>
 __device__ __forceinline__ bool soft_bunch(const Args& a, const SoftArgs& sa, const SoftStep& e,
                                            int32_t k, uint32_t seg_id, uint32_t shower_id, int s,
                                            double t_ref, const double* tsh, double* acc,
@@ -2333,21 +2362,16 @@ __device__ __forceinline__ bool soft_bunch(const Args& a, const SoftArgs& sa, co
     const double fe = x - (double)ie;
     double pa, pb, X1, X2, X3, X4, X5;
     if (NODE_LDS) {
-        // the LDS copy is read always (index clamped into it); a cell above it is
-        // read again from HBM with a distinct load kind, which keeps the compiler
-        // from fusing the two reads into one generic (flat) load
-        const double* nl = node_lds + (size_t)kNode64 * min(ie, n_lds - 2);
-        pa = nl[0]; X1 = nl[1]; X2 = nl[2]; X3 = nl[3]; X4 = nl[4]; X5 = nl[5];
-        pb = nl[kNode64];
-        if (ie + 1 >= n_lds) {
-            const double* nd = a.node64 + (size_t)kNode64 * ie;
-            pa = __builtin_nontemporal_load(nd);
-            X1 = __builtin_nontemporal_load(nd + 1);
-            X2 = __builtin_nontemporal_load(nd + 2);
-            X3 = __builtin_nontemporal_load(nd + 3);
-            X4 = __builtin_nontemporal_load(nd + 4);
-            X5 = __builtin_nontemporal_load(nd + 5);
-            pb = __builtin_nontemporal_load(nd + kNode64);
+        // the cell from the LDS copy when it holds it, else from HBM, each through
+        // its own address space (no generic load)
+        if (ie + 1 < n_lds) {
+            const LdsF64* nl = as_lds(node_lds) + (size_t)kNode64 * ie;
+            pa = nl[0]; X1 = nl[1]; X2 = nl[2]; X3 = nl[3]; X4 = nl[4]; X5 = nl[5];
+            pb = nl[kNode64];
+        } else {
+            const HbmF64* nd = as_hbm(a.node64) + (size_t)kNode64 * ie;
+            pa = nd[0]; X1 = nd[1]; X2 = nd[2]; X3 = nd[3]; X4 = nd[4]; X5 = nd[5];
+            pb = nd[kNode64];
         }
     } else {
         const double* nd = a.node64 + (size_t)kNode64 * ie;
@@ -2425,8 +2449,13 @@ __device__ __forceinline__ bool soft_bunch(const Args& a, const SoftArgs& sa, co
         seen = true;
         const double W = 0.5 * erfc(-z * inv_sqrt2);
         if (MODE == 0) {
-            atomicAdd(&acc[kt], p * W);
-            atomicAdd(&accA[kt], p * W * tt);
+            if (ACC_LDS) {
+                lds_add(&acc[kt], p * W);
+                lds_add(&accA[kt], p * W * tt);
+            } else {
+                hbm_add(&acc[kt], p * W);
+                hbm_add(&accA[kt], p * W * tt);
+            }
         } else {
             const double gSk = sa.gS[(int64_t)s * a.n_tel + kt];
             const double gAk = sa.gA[(int64_t)s * a.n_tel + kt];
@@ -2558,8 +2587,8 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
     __syncthreads();
     // j = 0: dL/dpsi_i, j = 1..5: dL/dP_j(h_i)
     auto add_bin = [&](int j, int i, double v) {
-        if (i < NB) atomicAdd(&bins[j * NB + i], v);
-        else atomicAdd(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
+        if (i < NB) lds_add(&bins[j * NB + i], v);
+        else hbm_add(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
     };
 
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -2625,14 +2654,14 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
                 SoftStep& e = stash[si];
                 const int32_t k = j - e.boff;
                 double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
-                soft_bunch<MODE, MODE == 0>(a, sa, e, k, e.ctr1, shower_id,
+                soft_bunch<MODE, MODE == 0, true>(a, sa, e, k, e.ctr1, shower_id,
                                                    s, t_ref, tsh, acc, acc + a.n_tel, add_bin, inv_nobs,
                                                    half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin,
                                                    o_phot);
                 if (MODE == 1 && (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)) {
-                    atomicAdd(&e.g_cos, o_cos);
-                    atomicAdd(&e.g_sin, o_sin);
-                    atomicAdd(&e.g_phot, o_phot);
+                    lds_add(&e.g_cos, o_cos);
+                    lds_add(&e.g_sin, o_sin);
+                    lds_add(&e.g_phot, o_phot);
                 }
             }
         }
@@ -2692,13 +2721,16 @@ __device__ __forceinline__ bool listed_setup(const Args& a, const SoftArgs& sa, 
     if (head) {
         int hi = a.n_showers;                   // the shower holding step i
         if (shr) {
+            // the LDS table through its own address space (no generic loads)
+            using LdsRec = const __attribute__((address_space(3))) ShowerRec;
+            LdsRec* sh = (LdsRec*)shr;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if (shr[mid].first <= i) lo = mid; else hi = mid;
+                if (sh[mid].first <= i) lo = mid; else hi = mid;
             }
-            c1 = a.step_id ? a.step_id[i] : (uint32_t)(shr[lo].ctr_base + i);
-            sid = shr[lo].id;
-            tr = shr[lo].t_ref;
+            c1 = a.step_id ? a.step_id[i] : (uint32_t)(sh[lo].ctr_base + i);
+            sid = sh[lo].id;
+            tr = sh[lo].t_ref;
         } else {
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
@@ -2775,8 +2807,8 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
     if (shr) stage_showers(a, shr);
     __syncthreads();
     auto add_bin = [&](int j, int i, double v) {
-        if (i < NB) atomicAdd(&bins[j * NB + i], v);
-        else atomicAdd(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
+        if (i < NB) lds_add(&bins[j * NB + i], v);
+        else hbm_add(j == 0 ? &sa.g_psi[i] : &sa.g_P[(size_t)(j - 1) * N + i], v);
     };
     const double inv_nobs = 1.0 / a.n_obs;
     const double half_inv_nobs3 = 0.5 * inv_nobs * inv_nobs * inv_nobs;
@@ -2798,7 +2830,7 @@ __global__ void __launch_bounds__(kSoftListThreads) soft_list_kernel(Args a, Sof
         if (listed_setup<true>(a, sa, id, q < n_ids, lane, shr, nlds, NL, e, lo, seg_id, shower_id,
                                t_ref, k)) {
             double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
-            soft_bunch<1, true>(a, sa, e, k, seg_id, shower_id, lo, t_ref, tsh, nullptr, nullptr,
+            soft_bunch<1, true, true>(a, sa, e, k, seg_id, shower_id, lo, t_ref, tsh, nullptr, nullptr,
                                 add_bin, inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin,
                                 o_phot);
             if (o_cos != 0.0 || o_sin != 0.0 || o_phot != 0.0)
@@ -2868,10 +2900,16 @@ __global__ void __launch_bounds__(kSoftCandThreads) soft_cand_kernel(Args a, Sof
         if (listed_setup<false>(a, sa, id, q < n_ids, lane, shr, nlds, NL, e, lo, seg_id, shower_id,
                                 t_ref, k)) {
             double o_cos = 0.0, o_sin = 0.0, o_phot = 0.0;
-            double* rowS = (sa.cand_lds_acc ? accS : sa.S) + (int64_t)lo * a.n_tel;
-            double* rowA = (sa.cand_lds_acc ? accA : sa.A) + (int64_t)lo * a.n_tel;
-            soft_bunch<0, true>(a, sa, e, k, seg_id, shower_id, lo, t_ref, tsh, rowS, rowA, no_bins,
-                                inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin, o_phot);
+            // S and A into the workgroup's LDS rows, or straight into HBM (a uniform
+            // choice; each branch keeps its address space)
+            if (sa.cand_lds_acc)
+                soft_bunch<0, true, true>(a, sa, e, k, seg_id, shower_id, lo, t_ref, tsh,
+                                          accS + (int64_t)lo * a.n_tel, accA + (int64_t)lo * a.n_tel, no_bins,
+                                          inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin, o_phot);
+            else
+                soft_bunch<0, true, false>(a, sa, e, k, seg_id, shower_id, lo, t_ref, tsh,
+                                           sa.S + (int64_t)lo * a.n_tel, sa.A + (int64_t)lo * a.n_tel, no_bins,
+                                           inv_nobs, half_inv_nobs3, nlds, NL, g_psi0, o_cos, o_sin, o_phot);
         }
         id = id_next;
     }
