@@ -281,10 +281,15 @@ __device__ __forceinline__ void step_setup(const Args& a, int64_t i, Setup& st)
     const double x0 = a.x0[i], y0 = a.y0[i], h0 = a.h0[i];
     const double u = a.u[i], v = a.v[i], w = a.w[i];
     const double L = a.len[i], t0 = a.t0[i], E = a.energy[i];
-    const bool finite = isfinite(x0) && isfinite(y0) && isfinite(h0) && isfinite(u) &&
-                        isfinite(v) && isfinite(w) && isfinite(L) && isfinite(t0) && isfinite(E);
-    if (!finite || !(L > 0.0)) { st.status = CKV_DROP_NONFINITE; return; }
     const double m = a.ptype[i] == CKV_MUON ? kMassMuon : kMassElectron;
+    // (E m is finite exactly when E is, m being a positive mass below 1 GeV; testing
+    // it, with every test evaluated (no short circuit), puts all the step's loads
+    // in one round)
+    const int n_finite = (int)isfinite(x0) + (int)isfinite(y0) + (int)isfinite(h0) + (int)isfinite(u) +
+                         (int)isfinite(v) + (int)isfinite(w) + (int)isfinite(L) + (int)isfinite(t0) +
+                         (int)isfinite(E * m);
+    const bool finite = n_finite == 9;
+    if (!finite || !(L > 0.0)) { st.status = CKV_DROP_NONFINITE; return; }
     const double r = m / E;
     const double r2 = r * r;                           // 1 - beta^2
     if (!(r2 < 1.0)) { st.status = CKV_DROP_MASS; return; }
