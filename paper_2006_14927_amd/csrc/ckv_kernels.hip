@@ -232,6 +232,7 @@ struct Setup {
     int64_t nb;
     double photons, cos_t, sin_t, ds, inv_bc;
     double b1x, b1y, b1z, b2x, b2y, b2z;
+    double x0, y0, h0, t0, u, v, w;   // the step's inputs as loaded (for its record)
 };
 
 __device__ __forceinline__ double psi_fp64(const Args& a, double h)
@@ -282,6 +283,7 @@ __device__ __forceinline__ void step_setup(const Args& a, int64_t i, Setup& st)
     const double u = a.u[i], v = a.v[i], w = a.w[i];
     const double L = a.len[i], t0 = a.t0[i], E = a.energy[i];
     const double m = a.ptype[i] == CKV_MUON ? kMassMuon : kMassElectron;
+    st.x0 = x0; st.y0 = y0; st.h0 = h0; st.t0 = t0; st.u = u; st.v = v; st.w = w;
     // (E m is finite exactly when E is, m being a positive mass below 1 GeV; testing
     // it, with every test evaluated (no short circuit), puts all the step's loads
     // in one round)
@@ -810,13 +812,25 @@ __device__ __forceinline__ TileSetup tile_setup(const Args& a, int64_t g0, int n
         const uint32_t ctr1 = a.step_id ? a.step_id[g] : (uint32_t)(seg_id0 + lane);
         if constexpr (PREC == 1) e.ctr1 = ctr1;
         else sctr[lane] = ctr1;
-        e.x0 = a.x0[g];
-        e.y0 = a.y0[g];
-        e.h0 = a.h0[g];
-        e.t0 = a.t0[g];
-        e.u = a.u[g];
-        e.v = a.v[g];
-        e.w = a.w[g];
+        if constexpr (PREC == 1 && (FEAT & kFeatProfile) == 0) {
+            // the called setup keeps the inputs it loaded rather than a second round
+            // (the profile build, short of registers, measured faster reloading)
+            e.x0 = st.x0;
+            e.y0 = st.y0;
+            e.h0 = st.h0;
+            e.t0 = st.t0;
+            e.u = st.u;
+            e.v = st.v;
+            e.w = st.w;
+        } else {
+            e.x0 = a.x0[g];
+            e.y0 = a.y0[g];
+            e.h0 = a.h0[g];
+            e.t0 = a.t0[g];
+            e.u = a.u[g];
+            e.v = a.v[g];
+            e.w = a.w[g];
+        }
         e.cos_t = st.cos_t;
         e.ds = st.ds;
         e.inv_bc = st.inv_bc;
