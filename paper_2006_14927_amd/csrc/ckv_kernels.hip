@@ -2276,10 +2276,13 @@ __device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, Sof
     const double x0 = a.x0[i], y0 = a.y0[i], h0 = a.h0[i];
     const double u = a.u[i], v = a.v[i], w = a.w[i];
     const double L = a.len[i], t0 = a.t0[i], E = a.energy[i];
-    if (!(isfinite(x0) && isfinite(y0) && isfinite(h0) && isfinite(u) && isfinite(v) &&
-          isfinite(w) && isfinite(L) && isfinite(t0) && isfinite(E)) || !(L > 0.0) || nb <= 0)
-        return false;
     const double m = a.ptype[i] == CKV_MUON ? kMassMuon : kMassElectron;
+    // every test evaluated (no short circuit) and the mass inside one of them
+    // (E m is finite exactly when E is): all the step's loads go out in one round
+    const int n_finite = (int)isfinite(x0) + (int)isfinite(y0) + (int)isfinite(h0) + (int)isfinite(u) +
+                         (int)isfinite(v) + (int)isfinite(w) + (int)isfinite(L) + (int)isfinite(t0) +
+                         (int)isfinite(E * m);
+    if (n_finite != 9 || !(L > 0.0) || nb <= 0) return false;
     const double r = m / E;
     const double r2 = r * r;
     if (!(r2 < 1.0)) return false;
