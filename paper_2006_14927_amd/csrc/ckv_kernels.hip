@@ -284,12 +284,11 @@ __device__ __forceinline__ void step_setup(const Args& a, int64_t i, Setup& st)
     const double L = a.len[i], t0 = a.t0[i], E = a.energy[i];
     const double m = a.ptype[i] == CKV_MUON ? kMassMuon : kMassElectron;
     st.x0 = x0; st.y0 = y0; st.h0 = h0; st.t0 = t0; st.u = u; st.v = v; st.w = w;
-    // (E m is finite exactly when E is, m being a positive mass below 1 GeV; testing
-    // it, with every test evaluated (no short circuit), puts all the step's loads
-    // in one round)
+    // (E c with c = m / 1 GeV in (0, 1) is finite exactly when E is; testing it, with
+    // every test evaluated (no short circuit), puts all the step's loads in one round)
     const int n_finite = (int)isfinite(x0) + (int)isfinite(y0) + (int)isfinite(h0) + (int)isfinite(u) +
                          (int)isfinite(v) + (int)isfinite(w) + (int)isfinite(L) + (int)isfinite(t0) +
-                         (int)isfinite(E * m);
+                         (int)isfinite(E * (m * 1e-3));
     const bool finite = n_finite == 9;
     if (!finite || !(L > 0.0)) { st.status = CKV_DROP_NONFINITE; return; }
     const double r = m / E;
@@ -2277,11 +2276,12 @@ __device__ inline bool soft_step_setup(const Args& a, int64_t i, int64_t nb, Sof
     const double u = a.u[i], v = a.v[i], w = a.w[i];
     const double L = a.len[i], t0 = a.t0[i], E = a.energy[i];
     const double m = a.ptype[i] == CKV_MUON ? kMassMuon : kMassElectron;
-    // every test evaluated (no short circuit) and the mass inside one of them
-    // (E m is finite exactly when E is): all the step's loads go out in one round
+    // every test evaluated (no short circuit) and the mass inside one of them (E c
+    // with c = m / 1 GeV in (0, 1) is finite exactly when E is): all the step's loads
+    // go out in one round
     const int n_finite = (int)isfinite(x0) + (int)isfinite(y0) + (int)isfinite(h0) + (int)isfinite(u) +
                          (int)isfinite(v) + (int)isfinite(w) + (int)isfinite(L) + (int)isfinite(t0) +
-                         (int)isfinite(E * m);
+                         (int)isfinite(E * (m * 1e-3));
     if (n_finite != 9 || !(L > 0.0) || nb <= 0) return false;
     const double r = m / E;
     const double r2 = r * r;
