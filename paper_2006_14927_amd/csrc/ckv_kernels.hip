@@ -139,7 +139,35 @@ __device__ __forceinline__ void hbm_add(double* p, double v)
 // --------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// x of the lane the DPP control CTRL names as source, in the rows ROWS enables; 0
+// where there is no source or the row is masked off
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int64_t dpp_take(int64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)x >> 32), CTRL, ROWS,
+                                                              0xf, false);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Inclusive sum of x over lanes 0..lane by DPP lane moves (no LDS round trips):
+// shifts by 1, 2, 4 and 8 inside each row of 16 lanes, then lane 15 of rows 0 and 2
+// into rows 1 and 3 (row_bcast:15), then lane 31 into rows 2 and 3 (row_bcast:31).
+// Called by the whole wave.
 __device__ __forceinline__ int64_t wave_incl_scan(int64_t x)
+{
+    x += dpp_take<0x111, 0xf>(x);   // row_shr:1
+    x += dpp_take<0x112, 0xf>(x);   // row_shr:2
+    x += dpp_take<0x114, 0xf>(x);   // row_shr:4
+    x += dpp_take<0x118, 0xf>(x);   // row_shr:8
+    x += dpp_take<0x142, 0xa>(x);   // row_bcast:15
+    x += dpp_take<0x143, 0xc>(x);   // row_bcast:31
+    return x;
+}
+
+// The same by lane shuffles (LDS round trips, fewer registers): the mixed
+// kernel's called tile setup, where the DPP form's registers cost the bunch loop.
+__device__ __forceinline__ int64_t wave_incl_scan_shfl(int64_t x)
 {
     const int lane = lane_id();
 #pragma unroll
@@ -148,6 +176,14 @@ __device__ __forceinline__ int64_t wave_incl_scan(int64_t x)
         if (lane >= d) x += y;
     }
     return x;
+}
+
+// x of lane 63 (a register read, not an LDS round trip)
+__device__ __forceinline__ int64_t wave_last(int64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, kWave - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), kWave - 1);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // Smallest x over the lanes where it is below `none` (at least one lane is):
@@ -661,7 +697,7 @@ __device__ __noinline__ void soft_list_flush(uint32_t lst_at, uint32_t bits_at, 
     uint64_t word = lane < nw ? bits[lane] : 0ull;
     const int c = __popcll(word);
     const int64_t incl = wave_incl_scan((int64_t)c);
-    const int64_t tot = __shfl(incl, kWave - 1);
+    const int64_t tot = wave_last(incl);
     if (tot == 0) return;
     using GU64 = __attribute__((address_space(1))) unsigned long long;
     unsigned long long* count = (unsigned long long*)reinterpret_cast<GU64*>(l_count);
@@ -788,8 +824,8 @@ __device__ __forceinline__ TileSetup tile_setup(const Args& a, int64_t g0, int n
             }
         }
     }
-    int64_t incl = wave_incl_scan(nb);
-    int64_t total = scalar64(__shfl(incl, kWave - 1));
+    int64_t incl = PREC == 1 ? wave_incl_scan_shfl(nb) : wave_incl_scan(nb);
+    int64_t total = scalar64(wave_last(incl));
     if (total >= ((int64_t)1 << 30)) {
         // bunch offsets inside a tile are 32-bit: refuse such a tile
         if (lane == 0 && a.result) atomicOr(&a.result->error, 2);
@@ -1699,7 +1735,7 @@ __device__ __forceinline__ void add_runs(const Args& a, int64_t t0, int64_t t1, 
         const int n = mine ? a.tile_run_n[t] : 0;
         const int64_t off = mine ? a.tile_run_off[t] : 0;
         const int64_t incl = wave_incl_scan((int64_t)n);
-        const int64_t total = __shfl(incl, kWave - 1);
+        const int64_t total = wave_last(incl);
         // the whole wave runs every round (the shuffles read every lane)
         for (int64_t q0 = 0; q0 < total; q0 += kWave) {
             const int64_t q = q0 + lane;
@@ -1859,7 +1895,7 @@ __global__ void __launch_bounds__(256) rowblock_scan_kernel(Args a)
                     if (bl + j < b_end) col[bl + j] = (int32_t)pre;
                     pre += x[j];
                 }
-                run += __shfl(incl, kWave - 1);
+                run += wave_last(incl);
             }
         }
         if (lane == 0) a.shower_tel[q] = (int32_t)run;
@@ -1889,7 +1925,7 @@ __global__ void __launch_bounds__(64) tile_prefix_kernel(Args a)
         const int n = tl < t1 ? a.tile_run_n[tl] : 0;
         const int64_t off = tl < t1 ? a.tile_run_off[tl] : 0;
         const int64_t incl = wave_incl_scan((int64_t)n);
-        const int64_t total = __shfl(incl, kWave - 1);
+        const int64_t total = wave_last(incl);
         const int my0 = (int)(incl - n);
         const bool in_lds = total <= kPrefixLdsRuns;
         // the block's runs into LDS in flat order, a run per lane (the loads of
@@ -2648,7 +2684,7 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
             if (emits) nb = nbf;
         }
         const int64_t incl = wave_incl_scan(nb);
-        const int64_t total = __shfl(incl, kWave - 1);
+        const int64_t total = wave_last(incl);
         if (total >= ((int64_t)1 << 30)) {
             if (lane == 0 && a.result) atomicOr(&a.result->error, 2);
             continue;
