@@ -384,6 +384,28 @@ def test_maximum_telescope_count(precision):
     say(f"[gpu] 1024 telescopes prec={precision}: {rep}")
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_tile_past_the_bunch_limit_is_refused(precision):
+    """One nearly horizontal 2e9 m step, more than 2^32 bunches, puts its 32-step tile
+    past the 2^30 bunches a tile's offsets allow: the run flags error 2 and leaves that
+    tile out; every other tile's bunches are counted as the oracle counts them (its
+    per-step counts: the oracle itself would emit the long step's bunches one by one)."""
+    wl = synth.vertical_gamma(3000)
+    cfg = oracle.Config.from_workload(wl)
+    s = wl.segs
+    f = {k: getattr(s, k).copy() for k in s.FIELDS}
+    k, w = 100, 5e-6
+    f["length"][k], f["w"][k], f["u"][k], f["v"][k], f["h0"][k] = 2e9, w, np.sqrt(1.0 - w * w), 0.0, 13000.0
+    segs = synth.Segments(*[f[n] for n in s.FIELDS], s.ptype, s.seg_offsets, s.t_ref, s.shower_ids)
+    nb = np.asarray(oracle.segment_details(cfg, segs)["n_b"], dtype=np.int64)
+    assert nb[k] > 2**32
+    t0 = (k // 32) * 32
+    g = gpu_run(wl, precision, segs=segs, tile_segments=32)
+    res = g["result"]
+    assert res["error"] == 2
+    assert res["n_bunches"] == int(nb.sum() - nb[t0:t0 + 32].sum())
+
+
 @pytest.mark.parametrize("n_tel", [128, 129])
 def test_tile_prefix_forms_on_either_side_of_the_switch(n_tel):
     """Up to 128 spheres the per-tile crossing prefix runs as a dense tiles x
