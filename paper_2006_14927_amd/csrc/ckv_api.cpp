@@ -380,6 +380,7 @@ static int array_create(const double* x_m, const double* y_m, const double* r_m,
             tel_screen[4 * k + 1] = y_m[k];
             tel_screen[4 * k + 2] = reff[k];
             tel_screen[4 * k + 3] = reff[k] * reff[k];
+            arr->screen_rmax = std::max(arr->screen_rmax, reff[k]);
         }
         rc = build_array_grid(arr, reff, &arr->soft);
     }

@@ -89,6 +89,8 @@ struct ckv_atmo {
     double n_obs = 1;                // sqrt(1 + psi_0)
     std::vector<double> psi;         // host, n_nodes
     std::vector<double> P;           // host, 5 x n_nodes
+    double psi_min = 0, psi_max = 0; // range of psi over the nodes
+    bool psi_falls = false;          // psi non-increasing with altitude at every node
     double* d_node64 = nullptr;      // device, n_nodes x kNode64
     float* d_cell32 = nullptr;       // device, (n_nodes - 1) x kCell32
     std::vector<double> depth;       // host, n_nodes, vertical depth [g/cm^2]; empty: none
@@ -123,6 +125,7 @@ struct ckv_array {
     ckv_grid hit;                    // radii R (sphere crossings)
     ckv_grid soft;                   // radii sqrt(R^2 + 2 R sigma z_cut) + margin (soft response)
     double soft_sigma = 0;           // 0: no soft grid
+    double screen_rmax = 0;          // largest screening radius (R_s of d_tel_screen)
     double* d_tel_screen = nullptr;  // device, n_tel x 4: X, Y, R_s, R_s^2 with R_s the soft
                                      // cut radius plus kScreenMargin (screening pass)
 };
@@ -136,6 +139,8 @@ int build_atmo_tables(const double* alt, const double* eta, int64_t n, double h_
                       ckv_atmo* a);
 // tables on the input's own altitudes above h_obs (node tables)
 int build_node_tables(const double* alt, const double* eta, int64_t n, double h_obs, ckv_atmo* a);
+// psi_min, psi_max and psi_falls of a's node values
+void psi_range(ckv_atmo* a);
 // depth at the nodes of a (after build_atmo_tables), the same interpolation as eta
 void build_depth_table(const double* alt, const double* depth, int64_t n, ckv_atmo* a);
 int build_array_grid(const ckv_array* arr, const std::vector<double>& radius, ckv_grid* g);

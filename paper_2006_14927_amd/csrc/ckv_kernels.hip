@@ -107,6 +107,11 @@ struct Args {
     uint64_t* list_ids;
     int64_t list_cap;
     int64_t* list_count;
+    // the screening pass's per-step cull (cull_rmax = 0: off): the largest screening
+    // radius; x0 = (psi_max - psi_min) / (1 + psi_min); b0 = x0 times the bound of
+    // |1 - T4(x)| / |x| (1/2 for psi non-increasing with altitude, 4/5 otherwise); a
+    // bound of (n_e / n_obs)^2
+    double cull_rmax, cull_x0, cull_b0, cull_rho2;
 };
 
 // Memory accesses whose address space is explicit.  Where one access may go to LDS
@@ -767,6 +772,16 @@ __host__ __device__ inline size_t search_bytes(int n_nodes)
     return ((size_t)(2 * n_nodes - 1) * sizeof(double) + 15) & ~(size_t)15;
 }
 
+// LDS layout of the bunch kernel: the atmosphere table (whole or in part), the node
+// altitudes of the search variant, then the sphere table {X, Y, R^2}
+template <int PREC, int FEAT>
+__device__ __forceinline__ size_t tel_lds_offset(const Args& a)
+{
+    constexpr bool PARTIAL = (FEAT & (kFeatProfile | kFeatScreen | kFeatNarrow)) != 0;
+    constexpr bool SEARCH = (FEAT & kFeatSearch) != 0;
+    return ((table_bytes(PREC, a.n_nodes, PARTIAL) + 15) & ~(size_t)15) + (SEARCH ? search_bytes(a.n_nodes) : 0);
+}
+
 // sphere table in LDS: {X, Y, R^2} per sphere (at most CKV_MAX_TEL: 24 KB)
 __host__ __device__ inline size_t tel_bytes(int n_tel)
 {
@@ -783,6 +798,59 @@ constexpr int emit_threads(int prec, int feat)
 {
     return (feat & kFeatNarrow) ? 1024
            : (prec == 0 || (feat & (kFeatExact | kFeatCurved | kFeatWide)) != 0) ? 512 : 1024;
+}
+
+// Screening cull (soft response, plane-parallel atmosphere, FP64 pass as computed by
+// soft_bunch).  A step's bunches leave from E(s) = P0 + s a, s in [0, L], in directions
+// p = cos_t a + sin_t e with e a unit vector normal to a.  With T(d) = d_h / w_d
+// (horizontal part over downward cosine) a bunch reaches the ground at
+// g = E_h + T(p) S, where S = int T4(x) dh over the path, T4 the four-term series of
+// (1 + x)^(-1/2) and x = q (psi - psi_e), q = 1 / (n_e w_p)^2 (App. B, the horizontal
+// displacement, here as the moment series).  All of E(s) project along a to one point
+// G = P0_h + (h0 - h_obs) T(a), so g - G = dh (T(p) - T(a)) - T(p) (dh - S), and:
+// |T(p) - T(a)| = sin_t |(e x a)_h| / (w_p w_a), with |(e x a)_h| in [w_a, 1];
+// w_p lies in [cos(zeta_a + t), cos(zeta_a - t)]; for x in [0, 1] (psi non-increasing
+// with altitude) 0 <= 1 - T4(x) <= x/2, for |x| <= 1/2 |1 - T4(x)| <= 4|x|/5; and
+// x <= x0 / w_p^2.  The bunch weights a sphere of radius R centred at c on the ground
+// only if its observed line passes within R of c, so only if |g - c| <= R / w_o, with
+// w_o^2 >= 1 - rho2 (1 - w_p^2).  Hence a step whose sphere centres all lie outside
+// the annulus returned here (centre G, |d^2 - mid| <= half) gives no bunch a soft
+// weight.  The bound takes a margin of 0.1 m plus 1e-6 relative for rounding; it is
+// not applied (false) where its conditions fail: a direction not unit to 1e-9, w_a
+// below 0.05, x0 / w_p^2 above 1/2 or w_o near zero.
+__device__ inline bool screen_annulus(const Args& a, double x0, double y0, double h0, double u,
+                                      double v, double w, double len, double ct, double st,
+                                      double& gx, double& gy, double& mid, double& half)
+{
+    const double n2 = u * u + v * v + w * w;
+    if (!(fabs(n2 - 1.0) <= 1e-9) || !(w >= 0.05)) return false;
+    const double sa = sqrt(fmax(0.0, (1.0 - w) * (1.0 + w)));
+    const double s_hi = st * (1.0 + 1e-9) + 1e-12, s_lo = fmax(st * (1.0 - 1e-9) - 1e-12, 0.0);
+    // w_p of the bunches the FP64 pass keeps (w_p > w_min)
+    const double wp_hi = fmin(1.0, w * ct + sa * s_hi + 1e-12);
+    const double wp_lo = fmax(w * ct - sa * s_hi - 1e-12, a.w_min);
+    if (!(wp_lo > 0.0)) return false;
+    const double iw2 = 1.0 / (wp_lo * wp_lo);
+    if (!(a.cull_x0 * iw2 <= 0.5)) return false;
+    const double B = a.cull_b0 * iw2;                          // bound of |1 - S / dh|
+    const double t_max = sqrt((1.0 - wp_lo) * (1.0 + wp_lo)) / wp_lo;   // bound of |T(p)|
+    const double dh0 = h0 - a.h_obs;
+    const double dh_top = fmax(dh0, 0.0), dh_bot = fmax(dh0 - len * w, 0.0);
+    const double f_lo = s_lo / wp_hi - B * t_max;
+    const double f_hi = s_hi / (wp_lo * w) + B * t_max;
+    const double r_lo = f_lo > 0.0 ? dh_bot * f_lo : 0.0;      // |g - G| in [r_lo, r_hi]
+    const double r_hi = dh_top * f_hi;
+    const double wo2 = 1.0 - fmin(1.0, a.cull_rho2 * (1.0 - wp_lo) * (1.0 + wp_lo));
+    if (!(wo2 > 1e-6)) return false;
+    const double reach = a.cull_rmax / sqrt(wo2);
+    const double m = 0.1 + 1e-6 * (dh_top + r_hi);
+    const double inner = fmax(r_lo - reach - m, 0.0), outer = r_hi + reach + m;
+    const double iw = 1.0 / w;
+    gx = x0 + dh0 * (u * iw);
+    gy = y0 + dh0 * (v * iw);
+    mid = 0.5 * (outer * outer + inner * inner);
+    half = 0.5 * (outer * outer - inner * inner) * (1.0 + 1e-9) + 1e-6;
+    return true;
 }
 
 // Step setups of a tile, one per lane (emitting steps compacted into the stash),
@@ -807,26 +875,68 @@ __device__ __forceinline__ TileSetup tile_setup(const Args& a, int64_t g0, int n
     int64_t nb = 0;
     int status = -2;   // -2: no step in this lane
     Setup st;
+    double len = 0.0;
     if (lane < nseg) {
+        // screening: the frozen count and the length loaded with the step's inputs,
+        // not after them
+        const int64_t f = SCREEN ? a.nb_frozen[g0 + lane] : 0;
+        if (SCREEN) len = a.len[g0 + lane];
         step_setup(a, g0 + lane, st);
         status = st.status;
         if (st.status < 0) nb = st.nb;
         if (SCREEN && st.status < 0) {
             // the soft response's sub-steps: the frozen count, light or not at
             // the current atmosphere decided above
-            const int64_t f = a.nb_frozen[g0 + lane];
             if (f > 0) {
                 nb = f;
-                st.ds = a.len[g0 + lane] / (double)f;
+                st.ds = len / (double)f;
             } else {
                 nb = 0;
                 status = -4;
             }
         }
     }
+    // the tile-size limit on the frozen counts, before the screening cull
+    const int64_t nb_all = nb;
+    if constexpr (SCREEN) {
+        static_assert(TS <= kWave / 2, "the cull splits the spheres between half-waves");
+        extern __shared__ __align__(16) unsigned char lds[];
+        const double* tel_sh = reinterpret_cast<const double*>(lds + tel_lds_offset<PREC, FEAT>(a));
+        // steps whose bunches can weight no sphere are not screened (screen_annulus):
+        // lanes l and l + 32 test the two halves of the sphere table for step l
+        double cgx = 0.0, cgy = 0.0, cmid = 0.0, chalf = -1.0;
+        int ok = 0;
+        if (lane < nseg && status == -1 && a.cull_rmax > 0.0)
+            ok = screen_annulus(a, st.x0, st.y0, st.h0, st.u, st.v, st.w, len, st.cos_t, st.sin_t, cgx, cgy,
+                                cmid, chalf) ? 1 : 0;
+        const int src = lane & (kWave / 2 - 1);
+        const int ok_s = __shfl(ok, src);
+        const double gx = __shfl(cgx, src), gy = __shfl(cgy, src);
+        const double mid = __shfl(cmid, src), half = __shfl(chalf, src);
+        // the lower half-wave tests spheres [0, nh), the upper one [n_tel - nh, n_tel)
+        // (one sphere twice when n_tel is odd): the same count and stride in both, a
+        // uniform loop whose loads are independent of the tests before them
+        const int nh = (a.n_tel + 1) >> 1;
+        const double* tp = tel_sh + 3 * (lane < kWave / 2 ? 0 : a.n_tel - nh);
+        bool reach = false;
+#pragma unroll 4
+        for (int i = 0; i < nh; ++i) {
+            const double dx = tp[3 * i] - gx, dy = tp[3 * i + 1] - gy;
+            reach |= fabs(fma(dy, dy, dx * dx) - mid) <= half;
+        }
+        reach = reach && ok_s;
+        const uint64_t rm = __ballot(reach);
+        const bool reached = (((rm >> src) | (rm >> (src + kWave / 2))) & 1ull) != 0;
+        if (ok && !reached) {
+            nb = 0;
+            status = -4;
+        }
+    }
     int64_t incl = PREC == 1 ? wave_incl_scan_shfl(nb) : wave_incl_scan(nb);
     int64_t total = scalar64(wave_last(incl));
-    if (total >= ((int64_t)1 << 30)) {
+    const int64_t total_all =
+        SCREEN ? scalar64(wave_last(PREC == 1 ? wave_incl_scan_shfl(nb_all) : wave_incl_scan(nb_all))) : total;
+    if (total_all >= ((int64_t)1 << 30)) {
         // bunch offsets inside a tile are 32-bit: refuse such a tile
         if (lane == 0 && a.result) atomicOr(&a.result->error, 2);
         total = 0;
@@ -948,7 +1058,7 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
     if (SEARCH)
         for (int q = threadIdx.x; q < 2 * a.n_nodes - 1; q += blockDim.x) hn_lds[q] = a.hnodes[q];
     // sphere table {X, Y, R^2} after them
-    double* tel_sh = reinterpret_cast<double*>(lds + ((tab_bytes + 15) & ~(size_t)15) + srch_bytes);
+    double* tel_sh = reinterpret_cast<double*>(lds + tel_lds_offset<PREC, FEAT>(a));
     for (int q = threadIdx.x; q < a.n_tel; q += blockDim.x) {
         tel_sh[3 * q] = a.tel[4 * q];
         tel_sh[3 * q + 1] = a.tel[4 * q + 1];
@@ -3295,6 +3405,14 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
         e.list_ids = sp.ids;
         e.list_cap = sp.ids_cap;
         e.list_count = sp.ids_count;
+        // the per-step cull's bound constants (screen_annulus)
+        const ckv_atmo* at = p.atmo;
+        if (ar->screen_rmax > 0.0 && 1.0 + at->psi_min >= 0.5) {
+            e.cull_rmax = ar->screen_rmax;
+            e.cull_x0 = (at->psi_max - at->psi_min) / (1.0 + at->psi_min);
+            e.cull_b0 = (at->psi_falls ? 0.5 : 0.8) * e.cull_x0;
+            e.cull_rho2 = at->psi_falls ? 1.0 : (1.0 + at->psi_max) / (1.0 + at->psi_min);
+        }
         const size_t tab = (table_bytes(1, e.n_nodes, true) + 15) & ~(size_t)15;
         const size_t per = wave_bytes(1, kSoftTS, e.n_tel, 0) + kScreenWaveBytes;
         for (int wv = kMaxEmitWaves; wv >= 1 && !e_waves; wv /= 2)

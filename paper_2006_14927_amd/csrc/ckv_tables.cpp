@@ -71,7 +71,19 @@ int build_atmo_tables(const double* alt, const double* eta, int64_t n, double h_
         }
     }
     a->n_obs = std::sqrt(1.0 + a->psi[0]);
+    psi_range(a);
     return CKV_OK;
+}
+
+void psi_range(ckv_atmo* a)
+{
+    a->psi_min = a->psi_max = a->psi[0];
+    a->psi_falls = true;
+    for (size_t i = 1; i < a->psi.size(); ++i) {
+        a->psi_min = std::min(a->psi_min, a->psi[i]);
+        a->psi_max = std::max(a->psi_max, a->psi[i]);
+        if (!(a->psi[i] <= a->psi[i - 1])) a->psi_falls = false;
+    }
 }
 
 int build_node_tables(const double* alt, const double* eta, int64_t n, double h_obs, ckv_atmo* a)
@@ -108,6 +120,7 @@ int build_node_tables(const double* alt, const double* eta, int64_t n, double h_
         }
     }
     a->n_obs = std::sqrt(1.0 + a->psi[0]);
+    psi_range(a);
     return CKV_OK;
 }
 

@@ -59,11 +59,23 @@ def test_parameterised_tables_and_frozen_counts(small):
     np.testing.assert_array_equal(model.n_b.cpu().numpy(), orc.nb)
 
 
-@pytest.mark.parametrize("which", ["theta0", "target"])
+def bumpy_theta(dw):
+    """theta0 with knots alternating +-0.1: psi rises with altitude at hundreds of
+    nodes, so the screening cull takes its bound for profiles that are not monotone."""
+    th = dw.theta0.copy()
+    th[:dw.n_knots] = 0.1 * (-1.0) ** np.arange(dw.n_knots)
+    return th
+
+
+@pytest.mark.parametrize("which", ["theta0", "target", "bumpy"])
 def test_soft_forward_matches_oracle(small, which):
+    """The listed forward (screening pass with its per-step cull, then FP64 over the
+    list) gives the oracle's S and A, also on a profile that is not monotone."""
     import torch
     dw, orc, model = small
-    th = dw.theta0 if which == "theta0" else dw.theta_target
+    th = {"theta0": dw.theta0, "target": dw.theta_target, "bumpy": bumpy_theta(dw)}[which]
+    if which == "bumpy":
+        assert (np.diff(oracle.tables_from_params(orc.spec, th).psi) > 0).sum() > 100
     S, A = model.forward(th)
     torch.cuda.synchronize()
     So, Ao = orc.SA(th)
