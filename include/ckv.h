@@ -389,7 +389,9 @@ int ckv_array_create_soft(const double* x_m, const double* y_m, const double* r_
 /* Bunch list of the soft response.  With a list, ckv_soft_forward first screens
    every bunch with the mixed-precision path against spheres of the cut radius
    sqrt(R^2 + 2 R sigma 40) plus 1 cm (far above that path's errors), lists the
-   candidates and recomputes only those in FP64 for S and A; the list thus holds
+   candidates and recomputes only those in FP64 for S and A.  Steps whose light
+   provably lands too far from every sphere centre (a bound on the ground ring of
+   the step's cone, refraction included) are not screened.  The list thus holds
    every bunch with z >= -40 at some sphere (the ones that enter S, A and the
    gradient) and a few just outside.  Ids are (global step index << 24) | bunch
    index k, in no particular order.  ckv_soft_backward then recomputes only the
