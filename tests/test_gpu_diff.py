@@ -84,6 +84,32 @@ def test_soft_forward_matches_oracle(small, which):
     np.testing.assert_allclose(A.cpu().numpy(), Ao, rtol=1e-10, atol=1e-12 * np.abs(Ao).max())
 
 
+@pytest.mark.parametrize("n_tel", [1, 37])
+def test_soft_forward_with_odd_sphere_counts(n_tel):
+    """The screening cull splits the sphere table between the two half-waves
+    ([0, nh) and [n - nh, n), one sphere tested twice when n is odd): the listed
+    forward still gives the oracle's S and A with 1 and 37 spheres."""
+    import dataclasses
+    import torch
+    dw = synth.diff_showers(2, 5000)
+    t = synth.telescopes_disk(n=n_tel, disk_radius=300.0, seed=11)
+    dw = dataclasses.replace(dw, tels=t)
+    orc = Oracle(dw)
+    spec = ckv.ParamSpec(dw.eta0, dw.layer_bounds, dw.n_knots, dw.knot_top, dw.obs_level, dw.step,
+                         dw.top)
+    # a list that holds every bunch, so that the forward takes the listed path
+    model = ckv.SoftModel(dw.segs, dw.tels, spec, dw.theta0, dw.sigma, seed=dw.seed,
+                          list_capacity=int(orc.nb.sum()))
+    S, A = model.forward(dw.theta0)
+    torch.cuda.synchronize()
+    n, cap = model.list_state()
+    assert 0 < n <= cap
+    So, Ao = orc.SA(dw.theta0)
+    assert So.sum() > 100
+    np.testing.assert_allclose(S.cpu().numpy(), So, rtol=1e-10, atol=1e-12 * So.max())
+    np.testing.assert_allclose(A.cpu().numpy(), Ao, rtol=1e-10, atol=1e-12 * np.abs(Ao).max())
+
+
 def test_gradient_matches_oracle_finite_differences(small):
     """All 72 coordinates: Richardson-extrapolated central differences of the
     FP64 oracle loss, (4 D(h) - D(2h)) / 3 (plain central differences at
