@@ -853,6 +853,36 @@ __device__ inline bool screen_annulus(const Args& a, double x0, double y0, doubl
     return true;
 }
 
+// The sphere test of the cull for a tile of at most 32 steps, step l in lane l: lanes
+// l and l + 32 test the lower half [0, nh) and the upper half [n_tel - nh, n_tel) of
+// the sphere table (STRIDE doubles per sphere, X and Y first; one sphere twice when
+// n_tel is odd), the same count and stride in both, in a uniform loop whose loads do
+// not wait on the tests before them.  ok: the lane's step has an annulus (gx, gy, mid,
+// half from screen_annulus).  True in lane l < 32 when step l's annulus holds a sphere
+// centre.  Called by the whole wave.
+template <int STRIDE>
+__device__ __forceinline__ bool annulus_holds_centre(const double* tel, int n_tel, int lane, int ok, double gx,
+                                                     double gy, double mid, double half)
+{
+    const int src = lane & (kWave / 2 - 1);
+    const int ok_s = __shfl(ok, src);
+    gx = __shfl(gx, src);
+    gy = __shfl(gy, src);
+    mid = __shfl(mid, src);
+    half = __shfl(half, src);
+    const int nh = (n_tel + 1) >> 1;
+    const double* tp = tel + STRIDE * (lane < kWave / 2 ? 0 : n_tel - nh);
+    bool reach = false;
+#pragma unroll 4
+    for (int i = 0; i < nh; ++i) {
+        const double dx = tp[STRIDE * i] - gx, dy = tp[STRIDE * i + 1] - gy;
+        reach |= fabs(fma(dy, dy, dx * dx) - mid) <= half;
+    }
+    reach = reach && ok_s;
+    const uint64_t rm = __ballot(reach);
+    return (((rm >> src) | (rm >> (src + kWave / 2))) & 1ull) != 0;
+}
+
 // Step setups of a tile, one per lane (emitting steps compacted into the stash),
 // the bunch-count scan and the step-level counters; returns the tile's bunch
 // count and this lane's step state.  Not inlined: the step arrays' pointers and
@@ -902,31 +932,13 @@ __device__ __forceinline__ TileSetup tile_setup(const Args& a, int64_t g0, int n
         static_assert(TS <= kWave / 2, "the cull splits the spheres between half-waves");
         extern __shared__ __align__(16) unsigned char lds[];
         const double* tel_sh = reinterpret_cast<const double*>(lds + tel_lds_offset<PREC, FEAT>(a));
-        // steps whose bunches can weight no sphere are not screened (screen_annulus):
-        // lanes l and l + 32 test the two halves of the sphere table for step l
+        // steps whose bunches can weight no sphere are not screened (screen_annulus)
         double cgx = 0.0, cgy = 0.0, cmid = 0.0, chalf = -1.0;
         int ok = 0;
         if (lane < nseg && status == -1 && a.cull_rmax > 0.0)
             ok = screen_annulus(a, st.x0, st.y0, st.h0, st.u, st.v, st.w, len, st.cos_t, st.sin_t, cgx, cgy,
                                 cmid, chalf) ? 1 : 0;
-        const int src = lane & (kWave / 2 - 1);
-        const int ok_s = __shfl(ok, src);
-        const double gx = __shfl(cgx, src), gy = __shfl(cgy, src);
-        const double mid = __shfl(cmid, src), half = __shfl(chalf, src);
-        // the lower half-wave tests spheres [0, nh), the upper one [n_tel - nh, n_tel)
-        // (one sphere twice when n_tel is odd): the same count and stride in both, a
-        // uniform loop whose loads are independent of the tests before them
-        const int nh = (a.n_tel + 1) >> 1;
-        const double* tp = tel_sh + 3 * (lane < kWave / 2 ? 0 : a.n_tel - nh);
-        bool reach = false;
-#pragma unroll 4
-        for (int i = 0; i < nh; ++i) {
-            const double dx = tp[3 * i] - gx, dy = tp[3 * i + 1] - gy;
-            reach |= fabs(fma(dy, dy, dx * dx) - mid) <= half;
-        }
-        reach = reach && ok_s;
-        const uint64_t rm = __ballot(reach);
-        const bool reached = (((rm >> src) | (rm >> (src + kWave / 2))) & 1ull) != 0;
+        const bool reached = annulus_holds_centre<3>(tel_sh, a.n_tel, lane, ok, cgx, cgy, cmid, chalf);
         if (ok && !reached) {
             nb = 0;
             status = -4;
@@ -2788,17 +2800,32 @@ __global__ void __launch_bounds__(soft_max_waves(MODE) * kWave) soft_kernel(Args
         SoftStep st;
         int64_t nb = 0;
         bool emits = false;
+        double len = 0.0;
         if (lane < nseg) {
             const int64_t nbf = sa.nb_frozen[g0 + lane];
+            len = a.len[g0 + lane];
             emits = soft_step_setup(a, g0 + lane, nbf, st);
             if (emits) nb = nbf;
         }
-        const int64_t incl = wave_incl_scan(nb);
-        const int64_t total = wave_last(incl);
-        if (total >= ((int64_t)1 << 30)) {
+        // the tile limit on the frozen counts, then the cull of the steps whose
+        // bunches can weight no sphere (screen_annulus, as in the screening pass)
+        if (wave_last(wave_incl_scan(nb)) >= ((int64_t)1 << 30)) {
             if (lane == 0 && a.result) atomicOr(&a.result->error, 2);
             continue;
         }
+        if (a.cull_rmax > 0.0) {
+            double cgx = 0.0, cgy = 0.0, cmid = 0.0, chalf = -1.0;
+            const int ok = emits && screen_annulus(a, st.x0, st.y0, st.h0, st.u, st.v, st.w, len, st.cos_t,
+                                                   st.sin_t, cgx, cgy, cmid, chalf) ? 1 : 0;
+            // (called by the whole wave: the upper half-wave tests spheres for the lower one)
+            const bool reached = annulus_holds_centre<4>(tsh, a.n_tel, lane, ok, cgx, cgy, cmid, chalf);
+            if (ok && !reached) {
+                emits = false;
+                nb = 0;
+            }
+        }
+        const int64_t incl = wave_incl_scan(nb);
+        const int64_t total = wave_last(incl);
         const uint64_t emit_mask = __ballot(emits);
         const int excl = (int)(incl - nb);
         if (emits) {
@@ -3352,6 +3379,17 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
     a.tile_segs = kSoftTS;          // the soft kernels walk 32-step tiles
     hipStream_t st = p.stream;
     const ckv_array* ar = p.arr;
+    // the per-step cull's bound constants (screen_annulus), for the screening pass and
+    // the FP64 tile kernels
+    {
+        const ckv_atmo* at = p.atmo;
+        if (ar->screen_rmax > 0.0 && 1.0 + at->psi_min >= 0.5) {
+            a.cull_rmax = ar->screen_rmax;
+            a.cull_x0 = (at->psi_max - at->psi_min) / (1.0 + at->psi_min);
+            a.cull_b0 = (at->psi_falls ? 0.5 : 0.8) * a.cull_x0;
+            a.cull_rho2 = at->psi_falls ? 1.0 : (1.0 + at->psi_max) / (1.0 + at->psi_min);
+        }
+    }
     SoftArgs s{};
     s.nb_frozen = sp.n_b_frozen;
     s.sigma = sp.sigma;
@@ -3405,14 +3443,6 @@ int launch_soft(RunPlan& p, const SoftPlan& sp, int mode)
         e.list_ids = sp.ids;
         e.list_cap = sp.ids_cap;
         e.list_count = sp.ids_count;
-        // the per-step cull's bound constants (screen_annulus)
-        const ckv_atmo* at = p.atmo;
-        if (ar->screen_rmax > 0.0 && 1.0 + at->psi_min >= 0.5) {
-            e.cull_rmax = ar->screen_rmax;
-            e.cull_x0 = (at->psi_max - at->psi_min) / (1.0 + at->psi_min);
-            e.cull_b0 = (at->psi_falls ? 0.5 : 0.8) * e.cull_x0;
-            e.cull_rho2 = at->psi_falls ? 1.0 : (1.0 + at->psi_max) / (1.0 + at->psi_min);
-        }
         const size_t tab = (table_bytes(1, e.n_nodes, true) + 15) & ~(size_t)15;
         const size_t per = wave_bytes(1, kSoftTS, e.n_tel, 0) + kScreenWaveBytes;
         for (int wv = kMaxEmitWaves; wv >= 1 && !e_waves; wv /= 2)

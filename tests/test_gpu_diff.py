@@ -110,6 +110,22 @@ def test_soft_forward_with_odd_sphere_counts(n_tel):
     np.testing.assert_allclose(A.cpu().numpy(), Ao, rtol=1e-10, atol=1e-12 * np.abs(Ao).max())
 
 
+@pytest.mark.parametrize("which", ["theta0", "bumpy"])
+def test_unlisted_forward_matches_oracle(small, which):
+    """Without a list the FP64 tile forward computes S and A from every bunch of
+    the steps the cull keeps: the oracle's S and A, also on a profile that is not
+    monotone."""
+    import torch
+    dw, orc, _ = small
+    th = dw.theta0 if which == "theta0" else bumpy_theta(dw)
+    model = gpu_model_nolist(dw)
+    S, A = model.forward(th)
+    torch.cuda.synchronize()
+    So, Ao = orc.SA(th)
+    np.testing.assert_allclose(S.cpu().numpy(), So, rtol=1e-10, atol=1e-12 * So.max())
+    np.testing.assert_allclose(A.cpu().numpy(), Ao, rtol=1e-10, atol=1e-12 * np.abs(Ao).max())
+
+
 def test_gradient_matches_oracle_finite_differences(small):
     """All 72 coordinates: Richardson-extrapolated central differences of the
     FP64 oracle loss, (4 D(h) - D(2h)) / 3 (plain central differences at
