@@ -1116,6 +1116,12 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
     const double inv_nobs64 = 1.0 / a.n_obs;
     const float d_obs = (float)(a.n_obs - 1.0);
     const float inv_1pdobs = 1.0f / (1.0f + d_obs);
+    // grazing limit of the drop rules, read once (a scalar load in the bunch loop made
+    // its wait cover the loop's LDS reads as well).  Screening keeps bunches down to
+    // w_min - 1e-6, ten times the mixed direction's error: the FP64 candidate pass
+    // applies the exact rule.
+    const double w_graze = __builtin_bit_cast(double, scalar64(__builtin_bit_cast(int64_t,
+                               SCREEN ? a.w_min - 1e-6 : a.w_min)));
 
     int64_t blk = -1;          // current staging block; -1: none yet, -2: staging full
     int blk_fill = 0;
@@ -1400,19 +1406,18 @@ __global__ void __launch_bounds__(emit_threads(PREC, FEAT)) emit_kernel(Args a)
                     pw = fma(ct, tw, -(double)pz);
                 }
                 r2_rec = r2;
-                // drop rules
-                if (he < a.h_obs) drop_why = CKV_DROP_BELOW_OBS;
-                else if (he >= a.h_top) drop_why = CKV_DROP_ABOVE_TOP;
-                else if (!CURVED && pw <= 0.0) drop_why = CKV_DROP_UPWARD;
+                // drop rules, in this order: below the observation level, above the top,
+                // upward, grazing (selects, no branches)
+                const bool d_below = he < a.h_obs, d_above = he >= a.h_top;
+                const bool d_up = !CURVED && pw <= 0.0, d_graze = !CURVED && pw <= w_graze;
+                const bool kept = !d_below && !d_above && !d_up;
+                drop_why = d_below ? CKV_DROP_BELOW_OBS
+                           : d_above ? CKV_DROP_ABOVE_TOP
+                           : d_up ? CKV_DROP_UPWARD
+                           : (d_graze && !EXACT) ? CKV_DROP_GRAZING : -1;
                 // slow: traced exactly, cell by cell (grazing bunches; every bunch when curved,
                 // whose upward and turning drops the tracer decides)
-                bool slow = CURVED && drop_why < 0;
-                // (screening keeps bunches down to w_min - 1e-6, ten times the mixed
-                // direction's error: the FP64 candidate pass applies the exact rule)
-                if (!CURVED && drop_why < 0 && pw <= (SCREEN ? a.w_min - 1e-6 : a.w_min)) {
-                    if (EXACT) slow = true;
-                    else drop_why = CKV_DROP_GRAZING;
-                }
+                bool slow = kept && (CURVED || (EXACT && d_graze));
                 if (SLOWPATH && slow) {
                     alive = true;
                     if (PREC == 1) {
